@@ -1,0 +1,236 @@
+/*
+ * nb6_oracle.c -- FP64 CPU oracle for the regular force of the Ahmad-Cohen
+ * neighbour scheme (Nitadori & Aarseth 2012, "Accelerating NBODY6 with
+ * Graphics Processing Units").
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the reference that the GPU library
+ * is checked against.  Only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark load it.  It shares no code, header or
+ * constant with the HIP library, and the library never calls it.
+ *
+ * Everything is plain IEEE double precision, written as the definitions in
+ * the paper state them, without blocking or reordering:
+ *
+ *   - nb6o_predict: the cubic Taylor predictor of positions and velocities
+ *     to the block time, built from the stored position, velocity,
+ *     acceleration and jerk (section 3.3, step 3, "predict all particles
+ *     needed"; the host routine that predicts all particles in Appendix C,
+ *     Listing C1).
+ *
+ *   - nb6o_regular_force: for each active i and every j != i, the velocity
+ *     neighbour criterion of section 3.2 (the smaller of the two end-point
+ *     distances |R_ij| and |R_ij + dt_reg,i V_ij| compared with h_i), then
+ *     the regular force and its time derivative of section 3.3, step 6
+ *     (the F_reg and dF_reg/dt sums over non-neighbours), and the neighbour
+ *     list L_i of the same step.
+ *
+ *   - nb6o_pair_terms: the same pair quantities for an explicit list of
+ *     (i, j) pairs; the tests use it to treat pairs that sit on the
+ *     neighbour-radius boundary.
+ *
+ * Readings of the paper taken here (each is listed with its reason in the
+ * design notes of the repository):
+ *   - R_ij = R_j - R_i and V_ij = V_j - V_i (section 3.2), G = 1.
+ *   - The neighbour test is strict: j is a neighbour iff
+ *     min(|R|^2, |R + dtr V|^2) < h^2.  Equality contributes force.  The two
+ *     force cases of section 3.3 are written with "> h" and the list with
+ *     "< h"; the appendix kernel (Listing B2) uses the strict "<" for the
+ *     list and adds force otherwise, which is the exact partition used here.
+ *   - Only the two end points of the interval enter the criterion
+ *     (section 3.2), not the closest approach between them.
+ *   - j = i is excluded by index; it is never a neighbour and never a term.
+ *   - Lists are returned in ascending j (section 3.6 relies on the
+ *     sequential ordering of neighbour lists).
+ *   - h^2 must be > 0.
+ *
+ * Sums over j use Neumaier's compensated summation in FP64 so that the
+ * oracle's own rounding error (~1e-16 relative to the sum of |terms|) is far
+ * below the 1e-6 tolerance of the checks that use it.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stddef.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ---------------------------------------------------------------------- */
+/* Neumaier compensated accumulator                                        */
+/* ---------------------------------------------------------------------- */
+typedef struct { double s, c; } nsum;
+
+static void nsum_add(nsum *a, double t)
+{
+    double s = a->s + t;
+    if (fabs(a->s) >= fabs(t))
+        a->c += (a->s - s) + t;
+    else
+        a->c += (t - s) + a->s;
+    a->s = s;
+}
+
+static double nsum_get(const nsum *a) { return a->s + a->c; }
+
+/* ---------------------------------------------------------------------- */
+/* Prediction (section 3.3 step 3; Appendix C predictor call)              */
+/* ---------------------------------------------------------------------- */
+/*
+ * For every particle k: dt = tb - t[k];
+ *   xp = x + v dt + a dt^2/2 + jerk dt^3/6
+ *   vp = v + a dt + jerk dt^2/2
+ * Arrays x, v, a, jerk, xp, vp are [n][3]; t is [n].
+ */
+void nb6o_predict(int64_t n, const double *x, const double *v,
+                  const double *a, const double *jerk, const double *t,
+                  double tb, double *xp, double *vp)
+{
+    for (int64_t k = 0; k < n; ++k) {
+        double dt = tb - t[k];
+        for (int c = 0; c < 3; ++c) {
+            int64_t q = 3 * k + c;
+            xp[q] = x[q] + v[q] * dt + a[q] * dt * dt / 2.0
+                  + jerk[q] * dt * dt * dt / 6.0;
+            vp[q] = v[q] + a[q] * dt + jerk[q] * dt * dt / 2.0;
+        }
+    }
+}
+
+/* ---------------------------------------------------------------------- */
+/* Regular force, jerk and neighbour list (sections 3.2 and 3.3 step 6)    */
+/* ---------------------------------------------------------------------- */
+/*
+ * Inputs
+ *   n            number of j-particles (the whole cluster)
+ *   m[n], xp[n][3], vp[n][3]  predicted j state
+ *   ni           number of active i-particles
+ *   idx[ni]      indices of the active particles (0 <= idx < n)
+ *   h2[ni]       squared neighbour radius of each active particle (> 0)
+ *   dtr[ni]      regular time-step of each active particle
+ *   lcap         capacity of each row of `list`
+ *   nthreads     OpenMP threads (<= 0: library default)
+ * Outputs
+ *   acc[ni][3], jrk[ni][3]  regular force and its time derivative
+ *   nnb[ni]      true neighbour count
+ *   list[ni][lcap]  first min(nnb, lcap) neighbours, ascending j
+ *   sa[ni]       sum over non-neighbours of m_j / r^2        (may be NULL)
+ *   sj[ni]       sum over non-neighbours of
+ *                m_j (|V|/r^3 + 3 |R.V| / r^4)               (may be NULL)
+ * Returns 0, or -1 for a bad index, -2 for h2 <= 0 (nothing is computed
+ * for that i).
+ */
+int nb6o_regular_force(int64_t n, const double *m, const double *xp,
+                       const double *vp, int64_t ni, const int32_t *idx,
+                       const double *h2, const double *dtr,
+                       double *acc, double *jrk, int32_t *nnb,
+                       int32_t *list, int64_t lcap,
+                       double *sa, double *sj, int nthreads)
+{
+    for (int64_t q = 0; q < ni; ++q) {
+        if (idx[q] < 0 || idx[q] >= n) return -1;
+        if (!(h2[q] > 0.0)) return -2;
+    }
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t q = 0; q < ni; ++q) {
+        const int64_t i = idx[q];
+        const double hi2 = h2[q];
+        const double dti = dtr[q];
+        nsum A[3] = {{0, 0}, {0, 0}, {0, 0}};
+        nsum J[3] = {{0, 0}, {0, 0}, {0, 0}};
+        nsum SA = {0, 0}, SJ = {0, 0};
+        int64_t count = 0;
+
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double R[3], V[3], P[3];
+            for (int c = 0; c < 3; ++c) {
+                R[c] = xp[3 * j + c] - xp[3 * i + c];
+                V[c] = vp[3 * j + c] - vp[3 * i + c];
+                P[c] = R[c] + dti * V[c];
+            }
+            double r2 = R[0] * R[0] + R[1] * R[1] + R[2] * R[2];
+            double p2 = P[0] * P[0] + P[1] * P[1] + P[2] * P[2];
+            double rmin2 = (p2 < r2) ? p2 : r2;
+
+            if (rmin2 < hi2) {
+                /* neighbour: listed, no regular force */
+                if (count < lcap) list[q * lcap + count] = (int32_t)j;
+                ++count;
+                continue;
+            }
+            double r = sqrt(r2);
+            double r3 = r2 * r;
+            double r5 = r3 * r2;
+            double rv = R[0] * V[0] + R[1] * V[1] + R[2] * V[2];
+            for (int c = 0; c < 3; ++c) {
+                nsum_add(&A[c], m[j] * R[c] / r3);
+                nsum_add(&J[c], m[j] * (V[c] / r3 - 3.0 * rv * R[c] / r5));
+            }
+            double vabs = sqrt(V[0] * V[0] + V[1] * V[1] + V[2] * V[2]);
+            nsum_add(&SA, m[j] / r2);
+            nsum_add(&SJ, m[j] * (vabs / r3 + 3.0 * fabs(rv) / (r2 * r2)));
+        }
+        for (int c = 0; c < 3; ++c) {
+            acc[3 * q + c] = nsum_get(&A[c]);
+            jrk[3 * q + c] = nsum_get(&J[c]);
+        }
+        nnb[q] = (int32_t)count;
+        if (sa) sa[q] = nsum_get(&SA);
+        if (sj) sj[q] = nsum_get(&SJ);
+    }
+    return 0;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Per-pair quantities for an explicit list of pairs                       */
+/* ---------------------------------------------------------------------- */
+/*
+ * For pair p (i = pi[p], j = pj[p], time-step dtr[p]):
+ *   rmin[p]     = sqrt(min(|R|^2, |R + dtr V|^2))
+ *   dacc[p][3]  = m_j R / r^3
+ *   djrk[p][3]  = m_j (V / r^3 - 3 (R.V) R / r^5)
+ * i.e. the contribution the pair makes to the regular sums when it is not a
+ * neighbour.  Used to move boundary pairs between the neighbour list and the
+ * force sum.
+ */
+void nb6o_pair_terms(int64_t np, const int32_t *pi, const int32_t *pj,
+                     const double *dtr, const double *m, const double *xp,
+                     const double *vp, double *rmin, double *dacc,
+                     double *djrk)
+{
+    for (int64_t p = 0; p < np; ++p) {
+        int64_t i = pi[p], j = pj[p];
+        double R[3], V[3], P[3];
+        for (int c = 0; c < 3; ++c) {
+            R[c] = xp[3 * j + c] - xp[3 * i + c];
+            V[c] = vp[3 * j + c] - vp[3 * i + c];
+            P[c] = R[c] + dtr[p] * V[c];
+        }
+        double r2 = R[0] * R[0] + R[1] * R[1] + R[2] * R[2];
+        double p2 = P[0] * P[0] + P[1] * P[1] + P[2] * P[2];
+        rmin[p] = sqrt((p2 < r2) ? p2 : r2);
+        double r = sqrt(r2);
+        double r3 = r2 * r;
+        double r5 = r3 * r2;
+        double rv = R[0] * V[0] + R[1] * V[1] + R[2] * V[2];
+        for (int c = 0; c < 3; ++c) {
+            dacc[3 * p + c] = m[j] * R[c] / r3;
+            djrk[3 * p + c] = m[j] * (V[c] / r3 - 3.0 * rv * R[c] / r5);
+        }
+    }
+}
+
+/* Number of OpenMP threads a parallel region of this library will use. */
+int nb6o_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

@@ -1,0 +1,245 @@
+"""Pins for the FP64 oracle: checks against facts the paper and mathematics fix.
+
+Each ``pin_*`` function takes the ctypes handle of an oracle build (``None``
+for the default build) and raises ``AssertionError`` when the oracle
+disagrees with:
+
+* hand-derived closed forms (``tests/golden/closed_forms.json``);
+* exact rational arithmetic on tiny random inputs (neighbour decisions and
+  the Taylor predictor);
+* Newton's third law (momentum conservation under a symmetric criterion);
+* a central finite difference of the acceleration along straight-line drift
+  (pins the jerk);
+* the smooth mean field of a Plummer sphere (pins sign, mass and distance
+  powers of the full sum);
+* the limits h -> infinity (everything is a neighbour) and the triangle
+  inequality for the force scales.
+
+The same functions run against deliberately broken builds of the oracle in
+``test_oracle_mutants.py``, which shows that each plausible slip fails at
+least one pin.
+"""
+from __future__ import annotations
+
+import json
+import os
+from fractions import Fraction
+
+import numpy as np
+
+import oracle
+from workloads import make_cluster
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "closed_forms.json")
+
+
+def _close(a, b, tol):
+    a = np.asarray(a, float)
+    b = np.asarray(b, float)
+    return np.all(np.abs(a - b) <= tol * (1.0 + np.abs(b)))
+
+
+# --------------------------------------------------------------------------
+def pin_golden_forces(lib=None):
+    cases = json.load(open(GOLDEN))["force_cases"]
+    for c in cases:
+        m = np.array(c["m"], float)
+        xp = np.array(c["x"], float)
+        vp = np.array(c["v"], float)
+        r = oracle.regular_force(m, xp, vp, c["active"], c["h2"], c["dtr"],
+                                 lcap=16, lib=lib)
+        assert _close(r.acc, c["acc"], 1e-14), (c["name"], r.acc, c["acc"])
+        if c["jerk"] != "skip":
+            assert _close(r.jerk, c["jerk"], 1e-14), (c["name"], r.jerk, c["jerk"])
+        got = [list(map(int, l)) for l in r.lists]
+        assert got == c["lists"], (c["name"], got, c["lists"])
+        assert list(map(int, r.nnb)) == [len(l) for l in c["lists"]], c["name"]
+
+
+def pin_golden_predict(lib=None):
+    cases = json.load(open(GOLDEN))["predict_cases"]
+    for c in cases:
+        xp, vp = oracle.predict(c["x"], c["v"], c["a"], c["jerk"], c["t"],
+                                c["tb"], lib=lib)
+        assert _close(xp, c["xp"], 1e-15), (c["name"], xp)
+        assert _close(vp, c["vp"], 1e-15), (c["name"], vp)
+
+
+# --------------------------------------------------------------------------
+def _tiny_inputs(seed, n=40):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    x = rng.uniform(-1.0, 1.0, (n, 3))
+    v = rng.normal(0.0, 1.0, (n, 3))
+    m = rng.uniform(0.5, 2.0, n) / n
+    h2 = rng.uniform(0.05, 0.6, n) ** 2
+    dtr = 2.0 ** -rng.integers(1, 5, n).astype(float)
+    return m, x, v, h2, dtr
+
+
+def pin_exact_rational_lists(lib=None):
+    """Neighbour sets against exact rational arithmetic on the FP64 inputs."""
+    for seed in (1, 2, 3):
+        m, x, v, h2, dtr = _tiny_inputs(seed)
+        n = len(m)
+        idx = np.arange(n)
+        r = oracle.regular_force(m, x, v, idx, h2, dtr, lcap=n, lib=lib)
+        X = [[Fraction(float(c)) for c in row] for row in x]
+        V = [[Fraction(float(c)) for c in row] for row in v]
+        n_checked = 0
+        for i in range(n):
+            H2 = Fraction(float(h2[i]))
+            D = Fraction(float(dtr[i]))
+            want, tie = [], set()
+            for j in range(n):
+                if j == i:
+                    continue
+                R = [X[j][k] - X[i][k] for k in range(3)]
+                W = [V[j][k] - V[i][k] for k in range(3)]
+                P = [R[k] + D * W[k] for k in range(3)]
+                r2 = sum(c * c for c in R)
+                p2 = sum(c * c for c in P)
+                q = min(r2, p2)
+                if abs(q - H2) <= H2 * Fraction(1, 10 ** 12):
+                    tie.add(j)
+                if q < H2:
+                    want.append(j)
+            got = list(map(int, r.lists[i]))
+            diff = set(got) ^ set(want)
+            assert diff <= tie, (seed, i, sorted(diff))
+            assert got == sorted(got)
+            n_checked += len(want)
+        assert n_checked > 0
+
+
+def pin_exact_rational_predict(lib=None):
+    rng = np.random.Generator(np.random.PCG64(7))
+    n = 12
+    x, v, a, j = (rng.normal(0, 1, (n, 3)) for _ in range(4))
+    t = rng.uniform(0.0, 1.0, n)
+    tb = 1.0 + 2.0 ** -7
+    xp, vp = oracle.predict(x, v, a, j, t, tb, lib=lib)
+    for k in range(n):
+        dt = Fraction(tb) - Fraction(float(t[k]))
+        for c in range(3):
+            X, Vv, A, J = (Fraction(float(q[k, c])) for q in (x, v, a, j))
+            ex = X + Vv * dt + A * dt ** 2 / 2 + J * dt ** 3 / 6
+            ev = Vv + A * dt + J * dt ** 2 / 2
+            sx = abs(X) + abs(Vv * dt) + abs(A * dt ** 2) + abs(J * dt ** 3)
+            sv = abs(Vv) + abs(A * dt) + abs(J * dt ** 2)
+            assert abs(Fraction(float(xp[k, c])) - ex) <= Fraction(1, 10 ** 15) * sx
+            assert abs(Fraction(float(vp[k, c])) - ev) <= Fraction(1, 10 ** 15) * sv
+
+
+# --------------------------------------------------------------------------
+def pin_momentum(lib=None):
+    """Uniform h and dt_reg = 0 make the criterion symmetric: sum m a = 0."""
+    for masses in ("equal", "imf"):
+        cl = make_cluster(512, 99, masses=masses, stored_state=False, k_nb=8)
+        n = cl.n
+        idx = np.arange(n)
+        r = oracle.regular_force(cl.m, cl.x, cl.v, idx, 0.15 ** 2, 0.0,
+                                 lcap=n, lib=lib)
+        assert r.nnb.sum() > n  # the criterion removed some pairs
+        for q in (r.acc, r.jerk):
+            tot = (cl.m[:, None] * q).sum(0)
+            scale = (cl.m * np.linalg.norm(q, axis=1)).sum()
+            assert np.all(np.abs(tot) <= 1e-13 * scale), (masses, tot, scale)
+
+
+def pin_fd_jerk(lib=None):
+    """Jerk = d(acc)/dt along straight-line drift, by central difference."""
+    cl = make_cluster(256, 5, masses="imf", stored_state=False, k_nb=8)
+    n = cl.n
+    idx = np.arange(n)
+    z = np.zeros((n, 3))
+    base = oracle.regular_force(cl.m, cl.x, cl.v, idx, 1e-30, 0.0, lcap=4, lib=lib)
+    d = 1e-6
+    xp, _ = oracle.predict(cl.x, cl.v, z, z, np.zeros(n), d, lib=lib)
+    xm, _ = oracle.predict(cl.x, cl.v, z, z, np.zeros(n), -d, lib=lib)
+    ap = oracle.regular_force(cl.m, xp, cl.v, idx, 1e-30, 0.0, lcap=4, lib=lib).acc
+    am = oracle.regular_force(cl.m, xm, cl.v, idx, 1e-30, 0.0, lcap=4, lib=lib).acc
+    fd = (ap - am) / (2 * d)
+    err = np.linalg.norm(fd - base.jerk, axis=1) / base.sj
+    assert err.max() < 1e-6, err.max()
+
+
+def pin_plummer_mean_field(lib=None):
+    """The regular force of a Plummer sphere follows its smooth mean field.
+
+    With a fixed exclusion radius h and no velocity term, the excluded ball
+    around each particle is nearly uniform, and a uniform ball exerts no
+    force at its own centre; so the regular acceleration follows the Plummer
+    field a(r) = -r (r^2 + b^2)^-3/2 (b = 3 pi/16, G = M = 1); the density
+    gradient across the ball adds its pull (2 pi/3) h^2 grad rho, which is
+    subtracted from the expectation.  The regular jerk holds the neighbour set fixed, so it
+    is the tidal tensor of the mass *outside* the ball applied to the
+    particle's velocity, plus a zero-mean term from the field particles'
+    motion.  The ball's own tidal tensor is -(4 pi/3) rho I, hence
+        J = (T_plummer + (4 pi/3) rho(r) I) v,
+        T_plummer = -I/s^3 + 3 x x^T / s^5,  s^2 = r^2 + b^2,
+        (4 pi/3) rho(r) = b^-3 (1 + r^2/b^2)^-5/2.
+    """
+    cl = make_cluster(16384, 11, masses="equal", stored_state=False, k_nb=8)
+    n = cl.n
+    idx = np.arange(n)
+    r = oracle.regular_force(cl.m, cl.x, cl.v, idx, 0.06 ** 2, 0.0, lcap=4096, lib=lib)
+    b = 3.0 * np.pi / 16.0
+    x, v = cl.x, cl.v
+    s2 = (x * x).sum(1) + b * b
+    rad = np.sqrt((x * x).sum(1))
+    h = 0.06
+    rho0 = 3.0 / (4.0 * np.pi * b ** 3)
+    drho = -5.0 * rho0 * (rad / b ** 2) * (1.0 + rad ** 2 / b ** 2) ** -3.5
+    a_mf = -x / s2[:, None] ** 1.5 - (2.0 * np.pi / 3.0) * h * h * (drho / rad)[:, None] * x
+    tv = -v / s2[:, None] ** 1.5 + 3.0 * ((x * v).sum(1) / s2 ** 2.5)[:, None] * x
+    ball = (1.0 / b ** 3) * (1.0 + rad ** 2 / b ** 2) ** -2.5
+    j_mf = tv + ball[:, None] * v
+    sel = rad < 3.0
+    ca = (r.acc[sel] * a_mf[sel]).sum() / (a_mf[sel] ** 2).sum()
+    cj = (r.jerk[sel] * j_mf[sel]).sum() / (j_mf[sel] ** 2).sum()
+    assert abs(ca - 1.0) < 0.02, ca
+    assert abs(cj - 1.0) < 0.05, cj
+    # radial profile of the acceleration in equal-count bins
+    edges = np.quantile(rad[sel], np.linspace(0, 1, 9))
+    for lo, hi in zip(edges[:-1], edges[1:]):
+        s = sel & (rad >= lo) & (rad < hi)
+        ar = (r.acc[s] * x[s]).sum(1) / rad[s]
+        am = (a_mf[s] * x[s]).sum(1) / rad[s]
+        assert abs(ar.mean() / am.mean() - 1.0) < 0.03, (lo, hi, ar.mean(), am.mean())
+
+
+# --------------------------------------------------------------------------
+def pin_everything_neighbour(lib=None):
+    m, x, v, h2, dtr = _tiny_inputs(4, n=24)
+    n = len(m)
+    r = oracle.regular_force(m, x, v, np.arange(n), 1e30, dtr, lcap=n, lib=lib)
+    assert np.all(r.acc == 0.0) and np.all(r.jerk == 0.0)
+    for i in range(n):
+        assert list(map(int, r.lists[i])) == [j for j in range(n) if j != i]
+    assert np.all(r.nnb == n - 1)
+
+
+def pin_scales_and_truncation(lib=None):
+    m, x, v, h2, dtr = _tiny_inputs(5, n=40)
+    n = len(m)
+    full = oracle.regular_force(m, x, v, np.arange(n), h2, dtr, lcap=n, lib=lib)
+    assert np.all(np.linalg.norm(full.acc, axis=1) <= full.sa * (1 + 1e-14))
+    assert np.all(np.linalg.norm(full.jerk, axis=1) <= full.sj * (1 + 1e-14))
+    short = oracle.regular_force(m, x, v, np.arange(n), h2, dtr, lcap=2, lib=lib)
+    assert np.array_equal(short.nnb, full.nnb)
+    for i in range(n):
+        assert np.array_equal(short.lists[i], full.lists[i][:2])
+    assert np.array_equal(short.acc, full.acc)
+
+
+ALL_PINS = [  # roughly cheapest first
+    pin_golden_forces,
+    pin_golden_predict,
+    pin_everything_neighbour,
+    pin_scales_and_truncation,
+    pin_exact_rational_predict,
+    pin_exact_rational_lists,
+    pin_momentum,
+    pin_fd_jerk,
+    pin_plummer_mean_field,
+]

@@ -1,0 +1,60 @@
+"""Each plausible slip in the oracle fails at least one of its pins.
+
+Every case copies ``oracle/nb6_oracle.c`` to a temporary directory, plants
+one mistake by text substitution, builds it with gcc and runs every pin
+against that build.  The clean oracle passes all pins (``test_oracle.py``);
+a mutant that passed them all would show a blind spot of the pins.
+"""
+import os
+
+import pytest
+
+import oracle
+import oracle_pins as P
+
+SRC = os.path.join(os.path.dirname(oracle.__file__), "nb6_oracle.c")
+
+MUTANTS = {
+    "R_sign": ("R[c] = xp[3 * j + c] - xp[3 * i + c];", "R[c] = xp[3 * i + c] - xp[3 * j + c];"),
+    "V_sign": ("V[c] = vp[3 * j + c] - vp[3 * i + c];", "V[c] = vp[3 * i + c] - vp[3 * j + c];"),
+    "drop_jerk_rv_term": ("m[j] * (V[c] / r3 - 3.0 * rv * R[c] / r5)", "m[j] * (V[c] / r3)"),
+    "jerk_rv_sign": ("m[j] * (V[c] / r3 - 3.0 * rv * R[c] / r5)", "m[j] * (V[c] / r3 + 3.0 * rv * R[c] / r5)"),
+    "jerk_factor_2": ("m[j] * (V[c] / r3 - 3.0 * rv * R[c] / r5)", "m[j] * (V[c] / r3 - 2.0 * rv * R[c] / r5)"),
+    "r_cubed_as_squared": ("double r3 = r2 * r;\n            double r5", "double r3 = r2;\n            double r5"),
+    "r5_as_r4": ("double r5 = r3 * r2;\n            double rv = R[0]", "double r5 = r2 * r2;\n            double rv = R[0]"),
+    "mass_of_i": ("nsum_add(&A[c], m[j] * R[c] / r3);", "nsum_add(&A[c], m[i] * R[c] / r3);"),
+    "no_velocity_criterion": ("P[c] = R[c] + dti * V[c];", "P[c] = R[c];"),
+    "velocity_criterion_backwards": ("P[c] = R[c] + dti * V[c];", "P[c] = R[c] - dti * V[c];"),
+    "max_not_min": ("double rmin2 = (p2 < r2) ? p2 : r2;\n\n", "double rmin2 = (p2 < r2) ? r2 : p2;\n\n"),
+    "tie_is_neighbour": ("if (rmin2 < hi2) {", "if (rmin2 <= hi2) {"),
+    "neighbours_keep_force": ("++count;\n                continue;", "++count;"),
+    "self_not_excluded": ("if (j == i) continue;", ""),
+    "list_stores_i": ("list[q * lcap + count] = (int32_t)j;", "list[q * lcap + count] = (int32_t)i;"),
+    "predict_half_missing": ("a[q] * dt * dt / 2.0\n", "a[q] * dt * dt\n"),
+    "predict_jerk_factorial": ("jerk[q] * dt * dt * dt / 6.0", "jerk[q] * dt * dt * dt / 2.0"),
+    "predict_velocity_jerk": ("vp[q] = v[q] + a[q] * dt + jerk[q] * dt * dt / 2.0;",
+                              "vp[q] = v[q] + a[q] * dt + jerk[q] * dt * dt / 6.0;"),
+    "predict_dt_sign": ("double dt = tb - t[k];", "double dt = t[k] - tb;"),
+    "uncompensated_drop": ("a->c += (a->s - s) + t;", "a->c += 0.0;"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(name, tmp_path):
+    old, new = MUTANTS[name]
+    src = open(SRC).read()
+    assert src.count(old) >= 1, f"mutation site for {name} not found"
+    mutated = src.replace(old, new, 1)
+    path = tmp_path / "mut.c"
+    path.write_text(mutated)
+    so = str(tmp_path / f"libmut_{name}.so")
+    oracle.build(str(path), so)
+    lib = oracle.oracle._load(so)
+    failed = None
+    for pin in P.ALL_PINS:  # cheapest first; the first failure settles it
+        try:
+            pin(lib)
+        except Exception as e:  # noqa: BLE001 - any failure counts
+            failed = (pin.__name__, type(e).__name__)
+            break
+    assert failed, f"mutant {name} passed every pin"
