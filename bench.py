@@ -1,0 +1,199 @@
+#!/usr/bin/env python3
+"""Benchmark of the regular-force path on one MI355X.
+
+One step is one pass of the whole hot path over one block:
+  1. nb6_load_particles  -- corrector update of the active particles' stored
+                            state (device-resident inputs),
+  2. nb6_predict_j       -- FP64 prediction of all N j-particles,
+  3. nb6_regular_force   -- force, jerk and neighbour lists of the block
+                            (force kernel + slice reduction/list gather).
+
+Default workload: Plummer N = 131072 with IMF masses 0.1-100 and 10 %
+primordial binaries, all particles active (1.7e10 pair interactions per
+step), float-float coordinates, neighbour-list capacity 256.
+
+Prints ONE JSON line on stdout.  ``value`` is Ginteractions/s of the whole
+step, N_i (N - 1) / step time.  ``roofline`` rates the force kernel alone:
+53 FP32 operations per interaction (the operation count of the paper's inner
+loop, rsqrt counted once) over its measured launch time, against the
+MI355X FP32 vector peak.  ``cpu_baseline`` is the FP64 oracle timed on the
+host cores for a bounded sample of the same block; its output for that
+sample also gives the ``accuracy`` report of the GPU result.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FLOP_PER_INTERACTION = 53
+FP32_PEAK_TFLOPS = 157.3          # 256 CU x 2.4 GHz x 256 FLOP/clk
+MODES = {"ff": 1, "fp64": 2, "fp32": 4}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(cl, idx, gpu_out, cap, target_s):
+    """Time the oracle on a sample of the block; compare the GPU rows."""
+    import oracle
+    from oracle.compare import compare
+
+    xp, vp = oracle.predict(cl.x, cl.v, cl.a, cl.jerk, cl.t, cl.tb)
+    rng = np.random.Generator(np.random.PCG64(12051222))
+    order = rng.permutation(len(idx))
+    nprobe = min(len(idx), 64)
+    probe = np.sort(order[:nprobe])
+    t0 = time.perf_counter()
+    oracle.regular_force(cl.m, xp, vp, idx[probe], cl.h2[idx[probe]], cl.dtr[idx[probe]],
+                         lcap=4096)
+    tp = time.perf_counter() - t0
+    ns = int(min(len(idx), max(nprobe, nprobe * target_s / max(tp, 1e-6))))
+    samp = np.sort(order[:ns])
+    si = idx[samp]
+    t0 = time.perf_counter()
+    ref = oracle.regular_force(cl.m, xp, vp, si, cl.h2[si], cl.dtr[si], lcap=4096)
+    dt = time.perf_counter() - t0
+    pairs = ns * (cl.n - 1)
+    acc, jerk, nnb, lst = gpu_out
+    c = compare(acc[samp], jerk[samp], nnb[samp], lst[samp], cap, ref, cl.m, xp, vp, si,
+                cl.h2[si], cl.dtr[si])
+    base = {"value": pairs / dt / 1e9, "unit": "Ginteractions/s",
+            "cores": oracle.max_threads(), "kind": "oracle",
+            "sample": f"{ns} of the {len(idx)} active i against all {cl.n} j "
+                      f"({pairs:.3g} pairs, {dt:.1f} s, FP64 C with OpenMP)"}
+    return base, c.summary()
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--mode", default="ff", choices=sorted(MODES))
+    ap.add_argument("--config", type=int, default=3, choices=[1, 2, 3, 5])
+    ap.add_argument("--block", default="all")
+    ap.add_argument("--cap", type=int, default=256)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: --gpus {args.gpus} is not supported: this build measures one "
+              "GPU only (the multi-GPU j-split is a design note, not code).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1205_1222_amd import nb6
+    from workloads import config
+
+    t_gen = time.perf_counter()
+    cfg = config(args.config)
+    cl = cfg["cluster"]
+    idx_np = cfg["blocks"][args.block]
+    n, ni = cl.n, len(idx_np)
+    log(f"bench: config {args.config} ({cfg['description']}), block {args.block}: "
+        f"N={n} N_i={ni}, inputs in {time.perf_counter() - t_gen:.1f} s")
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    T = lambda a, dt=torch.float64: torch.from_numpy(np.ascontiguousarray(a)).to(dev, dt)  # noqa: E731
+    m_d, x_d, v_d, a_d, j_d, t_d = (T(q) for q in (cl.m, cl.x, cl.v, cl.a, cl.jerk, cl.t))
+    idx_d = T(idx_np, torch.int32)
+    # corrector output of the active particles (device-resident)
+    um_d, ux_d, uv_d, ua_d, uj_d, ut_d = (
+        T(q[idx_np]) for q in (cl.m, cl.x, cl.v, cl.a, cl.jerk, cl.t))
+    h2_d = T(cl.h2[idx_np])
+    dtr_d = T(cl.dtr[idx_np])
+    acc = torch.empty((ni, 3), dtype=torch.float64, device=dev)
+    jerk = torch.empty_like(acc)
+    nnb = torch.empty(ni, dtype=torch.int32, device=dev)
+    lst = torch.empty((ni, max(args.cap, 1)), dtype=torch.int32, device=dev)
+    mode = MODES[args.mode]
+
+    ctx = nb6.nb6_create(0, flags=nb6.NB6_OPT_TIMING)
+    nb6.check(ctx, nb6.nb6_load_particles(ctx, 0, n, m_d, x_d, v_d, a_d, j_d, t_d,
+                                          mem_kind=nb6.NB6_MEM_DEVICE, stream=stream))
+
+    def step():
+        nb6.check(ctx, nb6.nb6_load_particles(ctx, 0, ni, um_d, ux_d, uv_d, ua_d, uj_d, ut_d,
+                                              idx_d, nb6.NB6_MEM_DEVICE, stream))
+        nb6.check(ctx, nb6.nb6_predict_j(ctx, 0, cl.tb, mode, stream))
+        nb6.check(ctx, nb6.nb6_regular_force(ctx, 0, ni, idx_d, h2_d, dtr_d, mode, acc, jerk,
+                                             nnb, lst, args.cap, nb6.NB6_MEM_DEVICE, stream))
+
+    for w in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    nb6.check(ctx, nb6.nb6_sync_status(ctx, stream))
+    nb6.nb6_kernel_times(ctx)  # drop the warm-up launches
+    log(f"bench: warm-up done ({args.warmup} steps), slices={nb6.nb6_last_slices(ctx)}")
+
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for k in range(args.steps):
+        step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_k, cnt_k = nb6.nb6_kernel_times(ctx)
+    nb6.check(ctx, nb6.nb6_sync_status(ctx, stream))
+    ev_ms = ev0.elapsed_time(ev1)
+    log(f"bench: {args.steps} steps in {wall * 1e3:.2f} ms wall, {ev_ms:.2f} ms events; "
+        f"kernel ms (predict, force, finalize) = {ms_k.round(4).tolist()}")
+
+    pairs = ni * (n - 1)
+    ms_step = wall * 1e3 / args.steps
+    value = pairs / (ms_step * 1e-3) / 1e9
+    regf_ms = ms_k[1] / max(cnt_k[1], 1)
+    achieved = FLOP_PER_INTERACTION * pairs / (regf_ms * 1e-3) / 1e12
+    out = {
+        "metric": "Ginteractions/s regular force+jerk+nblist, %FP32 peak; p50/p99 block latency",
+        "value": round(value, 3),
+        "unit": "Ginteractions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": cfg["description"] + f"; block {args.block}",
+            "N": n, "N_i": ni, "dx_mode": args.mode, "list_cap": args.cap,
+            "seed": cfg["seed"], "slices": nb6.nb6_last_slices(ctx),
+        },
+        "pct_fp32_peak": round(100.0 * achieved / FP32_PEAK_TFLOPS, 2),
+        "kernel_ginteractions_s": round(pairs / (regf_ms * 1e-3) / 1e9, 3),
+        "kernel_ms": {"predict": ms_k[0] / max(cnt_k[0], 1), "force": regf_ms,
+                      "finalize": ms_k[2] / max(cnt_k[2], 1)},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3),
+                     "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": None},
+    }
+    if not args.no_cpu_baseline:
+        gpu_out = (acc.cpu().numpy(), jerk.cpu().numpy(), nnb.cpu().numpy(),
+                   lst[:, :args.cap].cpu().numpy())
+        log("bench: timing the FP64 oracle on a sample of the block ...")
+        base, accuracy = cpu_baseline(cl, idx_np, gpu_out, args.cap, args.cpu_seconds)
+        out["cpu_baseline"] = base
+        out["accuracy"] = accuracy
+    nb6.nb6_destroy(ctx)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

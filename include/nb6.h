@@ -1,0 +1,189 @@
+/*
+ * nb6.h -- C ABI of the MI355X regular-force library.
+ *
+ * The library computes, for a block of active i-particles of a star cluster,
+ * the regular part of the Ahmad-Cohen force split: the acceleration and its
+ * time derivative (jerk) due to every j-particle outside the i-particle's
+ * neighbour sphere, and the list of j-particles inside it (Nitadori &
+ * Aarseth 2012, section 3.3 step 6, with the velocity neighbour criterion of
+ * section 3.2).  It plays the part of the paper's regular-force library
+ * (open / send / regular force / close, section 3.4 and Appendix C) with the
+ * j-particle prediction (section 3.3 step 3) moved onto the GPU.
+ *
+ * Conventions for every entry point
+ *   - Return value: NB6_OK (0) on success, a positive warning, or a negative
+ *     error code.  Nothing throws across the ABI.  nb6_last_error() returns
+ *     a text description of the last failure on a context.
+ *   - Units: G = 1.  R_ij = R_j - R_i, V_ij = V_j - V_i.
+ *   - Vectors are row-major [n][3] arrays of double (x, y, z per particle).
+ *   - mem_kind NB6_MEM_HOST: every array argument of the call is host
+ *     memory; the call returns when the results are in place.
+ *     mem_kind NB6_MEM_DEVICE: every array argument is device memory of the
+ *     context's GPU; the call is ordered on `stream` and returns without
+ *     waiting for the GPU.  Validation that needs device data is then done on
+ *     the GPU and reported by nb6_sync_status().
+ *   - stream is a hipStream_t (NULL: the null stream).  Calls that share a
+ *     context share its scratch buffers and must be ordered on one stream.
+ *   - The caller owns every array it passes; the library reads inputs and
+ *     writes outputs only during the call (HOST) or the stream-ordered work
+ *     the call enqueues (DEVICE).  The context owns all device state and
+ *     scratch and frees it in nb6_destroy().
+ */
+#ifndef NB6_H
+#define NB6_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define NB6_OK                  0
+#define NB6_WARN_NB_OVERFLOW    1   /* some i had more neighbours than cap   */
+#define NB6_ERR_ARG           (-1)  /* bad argument (index, size, h2, mode)  */
+#define NB6_ERR_STATE         (-2)  /* cluster missing or not predicted      */
+#define NB6_ERR_NOMEM         (-3)  /* device allocation failed              */
+#define NB6_ERR_ADMISSION     (-4)  /* request can never fit the HBM budget  */
+#define NB6_ERR_UNKNOWN_TICKET (-5) /* nb6_poll on a ticket never issued     */
+#define NB6_ERR_HIP           (-6)  /* HIP runtime error                     */
+#define NB6_ERR_DEVICE_INPUT  (-7)  /* GPU-side validation found bad input   */
+#define NB6_PENDING             2   /* nb6_poll: request not finished yet    */
+
+/* ---- memory kinds and coordinate-difference modes --------------------- */
+#define NB6_MEM_HOST    0
+#define NB6_MEM_DEVICE  1
+
+/*
+ * How the coordinate difference R_j - R_i is formed before the FP32 force
+ * arithmetic.  The paper's GPU default kept FP32 coordinates and left the
+ * 'two-float' form as an option (section 3.4 and its footnote); GPUIRR always
+ * uses two-float coordinates (section 3.5).
+ */
+#define NB6_DX_FF    1   /* float-float (hi + lo) coordinates, default   */
+#define NB6_DX_FP64  2   /* double coordinates, difference in FP64       */
+#define NB6_DX_FP32  4   /* plain float coordinates (the paper's default) */
+#define NB6_DX_ALL   7
+
+typedef struct nb6_ctx nb6_ctx;
+
+typedef struct nb6_options {
+    int     device;        /* HIP device ordinal                              */
+    int     slice_hint;    /* 0: choose the j-split per call; >0: force it    */
+    int64_t hbm_budget;    /* bytes the serving queue may hold; 0: 1/4 of free */
+    int     flags;         /* NB6_OPT_* bits                                  */
+} nb6_options;
+
+/* Record HIP events around every predictor, force and finalize launch so
+ * that nb6_kernel_times() can report their GPU durations. */
+#define NB6_OPT_TIMING 1
+
+/*
+ * Create a context on options->device (NULL options: device 0, defaults).
+ * *out receives the context.  Errors: NB6_ERR_ARG, NB6_ERR_HIP.
+ */
+int nb6_create(nb6_ctx **out, const nb6_options *options);
+
+/* Free every device buffer of the context.  NULL is accepted. */
+int nb6_destroy(nb6_ctx *ctx);
+
+/* Text of the last error on ctx (never NULL; "" when none). */
+const char *nb6_last_error(const nb6_ctx *ctx);
+
+/*
+ * Load or update the state of cluster `cluster` (0 <= cluster < 4096): the
+ * corrected mass, position, velocity, acceleration, jerk and time of each
+ * particle -- the data the host integrator keeps per body and from which
+ * the predictor works (section 3.3 step 3; Appendix C sends the predicted
+ * j-particles to the regular-force library before each regular block).
+ *
+ *   idx == NULL: full load.  n is the cluster size; m[n], x/v/a/jerk[n][3],
+ *                t[n].  Replaces any previous state of that cluster.
+ *   idx != NULL: update n existing particles; entry k of every array
+ *                belongs to particle idx[k].  0 <= idx[k] < cluster size.
+ * The cluster must be predicted again (nb6_predict_j) before the next force
+ * call.  Errors: NB6_ERR_ARG (n <= 0, bad idx, non-finite host data),
+ * NB6_ERR_NOMEM, NB6_ERR_HIP.
+ */
+int nb6_load_particles(nb6_ctx *ctx, int cluster, int64_t n,
+                       const double *m, const double *x, const double *v,
+                       const double *a, const double *jerk, const double *t,
+                       const int32_t *idx, int mem_kind, void *stream);
+
+/*
+ * Predict every particle of the cluster to t_block with the cubic Taylor
+ * series (section 3.3 step 3):
+ *   dt = t_block - t_j;  x_p = x + v dt + a dt^2/2 + jerk dt^3/6;
+ *   v_p = v + a dt + jerk dt^2/2     (FP64),
+ * and write the j-streams the force kernel reads for every coordinate mode
+ * in the bit mask `modes` (NB6_DX_*; 0 means all).  Errors: NB6_ERR_STATE
+ * (cluster not loaded), NB6_ERR_ARG, NB6_ERR_HIP.
+ */
+int nb6_predict_j(nb6_ctx *ctx, int cluster, double t_block, int modes,
+                  void *stream);
+
+/*
+ * Regular force, jerk and neighbour list of n_i active particles of the
+ * cluster, against all N predicted particles (section 3.3 step 6 with the
+ * velocity criterion of section 3.2):
+ *   j (!= i) is a neighbour iff min(|R|^2, |R + dtr_i V|^2) < h2_i;
+ *   otherwise it adds m_j R / r^3 to acc_i and
+ *   m_j (V / r^3 - 3 (R.V) R / r^5) to jerk_i.
+ * Inputs:  idx_i[n_i] (cluster indices, 0 <= idx_i < N), h2_i[n_i]
+ *          (squared neighbour radii, > 0 and >= 2^-126 as floats),
+ *          dtr_i[n_i] (regular time-steps), dx_mode (one NB6_DX_* value,
+ *          whose stream the last nb6_predict_j wrote), cap >= 0.
+ * Outputs: acc[n_i][3], jerk[n_i][3] (double), nnb[n_i] (true neighbour
+ *          count, self excluded), list[n_i][cap] (the first min(nnb, cap)
+ *          neighbours in ascending cluster index; entries past that are
+ *          left unspecified).  list may be NULL when cap == 0.
+ * The neighbour decision and the force arithmetic are done in FP32 (the
+ * coordinate difference per dx_mode), the sums are compensated, and the
+ * outputs are double.
+ * Returns NB6_OK, or NB6_WARN_NB_OVERFLOW (HOST mode only) when some nnb
+ * exceeds cap.  Errors: NB6_ERR_ARG, NB6_ERR_STATE, NB6_ERR_NOMEM,
+ * NB6_ERR_HIP.  n_i == 0 is a no-op.
+ */
+int nb6_regular_force(nb6_ctx *ctx, int cluster, int64_t n_i,
+                      const int32_t *idx_i, const double *h2_i,
+                      const double *dtr_i, int dx_mode, double *acc,
+                      double *jerk, int32_t *nnb, int32_t *list, int32_t cap,
+                      int mem_kind, void *stream);
+
+/*
+ * Wait for `stream` and return (and clear) the GPU-side validation state of
+ * the context: NB6_OK, or NB6_ERR_DEVICE_INPUT when a DEVICE-mode call met
+ * an out-of-range index, an h2 that is not a positive normal float, or a
+ * non-finite predicted coordinate.  Results of such a call are NaN for the
+ * offending i.
+ */
+int nb6_sync_status(nb6_ctx *ctx, void *stream);
+
+/*
+ * Read back the predicted positions and velocities of every particle of the
+ * cluster as the j-stream of `dx_mode` holds them (NB6_DX_FF: hi + lo,
+ * NB6_DX_FP64: the FP64 prediction, NB6_DX_FP32: the float), widened to
+ * double: x[N][3], v[N][3].  For checks of the predictor (section 3.3 step 3)
+ * and for callers that want the predicted state.  Errors: NB6_ERR_STATE when
+ * that stream is not current, NB6_ERR_ARG, NB6_ERR_NOMEM, NB6_ERR_HIP.
+ */
+int nb6_get_predicted(nb6_ctx *ctx, int cluster, int dx_mode, double *x, double *v,
+                      int mem_kind, void *stream);
+
+/*
+ * With NB6_OPT_TIMING: wait for the recorded launches and return, for the
+ * launches since the previous call, ms[0] = total predictor time,
+ * ms[1] = total force-kernel time, ms[2] = total finalize time, and
+ * counts[0..2] = the number of launches of each.  The record is then cleared.
+ * Errors: NB6_ERR_STATE when timing is off, NB6_ERR_HIP.
+ */
+int nb6_kernel_times(nb6_ctx *ctx, double *ms, int64_t *counts);
+
+/* Number of j-slices (the j-split across workgroups) the last force call
+ * used; for diagnostics and tests. */
+int nb6_last_slices(const nb6_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NB6_H */

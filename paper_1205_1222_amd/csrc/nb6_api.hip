@@ -1,0 +1,572 @@
+// nb6_api.hip -- the C ABI of include/nb6.h: contexts, cluster state,
+// argument checking, work partitioning and kernel launches.
+#include "../../include/nb6.h"
+#include "nb6_internal.h"
+
+#include <algorithm>
+#include <cfloat>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace nb6;
+
+namespace {
+
+constexpr int kMaxClusters = 4096;
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t cap = 0;
+};
+
+struct ClusterState {
+    int64_t n = 0;
+    double* state = nullptr;   // m[n] t[n] x[3n] v[3n] a[3n] jk[3n]
+    double *m = nullptr, *t = nullptr, *x = nullptr, *v = nullptr, *a = nullptr, *jk = nullptr;
+    DevBuf rec[3];             // j-records by mode index
+    int pred_valid = 0;        // NB6_DX_* bits whose records are current
+    double t_pred = 0.0;
+};
+
+int mode_index(int dx_mode) {
+    switch (dx_mode) {
+        case NB6_DX_FF: return MODE_FF;
+        case NB6_DX_FP64: return MODE_F64;
+        case NB6_DX_FP32: return MODE_F32;
+        default: return -1;
+    }
+}
+
+size_t rec_size(int mi) {
+    return mi == MODE_FF ? sizeof(RecFF) : mi == MODE_F64 ? sizeof(RecF64) : sizeof(RecF32);
+}
+
+}  // namespace
+
+struct nb6_ctx {
+    int device = 0;
+    int num_cu = 256;
+    int slice_hint = 0;
+    int64_t hbm_budget = 0;
+    std::vector<ClusterState*> clusters;
+    DevBuf part, cnt, lst;                       // force-kernel scratch
+    DevBuf in_idx, in_h2, in_dtr;                // HOST-mode inputs
+    DevBuf out_acc, out_jerk, out_nnb, out_list; // HOST-mode outputs
+    DevBuf ld[7];                                // HOST-mode load staging
+    unsigned* status = nullptr;                  // device status word
+    std::string err;
+    int last_slices = 0;
+    bool timing = false;
+    struct Timed { int kind; hipEvent_t a, b; };
+    std::vector<Timed> timed;                    // pending event pairs
+};
+
+namespace {
+
+int fail(nb6_ctx* c, int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    return code;
+}
+
+#define HIP_TRY(ctx, call)                                                          \
+    do {                                                                            \
+        hipError_t e_ = (call);                                                     \
+        if (e_ != hipSuccess)                                                       \
+            return fail((ctx), NB6_ERR_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+// Grow a device buffer to at least `bytes`.  Growing waits for the device,
+// because earlier stream-ordered work may still use the old allocation.
+int ensure(nb6_ctx* c, DevBuf& b, size_t bytes) {
+    if (bytes <= b.cap) return NB6_OK;
+    size_t want = std::max(bytes, b.cap + b.cap / 2);
+    HIP_TRY(c, hipDeviceSynchronize());
+    if (b.p) {
+        HIP_TRY(c, hipFree(b.p));
+        b.p = nullptr;
+        b.cap = 0;
+    }
+    if (hipMalloc(&b.p, want) != hipSuccess) {
+        (void)hipGetLastError();
+        b.p = nullptr;
+        if (hipMalloc(&b.p, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            b.p = nullptr;
+            return fail(c, NB6_ERR_NOMEM, "device allocation of %zu bytes failed", bytes);
+        }
+        want = bytes;
+    }
+    b.cap = want;
+    return NB6_OK;
+}
+
+void release(DevBuf& b) {
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.cap = 0;
+}
+
+bool finite_all(const double* p, int64_t n) {
+    for (int64_t k = 0; k < n; ++k)
+        if (!std::isfinite(p[k])) return false;
+    return true;
+}
+
+// Event pair around one launch when timing is on (kind: 0 predict, 1 force,
+// 2 finalize).
+struct TimedLaunch {
+    nb6_ctx* c;
+    int kind;
+    hipStream_t st;
+    hipEvent_t a = nullptr, b = nullptr;
+    TimedLaunch(nb6_ctx* c_, int k, hipStream_t s) : c(c_), kind(k), st(s) {
+        if (!c->timing) return;
+        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+            a = b = nullptr;
+            return;
+        }
+        (void)hipEventRecord(a, st);
+    }
+    void done() {
+        if (!a) return;
+        (void)hipEventRecord(b, st);
+        c->timed.push_back({kind, a, b});
+        a = b = nullptr;
+    }
+};
+
+// Wave-level work partition of one force call.
+struct Plan {
+    int ipl, wpb, nslices, slice_len;
+};
+
+Plan make_plan(const nb6_ctx* c, int64_t n, int64_t ni) {
+    Plan p;
+    p.ipl = ni >= 16384 ? 2 : 1;
+    const int64_t groups = (ni + 64 * p.ipl - 1) / (64 * p.ipl);
+    p.wpb = (int)std::min<int64_t>(4, groups);
+    // Enough waves for ~8 per SIMD across the chip; no slice shorter than
+    // 256 j-particles so the per-slice overhead stays small.
+    const int64_t target = (int64_t)c->num_cu * 4 * 8;
+    int64_t s = c->slice_hint > 0 ? c->slice_hint : (target + groups - 1) / groups;
+    s = std::max<int64_t>(1, std::min<int64_t>(s, (n + 255) / 256));
+    s = std::min<int64_t>(s, 65535);
+    int64_t len = (n + s - 1) / s;
+    len = (len + 3) / 4 * 4;
+    p.slice_len = (int)len;
+    p.nslices = (int)((n + len - 1) / len);
+    return p;
+}
+
+}  // namespace
+
+extern "C" {
+
+int nb6_create(nb6_ctx** out, const nb6_options* opt) {
+    if (!out) return NB6_ERR_ARG;
+    *out = nullptr;
+    nb6_ctx* c = new nb6_ctx();
+    if (opt) {
+        c->device = opt->device;
+        c->slice_hint = opt->slice_hint;
+        c->hbm_budget = opt->hbm_budget;
+        c->timing = (opt->flags & NB6_OPT_TIMING) != 0;
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || c->device < 0 || c->device >= ndev) {
+        delete c;
+        return NB6_ERR_ARG;
+    }
+    if (hipSetDevice(c->device) != hipSuccess) {
+        delete c;
+        return NB6_ERR_HIP;
+    }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, c->device) == hipSuccess && prop.multiProcessorCount > 0)
+        c->num_cu = prop.multiProcessorCount;
+    if (hipMalloc(&c->status, 4 * sizeof(unsigned)) != hipSuccess) {
+        delete c;
+        return NB6_ERR_NOMEM;
+    }
+    if (launch_zero_u32(c->status, 4, nullptr) != hipSuccess ||
+        hipDeviceSynchronize() != hipSuccess) {
+        (void)hipFree(c->status);
+        delete c;
+        return NB6_ERR_HIP;
+    }
+    if (c->hbm_budget <= 0) {
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) == hipSuccess) c->hbm_budget = (int64_t)(fr / 4);
+    }
+    c->clusters.assign(kMaxClusters, nullptr);
+    *out = c;
+    return NB6_OK;
+}
+
+int nb6_destroy(nb6_ctx* c) {
+    if (!c) return NB6_OK;
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    for (ClusterState* cl : c->clusters) {
+        if (!cl) continue;
+        if (cl->state) (void)hipFree(cl->state);
+        for (auto& r : cl->rec) release(r);
+        delete cl;
+    }
+    for (DevBuf* b : {&c->part, &c->cnt, &c->lst, &c->in_idx, &c->in_h2, &c->in_dtr,
+                      &c->out_acc, &c->out_jerk, &c->out_nnb, &c->out_list})
+        release(*b);
+    for (auto& b : c->ld) release(b);
+    if (c->status) (void)hipFree(c->status);
+    for (auto& t : c->timed) {
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
+    }
+    delete c;
+    return NB6_OK;
+}
+
+int nb6_kernel_times(nb6_ctx* c, double* ms, int64_t* counts) {
+    if (!c || !ms || !counts) return NB6_ERR_ARG;
+    if (!c->timing) return fail(c, NB6_ERR_STATE, "context created without NB6_OPT_TIMING");
+    HIP_TRY(c, hipSetDevice(c->device));
+    for (int k = 0; k < 3; ++k) { ms[k] = 0.0; counts[k] = 0; }
+    int rc = NB6_OK;
+    for (auto& t : c->timed) {
+        float e = 0.0f;
+        if (hipEventSynchronize(t.b) != hipSuccess || hipEventElapsedTime(&e, t.a, t.b) != hipSuccess)
+            rc = fail(c, NB6_ERR_HIP, "event timing failed");
+        ms[t.kind] += e;
+        counts[t.kind] += 1;
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
+    }
+    c->timed.clear();
+    return rc;
+}
+
+const char* nb6_last_error(const nb6_ctx* c) { return c ? c->err.c_str() : "no context"; }
+
+int nb6_last_slices(const nb6_ctx* c) { return c ? c->last_slices : 0; }
+
+int nb6_load_particles(nb6_ctx* c, int cluster, int64_t n, const double* m, const double* x,
+                       const double* v, const double* a, const double* jerk, const double* t,
+                       const int32_t* idx, int mem_kind, void* stream) {
+    if (!c) return NB6_ERR_ARG;
+    c->err.clear();
+    if (cluster < 0 || cluster >= kMaxClusters)
+        return fail(c, NB6_ERR_ARG, "cluster %d out of range [0, %d)", cluster, kMaxClusters);
+    if (n <= 0 || n > INT32_MAX) return fail(c, NB6_ERR_ARG, "n = %lld out of range", (long long)n);
+    if (!m || !x || !v || !a || !jerk || !t) return fail(c, NB6_ERR_ARG, "null state array");
+    if (mem_kind != NB6_MEM_HOST && mem_kind != NB6_MEM_DEVICE)
+        return fail(c, NB6_ERR_ARG, "bad mem_kind %d", mem_kind);
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(c, hipSetDevice(c->device));
+    ClusterState*& cl = c->clusters[cluster];
+
+    if (mem_kind == NB6_MEM_HOST) {
+        if (!finite_all(m, n) || !finite_all(t, n) || !finite_all(x, 3 * n) ||
+            !finite_all(v, 3 * n) || !finite_all(a, 3 * n) || !finite_all(jerk, 3 * n))
+            return fail(c, NB6_ERR_ARG, "non-finite value in the particle state");
+    }
+    const hipMemcpyKind kind =
+        mem_kind == NB6_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+
+    if (!idx) {  // full load
+        if (!cl) cl = new ClusterState();
+        if (cl->n != n) {
+            HIP_TRY(c, hipDeviceSynchronize());
+            if (cl->state) HIP_TRY(c, hipFree(cl->state));
+            cl->state = nullptr;
+            cl->n = 0;
+            if (hipMalloc(&cl->state, (size_t)14 * n * sizeof(double)) != hipSuccess) {
+                (void)hipGetLastError();
+                cl->state = nullptr;
+                return fail(c, NB6_ERR_NOMEM, "cluster state of %lld particles", (long long)n);
+            }
+            cl->n = n;
+            cl->m = cl->state;
+            cl->t = cl->m + n;
+            cl->x = cl->t + n;
+            cl->v = cl->x + 3 * n;
+            cl->a = cl->v + 3 * n;
+            cl->jk = cl->a + 3 * n;
+        }
+        HIP_TRY(c, hipMemcpyAsync(cl->m, m, n * sizeof(double), kind, st));
+        HIP_TRY(c, hipMemcpyAsync(cl->t, t, n * sizeof(double), kind, st));
+        HIP_TRY(c, hipMemcpyAsync(cl->x, x, 3 * n * sizeof(double), kind, st));
+        HIP_TRY(c, hipMemcpyAsync(cl->v, v, 3 * n * sizeof(double), kind, st));
+        HIP_TRY(c, hipMemcpyAsync(cl->a, a, 3 * n * sizeof(double), kind, st));
+        HIP_TRY(c, hipMemcpyAsync(cl->jk, jerk, 3 * n * sizeof(double), kind, st));
+        if (mem_kind == NB6_MEM_HOST) HIP_TRY(c, hipStreamSynchronize(st));
+        cl->pred_valid = 0;
+        return NB6_OK;
+    }
+
+    // subset update
+    if (!cl || cl->n == 0) return fail(c, NB6_ERR_STATE, "cluster %d is not loaded", cluster);
+    if (n > cl->n) return fail(c, NB6_ERR_ARG, "subset of %lld > cluster size", (long long)n);
+    ScatterArgs sa{};
+    sa.n = n;
+    sa.limit = cl->n;
+    sa.status = c->status;
+    sa.dm = cl->m; sa.dt = cl->t; sa.dx = cl->x; sa.dv = cl->v; sa.da = cl->a; sa.djk = cl->jk;
+    if (mem_kind == NB6_MEM_HOST) {
+        for (int64_t k = 0; k < n; ++k)
+            if (idx[k] < 0 || idx[k] >= cl->n)
+                return fail(c, NB6_ERR_ARG, "idx[%lld] = %d out of range", (long long)k, idx[k]);
+        const size_t sz[7] = {n * sizeof(int32_t), n * sizeof(double), n * sizeof(double),
+                              3 * n * sizeof(double), 3 * n * sizeof(double),
+                              3 * n * sizeof(double), 3 * n * sizeof(double)};
+        const void* src[7] = {idx, m, t, x, v, a, jerk};
+        for (int k = 0; k < 7; ++k) {
+            int rc = ensure(c, c->ld[k], sz[k]);
+            if (rc) return rc;
+            HIP_TRY(c, hipMemcpyAsync(c->ld[k].p, src[k], sz[k], hipMemcpyHostToDevice, st));
+        }
+        sa.idx = (const int32_t*)c->ld[0].p;
+        sa.m = (const double*)c->ld[1].p;
+        sa.t = (const double*)c->ld[2].p;
+        sa.x = (const double*)c->ld[3].p;
+        sa.v = (const double*)c->ld[4].p;
+        sa.a = (const double*)c->ld[5].p;
+        sa.jk = (const double*)c->ld[6].p;
+    } else {
+        sa.idx = idx; sa.m = m; sa.t = t; sa.x = x; sa.v = v; sa.a = a; sa.jk = jerk;
+    }
+    HIP_TRY(c, launch_scatter(sa, st));
+    if (mem_kind == NB6_MEM_HOST) HIP_TRY(c, hipStreamSynchronize(st));
+    cl->pred_valid = 0;
+    return NB6_OK;
+}
+
+int nb6_predict_j(nb6_ctx* c, int cluster, double t_block, int modes, void* stream) {
+    if (!c) return NB6_ERR_ARG;
+    c->err.clear();
+    if (cluster < 0 || cluster >= kMaxClusters || !c->clusters[cluster] ||
+        c->clusters[cluster]->n == 0)
+        return fail(c, NB6_ERR_STATE, "cluster %d is not loaded", cluster);
+    if (modes == 0) modes = NB6_DX_ALL;
+    if (modes & ~NB6_DX_ALL) return fail(c, NB6_ERR_ARG, "bad modes mask %d", modes);
+    if (!std::isfinite(t_block)) return fail(c, NB6_ERR_ARG, "non-finite t_block");
+    HIP_TRY(c, hipSetDevice(c->device));
+    ClusterState* cl = c->clusters[cluster];
+    PredictArgs pa{};
+    pa.n = cl->n;
+    pa.m = cl->m; pa.x = cl->x; pa.v = cl->v; pa.a = cl->a; pa.jk = cl->jk; pa.t = cl->t;
+    pa.tb = t_block;
+    pa.status = c->status;
+    const int bits[3] = {NB6_DX_FF, NB6_DX_FP64, NB6_DX_FP32};
+    for (int mi = 0; mi < 3; ++mi) {
+        if (!(modes & bits[mi])) continue;
+        int rc = ensure(c, cl->rec[mi], (size_t)cl->n * rec_size(mi));
+        if (rc) return rc;
+    }
+    pa.ff = (modes & NB6_DX_FF) ? (RecFF*)cl->rec[MODE_FF].p : nullptr;
+    pa.f64 = (modes & NB6_DX_FP64) ? (RecF64*)cl->rec[MODE_F64].p : nullptr;
+    pa.f32 = (modes & NB6_DX_FP32) ? (RecF32*)cl->rec[MODE_F32].p : nullptr;
+    TimedLaunch tl(c, 0, (hipStream_t)stream);
+    HIP_TRY(c, launch_predict(pa, (hipStream_t)stream));
+    tl.done();
+    cl->pred_valid = modes;
+    cl->t_pred = t_block;
+    return NB6_OK;
+}
+
+int nb6_regular_force(nb6_ctx* c, int cluster, int64_t n_i, const int32_t* idx_i,
+                      const double* h2_i, const double* dtr_i, int dx_mode, double* acc,
+                      double* jerk, int32_t* nnb, int32_t* list, int32_t cap, int mem_kind,
+                      void* stream) {
+    if (!c) return NB6_ERR_ARG;
+    c->err.clear();
+    if (cluster < 0 || cluster >= kMaxClusters || !c->clusters[cluster] ||
+        c->clusters[cluster]->n == 0)
+        return fail(c, NB6_ERR_STATE, "cluster %d is not loaded", cluster);
+    ClusterState* cl = c->clusters[cluster];
+    const int mi = mode_index(dx_mode);
+    if (mi < 0) return fail(c, NB6_ERR_ARG, "bad dx_mode %d", dx_mode);
+    if (!(cl->pred_valid & dx_mode))
+        return fail(c, NB6_ERR_STATE, "cluster %d has no current prediction for dx_mode %d",
+                    cluster, dx_mode);
+    if (n_i < 0 || n_i > INT32_MAX / 2) return fail(c, NB6_ERR_ARG, "n_i = %lld", (long long)n_i);
+    if (cap < 0) return fail(c, NB6_ERR_ARG, "cap = %d < 0", cap);
+    if (mem_kind != NB6_MEM_HOST && mem_kind != NB6_MEM_DEVICE)
+        return fail(c, NB6_ERR_ARG, "bad mem_kind %d", mem_kind);
+    if (n_i == 0) return NB6_OK;
+    if (!idx_i || !h2_i || !dtr_i || !acc || !jerk || !nnb || (cap > 0 && !list))
+        return fail(c, NB6_ERR_ARG, "null argument");
+    HIP_TRY(c, hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t n = cl->n;
+    const int ni = (int)n_i;
+
+    const int32_t* d_idx = idx_i;
+    const double* d_h2 = h2_i;
+    const double* d_dtr = dtr_i;
+    double* d_acc = acc;
+    double* d_jerk = jerk;
+    int32_t* d_nnb = nnb;
+    int32_t* d_list = list;
+    if (mem_kind == NB6_MEM_HOST) {
+        for (int q = 0; q < ni; ++q) {
+            if (idx_i[q] < 0 || idx_i[q] >= n)
+                return fail(c, NB6_ERR_ARG, "idx_i[%d] = %d out of range", q, idx_i[q]);
+            const float h2f = (float)h2_i[q];
+            if (!(h2f >= FLT_MIN) || !(h2f <= FLT_MAX))
+                return fail(c, NB6_ERR_ARG, "h2_i[%d] = %g is not a positive normal float", q,
+                            h2_i[q]);
+            if (!std::isfinite(dtr_i[q]))
+                return fail(c, NB6_ERR_ARG, "dtr_i[%d] is not finite", q);
+        }
+        int rc;
+        if ((rc = ensure(c, c->in_idx, ni * sizeof(int32_t))) ||
+            (rc = ensure(c, c->in_h2, ni * sizeof(double))) ||
+            (rc = ensure(c, c->in_dtr, ni * sizeof(double))) ||
+            (rc = ensure(c, c->out_acc, 3 * ni * sizeof(double))) ||
+            (rc = ensure(c, c->out_jerk, 3 * ni * sizeof(double))) ||
+            (rc = ensure(c, c->out_nnb, ni * sizeof(int32_t))) ||
+            (rc = ensure(c, c->out_list, std::max<size_t>(1, (size_t)ni * cap) * sizeof(int32_t))))
+            return rc;
+        HIP_TRY(c, hipMemcpyAsync(c->in_idx.p, idx_i, ni * sizeof(int32_t), hipMemcpyHostToDevice, st));
+        HIP_TRY(c, hipMemcpyAsync(c->in_h2.p, h2_i, ni * sizeof(double), hipMemcpyHostToDevice, st));
+        HIP_TRY(c, hipMemcpyAsync(c->in_dtr.p, dtr_i, ni * sizeof(double), hipMemcpyHostToDevice, st));
+        d_idx = (const int32_t*)c->in_idx.p;
+        d_h2 = (const double*)c->in_h2.p;
+        d_dtr = (const double*)c->in_dtr.p;
+        d_acc = (double*)c->out_acc.p;
+        d_jerk = (double*)c->out_jerk.p;
+        d_nnb = (int32_t*)c->out_nnb.p;
+        d_list = (int32_t*)c->out_list.p;
+    }
+
+    const Plan p = make_plan(c, n, ni);
+    const int caps = cap + 1;  // room for the i-particle itself
+    int rc;
+    if ((rc = ensure(c, c->part, (size_t)p.nslices * NPART * ni * sizeof(double))) ||
+        (rc = ensure(c, c->cnt, (size_t)p.nslices * ni * sizeof(int32_t))) ||
+        (rc = ensure(c, c->lst, (size_t)p.nslices * ni * caps * sizeof(int32_t))))
+        return rc;
+
+    RegfArgs ra{};
+    ra.rec = cl->rec[mi].p;
+    ra.n = (int)n;
+    ra.idx = d_idx;
+    ra.h2 = d_h2;
+    ra.dtr = d_dtr;
+    ra.ni = ni;
+    ra.slice_len = p.slice_len;
+    ra.nslices = p.nslices;
+    ra.part = (double*)c->part.p;
+    ra.cnt = (int32_t*)c->cnt.p;
+    ra.lst = (int32_t*)c->lst.p;
+    ra.caps = caps;
+    ra.status = c->status;
+    {
+        TimedLaunch tl(c, 1, st);
+        HIP_TRY(c, launch_regf(mi, p.ipl, p.wpb, ra, st));
+        tl.done();
+    }
+
+    FinalArgs fa{};
+    fa.part = ra.part;
+    fa.cnt = ra.cnt;
+    fa.lst = ra.lst;
+    fa.nslices = p.nslices;
+    fa.ni = ni;
+    fa.caps = caps;
+    fa.n = (int)n;
+    fa.idx = d_idx;
+    fa.h2 = d_h2;
+    fa.acc = d_acc;
+    fa.jerk = d_jerk;
+    fa.nnb = d_nnb;
+    fa.list = d_list;
+    fa.cap = cap;
+    fa.status = c->status;
+    {
+        TimedLaunch tl(c, 2, st);
+        HIP_TRY(c, launch_finalize(fa, st));
+        tl.done();
+    }
+    c->last_slices = p.nslices;
+
+    if (mem_kind == NB6_MEM_DEVICE) return NB6_OK;
+
+    HIP_TRY(c, hipMemcpyAsync(acc, d_acc, 3 * ni * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(c, hipMemcpyAsync(jerk, d_jerk, 3 * ni * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(c, hipMemcpyAsync(nnb, d_nnb, ni * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    if (cap > 0)
+        HIP_TRY(c, hipMemcpyAsync(list, d_list, (size_t)ni * cap * sizeof(int32_t),
+                                  hipMemcpyDeviceToHost, st));
+    unsigned status[4];
+    HIP_TRY(c, hipMemcpyAsync(status, c->status, sizeof status, hipMemcpyDeviceToHost, st));
+    HIP_TRY(c, hipStreamSynchronize(st));
+    HIP_TRY(c, launch_zero_u32(c->status, 4, st));
+    if (status[0] & (ST_BAD_INDEX | ST_BAD_H2 | ST_NONFINITE))
+        return fail(c, NB6_ERR_DEVICE_INPUT, "GPU validation flagged 0x%x", status[0]);
+    for (int q = 0; q < ni; ++q)
+        if (nnb[q] > cap) return NB6_WARN_NB_OVERFLOW;
+    return NB6_OK;
+}
+
+int nb6_get_predicted(nb6_ctx* c, int cluster, int dx_mode, double* x, double* v,
+                      int mem_kind, void* stream) {
+    if (!c) return NB6_ERR_ARG;
+    c->err.clear();
+    if (cluster < 0 || cluster >= kMaxClusters || !c->clusters[cluster] ||
+        c->clusters[cluster]->n == 0)
+        return fail(c, NB6_ERR_STATE, "cluster %d is not loaded", cluster);
+    ClusterState* cl = c->clusters[cluster];
+    const int mi = mode_index(dx_mode);
+    if (mi < 0) return fail(c, NB6_ERR_ARG, "bad dx_mode %d", dx_mode);
+    if (!(cl->pred_valid & dx_mode))
+        return fail(c, NB6_ERR_STATE, "no current prediction for dx_mode %d", dx_mode);
+    if (!x || !v) return fail(c, NB6_ERR_ARG, "null output");
+    if (mem_kind != NB6_MEM_HOST && mem_kind != NB6_MEM_DEVICE)
+        return fail(c, NB6_ERR_ARG, "bad mem_kind %d", mem_kind);
+    HIP_TRY(c, hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t n = cl->n;
+    double* dx = x;
+    double* dv = v;
+    if (mem_kind == NB6_MEM_HOST) {
+        int rc;
+        if ((rc = ensure(c, c->out_acc, 3 * n * sizeof(double))) ||
+            (rc = ensure(c, c->out_jerk, 3 * n * sizeof(double))))
+            return rc;
+        dx = (double*)c->out_acc.p;
+        dv = (double*)c->out_jerk.p;
+    }
+    HIP_TRY(c, launch_unpack(mi, cl->rec[mi].p, n, dx, dv, st));
+    if (mem_kind == NB6_MEM_HOST) {
+        HIP_TRY(c, hipMemcpyAsync(x, dx, 3 * n * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIP_TRY(c, hipMemcpyAsync(v, dv, 3 * n * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIP_TRY(c, hipStreamSynchronize(st));
+    }
+    return NB6_OK;
+}
+
+int nb6_sync_status(nb6_ctx* c, void* stream) {
+    if (!c) return NB6_ERR_ARG;
+    HIP_TRY(c, hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)stream;
+    unsigned status[4];
+    HIP_TRY(c, hipMemcpyAsync(status, c->status, sizeof status, hipMemcpyDeviceToHost, st));
+    HIP_TRY(c, hipStreamSynchronize(st));
+    HIP_TRY(c, launch_zero_u32(c->status, 4, st));
+    HIP_TRY(c, hipStreamSynchronize(st));
+    if (status[0] & (ST_BAD_INDEX | ST_BAD_H2 | ST_NONFINITE))
+        return fail(c, NB6_ERR_DEVICE_INPUT, "GPU validation flagged 0x%x", status[0]);
+    return NB6_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,216 @@
+"""ctypes binding of ``libnb6.so`` (the C ABI of ``include/nb6.h``).
+
+Argument marshalling only: every step of the regular-force path runs in the
+HIP library.  The functions keep the C names.  Array arguments may be
+
+* numpy arrays (host memory, ``NB6_MEM_HOST`` calls),
+* torch tensors on the GPU (``NB6_MEM_DEVICE`` calls), or
+* raw integer addresses.
+
+Streams are ``torch.cuda.Stream`` objects, raw ``hipStream_t`` integers, or
+``None`` for the null stream.
+
+torch is imported before the library is loaded so that the process holds a
+single HIP runtime (torch ships its own; the library binds to it by soname).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch  # noqa: F401  (loads the HIP runtime the library binds to)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnb6.so")
+
+NB6_OK = 0
+NB6_WARN_NB_OVERFLOW = 1
+NB6_PENDING = 2
+NB6_ERR_ARG = -1
+NB6_ERR_STATE = -2
+NB6_ERR_NOMEM = -3
+NB6_ERR_ADMISSION = -4
+NB6_ERR_UNKNOWN_TICKET = -5
+NB6_ERR_HIP = -6
+NB6_ERR_DEVICE_INPUT = -7
+
+NB6_MEM_HOST = 0
+NB6_MEM_DEVICE = 1
+
+NB6_DX_FF = 1
+NB6_DX_FP64 = 2
+NB6_DX_FP32 = 4
+NB6_DX_ALL = 7
+
+EXPORTED = [
+    "nb6_create", "nb6_destroy", "nb6_last_error", "nb6_load_particles",
+    "nb6_predict_j", "nb6_regular_force", "nb6_sync_status", "nb6_last_slices",
+    "nb6_get_predicted", "nb6_kernel_times",
+]
+
+NB6_OPT_TIMING = 1
+
+
+class nb6_options(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int), ("slice_hint", ctypes.c_int),
+                ("hbm_budget", ctypes.c_int64), ("flags", ctypes.c_int)]
+
+
+class NB6Error(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"nb6 error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(
+                f"{LIB_PATH} is missing: build it with "
+                "`python -m paper_1205_1222_amd.build` (there is no fallback)")
+        L = ctypes.CDLL(LIB_PATH)
+        vp = ctypes.c_void_p
+        i64 = ctypes.c_int64
+        L.nb6_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(nb6_options)]
+        L.nb6_destroy.argtypes = [vp]
+        L.nb6_last_error.argtypes = [vp]
+        L.nb6_last_error.restype = ctypes.c_char_p
+        L.nb6_last_slices.argtypes = [vp]
+        L.nb6_load_particles.argtypes = [vp, ctypes.c_int, i64, vp, vp, vp, vp, vp, vp, vp,
+                                         ctypes.c_int, vp]
+        L.nb6_predict_j.argtypes = [vp, ctypes.c_int, ctypes.c_double, ctypes.c_int, vp]
+        L.nb6_regular_force.argtypes = [vp, ctypes.c_int, i64, vp, vp, vp, ctypes.c_int,
+                                        vp, vp, vp, vp, ctypes.c_int32, ctypes.c_int, vp]
+        L.nb6_sync_status.argtypes = [vp, vp]
+        L.nb6_kernel_times.argtypes = [vp, vp, vp]
+        L.nb6_get_predicted.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp, ctypes.c_int, vp]
+        for name in EXPORTED:
+            if name != "nb6_last_error":
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(a, dtype=None):
+    """Address of a numpy array / torch tensor / int (None -> 0)."""
+    if a is None:
+        return None
+    if isinstance(a, int):
+        return a
+    if isinstance(a, np.ndarray):
+        if not a.flags["C_CONTIGUOUS"]:
+            raise ValueError("arrays must be C-contiguous")
+        if dtype is not None and a.dtype != dtype:
+            raise TypeError(f"expected {np.dtype(dtype)}, got {a.dtype}")
+        return a.ctypes.data
+    if isinstance(a, torch.Tensor):
+        if not a.is_contiguous():
+            raise ValueError("tensors must be contiguous")
+        if dtype is not None and a.dtype != _TORCH[np.dtype(dtype)]:
+            raise TypeError(f"expected {np.dtype(dtype)}, got {a.dtype}")
+        return a.data_ptr()
+    raise TypeError(f"unsupported array type {type(a)}")
+
+
+_TORCH = {np.dtype(np.float64): torch.float64, np.dtype(np.int32): torch.int32,
+          np.dtype(np.float32): torch.float32}
+
+
+def _stream(s):
+    if s is None:
+        return None
+    if isinstance(s, int):
+        return s
+    return s.cuda_stream
+
+
+def check(ctx, rc, allow=(NB6_OK,)):
+    if rc in allow:
+        return rc
+    msg = lib().nb6_last_error(ctx)
+    raise NB6Error(rc, msg.decode() if msg else "")
+
+
+# ---- the C entry points ---------------------------------------------------
+def nb6_create(device=0, slice_hint=0, hbm_budget=0, flags=0):
+    h = ctypes.c_void_p()
+    opt = nb6_options(device, slice_hint, hbm_budget, flags)
+    rc = lib().nb6_create(ctypes.byref(h), ctypes.byref(opt))
+    if rc != NB6_OK:
+        raise NB6Error(rc, "nb6_create failed")
+    return h.value
+
+
+def nb6_destroy(ctx):
+    return lib().nb6_destroy(ctx)
+
+
+def nb6_last_error(ctx):
+    return lib().nb6_last_error(ctx).decode()
+
+
+def nb6_last_slices(ctx):
+    return lib().nb6_last_slices(ctx)
+
+
+def nb6_load_particles(ctx, cluster, n, m, x, v, a, jerk, t, idx=None,
+                       mem_kind=NB6_MEM_HOST, stream=None):
+    f = np.float64
+    return lib().nb6_load_particles(
+        ctx, cluster, n, _ptr(m, f), _ptr(x, f), _ptr(v, f), _ptr(a, f),
+        _ptr(jerk, f), _ptr(t, f), _ptr(idx, np.int32), mem_kind, _stream(stream))
+
+
+def nb6_predict_j(ctx, cluster, t_block, modes=0, stream=None):
+    return lib().nb6_predict_j(ctx, cluster, float(t_block), modes, _stream(stream))
+
+
+def nb6_regular_force(ctx, cluster, n_i, idx_i, h2_i, dtr_i, dx_mode, acc, jerk,
+                      nnb, nblist, cap, mem_kind=NB6_MEM_HOST, stream=None):
+    f = np.float64
+    return lib().nb6_regular_force(
+        ctx, cluster, n_i, _ptr(idx_i, np.int32), _ptr(h2_i, f), _ptr(dtr_i, f),
+        dx_mode, _ptr(acc, f), _ptr(jerk, f), _ptr(nnb, np.int32),
+        _ptr(nblist, np.int32), cap, mem_kind, _stream(stream))
+
+
+def nb6_get_predicted(ctx, cluster, dx_mode, x, v, mem_kind=NB6_MEM_HOST, stream=None):
+    f = np.float64
+    return lib().nb6_get_predicted(ctx, cluster, dx_mode, _ptr(x, f), _ptr(v, f), mem_kind,
+                                   _stream(stream))
+
+
+def nb6_kernel_times(ctx):
+    """(ms[3], counts[3]) for predictor, force and finalize launches."""
+    ms = np.zeros(3)
+    counts = np.zeros(3, np.int64)
+    rc = lib().nb6_kernel_times(ctx, ms.ctypes.data, counts.ctypes.data)
+    check(ctx, rc)
+    return ms, counts
+
+
+def nb6_sync_status(ctx, stream=None):
+    return lib().nb6_sync_status(ctx, _stream(stream))
+
+
+# ---- convenience: allocate outputs, raise on errors ------------------------
+def regular_force_host(ctx, cluster, idx_i, h2_i, dtr_i, dx_mode=NB6_DX_FF, cap=256):
+    """Host-memory call; returns (acc, jerk, nnb, lists, status)."""
+    idx_i = np.ascontiguousarray(idx_i, dtype=np.int32)
+    ni = len(idx_i)
+    h2_i = np.ascontiguousarray(np.broadcast_to(h2_i, (ni,)), dtype=np.float64)
+    dtr_i = np.ascontiguousarray(np.broadcast_to(dtr_i, (ni,)), dtype=np.float64)
+    acc = np.empty((ni, 3))
+    jerk = np.empty((ni, 3))
+    nnb = np.empty(ni, np.int32)
+    lst = np.empty((ni, max(cap, 1)), np.int32)
+    rc = nb6_regular_force(ctx, cluster, ni, idx_i, h2_i, dtr_i, dx_mode, acc, jerk,
+                           nnb, lst if cap > 0 else None, cap, NB6_MEM_HOST)
+    check(ctx, rc, (NB6_OK, NB6_WARN_NB_OVERFLOW))
+    return acc, jerk, nnb, lst[:, :cap], rc

@@ -1,0 +1,311 @@
+"""GPU parity: the HIP path against the FP64 oracle, through the C ABI.
+
+Bars (see the design notes for their derivation):
+* neighbour lists: exact, except pairs within 1e-6 (relative) of the
+  neighbour radius, which may fall on either side;
+* FF and FP64 coordinate modes: per-particle force and jerk errors scaled by
+  the sum of term magnitudes <= 1e-6; relative to the net value <= 1e-6
+  wherever the net acceleration is at least 1e-3 of its scale and the net
+  jerk at least 0.1 of its scale (below that, FP32 rounding of the individual
+  terms, about 1e-7 of the scale, can exceed 1e-6 of the net value);
+* FP32 coordinate mode (the paper's plain single precision): scaled errors
+  <= 1e-4, list mismatches reported.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+from oracle.compare import compare  # noqa: E402
+from workloads import config, make_cluster  # noqa: E402
+
+MODES = {"ff": 1, "fp64": 2, "fp32": 4}
+TOL_SCALED = {"ff": 1e-6, "fp64": 1e-6, "fp32": 1e-4}
+TOL_REL = {"ff": 1e-6, "fp64": 1e-6, "fp32": None}
+OUT = os.path.join(os.path.dirname(os.path.dirname(__file__)), "gpurun_out")
+
+
+def _nb6():
+    from paper_1205_1222_amd import nb6
+    return nb6
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    nb6 = _nb6()
+    c = nb6.nb6_create(0)
+    yield c
+    nb6.nb6_destroy(c)
+
+
+def _record(name, summary):
+    os.makedirs(OUT, exist_ok=True)
+    with open(os.path.join(OUT, "parity_summaries.jsonl"), "a") as f:
+        f.write(json.dumps({"case": name, **summary}) + "\n")
+    print(name, json.dumps(summary), flush=True)
+
+
+def load(ctx, cl, cluster=0):
+    nb6 = _nb6()
+    nb6.check(ctx, nb6.nb6_load_particles(ctx, cluster, cl.n, cl.m, cl.x, cl.v, cl.a,
+                                          cl.jerk, cl.t))
+    nb6.check(ctx, nb6.nb6_predict_j(ctx, cluster, cl.tb, 0))
+
+
+def oracle_ref(cl, idx, lcap=4096):
+    xp, vp = oracle.predict(cl.x, cl.v, cl.a, cl.jerk, cl.t, cl.tb)
+    ref = oracle.regular_force(cl.m, xp, vp, idx, cl.h2[idx], cl.dtr[idx], lcap=lcap)
+    return xp, vp, ref
+
+
+def check_mode(ctx, cl, idx, mode, name, cap=512, ref=None, cluster=0):
+    nb6 = _nb6()
+    if ref is None:
+        ref = oracle_ref(cl, idx)
+    xp, vp, r = ref
+    acc, jerk, nnb, lst, rc = nb6.regular_force_host(ctx, cluster, idx, cl.h2[idx],
+                                                     cl.dtr[idx], MODES[mode], cap)
+    c = compare(acc, jerk, nnb, lst, cap, r, cl.m, xp, vp, idx, cl.h2[idx], cl.dtr[idx])
+    s = c.summary()
+    s["mode"] = mode
+    s["slices"] = nb6.nb6_last_slices(ctx)
+    _record(name, s)
+    assert c.incomplete == 0
+    if mode != "fp32":
+        assert c.list_mismatch == 0, c.mismatches[:10]
+        assert c.nnb_mismatch == 0
+    else:
+        assert c.list_mismatch <= max(1, len(idx) // 100), c.mismatches[:10]
+    assert s["acc_scaled_max"] <= TOL_SCALED[mode], s
+    assert s["jerk_scaled_max"] <= TOL_SCALED[mode], s
+    if TOL_REL[mode] is not None:
+        assert s.get("acc_rel_max", 0.0) <= TOL_REL[mode], s
+        assert s.get("jerk_rel_max", 0.0) <= TOL_REL[mode], s
+    return acc, jerk, nnb, lst
+
+
+# ---------------------------------------------------------------------------
+def test_predict_matches_oracle(ctx):
+    nb6 = _nb6()
+    cl = config(2, n=4096)["cluster"]
+    load(ctx, cl)
+    xo, vo = oracle.predict(cl.x, cl.v, cl.a, cl.jerk, cl.t, cl.tb)
+    for mode, tol_x in (("fp64", 1e-15), ("ff", 1e-14), ("fp32", 2.0 ** -23)):
+        x = np.empty((cl.n, 3))
+        v = np.empty((cl.n, 3))
+        nb6.check(ctx, nb6.nb6_get_predicted(ctx, 0, MODES[mode], x, v))
+        scale = np.abs(cl.x) + np.abs(cl.v) + np.abs(cl.a) + np.abs(cl.jerk) + 1e-300
+        ex = np.max(np.abs(x - xo) / scale)
+        ev = np.max(np.abs(v - vo) / (np.abs(vo) + 1e-300))
+        print(mode, "predict", ex, ev, flush=True)
+        assert ex <= tol_x, (mode, ex)
+        assert ev <= 2.0 ** -24, (mode, ev)
+
+
+@pytest.mark.parametrize("mode", ["ff", "fp64", "fp32"])
+def test_config1_all_active(ctx, mode):
+    cfg = config(1)
+    cl = cfg["cluster"]
+    idx = cfg["blocks"]["all"]
+    load(ctx, cl)
+    check_mode(ctx, cl, idx, mode, f"C1_all_{mode}")
+
+
+@pytest.mark.parametrize("mode", ["ff", "fp64"])
+def test_config2_random_block(ctx, mode):
+    cfg = config(2)
+    cl = cfg["cluster"]
+    idx = cfg["blocks"]["random1024"]
+    load(ctx, cl)
+    check_mode(ctx, cl, idx, mode, f"C2_random1024_{mode}")
+
+
+def test_ragged_sizes_and_slicings(ctx):
+    nb6 = _nb6()
+    cl = make_cluster(1003, 77, masses="imf", k_nb=20)
+    load(ctx, cl)
+    rng = np.random.Generator(np.random.PCG64(3))
+    results = {}
+    for ni in (1, 63, 65, 130, 1003):
+        idx = np.sort(rng.choice(cl.n, ni, replace=False)).astype(np.int32)
+        ref = oracle_ref(cl, idx)
+        check_mode(ctx, cl, idx, "ff", f"ragged_n{ni}", ref=ref)
+        results[ni] = (idx, ref)
+    # force many slices (wavefront finalize) and a single slice
+    for hint in (1, 3, 40):
+        c2 = nb6.nb6_create(0, slice_hint=hint)
+        try:
+            load(c2, cl)
+            idx, ref = results[130]
+            check_mode(c2, cl, idx, "ff", f"ragged_hint{hint}", ref=ref)
+            assert nb6.nb6_last_slices(c2) == min(hint, (cl.n + 255) // 256)
+        finally:
+            nb6.nb6_destroy(c2)
+
+
+def test_neighbour_overflow_and_cap(ctx):
+    nb6 = _nb6()
+    cfg = config(1)
+    cl = cfg["cluster"]
+    idx = cfg["blocks"]["all"][:200]
+    load(ctx, cl)
+    _, _, ref = oracle_ref(cl, idx)
+    full = check_mode(ctx, cl, idx, "ff", "cap_full")
+    acc, jerk, nnb, lst, rc = nb6.regular_force_host(ctx, 0, idx, cl.h2[idx], cl.dtr[idx],
+                                                     1, cap=3)
+    assert rc == nb6.NB6_WARN_NB_OVERFLOW
+    np.testing.assert_array_equal(nnb, full[2])
+    for q in range(len(idx)):
+        k = min(3, nnb[q])
+        np.testing.assert_array_equal(lst[q, :k], full[3][q, :k])
+    np.testing.assert_array_equal(acc, full[0])
+    acc0, jerk0, nnb0, _, rc0 = nb6.regular_force_host(ctx, 0, idx, cl.h2[idx], cl.dtr[idx],
+                                                       1, cap=0)
+    np.testing.assert_array_equal(nnb0, full[2])
+    np.testing.assert_array_equal(acc0, full[0])
+
+
+def test_device_mode_matches_host_mode(ctx):
+    import torch
+    nb6 = _nb6()
+    cfg = config(1)
+    cl = cfg["cluster"]
+    idx = cfg["blocks"]["all"]
+    load(ctx, cl)
+    acc_h, jerk_h, nnb_h, lst_h, _ = nb6.regular_force_host(ctx, 0, idx, cl.h2[idx],
+                                                            cl.dtr[idx], 1, 128)
+    dev = torch.device("cuda:0")
+    ni = len(idx)
+    t_idx = torch.from_numpy(idx).to(dev)
+    t_h2 = torch.from_numpy(cl.h2[idx].copy()).to(dev)
+    t_dtr = torch.from_numpy(cl.dtr[idx].copy()).to(dev)
+    acc = torch.empty((ni, 3), dtype=torch.float64, device=dev)
+    jerk = torch.empty_like(acc)
+    nnb = torch.empty(ni, dtype=torch.int32, device=dev)
+    lst = torch.empty((ni, 128), dtype=torch.int32, device=dev)
+    s = torch.cuda.current_stream()
+    rc = nb6.nb6_regular_force(ctx, 0, ni, t_idx, t_h2, t_dtr, 1, acc, jerk, nnb, lst, 128,
+                               nb6.NB6_MEM_DEVICE, s)
+    nb6.check(ctx, rc)
+    nb6.check(ctx, nb6.nb6_sync_status(ctx, s))
+    np.testing.assert_array_equal(acc.cpu().numpy(), acc_h)
+    np.testing.assert_array_equal(jerk.cpu().numpy(), jerk_h)
+    np.testing.assert_array_equal(nnb.cpu().numpy(), nnb_h)
+    l = lst.cpu().numpy()
+    for q in range(ni):
+        k = min(128, nnb_h[q])
+        np.testing.assert_array_equal(l[q, :k], lst_h[q, :k])
+
+
+def test_errors(ctx):
+    import torch
+    nb6 = _nb6()
+    cfg = config(1)
+    cl = cfg["cluster"]
+    load(ctx, cl)
+    idx = np.array([0, 5, 9], np.int32)
+    h2 = cl.h2[idx].copy()
+    dtr = cl.dtr[idx].copy()
+    out = [np.empty((3, 3)), np.empty((3, 3)), np.empty(3, np.int32), np.empty((3, 8), np.int32)]
+    bad = idx.copy()
+    bad[1] = cl.n
+    assert nb6.nb6_regular_force(ctx, 0, 3, bad, h2, dtr, 1, *out, 8) == nb6.NB6_ERR_ARG
+    h2b = h2.copy()
+    h2b[2] = 0.0
+    assert nb6.nb6_regular_force(ctx, 0, 3, idx, h2b, dtr, 1, *out, 8) == nb6.NB6_ERR_ARG
+    assert nb6.nb6_regular_force(ctx, 0, 3, idx, h2, dtr, 3, *out, 8) == nb6.NB6_ERR_ARG
+    assert nb6.nb6_regular_force(ctx, 0, 3, idx, h2, dtr, 1, *out, -1) == nb6.NB6_ERR_ARG
+    assert nb6.nb6_regular_force(ctx, 7, 3, idx, h2, dtr, 1, *out, 8) == nb6.NB6_ERR_STATE
+    # only the FF stream predicted -> FP64 call refused
+    nb6.check(ctx, nb6.nb6_predict_j(ctx, 0, cl.tb, nb6.NB6_DX_FF))
+    assert nb6.nb6_regular_force(ctx, 0, 3, idx, h2, dtr, 2, *out, 8) == nb6.NB6_ERR_STATE
+    # a load invalidates the prediction
+    load(ctx, cl)
+    nb6.check(ctx, nb6.nb6_load_particles(ctx, 0, 2, cl.m[:2], cl.x[:2], cl.v[:2], cl.a[:2],
+                                          cl.jerk[:2], cl.t[:2], np.array([0, 1], np.int32)))
+    assert nb6.nb6_regular_force(ctx, 0, 3, idx, h2, dtr, 1, *out, 8) == nb6.NB6_ERR_STATE
+    # non-finite host state is refused
+    xb = cl.x.copy()
+    xb[4, 1] = np.nan
+    assert nb6.nb6_load_particles(ctx, 1, cl.n, cl.m, xb, cl.v, cl.a, cl.jerk,
+                                  cl.t) == nb6.NB6_ERR_ARG
+    # device-side validation: bad index and bad h2 become NaN rows + status
+    load(ctx, cl)
+    dev = torch.device("cuda:0")
+    t_idx = torch.tensor([0, cl.n + 5, 9], dtype=torch.int32, device=dev)
+    t_h2 = torch.tensor([h2[0], h2[1], -1.0], dtype=torch.float64, device=dev)
+    t_dtr = torch.tensor(dtr, dtype=torch.float64, device=dev)
+    acc = torch.empty((3, 3), dtype=torch.float64, device=dev)
+    jerk = torch.empty_like(acc)
+    nnb = torch.empty(3, dtype=torch.int32, device=dev)
+    lst = torch.empty((3, 8), dtype=torch.int32, device=dev)
+    s = torch.cuda.current_stream()
+    nb6.check(ctx, nb6.nb6_regular_force(ctx, 0, 3, t_idx, t_h2, t_dtr, 1, acc, jerk, nnb,
+                                         lst, 8, nb6.NB6_MEM_DEVICE, s))
+    assert nb6.nb6_sync_status(ctx, s) == nb6.NB6_ERR_DEVICE_INPUT
+    assert nb6.nb6_sync_status(ctx, s) == nb6.NB6_OK  # cleared
+    a = acc.cpu().numpy()
+    assert np.all(np.isfinite(a[0])) and np.all(np.isnan(a[1])) and np.all(np.isnan(a[2]))
+    assert list(nnb.cpu().numpy()[1:]) == [-1, -1]
+
+
+def test_subset_update_then_predict(ctx):
+    nb6 = _nb6()
+    cfg = config(2, n=4096)
+    cl = cfg["cluster"]
+    load(ctx, cl)
+    rng = np.random.Generator(np.random.PCG64(9))
+    upd = np.sort(rng.choice(cl.n, 300, replace=False)).astype(np.int32)
+    cl.x[upd] += rng.normal(0, 1e-3, (300, 3))
+    cl.v[upd] *= 1.01
+    cl.t[upd] = cl.tb - 2.0 ** -10
+    nb6.check(ctx, nb6.nb6_load_particles(
+        ctx, 0, len(upd), np.ascontiguousarray(cl.m[upd]), np.ascontiguousarray(cl.x[upd]),
+        np.ascontiguousarray(cl.v[upd]), np.ascontiguousarray(cl.a[upd]),
+        np.ascontiguousarray(cl.jerk[upd]), np.ascontiguousarray(cl.t[upd]), upd))
+    nb6.check(ctx, nb6.nb6_predict_j(ctx, 0, cl.tb, 0))
+    idx = np.sort(rng.choice(cl.n, 512, replace=False)).astype(np.int32)
+    check_mode(ctx, cl, idx, "fp64", "subset_update")
+
+
+def test_repeat_calls_are_bitwise_identical(ctx):
+    nb6 = _nb6()
+    cfg = config(2)
+    cl = cfg["cluster"]
+    idx = cfg["blocks"]["random1024"]
+    load(ctx, cl)
+    a = nb6.regular_force_host(ctx, 0, idx, cl.h2[idx], cl.dtr[idx], 1, 256)
+    b = nb6.regular_force_host(ctx, 0, idx, cl.h2[idx], cl.dtr[idx], 1, 256)
+    for x, y in zip(a[:3], b[:3]):
+        np.testing.assert_array_equal(x, y)
+
+
+@pytest.mark.parametrize("block", ["all", "pow2_0", "pow2_4", "pow2_10", "pow2_14"])
+def test_config3_full_size_sampled(ctx, block):
+    """N = 131072 with binaries, in the launch configuration the benchmark
+    times; the oracle checks a sample of the active i."""
+    nb6 = _nb6()
+    cfg = config(3)
+    cl = cfg["cluster"]
+    idx = cfg["blocks"][block]
+    load(ctx, cl)
+    cap = 256
+    acc, jerk, nnb, lst, rc = nb6.regular_force_host(ctx, 0, idx, cl.h2[idx], cl.dtr[idx],
+                                                     1, cap)
+    rng = np.random.Generator(np.random.PCG64(5))
+    samp = np.sort(rng.choice(len(idx), min(256, len(idx)), replace=False))
+    xp, vp = oracle.predict(cl.x, cl.v, cl.a, cl.jerk, cl.t, cl.tb)
+    si = idx[samp]
+    ref = oracle.regular_force(cl.m, xp, vp, si, cl.h2[si], cl.dtr[si], lcap=4096)
+    c = compare(acc[samp], jerk[samp], nnb[samp], lst[samp], cap, ref, cl.m, xp, vp, si,
+                cl.h2[si], cl.dtr[si])
+    s = c.summary()
+    s["slices"] = nb6.nb6_last_slices(ctx)
+    _record(f"C3_{block}_ff", s)
+    assert c.incomplete == 0 and c.list_mismatch == 0 and c.nnb_mismatch == 0
+    assert s["acc_scaled_max"] <= 1e-6 and s["jerk_scaled_max"] <= 1e-6, s
+    assert s.get("acc_rel_max", 0.0) <= 1e-6 and s.get("jerk_rel_max", 0.0) <= 1e-6, s
