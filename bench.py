@@ -82,6 +82,8 @@ def main():
     ap.add_argument("--config", type=int, default=3, choices=[1, 2, 3, 5])
     ap.add_argument("--block", default="all")
     ap.add_argument("--cap", type=int, default=256)
+    ap.add_argument("--ipl", type=int, default=0, help="i-particles per lane (0: auto)")
+    ap.add_argument("--slices", type=int, default=0, help="j-slices (0: auto)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -119,7 +121,8 @@ def main():
     lst = torch.empty((ni, max(args.cap, 1)), dtype=torch.int32, device=dev)
     mode = MODES[args.mode]
 
-    ctx = nb6.nb6_create(0, flags=nb6.NB6_OPT_TIMING)
+    ctx = nb6.nb6_create(0, flags=nb6.NB6_OPT_TIMING, ipl_hint=args.ipl,
+                         slice_hint=args.slices)
     nb6.check(ctx, nb6.nb6_load_particles(ctx, 0, n, m_d, x_d, v_d, a_d, j_d, t_d,
                                           mem_kind=nb6.NB6_MEM_DEVICE, stream=stream))
 

@@ -65,6 +65,9 @@ extern "C" {
 #define NB6_DX_FP32  4   /* plain float coordinates (the paper's default) */
 #define NB6_DX_ALL   7
 
+/* Largest neighbour-list capacity of nb6_regular_force. */
+#define NB6_MAX_CAP  1023
+
 typedef struct nb6_ctx nb6_ctx;
 
 typedef struct nb6_options {
@@ -72,6 +75,7 @@ typedef struct nb6_options {
     int     slice_hint;    /* 0: choose the j-split per call; >0: force it    */
     int64_t hbm_budget;    /* bytes the serving queue may hold; 0: 1/4 of free */
     int     flags;         /* NB6_OPT_* bits                                  */
+    int     ipl_hint;      /* 0: choose i-particles per lane; 1 or 2: force it */
 } nb6_options;
 
 /* Record HIP events around every predictor, force and finalize launch so
@@ -132,7 +136,8 @@ int nb6_predict_j(nb6_ctx *ctx, int cluster, double t_block, int modes,
  * Inputs:  idx_i[n_i] (cluster indices, 0 <= idx_i < N), h2_i[n_i]
  *          (squared neighbour radii, > 0 and >= 2^-126 as floats),
  *          dtr_i[n_i] (regular time-steps), dx_mode (one NB6_DX_* value,
- *          whose stream the last nb6_predict_j wrote), cap >= 0.
+ *          whose stream the last nb6_predict_j wrote),
+ *          0 <= cap <= NB6_MAX_CAP.
  * Outputs: acc[n_i][3], jerk[n_i][3] (double), nnb[n_i] (true neighbour
  *          count, self excluded), list[n_i][cap] (the first min(nnb, cap)
  *          neighbours in ascending cluster index; entries past that are

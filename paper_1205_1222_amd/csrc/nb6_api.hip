@@ -51,9 +51,10 @@ struct nb6_ctx {
     int device = 0;
     int num_cu = 256;
     int slice_hint = 0;
+    int ipl_hint = 0;
     int64_t hbm_budget = 0;
     std::vector<ClusterState*> clusters;
-    DevBuf part, cnt, lst;                       // force-kernel scratch
+    DevBuf part, cnt, lst, ovf;                  // force-kernel scratch
     DevBuf in_idx, in_h2, in_dtr;                // HOST-mode inputs
     DevBuf out_acc, out_jerk, out_nnb, out_list; // HOST-mode outputs
     DevBuf ld[7];                                // HOST-mode load staging
@@ -151,12 +152,13 @@ struct Plan {
 
 Plan make_plan(const nb6_ctx* c, int64_t n, int64_t ni) {
     Plan p;
-    p.ipl = ni >= 16384 ? 2 : 1;
+    p.ipl = c->ipl_hint > 0 ? c->ipl_hint : (ni >= 16384 ? 2 : 1);
     const int64_t groups = (ni + 64 * p.ipl - 1) / (64 * p.ipl);
     p.wpb = (int)std::min<int64_t>(4, groups);
-    // Enough waves for ~8 per SIMD across the chip; no slice shorter than
-    // 256 j-particles so the per-slice overhead stays small.
-    const int64_t target = (int64_t)c->num_cu * 4 * 8;
+    // About 32 waves per SIMD over the launch (several rounds at the
+    // kernel's occupancy, so the last round's imbalance is a small part);
+    // no slice shorter than 256 j-particles.
+    const int64_t target = (int64_t)c->num_cu * 4 * 32;
     int64_t s = c->slice_hint > 0 ? c->slice_hint : (target + groups - 1) / groups;
     s = std::max<int64_t>(1, std::min<int64_t>(s, (n + 255) / 256));
     s = std::min<int64_t>(s, 65535);
@@ -180,6 +182,11 @@ int nb6_create(nb6_ctx** out, const nb6_options* opt) {
         c->slice_hint = opt->slice_hint;
         c->hbm_budget = opt->hbm_budget;
         c->timing = (opt->flags & NB6_OPT_TIMING) != 0;
+        c->ipl_hint = opt->ipl_hint;
+        if (c->ipl_hint < 0 || c->ipl_hint > 2) {
+            delete c;
+            return NB6_ERR_ARG;
+        }
     }
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || c->device < 0 || c->device >= ndev) {
@@ -222,7 +229,7 @@ int nb6_destroy(nb6_ctx* c) {
         for (auto& r : cl->rec) release(r);
         delete cl;
     }
-    for (DevBuf* b : {&c->part, &c->cnt, &c->lst, &c->in_idx, &c->in_h2, &c->in_dtr,
+    for (DevBuf* b : {&c->part, &c->cnt, &c->lst, &c->ovf, &c->in_idx, &c->in_h2, &c->in_dtr,
                       &c->out_acc, &c->out_jerk, &c->out_nnb, &c->out_list})
         release(*b);
     for (auto& b : c->ld) release(b);
@@ -398,7 +405,9 @@ int nb6_regular_force(nb6_ctx* c, int cluster, int64_t n_i, const int32_t* idx_i
         return fail(c, NB6_ERR_STATE, "cluster %d has no current prediction for dx_mode %d",
                     cluster, dx_mode);
     if (n_i < 0 || n_i > INT32_MAX / 2) return fail(c, NB6_ERR_ARG, "n_i = %lld", (long long)n_i);
-    if (cap < 0) return fail(c, NB6_ERR_ARG, "cap = %d < 0", cap);
+    static_assert(MAX_CAPS - 1 == NB6_MAX_CAP, "list capacity limits disagree");
+    if (cap < 0 || cap > MAX_CAPS - 1)
+        return fail(c, NB6_ERR_ARG, "cap = %d outside [0, %d]", cap, MAX_CAPS - 1);
     if (mem_kind != NB6_MEM_HOST && mem_kind != NB6_MEM_DEVICE)
         return fail(c, NB6_ERR_ARG, "bad mem_kind %d", mem_kind);
     if (n_i == 0) return NB6_OK;
@@ -452,9 +461,12 @@ int nb6_regular_force(nb6_ctx* c, int cluster, int64_t n_i, const int32_t* idx_i
     const int caps = cap + 1;  // room for the i-particle itself
     int rc;
     if ((rc = ensure(c, c->part, (size_t)p.nslices * NPART * ni * sizeof(double))) ||
-        (rc = ensure(c, c->cnt, (size_t)p.nslices * ni * sizeof(int32_t))) ||
-        (rc = ensure(c, c->lst, (size_t)p.nslices * ni * caps * sizeof(int32_t))))
+        (rc = ensure(c, c->cnt, ((size_t)ni + 1) * sizeof(int32_t))) ||
+        (rc = ensure(c, c->lst, (size_t)ni * caps * sizeof(int32_t))) ||
+        (rc = ensure(c, c->ovf, (size_t)ni * sizeof(int32_t))))
         return rc;
+    int32_t* d_cnt = (int32_t*)c->cnt.p;      // [ni] counts, then the overflow count
+    HIP_TRY(c, launch_zero_u32((unsigned*)d_cnt, ni + 1, st));
 
     RegfArgs ra{};
     ra.rec = cl->rec[mi].p;
@@ -466,7 +478,7 @@ int nb6_regular_force(nb6_ctx* c, int cluster, int64_t n_i, const int32_t* idx_i
     ra.slice_len = p.slice_len;
     ra.nslices = p.nslices;
     ra.part = (double*)c->part.p;
-    ra.cnt = (int32_t*)c->cnt.p;
+    ra.cnt = d_cnt;
     ra.lst = (int32_t*)c->lst.p;
     ra.caps = caps;
     ra.status = c->status;
@@ -492,10 +504,25 @@ int nb6_regular_force(nb6_ctx* c, int cluster, int64_t n_i, const int32_t* idx_i
     fa.list = d_list;
     fa.cap = cap;
     fa.status = c->status;
+    fa.ovf_count = d_cnt + ni;
+    fa.ovf_list = (int32_t*)c->ovf.p;
     {
         TimedLaunch tl(c, 2, st);
         HIP_TRY(c, launch_finalize(fa, st));
         tl.done();
+    }
+    if (cap > 0) {
+        OverflowArgs oa{};
+        oa.rec = ra.rec;
+        oa.n = (int)n;
+        oa.idx = d_idx;
+        oa.h2 = d_h2;
+        oa.dtr = d_dtr;
+        oa.list = d_list;
+        oa.cap = cap;
+        oa.ovf_count = fa.ovf_count;
+        oa.ovf_list = fa.ovf_list;
+        HIP_TRY(c, launch_overflow(mi, oa, st));
     }
     c->last_slices = p.nslices;
 

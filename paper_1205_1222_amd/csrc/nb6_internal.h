@@ -13,19 +13,22 @@ namespace nb6 {
 // whole record with a few scalar loads (the record address is the same for
 // every lane).
 // ---------------------------------------------------------------------------
+// vabs is an upper bound of |v| of the stored float velocity; the force
+// kernel uses it to skip the velocity criterion for pairs that cannot be
+// neighbours.
 struct __attribute__((aligned(16))) RecFF {   // float-float coordinates, 48 B
     float xh, yh, zh, m;
-    float xl, yl, zl, pad0;
-    float vx, vy, vz, pad1;
+    float xl, yl, zl, vabs;
+    float vx, vy, vz, pad;
 };
 struct __attribute__((aligned(16))) RecF64 {  // double coordinates, 48 B
     double x, y, z;
     float vx, vy, vz, m;
-    double pad;
+    float vabs, pad;
 };
 struct __attribute__((aligned(16))) RecF32 {  // plain float coordinates, 32 B
     float x, y, z, m;
-    float vx, vy, vz, pad;
+    float vx, vy, vz, vabs;
 };
 
 enum Mode { MODE_FF = 0, MODE_F64 = 1, MODE_F32 = 2 };
@@ -33,9 +36,13 @@ enum Mode { MODE_FF = 0, MODE_F64 = 1, MODE_F32 = 2 };
 // Bits of the device status word.
 enum StatusBits { ST_BAD_INDEX = 1, ST_BAD_H2 = 2, ST_NONFINITE = 4, ST_OVERFLOW = 8 };
 
-// Partial sums leave the force kernel as 6 FP64 components per (slice, i):
+// Partial sums leave the force kernel as 6 FP64 components per (i, slice):
 // acc xyz, jerk xyz.
 constexpr int NPART = 6;
+// Largest per-i list capacity (cap + 1 slots: the i itself is found too).
+constexpr int MAX_CAPS = 1024;
+// Workgroups of the overflow scan (each loops over the queued i).
+constexpr int OVERFLOW_BLOCKS = 64;
 
 struct RegfArgs {
     const void*    rec;       // records of the cluster (mode dependent)
@@ -46,10 +53,10 @@ struct RegfArgs {
     int            ni;
     int            slice_len; // j per slice (multiple of 4)
     int            nslices;
-    double*        part;      // [nslices][NPART][ni]
-    int32_t*       cnt;       // [nslices][ni] neighbours found (true count)
-    int32_t*       lst;       // [nslices][ni][caps]
-    int            caps;      // per-(i, slice) list capacity
+    double*        part;      // [ni][nslices][NPART]
+    int32_t*       cnt;       // [ni] neighbours found, the i itself included (zeroed)
+    int32_t*       lst;       // [ni][caps] neighbours in the order found
+    int            caps;      // per-i list capacity (cap + 1)
     unsigned*      status;    // device status word
 };
 
@@ -69,6 +76,20 @@ struct FinalArgs {
     int32_t*       list;      // [ni][cap]
     int            cap;
     unsigned*      status;
+    int32_t*       ovf_count; // number of queued overflowed i (zeroed)
+    int32_t*       ovf_list;  // [ni] queued i
+};
+
+struct OverflowArgs {
+    const void*    rec;
+    int            n;
+    const int32_t* idx;
+    const double*  h2;
+    const double*  dtr;
+    int32_t*       list;      // [ni][cap]
+    int            cap;
+    const int32_t* ovf_count;
+    const int32_t* ovf_list;
 };
 
 struct PredictArgs {
@@ -104,6 +125,7 @@ struct ScatterArgs {
 hipError_t launch_regf(int mode, int ipl, int waves_per_block, const RegfArgs& a,
                        hipStream_t s);
 hipError_t launch_finalize(const FinalArgs& a, hipStream_t s);
+hipError_t launch_overflow(int mode, const OverflowArgs& a, hipStream_t s);
 hipError_t launch_predict(const PredictArgs& a, hipStream_t s);
 hipError_t launch_scatter(const ScatterArgs& a, hipStream_t s);
 // Widen the j-records of one mode to double position and velocity arrays.

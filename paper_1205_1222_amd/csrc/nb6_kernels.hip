@@ -1,36 +1,47 @@
 // nb6_kernels.hip -- gfx950 kernels of the regular-force path.
 //
-//   predict_kernel   cubic Taylor prediction of every j-particle to the block
-//                    time in FP64, writing the j-records the force kernel
-//                    reads (section 3.3 step 3).
-//   regf_kernel      regular force, jerk and neighbour appends for one
-//                    (i-group, j-slice) pair (section 3.3 step 6 with the
-//                    velocity criterion of section 3.2).
-//   finalize_*       fixed-order reduction of the j-slice partial sums and
-//                    gathering of the per-slice neighbour lists into one
-//                    ascending list per i (the reduction and list-gathering
-//                    kernels of section 3.4).
+//   predict_kernel    cubic Taylor prediction of every j-particle to the block
+//                     time in FP64, writing the j-records the force kernel
+//                     reads (section 3.3 step 3).
+//   regf_kernel       regular force, jerk and neighbour appends for one
+//                     (i-group, j-slice) pair (section 3.3 step 6 with the
+//                     velocity criterion of section 3.2).
+//   finalize_kernel   fixed-order reduction of the j-slice partial sums and
+//                     the sorted neighbour list of each i (the reduction and
+//                     list-gathering kernels of section 3.4).
+//   overflow_kernel   exact list of an i whose neighbours outnumber the list
+//                     capacity: the first `cap` in ascending j.
 //
-// Design (see the repository's design notes for the derivation):
+// Design:
 //   * i-particles live in VGPRs, IPL of them per lane.
-//   * Every lane of a wavefront reads the same j-record, so the record is
-//     fetched with scalar loads into SGPRs and used directly as an operand
-//     of the vector instructions: no LDS traffic and no VGPRs spent on j.
+//   * Every lane of a wavefront reads the same j-record, so records are
+//     fetched with scalar loads into SGPRs and used directly as operands of
+//     the vector instructions: no LDS traffic and no VGPRs spent on j.
 //   * The neighbour test and the force use FP32; the coordinate difference
 //     is formed from float-float, FP64 or FP32 coordinates.
 //   * Force terms are summed in FP32 over tiles of TILE j-particles and each
 //     tile sum is added into an FP64 accumulator (FP64 adds run at the full
 //     vector rate on CDNA), so the rounding error is that of a TILE-term
 //     FP32 sum and does not grow with N.
-//   * A neighbour is appended to the lane's own list for this slice; slices
-//     are visited in ascending j, so the gathered list is already sorted.
+//   * The velocity criterion is evaluated only for candidate pairs inside a
+//     conservative radius, behind a branch that a wavefront almost never
+//     takes.
+//   * A neighbour is appended to its i's list with one atomic slot
+//     reservation; the finalize kernel sorts each list.  A list that
+//     overflows its capacity is rebuilt by an ordered scan, so the result is
+//     always the first `cap` neighbours in ascending j.
 #include "nb6_internal.h"
 
 #include <float.h>
 
+// No implicit fused multiply-adds: the force kernel and the overflow scan
+// must take bit-identical neighbour decisions, so every fma is explicit.
+#pragma clang fp contract(off)
+
 namespace nb6 {
 
 constexpr int TILE = 32;    // j per FP32 tile before the FP64 fold
+constexpr int JG = 4;       // j-records loaded together
 
 template <int MODE> struct RecOf;
 template <> struct RecOf<MODE_FF>  { using T = RecFF; };
@@ -42,20 +53,22 @@ template <> struct IPos<MODE_FF>  { float xh, yh, zh, xl, yl, zl; };
 template <> struct IPos<MODE_F64> { double x, y, z; };
 template <> struct IPos<MODE_F32> { float x, y, z; };
 
-struct IAux { float vx, vy, vz, h2, dtr; };
+// h2: squared neighbour radius; c: (h + dtr |v_i|) (1 + 2^-16), the i-part
+// of the candidate radius.
+struct IAux { float vx, vy, vz, vabs, h2, dtr, c; };
 
 __device__ __forceinline__ void get_ipos(const RecFF& r, IPos<MODE_FF>& p, IAux& v) {
     p.xh = r.xh; p.yh = r.yh; p.zh = r.zh;
     p.xl = r.xl; p.yl = r.yl; p.zl = r.zl;
-    v.vx = r.vx; v.vy = r.vy; v.vz = r.vz;
+    v.vx = r.vx; v.vy = r.vy; v.vz = r.vz; v.vabs = r.vabs;
 }
 __device__ __forceinline__ void get_ipos(const RecF64& r, IPos<MODE_F64>& p, IAux& v) {
     p.x = r.x; p.y = r.y; p.z = r.z;
-    v.vx = r.vx; v.vy = r.vy; v.vz = r.vz;
+    v.vx = r.vx; v.vy = r.vy; v.vz = r.vz; v.vabs = r.vabs;
 }
 __device__ __forceinline__ void get_ipos(const RecF32& r, IPos<MODE_F32>& p, IAux& v) {
     p.x = r.x; p.y = r.y; p.z = r.z;
-    v.vx = r.vx; v.vy = r.vy; v.vz = r.vz;
+    v.vx = r.vx; v.vy = r.vy; v.vz = r.vz; v.vabs = r.vabs;
 }
 
 // R_j - R_i in FP32 from each coordinate representation.
@@ -78,32 +91,54 @@ __device__ __forceinline__ void coord_diff(const RecF32& j, const IPos<MODE_F32>
     dz = j.z - i.z;
 }
 
+// |R|^2 in FP32.
+__device__ __forceinline__ float dist2(float dx, float dy, float dz) {
+    return fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+}
+
+// The neighbour criterion of section 3.2 on FP32 differences:
+// min(|R|^2, |R + dtr V|^2) < h^2.  Used verbatim by the force kernel (for
+// candidates) and by the overflow scan, so both take the same decisions.
+__device__ __forceinline__ bool velocity_criterion(float r2, float dx, float dy, float dz,
+                                                   float dvx, float dvy, float dvz,
+                                                   float dtr, float h2) {
+    const float px = fmaf(dtr, dvx, dx);
+    const float py = fmaf(dtr, dvy, dy);
+    const float pz = fmaf(dtr, dvz, dz);
+    const float p2 = dist2(px, py, pz);
+    return fminf(r2, p2) < h2;
+}
+
 // One i-j interaction.  run[0..2] += m r^-3 R, run[3..5] += m r^-3 (V + alpha R)
 // with alpha = -3 (R.V)/r^2, unless j is a neighbour of i, in which case j is
-// appended to the lane's list instead.
+// appended to i's list instead.
+//
+// The velocity criterion is evaluated only for candidate pairs,
+// r^2 < (c_i + dtr_i |v_j|)^2: since |R + dtr V| >= |R| - dtr (|v_i| + |v_j|),
+// a pair outside that radius is not a neighbour, and the 2^-16 relative
+// margin folded into c_i covers the FP32 rounding of every quantity involved,
+// so the decision equals that of the full test.  Candidates are rare, so the
+// branch is almost never taken by any lane of a wavefront.
 template <int MODE>
 __device__ __forceinline__ void interact(const typename RecOf<MODE>::T& r, int j,
                                          const IPos<MODE>& ip, const IAux& ia,
-                                         float run[6], int& count,
-                                         int32_t* __restrict__ lb, int caps) {
+                                         float run[6], int qq, const RegfArgs& a) {
     float dx, dy, dz;
     coord_diff(r, ip, dx, dy, dz);
     const float dvx = r.vx - ia.vx;
     const float dvy = r.vy - ia.vy;
     const float dvz = r.vz - ia.vz;
-    const float px = fmaf(ia.dtr, dvx, dx);
-    const float py = fmaf(ia.dtr, dvy, dy);
-    const float pz = fmaf(ia.dtr, dvz, dz);
-    const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-    const float p2 = fmaf(pz, pz, fmaf(py, py, px * px));
+    const float r2 = dist2(dx, dy, dz);
     const float rv = fmaf(dz, dvz, fmaf(dy, dvy, dx * dvx));
     float rinv = __builtin_amdgcn_rsqf(r2);
-    const bool nb = fminf(r2, p2) < ia.h2;
-    if (nb) {
-        if (count < caps) lb[count] = j;
-        ++count;
+    const float bnd = fmaf(ia.dtr, r.vabs, ia.c);
+    if (r2 < bnd * bnd) {
+        if (velocity_criterion(r2, dx, dy, dz, dvx, dvy, dvz, ia.dtr, ia.h2)) {
+            const int slot = atomicAdd(a.cnt + qq, 1);
+            if (slot < a.caps) a.lst[(size_t)qq * a.caps + slot] = j;
+            rinv = 0.0f;
+        }
     }
-    rinv = nb ? 0.0f : rinv;
     const float rinv2 = rinv * rinv;
     const float mr3 = (r.m * rinv) * rinv2;
     const float alpha = (-3.0f * rv) * rinv2;
@@ -124,25 +159,36 @@ using const_ptr = const __attribute__((address_space(4))) T*;
 __device__ __forceinline__ RecFF load_rec(const_ptr<RecFF> p) {
     RecFF r;
     r.xh = p->xh; r.yh = p->yh; r.zh = p->zh; r.m = p->m;
-    r.xl = p->xl; r.yl = p->yl; r.zl = p->zl; r.pad0 = 0.0f;
-    r.vx = p->vx; r.vy = p->vy; r.vz = p->vz; r.pad1 = 0.0f;
+    r.xl = p->xl; r.yl = p->yl; r.zl = p->zl; r.vabs = p->vabs;
+    r.vx = p->vx; r.vy = p->vy; r.vz = p->vz; r.pad = 0.0f;
     return r;
 }
 __device__ __forceinline__ RecF64 load_rec(const_ptr<RecF64> p) {
     RecF64 r;
     r.x = p->x; r.y = p->y; r.z = p->z;
-    r.vx = p->vx; r.vy = p->vy; r.vz = p->vz; r.m = p->m; r.pad = 0.0;
+    r.vx = p->vx; r.vy = p->vy; r.vz = p->vz; r.m = p->m;
+    r.vabs = p->vabs; r.pad = 0.0f;
     return r;
 }
 __device__ __forceinline__ RecF32 load_rec(const_ptr<RecF32> p) {
     RecF32 r;
     r.x = p->x; r.y = p->y; r.z = p->z; r.m = p->m;
-    r.vx = p->vx; r.vy = p->vy; r.vz = p->vz; r.pad = 0.0f;
+    r.vx = p->vx; r.vy = p->vy; r.vz = p->vz; r.vabs = p->vabs;
     return r;
 }
 
+// h2 as the float the kernels compare against, or -1 when it is not a
+// positive normal float (then the i is invalid).
+__device__ __forceinline__ float checked_h2(double h2) {
+    const float f = (float)h2;
+    return (f >= FLT_MIN && f <= FLT_MAX) ? f : -1.0f;
+}
+
+// At least 4 waves per SIMD (<= 128 VGPRs): below that the scalar-load
+// latency of the j-records is no longer hidden.
 template <int MODE, int IPL>
-__global__ void __launch_bounds__(256) regf_kernel(RegfArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+regf_kernel(RegfArgs a) {
     using Rec = typename RecOf<MODE>::T;
     const_ptr<Rec> rec = (const_ptr<Rec>)(a.rec);
     const int lane = threadIdx.x & 63;
@@ -156,44 +202,43 @@ __global__ void __launch_bounds__(256) regf_kernel(RegfArgs a) {
     IPos<MODE> ip[IPL];
     IAux ia[IPL];
     int q[IPL];
-    bool live[IPL];
-    int32_t* lb[IPL];
+    int qq[IPL];  // list row of the lane's i (row 0 for invalid lanes, which never append)
 #pragma unroll
     for (int k = 0; k < IPL; ++k) {
         q[k] = ibase + k * 64 + lane;
-        live[k] = q[k] < a.ni;
-        int pi = live[k] ? a.idx[q[k]] : 0;
-        float h2f = live[k] ? (float)a.h2[q[k]] : -1.0f;
-        float dtf = live[k] ? (float)a.dtr[q[k]] : 0.0f;
-        if (live[k]) {
+        bool live = q[k] < a.ni;
+        int pi = live ? a.idx[q[k]] : 0;
+        float h2f = live ? checked_h2(a.h2[q[k]]) : -1.0f;
+        const float dtf = live ? (float)a.dtr[q[k]] : 0.0f;
+        if (live) {
             unsigned bad = 0;
             if (pi < 0 || pi >= a.n) bad |= ST_BAD_INDEX;
-            if (!(h2f >= FLT_MIN) || !(h2f <= FLT_MAX)) bad |= ST_BAD_H2;
+            if (h2f < 0.0f) bad |= ST_BAD_H2;
             if (bad) {
                 if (s == 0) atomicOr(a.status, bad);
                 pi = 0;
-                h2f = -1.0f;   // never a neighbour: this lane appends nothing
-                live[k] = false;
+                h2f = -1.0f;
+                live = false;
             }
         }
         const Rec* rv = static_cast<const Rec*>(a.rec);  // per-lane address
         get_ipos(rv[pi], ip[k], ia[k]);
         ia[k].h2 = h2f;
         ia[k].dtr = dtf;
-        lb[k] = a.lst + ((size_t)s * a.ni + (live[k] ? q[k] : 0)) * (size_t)a.caps;
+        // NaN for invalid lanes (h2f = -1): never a candidate, never appends
+        ia[k].c = (float)((sqrt((double)h2f) + (double)dtf * (double)ia[k].vabs) *
+                          (1.0 + 0x1p-16));
+        qq[k] = live ? q[k] : 0;
     }
 
     const int j0 = s * a.slice_len;
     const int j1 = min(j0 + a.slice_len, a.n);
 
     double sum[IPL][6];
-    int count[IPL];
 #pragma unroll
-    for (int k = 0; k < IPL; ++k) {
-        count[k] = 0;
+    for (int k = 0; k < IPL; ++k)
 #pragma unroll
         for (int c = 0; c < 6; ++c) sum[k][c] = 0.0;
-    }
 
     for (int jt = j0; jt < j1; jt += TILE) {
         const int je = min(jt + TILE, j1);
@@ -203,12 +248,24 @@ __global__ void __launch_bounds__(256) regf_kernel(RegfArgs a) {
 #pragma unroll
             for (int c = 0; c < 6; ++c) run[k][c] = 0.0f;
 
-#pragma unroll 4
-        for (int j = jt; j < je; ++j) {
+        // groups of JG records: all their scalar loads are issued before the
+        // first interaction of the group, so one load latency covers JG j.
+        int j = jt;
+        for (; j + JG <= je; j += JG) {
+            Rec r[JG];
+#pragma unroll
+            for (int g = 0; g < JG; ++g) r[g] = load_rec(rec + j + g);
+#pragma unroll
+            for (int g = 0; g < JG; ++g)
+#pragma unroll
+                for (int k = 0; k < IPL; ++k)
+                    interact<MODE>(r[g], j + g, ip[k], ia[k], run[k], qq[k], a);
+        }
+        for (; j < je; ++j) {
             const Rec r = load_rec(rec + j);
 #pragma unroll
             for (int k = 0; k < IPL; ++k)
-                interact<MODE>(r, j, ip[k], ia[k], run[k], count[k], lb[k], a.caps);
+                interact<MODE>(r, j, ip[k], ia[k], run[k], qq[k], a);
         }
 #pragma unroll
         for (int k = 0; k < IPL; ++k)
@@ -216,138 +273,130 @@ __global__ void __launch_bounds__(256) regf_kernel(RegfArgs a) {
             for (int c = 0; c < 6; ++c) sum[k][c] += (double)run[k][c];
     }
 
+    // partial sums, i-major: part[q][s][0..5]
 #pragma unroll
     for (int k = 0; k < IPL; ++k) {
         if (q[k] < a.ni) {
-            double* p = a.part + (size_t)s * NPART * a.ni + q[k];
+            double* p = a.part + ((size_t)q[k] * a.nslices + s) * NPART;
 #pragma unroll
-            for (int c = 0; c < NPART; ++c) p[(size_t)c * a.ni] = sum[k][c];
-            a.cnt[(size_t)s * a.ni + q[k]] = live[k] ? count[k] : 0;
+            for (int c = 0; c < NPART; ++c) p[c] = sum[k][c];
         }
     }
 }
 
 // ---------------------------------------------------------------------------
-// Finalize: one thread per i (few slices; partial loads are coalesced).
+// Finalize: one wavefront per i.
+//   sums  -- the wave loads i's S x 6 partials (contiguous) into LDS and
+//            lanes 0..5 add them in slice order: a fixed summation order.
+//   lists -- count <= caps: every neighbour was stored; each entry's output
+//            position is its rank among the entries (entries are distinct),
+//            less one past the i itself.  count > caps: the list overflowed
+//            and i is queued for the ordered overflow scan.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ bool bad_i(const FinalArgs& a, int q, int32_t self) {
-    float h2f = (float)a.h2[q];
-    return self < 0 || self >= a.n || !(h2f >= FLT_MIN) || !(h2f <= FLT_MAX);
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ __forceinline__ void write_bad(const FinalArgs& a, int q) {
-    const double nan = __builtin_nan("");
-    for (int c = 0; c < 3; ++c) { a.acc[3 * q + c] = nan; a.jerk[3 * q + c] = nan; }
-    a.nnb[q] = -1;
-}
-
-__global__ void __launch_bounds__(256) finalize_thread_kernel(FinalArgs a) {
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= a.ni) return;
-    const int32_t self = a.idx[q];
-    if (bad_i(a, q, self)) { write_bad(a, q); return; }
-
-    double sum[6];
-#pragma unroll
-    for (int c = 0; c < 6; ++c) sum[c] = 0.0;
-    int64_t total = 0;
-    int out = 0;
-    for (int s = 0; s < a.nslices; ++s) {
-        const double* p = a.part + (size_t)s * NPART * a.ni + q;
-#pragma unroll
-        for (int c = 0; c < NPART; ++c) sum[c] += p[(size_t)c * a.ni];
-        const int c_s = a.cnt[(size_t)s * a.ni + q];
-        total += c_s;
-        const int st = min(c_s, a.caps);
-        const int32_t* l = a.lst + ((size_t)s * a.ni + q) * (size_t)a.caps;
-        for (int e = 0; e < st && out < a.cap; ++e) {
-            const int32_t j = l[e];
-            if (j == self) continue;
-            a.list[(size_t)q * a.cap + out] = j;
-            ++out;
-        }
-    }
-    a.acc[3 * q + 0] = sum[0];
-    a.acc[3 * q + 1] = sum[1];
-    a.acc[3 * q + 2] = sum[2];
-    a.jerk[3 * q + 0] = sum[3];
-    a.jerk[3 * q + 1] = sum[4];
-    a.jerk[3 * q + 2] = sum[5];
-    const int32_t nn = (int32_t)(total - 1);  // the i-particle itself
-    a.nnb[q] = nn;
-    if (nn > a.cap) atomicOr(a.status, (unsigned)ST_OVERFLOW);
-}
-
-// ---------------------------------------------------------------------------
-// Finalize: one wavefront per i (many slices, few i).
-// ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) finalize_wave_kernel(FinalArgs a) {
+__global__ void __launch_bounds__(256) finalize_kernel(FinalArgs a) {
+    __shared__ double sh_part[4][NPART * 64];
+    __shared__ int32_t sh_list[4][MAX_CAPS];
     const int lane = threadIdx.x & 63;
-    const int q = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int w = threadIdx.x >> 6;
+    const int q = blockIdx.x * 4 + w;
     if (q >= a.ni) return;
     const int32_t self = a.idx[q];
-    if (bad_i(a, q, self)) {
-        if (lane == 0) write_bad(a, q);
+    if (self < 0 || self >= a.n || checked_h2(a.h2[q]) < 0.0f) {
+        if (lane < 3) {
+            const double nan = __builtin_nan("");
+            a.acc[3 * q + lane] = nan;
+            a.jerk[3 * q + lane] = nan;
+        }
+        if (lane == 0) a.nnb[q] = -1;
         return;
     }
 
-    double sum[6];
-#pragma unroll
-    for (int c = 0; c < 6; ++c) sum[c] = 0.0;
-    for (int s = lane; s < a.nslices; s += 64) {
-        const double* p = a.part + (size_t)s * NPART * a.ni + q;
-#pragma unroll
-        for (int c = 0; c < NPART; ++c) sum[c] += p[(size_t)c * a.ni];
-    }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1)
-#pragma unroll
-        for (int c = 0; c < 6; ++c) sum[c] += __shfl_xor(sum[c], off);
-
-    int64_t total = 0;
-    int running = 0;  // stored entries of all earlier slices
+    double total = 0.0;  // lane c < 6: component c
+    const double* src = a.part + (size_t)q * a.nslices * NPART;
     for (int s0 = 0; s0 < a.nslices; s0 += 64) {
-        const int s = s0 + lane;
-        const int c_s = (s < a.nslices) ? a.cnt[(size_t)s * a.ni + q] : 0;
-        total += c_s;
-        const int st = min(c_s, a.caps);
-        int incl = st;
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const int y = __shfl_up(incl, off);
-            if (lane >= off) incl += y;
-        }
-        const int excl = running + incl - st;
-        running += __shfl(incl, 63);
-        unsigned long long mask = __ballot(st > 0 && excl <= a.cap);
-        while (mask) {
-            const int l = __ffsll((long long)mask) - 1;
-            mask &= mask - 1;
-            const int sl = s0 + l;
-            const int ne = __shfl(st, l);
-            const int base = __shfl(excl, l);
-            const int32_t* lst = a.lst + ((size_t)sl * a.ni + q) * (size_t)a.caps;
-            for (int e = lane; e < ne; e += 64) {
-                const int32_t j = lst[e];
-                if (j == self) continue;
-                const int pos = base + e - (j > self ? 1 : 0);
-                if (pos >= 0 && pos < a.cap) a.list[(size_t)q * a.cap + pos] = j;
-            }
-        }
+        const int ns = min(64, a.nslices - s0);
+        for (int e = lane; e < ns * NPART; e += 64) sh_part[w][e] = src[(size_t)s0 * NPART + e];
+        wave_sync();
+        if (lane < NPART)
+            for (int s = 0; s < ns; ++s) total += sh_part[w][s * NPART + lane];
+        wave_sync();
     }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) total += __shfl_xor(total, off);
+    if (lane < 3) a.acc[3 * q + lane] = total;
+    else if (lane < 6) a.jerk[3 * q + lane - 3] = total;
 
-    if (lane == 0) {
-        a.acc[3 * q + 0] = sum[0];
-        a.acc[3 * q + 1] = sum[1];
-        a.acc[3 * q + 2] = sum[2];
-        a.jerk[3 * q + 0] = sum[3];
-        a.jerk[3 * q + 1] = sum[4];
-        a.jerk[3 * q + 2] = sum[5];
-        const int32_t nn = (int32_t)(total - 1);
-        a.nnb[q] = nn;
-        if (nn > a.cap) atomicOr(a.status, (unsigned)ST_OVERFLOW);
+    const int count = a.cnt[q];          // neighbours found, the i itself included
+    if (lane == 0) a.nnb[q] = count - 1;
+    if (count > a.caps) {
+        if (lane == 0) {
+            atomicOr(a.status, (unsigned)ST_OVERFLOW);
+            const int slot = atomicAdd(a.ovf_count, 1);
+            a.ovf_list[slot] = q;
+        }
+        return;
+    }
+    const int32_t* l = a.lst + (size_t)q * a.caps;
+    for (int e = lane; e < count; e += 64) sh_list[w][e] = l[e];
+    wave_sync();
+    for (int e = lane; e < count; e += 64) {
+        const int32_t v = sh_list[w][e];
+        if (v == self) continue;
+        int rank = 0;
+        for (int k = 0; k < count; ++k) rank += sh_list[w][k] < v ? 1 : 0;
+        const int pos = rank - (v > self ? 1 : 0);
+        if (pos >= 0 && pos < a.cap) a.list[(size_t)q * a.cap + pos] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Overflowed lists: one workgroup per queued i scans all j in ascending
+// order with the force kernel's neighbour test and keeps the first `cap`.
+// ---------------------------------------------------------------------------
+template <int MODE>
+__global__ void __launch_bounds__(256) overflow_kernel(OverflowArgs a) {
+    using Rec = typename RecOf<MODE>::T;
+    const Rec* rec = static_cast<const Rec*>(a.rec);
+    __shared__ int sh_wave[4];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int w = tid >> 6;
+    const int nq = *a.ovf_count;
+    for (int item = blockIdx.x; item < nq; item += gridDim.x) {
+        const int q = a.ovf_list[item];
+        const int32_t self = a.idx[q];
+        IPos<MODE> ip;
+        IAux ia;
+        get_ipos(rec[self], ip, ia);
+        const float h2f = checked_h2(a.h2[q]);
+        const float dtf = (float)a.dtr[q];
+        int out = 0;  // identical in every thread
+        for (int j0 = 0; j0 < a.n && out < a.cap; j0 += 256) {
+            const int j = j0 + tid;
+            bool nb = false;
+            if (j < a.n && j != self) {
+                const Rec r = rec[j];
+                float dx, dy, dz;
+                coord_diff(r, ip, dx, dy, dz);
+                const float r2 = dist2(dx, dy, dz);
+                nb = velocity_criterion(r2, dx, dy, dz, r.vx - ia.vx, r.vy - ia.vy,
+                                        r.vz - ia.vz, dtf, h2f);
+            }
+            const unsigned long long m = __ballot(nb);
+            if (lane == 0) sh_wave[w] = __popcll(m);
+            __syncthreads();
+            int base = out;
+            for (int v = 0; v < w; ++v) base += sh_wave[v];
+            const int off = __popcll(m & ((1ull << lane) - 1ull));
+            if (nb && base + off < a.cap) a.list[(size_t)q * a.cap + base + off] = j;
+            const int found = sh_wave[0] + sh_wave[1] + sh_wave[2] + sh_wave[3];
+            __syncthreads();
+            out += found;
+        }
     }
 }
 
@@ -366,32 +415,36 @@ __global__ void __launch_bounds__(256) predict_kernel(PredictArgs a) {
     for (int c = 0; c < 3; ++c) {
         const double x = a.x[3 * k + c], v = a.v[3 * k + c];
         const double acc = a.a[3 * k + c], jk = a.jk[3 * k + c];
-        xp[c] = x + dt * (v + h * (acc + t3 * jk));
-        vp[c] = v + dt * (acc + h * jk);
+        xp[c] = fma(dt, fma(h, fma(t3, jk, acc), v), x);
+        vp[c] = fma(dt, fma(h, jk, acc), v);
         finite = finite && isfinite(xp[c]) && isfinite(vp[c]);
     }
     const float m = (float)a.m[k];
     if (!finite) atomicOr(a.status, (unsigned)ST_NONFINITE);
+    // upper bound of the float velocity's magnitude (rounded up by 2^-20)
+    const float vf[3] = {(float)vp[0], (float)vp[1], (float)vp[2]};
+    const float vabs = (float)(sqrt((double)vf[0] * vf[0] + (double)vf[1] * vf[1] +
+                                    (double)vf[2] * vf[2]) * (1.0 + 0x1p-20));
     if (a.ff) {
         RecFF r;
         r.xh = (float)xp[0]; r.xl = (float)(xp[0] - (double)r.xh);
         r.yh = (float)xp[1]; r.yl = (float)(xp[1] - (double)r.yh);
         r.zh = (float)xp[2]; r.zl = (float)(xp[2] - (double)r.zh);
-        r.m = m; r.pad0 = 0.0f;
-        r.vx = (float)vp[0]; r.vy = (float)vp[1]; r.vz = (float)vp[2]; r.pad1 = 0.0f;
+        r.m = m; r.vabs = vabs;
+        r.vx = vf[0]; r.vy = vf[1]; r.vz = vf[2]; r.pad = 0.0f;
         a.ff[k] = r;
     }
     if (a.f64) {
         RecF64 r;
         r.x = xp[0]; r.y = xp[1]; r.z = xp[2];
-        r.vx = (float)vp[0]; r.vy = (float)vp[1]; r.vz = (float)vp[2]; r.m = m;
-        r.pad = 0.0;
+        r.vx = vf[0]; r.vy = vf[1]; r.vz = vf[2]; r.m = m;
+        r.vabs = vabs; r.pad = 0.0f;
         a.f64[k] = r;
     }
     if (a.f32) {
         RecF32 r;
         r.x = (float)xp[0]; r.y = (float)xp[1]; r.z = (float)xp[2]; r.m = m;
-        r.vx = (float)vp[0]; r.vy = (float)vp[1]; r.vz = (float)vp[2]; r.pad = 0.0f;
+        r.vx = vf[0]; r.vy = vf[1]; r.vz = vf[2]; r.vabs = vabs;
         a.f32[k] = r;
     }
 }
@@ -472,12 +525,18 @@ hipError_t launch_regf(int mode, int ipl, int wpb, const RegfArgs& a, hipStream_
 
 hipError_t launch_finalize(const FinalArgs& a, hipStream_t s) {
     if (a.ni <= 0) return hipSuccess;
-    if (a.nslices <= 16) {
-        dim3 grid((a.ni + 255) / 256);
-        hipLaunchKernelGGL(finalize_thread_kernel, grid, dim3(256), 0, s, a);
-    } else {
-        dim3 grid((a.ni + 3) / 4);
-        hipLaunchKernelGGL(finalize_wave_kernel, grid, dim3(256), 0, s, a);
+    if (a.caps > MAX_CAPS) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(finalize_kernel, dim3((a.ni + 3) / 4), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_overflow(int mode, const OverflowArgs& a, hipStream_t s) {
+    const dim3 grid(OVERFLOW_BLOCKS), block(256);
+    switch (mode) {
+        case MODE_FF: hipLaunchKernelGGL(overflow_kernel<MODE_FF>, grid, block, 0, s, a); break;
+        case MODE_F64: hipLaunchKernelGGL(overflow_kernel<MODE_F64>, grid, block, 0, s, a); break;
+        case MODE_F32: hipLaunchKernelGGL(overflow_kernel<MODE_F32>, grid, block, 0, s, a); break;
+        default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }

@@ -42,6 +42,7 @@ NB6_DX_FF = 1
 NB6_DX_FP64 = 2
 NB6_DX_FP32 = 4
 NB6_DX_ALL = 7
+NB6_MAX_CAP = 1023
 
 EXPORTED = [
     "nb6_create", "nb6_destroy", "nb6_last_error", "nb6_load_particles",
@@ -54,7 +55,8 @@ NB6_OPT_TIMING = 1
 
 class nb6_options(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int), ("slice_hint", ctypes.c_int),
-                ("hbm_budget", ctypes.c_int64), ("flags", ctypes.c_int)]
+                ("hbm_budget", ctypes.c_int64), ("flags", ctypes.c_int),
+                ("ipl_hint", ctypes.c_int)]
 
 
 class NB6Error(RuntimeError):
@@ -138,9 +140,9 @@ def check(ctx, rc, allow=(NB6_OK,)):
 
 
 # ---- the C entry points ---------------------------------------------------
-def nb6_create(device=0, slice_hint=0, hbm_budget=0, flags=0):
+def nb6_create(device=0, slice_hint=0, hbm_budget=0, flags=0, ipl_hint=0):
     h = ctypes.c_void_p()
-    opt = nb6_options(device, slice_hint, hbm_budget, flags)
+    opt = nb6_options(device, slice_hint, hbm_budget, flags, ipl_hint)
     rc = lib().nb6_create(ctypes.byref(h), ctypes.byref(opt))
     if rc != NB6_OK:
         raise NB6Error(rc, "nb6_create failed")

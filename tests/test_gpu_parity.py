@@ -309,3 +309,24 @@ def test_config3_full_size_sampled(ctx, block):
     assert c.incomplete == 0 and c.list_mismatch == 0 and c.nnb_mismatch == 0
     assert s["acc_scaled_max"] <= 1e-6 and s["jerk_scaled_max"] <= 1e-6, s
     assert s.get("acc_rel_max", 0.0) <= 1e-6 and s.get("jerk_rel_max", 0.0) <= 1e-6, s
+
+
+@pytest.mark.parametrize("n", [1024, 1500])
+def test_everything_neighbour_long_lists(ctx, n):
+    """h -> infinity: every j is a neighbour.  N = 1024 fills the largest list
+    exactly (1023 entries, sorted on the GPU); N = 1500 overflows it and the
+    ordered overflow scan must return the first 1023 indices."""
+    nb6 = _nb6()
+    cl = make_cluster(n, 31, masses="equal", k_nb=8)
+    load(ctx, cl)
+    idx = np.array([0, 7, n // 2, n - 1], np.int32)
+    cap = nb6.NB6_MAX_CAP
+    acc, jerk, nnb, lst, rc = nb6.regular_force_host(ctx, 0, idx, 1e30, cl.dtr[idx], 1, cap)
+    assert np.all(acc == 0.0) and np.all(jerk == 0.0)
+    assert np.all(nnb == n - 1)
+    assert rc == (nb6.NB6_OK if n - 1 <= cap else nb6.NB6_WARN_NB_OVERFLOW)
+    for q, i in enumerate(idx):
+        want = [j for j in range(n) if j != i][:cap]
+        np.testing.assert_array_equal(lst[q, :min(cap, n - 1)], want)
+    with pytest.raises(Exception):
+        nb6.regular_force_host(ctx, 0, idx, 1e30, cl.dtr[idx], 1, cap + 1)
