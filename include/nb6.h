@@ -184,6 +184,67 @@ int nb6_get_predicted(nb6_ctx *ctx, int cluster, int dx_mode, double *x, double 
  */
 int nb6_kernel_times(nb6_ctx *ctx, double *ms, int64_t *counts);
 
+/* ---- serving: continuously batched requests ---------------------------- */
+
+/*
+ * One regular-force block of one cluster, for the serving queue.  The
+ * fields mean what the arguments of nb6_regular_force mean; t_block is the
+ * block time the cluster is predicted to before the force (section 3.3,
+ * steps 3 and 6).  All arrays stay owned by the caller and must stay valid,
+ * and untouched, until nb6_poll reports the request finished.
+ */
+typedef struct nb6_request {
+    int            cluster;
+    double         t_block;
+    int            dx_mode;     /* NB6_DX_FF, NB6_DX_FP64 or NB6_DX_FP32 */
+    int64_t        n_i;
+    const int32_t *idx_i;
+    const double  *h2_i;
+    const double  *dtr_i;
+    double        *acc;         /* [n_i][3] */
+    double        *jerk;        /* [n_i][3] */
+    int32_t       *nnb;         /* [n_i]    */
+    int32_t       *list;        /* [n_i][cap] */
+    int32_t        cap;         /* 0 <= cap <= NB6_MAX_CAP */
+    int            mem_kind;    /* NB6_MEM_HOST or NB6_MEM_DEVICE */
+} nb6_request;
+
+/* What nb6_poll reports about a finished request. */
+typedef struct nb6_ticket_info {
+    int    status;      /* the request's final status code                     */
+    int    slices;      /* j-slices its force work was split into              */
+    int    batch_size;  /* requests fused into the launch that served it       */
+    double submit_us;   /* steady-clock microseconds since the queue started:  */
+    double admit_us;    /*   submitted, admitted to a launch,                  */
+    double done_us;     /*   and finished on the GPU                           */
+} nb6_ticket_info;
+
+/*
+ * Queue one request; *ticket identifies it.  A scheduler thread of the
+ * context admits queued requests in arrival order while their device scratch
+ * (slice partials, lists, staging; the request's "footprint") fits the
+ * context's HBM budget (nb6_options.hbm_budget) and no other request of the
+ * same cluster is in flight; it fuses every admitted request into one
+ * persistent launch (up to three launches in flight), so requests that
+ * arrive while others run are served as memory and launch slots free up.
+ * A request's result does not depend on the other requests it is fused with.
+ * There is no paper counterpart: the paper keeps two GPUs busy by running
+ * two simulations at once (section 4); this queue serves many.
+ * Errors: NB6_ERR_ARG, NB6_ERR_STATE (cluster not loaded),
+ * NB6_ERR_ADMISSION (the footprint alone exceeds the budget), NB6_ERR_NOMEM,
+ * NB6_ERR_HIP.
+ */
+int nb6_submit(nb6_ctx *ctx, const nb6_request *req, uint64_t *ticket);
+
+/*
+ * NB6_PENDING while the request runs (wait == 0), else its final status
+ * (NB6_OK, NB6_WARN_NB_OVERFLOW, or an error code), after which the ticket is
+ * released.  wait != 0 blocks until the request finishes.  info (may be
+ * NULL) receives its timing.  NB6_ERR_UNKNOWN_TICKET for a ticket that was
+ * never issued or was already released.
+ */
+int nb6_poll(nb6_ctx *ctx, uint64_t ticket, int wait, nb6_ticket_info *info);
+
 /* Number of j-slices (the j-split across workgroups) the last force call
  * used; for diagnostics and tests. */
 int nb6_last_slices(const nb6_ctx *ctx);

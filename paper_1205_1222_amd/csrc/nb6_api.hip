@@ -1,7 +1,6 @@
 // nb6_api.hip -- the C ABI of include/nb6.h: contexts, cluster state,
 // argument checking, work partitioning and kernel launches.
-#include "../../include/nb6.h"
-#include "nb6_internal.h"
+#include "nb6_context.h"
 
 #include <algorithm>
 #include <cfloat>
@@ -14,59 +13,7 @@
 
 using namespace nb6;
 
-namespace {
-
-constexpr int kMaxClusters = 4096;
-
-struct DevBuf {
-    void* p = nullptr;
-    size_t cap = 0;
-};
-
-struct ClusterState {
-    int64_t n = 0;
-    double* state = nullptr;   // m[n] t[n] x[3n] v[3n] a[3n] jk[3n]
-    double *m = nullptr, *t = nullptr, *x = nullptr, *v = nullptr, *a = nullptr, *jk = nullptr;
-    DevBuf rec[3];             // j-records by mode index
-    int pred_valid = 0;        // NB6_DX_* bits whose records are current
-    double t_pred = 0.0;
-};
-
-int mode_index(int dx_mode) {
-    switch (dx_mode) {
-        case NB6_DX_FF: return MODE_FF;
-        case NB6_DX_FP64: return MODE_F64;
-        case NB6_DX_FP32: return MODE_F32;
-        default: return -1;
-    }
-}
-
-size_t rec_size(int mi) {
-    return mi == MODE_FF ? sizeof(RecFF) : mi == MODE_F64 ? sizeof(RecF64) : sizeof(RecF32);
-}
-
-}  // namespace
-
-struct nb6_ctx {
-    int device = 0;
-    int num_cu = 256;
-    int slice_hint = 0;
-    int ipl_hint = 0;
-    int64_t hbm_budget = 0;
-    std::vector<ClusterState*> clusters;
-    DevBuf part, cnt, lst, ovf;                  // force-kernel scratch
-    DevBuf in_idx, in_h2, in_dtr;                // HOST-mode inputs
-    DevBuf out_acc, out_jerk, out_nnb, out_list; // HOST-mode outputs
-    DevBuf ld[7];                                // HOST-mode load staging
-    unsigned* status = nullptr;                  // device status word
-    std::string err;
-    int last_slices = 0;
-    bool timing = false;
-    struct Timed { int kind; hipEvent_t a, b; };
-    std::vector<Timed> timed;                    // pending event pairs
-};
-
-namespace {
+namespace nb6 {
 
 int fail(nb6_ctx* c, int code, const char* fmt, ...) {
     char buf[512];
@@ -77,13 +24,6 @@ int fail(nb6_ctx* c, int code, const char* fmt, ...) {
     if (c) c->err = buf;
     return code;
 }
-
-#define HIP_TRY(ctx, call)                                                          \
-    do {                                                                            \
-        hipError_t e_ = (call);                                                     \
-        if (e_ != hipSuccess)                                                       \
-            return fail((ctx), NB6_ERR_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
-    } while (0)
 
 // Grow a device buffer to at least `bytes`.  Growing waits for the device,
 // because earlier stream-ordered work may still use the old allocation.
@@ -116,6 +56,29 @@ void release(DevBuf& b) {
     b.cap = 0;
 }
 
+Plan make_plan(const nb6_ctx* c, int64_t n, int64_t ni, int ipl) {
+    Plan p;
+    p.ipl = ipl > 0 ? ipl : c->ipl_hint > 0 ? c->ipl_hint : (ni >= 16384 ? 2 : 1);
+    const int64_t groups = (ni + 64 * p.ipl - 1) / (64 * p.ipl);
+    p.wpb = (int)std::min<int64_t>(4, groups);
+    // About 32 waves per SIMD over the launch (several rounds at the
+    // kernel's occupancy, so the last round's imbalance is a small part);
+    // no slice shorter than 256 j-particles.
+    const int64_t target = (int64_t)c->num_cu * 4 * 32;
+    int64_t s = c->slice_hint > 0 ? c->slice_hint : (target + groups - 1) / groups;
+    s = std::max<int64_t>(1, std::min<int64_t>(s, (n + 255) / 256));
+    s = std::min<int64_t>(s, 65535);
+    int64_t len = (n + s - 1) / s;
+    len = (len + 3) / 4 * 4;
+    p.slice_len = (int)len;
+    p.nslices = (int)((n + len - 1) / len);
+    return p;
+}
+
+}  // namespace nb6
+
+namespace {
+
 bool finite_all(const double* p, int64_t n) {
     for (int64_t k = 0; k < n; ++k)
         if (!std::isfinite(p[k])) return false;
@@ -145,28 +108,15 @@ struct TimedLaunch {
     }
 };
 
-// Wave-level work partition of one force call.
-struct Plan {
-    int ipl, wpb, nslices, slice_len;
-};
-
-Plan make_plan(const nb6_ctx* c, int64_t n, int64_t ni) {
-    Plan p;
-    p.ipl = c->ipl_hint > 0 ? c->ipl_hint : (ni >= 16384 ? 2 : 1);
-    const int64_t groups = (ni + 64 * p.ipl - 1) / (64 * p.ipl);
-    p.wpb = (int)std::min<int64_t>(4, groups);
-    // About 32 waves per SIMD over the launch (several rounds at the
-    // kernel's occupancy, so the last round's imbalance is a small part);
-    // no slice shorter than 256 j-particles.
-    const int64_t target = (int64_t)c->num_cu * 4 * 32;
-    int64_t s = c->slice_hint > 0 ? c->slice_hint : (target + groups - 1) / groups;
-    s = std::max<int64_t>(1, std::min<int64_t>(s, (n + 255) / 256));
-    s = std::min<int64_t>(s, 65535);
-    int64_t len = (n + s - 1) / s;
-    len = (len + 3) / 4 * 4;
-    p.slice_len = (int)len;
-    p.nslices = (int)((n + len - 1) / len);
-    return p;
+// The cluster, if loaded, and not in use by the serving queue.
+int get_cluster(nb6_ctx* c, int cluster, ClusterState** out) {
+    if (cluster < 0 || cluster >= kMaxClusters || !c->clusters[cluster] ||
+        c->clusters[cluster]->n == 0)
+        return fail(c, NB6_ERR_STATE, "cluster %d is not loaded", cluster);
+    if (c->clusters[cluster]->in_service)
+        return fail(c, NB6_ERR_STATE, "cluster %d is in use by the serving queue", cluster);
+    *out = c->clusters[cluster];
+    return NB6_OK;
 }
 
 }  // namespace
@@ -221,6 +171,7 @@ int nb6_create(nb6_ctx** out, const nb6_options* opt) {
 
 int nb6_destroy(nb6_ctx* c) {
     if (!c) return NB6_OK;
+    engine_shutdown(c);
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
     for (ClusterState* cl : c->clusters) {
@@ -278,7 +229,10 @@ int nb6_load_particles(nb6_ctx* c, int cluster, int64_t n, const double* m, cons
         return fail(c, NB6_ERR_ARG, "bad mem_kind %d", mem_kind);
     hipStream_t st = (hipStream_t)stream;
     HIP_TRY(c, hipSetDevice(c->device));
+    std::lock_guard<std::mutex> lk(c->cluster_mu);
     ClusterState*& cl = c->clusters[cluster];
+    if (cl && cl->in_service)
+        return fail(c, NB6_ERR_STATE, "cluster %d is in use by the serving queue", cluster);
 
     if (mem_kind == NB6_MEM_HOST) {
         if (!finite_all(m, n) || !finite_all(t, n) || !finite_all(x, 3 * n) ||
@@ -359,14 +313,13 @@ int nb6_load_particles(nb6_ctx* c, int cluster, int64_t n, const double* m, cons
 int nb6_predict_j(nb6_ctx* c, int cluster, double t_block, int modes, void* stream) {
     if (!c) return NB6_ERR_ARG;
     c->err.clear();
-    if (cluster < 0 || cluster >= kMaxClusters || !c->clusters[cluster] ||
-        c->clusters[cluster]->n == 0)
-        return fail(c, NB6_ERR_STATE, "cluster %d is not loaded", cluster);
+    std::lock_guard<std::mutex> lk(c->cluster_mu);
+    ClusterState* cl = nullptr;
+    if (int rc = get_cluster(c, cluster, &cl)) return rc;
     if (modes == 0) modes = NB6_DX_ALL;
     if (modes & ~NB6_DX_ALL) return fail(c, NB6_ERR_ARG, "bad modes mask %d", modes);
     if (!std::isfinite(t_block)) return fail(c, NB6_ERR_ARG, "non-finite t_block");
     HIP_TRY(c, hipSetDevice(c->device));
-    ClusterState* cl = c->clusters[cluster];
     PredictArgs pa{};
     pa.n = cl->n;
     pa.m = cl->m; pa.x = cl->x; pa.v = cl->v; pa.a = cl->a; pa.jk = cl->jk; pa.t = cl->t;
@@ -395,10 +348,9 @@ int nb6_regular_force(nb6_ctx* c, int cluster, int64_t n_i, const int32_t* idx_i
                       void* stream) {
     if (!c) return NB6_ERR_ARG;
     c->err.clear();
-    if (cluster < 0 || cluster >= kMaxClusters || !c->clusters[cluster] ||
-        c->clusters[cluster]->n == 0)
-        return fail(c, NB6_ERR_STATE, "cluster %d is not loaded", cluster);
-    ClusterState* cl = c->clusters[cluster];
+    std::lock_guard<std::mutex> lk(c->cluster_mu);
+    ClusterState* cl = nullptr;
+    if (int rc = get_cluster(c, cluster, &cl)) return rc;
     const int mi = mode_index(dx_mode);
     if (mi < 0) return fail(c, NB6_ERR_ARG, "bad dx_mode %d", dx_mode);
     if (!(cl->pred_valid & dx_mode))
@@ -549,10 +501,9 @@ int nb6_get_predicted(nb6_ctx* c, int cluster, int dx_mode, double* x, double* v
                       int mem_kind, void* stream) {
     if (!c) return NB6_ERR_ARG;
     c->err.clear();
-    if (cluster < 0 || cluster >= kMaxClusters || !c->clusters[cluster] ||
-        c->clusters[cluster]->n == 0)
-        return fail(c, NB6_ERR_STATE, "cluster %d is not loaded", cluster);
-    ClusterState* cl = c->clusters[cluster];
+    std::lock_guard<std::mutex> lk(c->cluster_mu);
+    ClusterState* cl = nullptr;
+    if (int rc = get_cluster(c, cluster, &cl)) return rc;
     const int mi = mode_index(dx_mode);
     if (mi < 0) return fail(c, NB6_ERR_ARG, "bad dx_mode %d", dx_mode);
     if (!(cl->pred_valid & dx_mode))

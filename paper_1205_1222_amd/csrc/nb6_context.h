@@ -1,0 +1,98 @@
+// nb6_context.h -- the context object behind the C ABI and the helpers its
+// translation units share (nb6_api.hip: plain calls; nb6_serve.hip: the
+// serving queue).
+#pragma once
+
+#include "../../include/nb6.h"
+#include "nb6_internal.h"
+
+#include <cstdint>
+#include <mutex>
+#include <string>
+#include <vector>
+
+namespace nb6 {
+
+constexpr int kMaxClusters = 4096;
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t cap = 0;
+};
+
+struct ClusterState {
+    int64_t n = 0;
+    double* state = nullptr;   // m[n] t[n] x[3n] v[3n] a[3n] jk[3n]
+    double *m = nullptr, *t = nullptr, *x = nullptr, *v = nullptr, *a = nullptr, *jk = nullptr;
+    DevBuf rec[3];             // j-records by mode index
+    int pred_valid = 0;        // NB6_DX_* bits whose records are current
+    double t_pred = 0.0;
+    int in_service = 0;        // requests of the serving queue in flight on it
+};
+
+inline int mode_index(int dx_mode) {
+    switch (dx_mode) {
+        case NB6_DX_FF: return MODE_FF;
+        case NB6_DX_FP64: return MODE_F64;
+        case NB6_DX_FP32: return MODE_F32;
+        default: return -1;
+    }
+}
+
+inline int mode_bit(int mi) {
+    return mi == MODE_FF ? NB6_DX_FF : mi == MODE_F64 ? NB6_DX_FP64 : NB6_DX_FP32;
+}
+
+inline size_t rec_size(int mi) {
+    return mi == MODE_FF ? sizeof(RecFF) : mi == MODE_F64 ? sizeof(RecF64) : sizeof(RecF32);
+}
+
+// Wave-level work partition of one force call.
+struct Plan {
+    int ipl, wpb, nslices, slice_len;
+};
+
+class Engine;  // serving queue (nb6_serve.hip)
+
+}  // namespace nb6
+
+struct nb6_ctx {
+    int device = 0;
+    int num_cu = 256;
+    int slice_hint = 0;
+    int ipl_hint = 0;
+    int64_t hbm_budget = 0;
+    std::vector<nb6::ClusterState*> clusters;
+    nb6::DevBuf part, cnt, lst, ovf;                  // force-kernel scratch
+    nb6::DevBuf in_idx, in_h2, in_dtr;                // HOST-mode inputs
+    nb6::DevBuf out_acc, out_jerk, out_nnb, out_list; // HOST-mode outputs
+    nb6::DevBuf ld[7];                                // HOST-mode load staging
+    unsigned* status = nullptr;                       // device status word
+    std::string err;
+    int last_slices = 0;
+    bool timing = false;
+    struct Timed { int kind; hipEvent_t a, b; };
+    std::vector<Timed> timed;                         // pending event pairs
+    // Cluster states are shared with the serving queue's thread.
+    std::mutex cluster_mu;
+    nb6::Engine* engine = nullptr;
+};
+
+namespace nb6 {
+
+int fail(nb6_ctx* c, int code, const char* fmt, ...);
+int ensure(nb6_ctx* c, DevBuf& b, size_t bytes);
+void release(DevBuf& b);
+// ipl: 0 = the context's choice (its hint, else by n_i).
+Plan make_plan(const nb6_ctx* c, int64_t n, int64_t ni, int ipl = 0);
+// Shut the serving queue down (nb6_destroy).
+void engine_shutdown(nb6_ctx* c);
+
+#define HIP_TRY(ctx, call)                                                          \
+    do {                                                                            \
+        hipError_t e_ = (call);                                                     \
+        if (e_ != hipSuccess)                                                       \
+            return ::nb6::fail((ctx), NB6_ERR_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+}  // namespace nb6

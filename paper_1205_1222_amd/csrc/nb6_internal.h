@@ -121,6 +121,38 @@ struct ScatterArgs {
     unsigned*      status;
 };
 
+// ---------------------------------------------------------------------------
+// Serving: one descriptor per request of a fused batch.
+// ---------------------------------------------------------------------------
+struct ReqDesc {
+    RegfArgs     rg;          // force work of the request
+    FinalArgs    fin;         // its reduction and lists
+    OverflowArgs ov;          // its overflow scan
+    PredictArgs  pred;        // prediction of its cluster (when do_predict)
+    int          do_predict;
+    int          mode;        // MODE_*
+    int          groups;      // i-groups of 64
+    long long    item0;       // first force work item within its mode group
+    long long    i0;          // first particle within the batch
+};
+
+struct BatchArgs {
+    const ReqDesc*      reqs;      // device copy of the batch's descriptors
+    int                 nreq;
+    long long           nitems;    // force work items of this launch
+    long long           ni_total;  // particles of the batch
+    unsigned long long* counter;   // work-item counter (zeroed before the launch)
+};
+
+// Persistent fused force kernel over requests [reqs, reqs + nreq) of one mode.
+hipError_t launch_serve_regf(int mode, const BatchArgs& b, int blocks, hipStream_t s);
+hipError_t launch_serve_finalize(const BatchArgs& b, hipStream_t s);
+hipError_t launch_serve_overflow(int mode, const BatchArgs& b, hipStream_t s);
+// Predictions and count resets of every request of the batch, in one launch
+// of (requests x chunks) blocks; a chunk covers PREPARE_CHUNK particles.
+constexpr int PREPARE_CHUNK = 1024;
+hipError_t launch_serve_prepare(const BatchArgs& b, int chunks, hipStream_t s);
+
 // i-particles per lane of the force kernel.
 hipError_t launch_regf(int mode, int ipl, int waves_per_block, const RegfArgs& a,
                        hipStream_t s);

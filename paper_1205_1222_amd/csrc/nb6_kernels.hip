@@ -184,20 +184,15 @@ __device__ __forceinline__ float checked_h2(double h2) {
     return (f >= FLT_MIN && f <= FLT_MAX) ? f : -1.0f;
 }
 
-// At least 4 waves per SIMD (<= 128 VGPRs): below that the scalar-load
-// latency of the j-records is no longer hidden.
+// Force, jerk and neighbour appends of one (i-group, j-slice) work item:
+// 64 * IPL active particles starting at group * 64 * IPL, against the
+// j-particles of slice s.
 template <int MODE, int IPL>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
-regf_kernel(RegfArgs a) {
+__device__ __forceinline__ void regf_item(const RegfArgs& a, const int group, const int s) {
     using Rec = typename RecOf<MODE>::T;
     const_ptr<Rec> rec = (const_ptr<Rec>)(a.rec);
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const int wpb = blockDim.x >> 6;
-    const int group = blockIdx.x * wpb + wave;
-    const int s = blockIdx.y;
     const int ibase = group * 64 * IPL;
-    if (ibase >= a.ni) return;  // uniform across the wave
 
     IPos<MODE> ip[IPL];
     IAux ia[IPL];
@@ -284,6 +279,18 @@ regf_kernel(RegfArgs a) {
     }
 }
 
+// One launch of one request: grid (i-groups / waves per block, slices).
+// At least 4 waves per SIMD (<= 128 VGPRs): below that the scalar-load
+// latency of the j-records is no longer hidden.
+template <int MODE, int IPL>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+regf_kernel(RegfArgs a) {
+    const int wpb = blockDim.x >> 6;
+    const int group = blockIdx.x * wpb + (threadIdx.x >> 6);
+    if (group * 64 * IPL >= a.ni) return;  // uniform across the wave
+    regf_item<MODE, IPL>(a, group, blockIdx.y);
+}
+
 // ---------------------------------------------------------------------------
 // Finalize: one wavefront per i.
 //   sums  -- the wave loads i's S x 6 partials (contiguous) into LDS and
@@ -299,13 +306,12 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__global__ void __launch_bounds__(256) finalize_kernel(FinalArgs a) {
-    __shared__ double sh_part[4][NPART * 64];
-    __shared__ int32_t sh_list[4][MAX_CAPS];
+// Finalize of particle q of one request by the calling wavefront; sh_part
+// and sh_list are this wave's LDS buffers.
+__device__ __forceinline__ void finalize_item(const FinalArgs& a, const int q,
+                                              double* __restrict__ sh_part,
+                                              int32_t* __restrict__ sh_list) {
     const int lane = threadIdx.x & 63;
-    const int w = threadIdx.x >> 6;
-    const int q = blockIdx.x * 4 + w;
-    if (q >= a.ni) return;
     const int32_t self = a.idx[q];
     if (self < 0 || self >= a.n || checked_h2(a.h2[q]) < 0.0f) {
         if (lane < 3) {
@@ -321,10 +327,10 @@ __global__ void __launch_bounds__(256) finalize_kernel(FinalArgs a) {
     const double* src = a.part + (size_t)q * a.nslices * NPART;
     for (int s0 = 0; s0 < a.nslices; s0 += 64) {
         const int ns = min(64, a.nslices - s0);
-        for (int e = lane; e < ns * NPART; e += 64) sh_part[w][e] = src[(size_t)s0 * NPART + e];
+        for (int e = lane; e < ns * NPART; e += 64) sh_part[e] = src[(size_t)s0 * NPART + e];
         wave_sync();
         if (lane < NPART)
-            for (int s = 0; s < ns; ++s) total += sh_part[w][s * NPART + lane];
+            for (int s = 0; s < ns; ++s) total += sh_part[s * NPART + lane];
         wave_sync();
     }
     if (lane < 3) a.acc[3 * q + lane] = total;
@@ -341,62 +347,179 @@ __global__ void __launch_bounds__(256) finalize_kernel(FinalArgs a) {
         return;
     }
     const int32_t* l = a.lst + (size_t)q * a.caps;
-    for (int e = lane; e < count; e += 64) sh_list[w][e] = l[e];
+    for (int e = lane; e < count; e += 64) sh_list[e] = l[e];
     wave_sync();
     for (int e = lane; e < count; e += 64) {
-        const int32_t v = sh_list[w][e];
+        const int32_t v = sh_list[e];
         if (v == self) continue;
         int rank = 0;
-        for (int k = 0; k < count; ++k) rank += sh_list[w][k] < v ? 1 : 0;
+        for (int k = 0; k < count; ++k) rank += sh_list[k] < v ? 1 : 0;
         const int pos = rank - (v > self ? 1 : 0);
         if (pos >= 0 && pos < a.cap) a.list[(size_t)q * a.cap + pos] = v;
     }
+    wave_sync();  // sh_list may be reused by this wave's next item
+}
+
+__global__ void __launch_bounds__(256) finalize_kernel(FinalArgs a) {
+    __shared__ double sh_part[4][NPART * 64];
+    __shared__ int32_t sh_list[4][MAX_CAPS];
+    const int w = threadIdx.x >> 6;
+    const int q = blockIdx.x * 4 + w;
+    if (q >= a.ni) return;
+    finalize_item(a, q, sh_part[w], sh_list[w]);
 }
 
 // ---------------------------------------------------------------------------
 // Overflowed lists: one workgroup per queued i scans all j in ascending
 // order with the force kernel's neighbour test and keeps the first `cap`.
 // ---------------------------------------------------------------------------
+// Ordered scan for queued particle q, by the whole calling workgroup.
 template <int MODE>
-__global__ void __launch_bounds__(256) overflow_kernel(OverflowArgs a) {
+__device__ __forceinline__ void overflow_item(const OverflowArgs& a, const int q,
+                                              int* __restrict__ sh_wave) {
     using Rec = typename RecOf<MODE>::T;
     const Rec* rec = static_cast<const Rec*>(a.rec);
-    __shared__ int sh_wave[4];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int w = tid >> 6;
-    const int nq = *a.ovf_count;
-    for (int item = blockIdx.x; item < nq; item += gridDim.x) {
-        const int q = a.ovf_list[item];
-        const int32_t self = a.idx[q];
-        IPos<MODE> ip;
-        IAux ia;
-        get_ipos(rec[self], ip, ia);
-        const float h2f = checked_h2(a.h2[q]);
-        const float dtf = (float)a.dtr[q];
-        int out = 0;  // identical in every thread
-        for (int j0 = 0; j0 < a.n && out < a.cap; j0 += 256) {
-            const int j = j0 + tid;
-            bool nb = false;
-            if (j < a.n && j != self) {
-                const Rec r = rec[j];
-                float dx, dy, dz;
-                coord_diff(r, ip, dx, dy, dz);
-                const float r2 = dist2(dx, dy, dz);
-                nb = velocity_criterion(r2, dx, dy, dz, r.vx - ia.vx, r.vy - ia.vy,
-                                        r.vz - ia.vz, dtf, h2f);
-            }
-            const unsigned long long m = __ballot(nb);
-            if (lane == 0) sh_wave[w] = __popcll(m);
-            __syncthreads();
-            int base = out;
-            for (int v = 0; v < w; ++v) base += sh_wave[v];
-            const int off = __popcll(m & ((1ull << lane) - 1ull));
-            if (nb && base + off < a.cap) a.list[(size_t)q * a.cap + base + off] = j;
-            const int found = sh_wave[0] + sh_wave[1] + sh_wave[2] + sh_wave[3];
-            __syncthreads();
-            out += found;
+    const int32_t self = a.idx[q];
+    IPos<MODE> ip;
+    IAux ia;
+    get_ipos(rec[self], ip, ia);
+    const float h2f = checked_h2(a.h2[q]);
+    const float dtf = (float)a.dtr[q];
+    int out = 0;  // identical in every thread
+    for (int j0 = 0; j0 < a.n && out < a.cap; j0 += 256) {
+        const int j = j0 + tid;
+        bool nb = false;
+        if (j < a.n && j != self) {
+            const Rec r = rec[j];
+            float dx, dy, dz;
+            coord_diff(r, ip, dx, dy, dz);
+            const float r2 = dist2(dx, dy, dz);
+            nb = velocity_criterion(r2, dx, dy, dz, r.vx - ia.vx, r.vy - ia.vy,
+                                    r.vz - ia.vz, dtf, h2f);
         }
+        const unsigned long long m = __ballot(nb);
+        if (lane == 0) sh_wave[w] = __popcll(m);
+        __syncthreads();
+        int base = out;
+        for (int v = 0; v < w; ++v) base += sh_wave[v];
+        const int off = __popcll(m & ((1ull << lane) - 1ull));
+        if (nb && base + off < a.cap) a.list[(size_t)q * a.cap + base + off] = j;
+        const int found = sh_wave[0] + sh_wave[1] + sh_wave[2] + sh_wave[3];
+        __syncthreads();
+        out += found;
+    }
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(256) overflow_kernel(OverflowArgs a) {
+    __shared__ int sh_wave[4];
+    const int nq = *a.ovf_count;
+    for (int item = blockIdx.x; item < nq; item += gridDim.x)
+        overflow_item<MODE>(a, a.ovf_list[item], sh_wave);
+}
+
+// ---------------------------------------------------------------------------
+// Serving: fused launches over the requests of a batch.  The descriptors are
+// copied to the device before the launches and read with scalar loads.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ RegfArgs load_regf_args(const_ptr<ReqDesc> d) {
+    RegfArgs a;
+    a.rec = d->rg.rec; a.n = d->rg.n; a.idx = d->rg.idx; a.h2 = d->rg.h2; a.dtr = d->rg.dtr;
+    a.ni = d->rg.ni; a.slice_len = d->rg.slice_len; a.nslices = d->rg.nslices;
+    a.part = d->rg.part; a.cnt = d->rg.cnt; a.lst = d->rg.lst; a.caps = d->rg.caps;
+    a.status = d->rg.status;
+    return a;
+}
+__device__ __forceinline__ FinalArgs load_final_args(const_ptr<ReqDesc> d) {
+    FinalArgs f;
+    f.part = d->fin.part; f.cnt = d->fin.cnt; f.lst = d->fin.lst; f.nslices = d->fin.nslices;
+    f.ni = d->fin.ni; f.caps = d->fin.caps; f.n = d->fin.n; f.idx = d->fin.idx; f.h2 = d->fin.h2;
+    f.acc = d->fin.acc; f.jerk = d->fin.jerk; f.nnb = d->fin.nnb; f.list = d->fin.list;
+    f.cap = d->fin.cap; f.status = d->fin.status; f.ovf_count = d->fin.ovf_count;
+    f.ovf_list = d->fin.ovf_list;
+    return f;
+}
+__device__ __forceinline__ OverflowArgs load_overflow_args(const_ptr<ReqDesc> d) {
+    OverflowArgs o;
+    o.rec = d->ov.rec; o.n = d->ov.n; o.idx = d->ov.idx; o.h2 = d->ov.h2; o.dtr = d->ov.dtr;
+    o.list = d->ov.list; o.cap = d->ov.cap; o.ovf_count = d->ov.ovf_count;
+    o.ovf_list = d->ov.ovf_list;
+    return o;
+}
+
+__device__ __forceinline__ long long uniform_ll(long long v) {
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)(unsigned long long)v);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)((unsigned long long)v >> 32));
+    return (long long)(((unsigned long long)hi << 32) | lo);
+}
+
+// Persistent: every wavefront takes work items (request, i-group, j-slice)
+// from the batch counter until none is left.  An item's result depends only
+// on its request, so a request gives the same bits alone or in any batch.
+template <int MODE>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+serve_regf_kernel(BatchArgs b) {
+    const_ptr<ReqDesc> reqs = (const_ptr<ReqDesc>)(b.reqs);
+    for (;;) {
+        unsigned long long got = 0;
+        if ((threadIdx.x & 63) == 0) got = atomicAdd(b.counter, 1ull);
+        const long long item = uniform_ll((long long)got);
+        if (item >= b.nitems) break;
+        int lo = 0, hi = b.nreq - 1;  // last request with item0 <= item
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (reqs[mid].item0 <= item) lo = mid; else hi = mid - 1;
+        }
+        const RegfArgs a = load_regf_args(reqs + lo);
+        const long long local = item - reqs[lo].item0;
+        const int groups = reqs[lo].groups;
+        regf_item<MODE, 1>(a, (int)(local % groups), (int)(local / groups));
+    }
+}
+
+__global__ void __launch_bounds__(256) serve_finalize_kernel(BatchArgs b) {
+    __shared__ double sh_part[4][NPART * 64];
+    __shared__ int32_t sh_list[4][MAX_CAPS];
+    const_ptr<ReqDesc> reqs = (const_ptr<ReqDesc>)(b.reqs);
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const long long gi = (long long)blockIdx.x * 4 + w;
+    if (gi >= b.ni_total) return;
+    int lo = 0, hi = b.nreq - 1;  // last request with i0 <= gi
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (reqs[mid].i0 <= gi) lo = mid; else hi = mid - 1;
+    }
+    const FinalArgs f = load_final_args(reqs + lo);
+    finalize_item(f, (int)(gi - reqs[lo].i0), sh_part[w], sh_list[w]);
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(256) serve_overflow_kernel(BatchArgs b) {
+    __shared__ int sh_wave[4];
+    const_ptr<ReqDesc> reqs = (const_ptr<ReqDesc>)(b.reqs);
+    for (int r = 0; r < b.nreq; ++r) {
+        if (reqs[r].fin.cap <= 0) continue;
+        const OverflowArgs o = load_overflow_args(reqs + r);
+        const int nq = *o.ovf_count;
+        for (int item = blockIdx.x; item < nq; item += gridDim.x)
+            overflow_item<MODE>(o, o.ovf_list[item], sh_wave);
+    }
+}
+
+// Block (r, chunk): predict chunk of request r's cluster (when flagged) and
+// clear the same chunk of its counts (n_i counts and the overflow count).
+__device__ __forceinline__ void predict_one(const PredictArgs& a, int64_t k);
+
+__global__ void __launch_bounds__(256) serve_prepare_kernel(BatchArgs b) {
+    const ReqDesc* d = b.reqs + blockIdx.x;
+    const int ni = d->rg.ni;
+    const int64_t base = (int64_t)blockIdx.y * PREPARE_CHUNK;
+    for (int64_t e = base + threadIdx.x; e < base + PREPARE_CHUNK; e += blockDim.x) {
+        if (e <= ni) d->rg.cnt[e] = 0;
+        if (d->do_predict && e < d->pred.n) predict_one(d->pred, e);
     }
 }
 
@@ -404,9 +527,7 @@ __global__ void __launch_bounds__(256) overflow_kernel(OverflowArgs a) {
 // Prediction of every j-particle to the block time (FP64 Horner form of the
 // cubic Taylor series), and the j-records of each requested mode.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) predict_kernel(PredictArgs a) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= a.n) return;
+__device__ __forceinline__ void predict_one(const PredictArgs& a, const int64_t k) {
     const double dt = a.tb - a.t[k];
     const double h = 0.5 * dt, t3 = dt * (1.0 / 3.0);
     double xp[3], vp[3];
@@ -447,6 +568,12 @@ __global__ void __launch_bounds__(256) predict_kernel(PredictArgs a) {
         r.vx = vf[0]; r.vy = vf[1]; r.vz = vf[2]; r.vabs = vabs;
         a.f32[k] = r;
     }
+}
+
+__global__ void __launch_bounds__(256) predict_kernel(PredictArgs a) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.n) return;
+    predict_one(a, k);
 }
 
 // Subset update of the stored state: entry e goes to particle idx[e].  An
@@ -572,6 +699,43 @@ hipError_t launch_unpack(int mode, const void* rec, int64_t n, double* x, double
         default:
             return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_serve_regf(int mode, const BatchArgs& b, int blocks, hipStream_t s) {
+    if (b.nitems <= 0) return hipSuccess;
+    const dim3 grid(blocks), block(256);
+    switch (mode) {
+        case MODE_FF: hipLaunchKernelGGL(serve_regf_kernel<MODE_FF>, grid, block, 0, s, b); break;
+        case MODE_F64: hipLaunchKernelGGL(serve_regf_kernel<MODE_F64>, grid, block, 0, s, b); break;
+        case MODE_F32: hipLaunchKernelGGL(serve_regf_kernel<MODE_F32>, grid, block, 0, s, b); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_serve_finalize(const BatchArgs& b, hipStream_t s) {
+    if (b.ni_total <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((b.ni_total + 3) / 4)), block(256);
+    hipLaunchKernelGGL(serve_finalize_kernel, grid, block, 0, s, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_serve_overflow(int mode, const BatchArgs& b, hipStream_t s) {
+    if (b.nreq <= 0) return hipSuccess;
+    const dim3 grid(OVERFLOW_BLOCKS), block(256);
+    switch (mode) {
+        case MODE_FF: hipLaunchKernelGGL(serve_overflow_kernel<MODE_FF>, grid, block, 0, s, b); break;
+        case MODE_F64: hipLaunchKernelGGL(serve_overflow_kernel<MODE_F64>, grid, block, 0, s, b); break;
+        case MODE_F32: hipLaunchKernelGGL(serve_overflow_kernel<MODE_F32>, grid, block, 0, s, b); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_serve_prepare(const BatchArgs& b, int chunks, hipStream_t s) {
+    if (b.nreq <= 0 || chunks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(serve_prepare_kernel, dim3(b.nreq, chunks), dim3(256), 0, s, b);
     return hipGetLastError();
 }
 

@@ -1,0 +1,591 @@
+// nb6_serve.hip -- the serving queue behind nb6_submit / nb6_poll.
+//
+// Requests (one regular-force block of one cluster each) are admitted in
+// arrival order while their device scratch fits an arena of the context's
+// HBM budget and no request of the same cluster is in flight.  A scheduler
+// thread fuses every admitted request into one batch:
+//   prepare      predict each request's cluster to its block time and clear
+//                its neighbour counts (one launch for the batch),
+//   force        one persistent launch per coordinate mode: wavefronts take
+//                (request, i-group, j-slice) items from an atomic counter,
+//   finalize     one launch over every active particle of the batch,
+//   overflow     ordered rebuild of overflowed lists,
+// on one of kSlots streams, so up to kSlots batches run at once and requests
+// that arrive meanwhile form the next batch.  A completion thread waits for
+// each batch, stamps its requests and frees their memory and clusters.
+//
+// A request's slicing (make_plan with one i per lane) and its summation
+// order depend only on the request, so its results are bit-identical alone
+// and in any mix.
+#include "nb6_context.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <thread>
+#include <unordered_map>
+
+namespace nb6 {
+
+namespace {
+
+constexpr int kSlots = 3;          // batches in flight
+constexpr int kMaxBatch = 512;     // requests per batch
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// First-fit allocator over one device arena, coalescing on free.
+class Arena {
+  public:
+    int init(nb6_ctx* c, size_t bytes) {
+        size_ = bytes / kAlign * kAlign;
+        if (size_ == 0) return fail(c, NB6_ERR_ARG, "serving budget is zero");
+        if (hipMalloc(&base_, size_) != hipSuccess) {
+            (void)hipGetLastError();
+            base_ = nullptr;
+            return fail(c, NB6_ERR_NOMEM, "serving arena of %zu bytes", size_);
+        }
+        free_[0] = size_;
+        return NB6_OK;
+    }
+    void release() {
+        if (base_) (void)hipFree(base_);
+        base_ = nullptr;
+        free_.clear();
+    }
+    size_t size() const { return size_; }
+    size_t used() const { return used_; }
+    bool alloc(size_t bytes, size_t* off) {
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < bytes) continue;
+            *off = it->first;
+            const size_t rest = it->second - bytes;
+            const size_t at = it->first + bytes;
+            free_.erase(it);
+            if (rest) free_[at] = rest;
+            used_ += bytes;
+            return true;
+        }
+        return false;
+    }
+    void free(size_t off, size_t bytes) {
+        used_ -= bytes;
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    char* base() const { return static_cast<char*>(base_); }
+
+  private:
+    void* base_ = nullptr;
+    size_t size_ = 0, used_ = 0;
+    std::map<size_t, size_t> free_;  // offset -> bytes
+};
+
+struct ServeReq {
+    uint64_t ticket = 0;
+    nb6_request rq{};
+    int mi = 0;
+    Plan plan{};
+    size_t bytes = 0, off = 0;
+    ClusterState* cl = nullptr;
+    int status = NB6_PENDING;
+    int batch_size = 0;
+    double t_submit = 0, t_admit = 0, t_done = 0;
+    // scratch carved from the arena
+    double* part = nullptr;
+    int32_t* cnt = nullptr;   // [ni] + overflow count
+    int32_t* lst = nullptr;
+    int32_t* ovf = nullptr;
+    int32_t* d_idx = nullptr;
+    double* d_h2 = nullptr;
+    double* d_dtr = nullptr;
+    double* d_acc = nullptr;
+    double* d_jerk = nullptr;
+    int32_t* d_nnb = nullptr;
+    int32_t* d_list = nullptr;
+};
+
+// Arena bytes of a request, and (when base != null) its buffers.
+size_t carve(ServeReq* r, char* base) {
+    const size_t ni = (size_t)r->rq.n_i, cap = (size_t)r->rq.cap, caps = cap + 1;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char* p = base ? base + off : nullptr;
+        off += align_up(bytes);
+        return p;
+    };
+    r->part = (double*)take(ni * r->plan.nslices * NPART * sizeof(double));
+    r->cnt = (int32_t*)take((ni + 1) * sizeof(int32_t));
+    r->lst = (int32_t*)take(ni * caps * sizeof(int32_t));
+    r->ovf = (int32_t*)take(ni * sizeof(int32_t));
+    if (r->rq.mem_kind == NB6_MEM_HOST) {
+        r->d_idx = (int32_t*)take(ni * sizeof(int32_t));
+        r->d_h2 = (double*)take(ni * sizeof(double));
+        r->d_dtr = (double*)take(ni * sizeof(double));
+        r->d_acc = (double*)take(3 * ni * sizeof(double));
+        r->d_jerk = (double*)take(3 * ni * sizeof(double));
+        r->d_nnb = (int32_t*)take(ni * sizeof(int32_t));
+        r->d_list = (int32_t*)take(std::max<size_t>(1, ni * cap) * sizeof(int32_t));
+    } else {
+        r->d_idx = const_cast<int32_t*>(r->rq.idx_i);
+        r->d_h2 = const_cast<double*>(r->rq.h2_i);
+        r->d_dtr = const_cast<double*>(r->rq.dtr_i);
+        r->d_acc = r->rq.acc;
+        r->d_jerk = r->rq.jerk;
+        r->d_nnb = r->rq.nnb;
+        r->d_list = r->rq.list;
+    }
+    return off;
+}
+
+struct Slot {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    ReqDesc* host_desc = nullptr;        // pinned
+    ReqDesc* dev_desc = nullptr;
+    unsigned* host_status = nullptr;     // pinned [kMaxBatch]
+    unsigned* dev_status = nullptr;      // [kMaxBatch] status words + 6 counter words
+    bool busy = false;
+    std::vector<ServeReq*> reqs;
+};
+
+}  // namespace
+
+class Engine {
+  public:
+    explicit Engine(nb6_ctx* c) : c_(c), t0_(std::chrono::steady_clock::now()) {}
+
+    int start() {
+        HIP_TRY(c_, hipSetDevice(c_->device));
+        if (int rc = arena_.init(c_, (size_t)c_->hbm_budget)) return rc;
+        for (Slot& s : slots_) {
+            HIP_TRY(c_, hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking));
+            HIP_TRY(c_, hipEventCreateWithFlags(&s.done, hipEventDisableTiming));
+            HIP_TRY(c_, hipHostMalloc((void**)&s.host_desc, kMaxBatch * sizeof(ReqDesc)));
+            HIP_TRY(c_, hipMalloc((void**)&s.dev_desc, kMaxBatch * sizeof(ReqDesc)));
+            HIP_TRY(c_, hipHostMalloc((void**)&s.host_status, kMaxBatch * sizeof(unsigned)));
+            HIP_TRY(c_, hipMalloc((void**)&s.dev_status, (kMaxBatch + 6) * sizeof(unsigned)));
+        }
+        sched_ = std::thread([this] { sched_loop(); });
+        done_ = std::thread([this] { done_loop(); });
+        return NB6_OK;
+    }
+
+    void shutdown() {
+        {
+            std::unique_lock<std::mutex> lk(mu_);
+            stop_ = true;
+            for (ServeReq* r : pending_) {
+                r->status = NB6_ERR_STATE;
+                r->t_done = now();
+            }
+            pending_.clear();
+            cv_sched_.notify_all();
+            cv_inflight_.notify_all();
+            cv_polled_.notify_all();
+        }
+        if (sched_.joinable()) sched_.join();
+        if (done_.joinable()) done_.join();
+        (void)hipSetDevice(c_->device);
+        for (Slot& s : slots_) {
+            if (s.stream) (void)hipStreamSynchronize(s.stream);
+            if (s.stream) (void)hipStreamDestroy(s.stream);
+            if (s.done) (void)hipEventDestroy(s.done);
+            if (s.host_desc) (void)hipHostFree(s.host_desc);
+            if (s.dev_desc) (void)hipFree(s.dev_desc);
+            if (s.host_status) (void)hipHostFree(s.host_status);
+            if (s.dev_status) (void)hipFree(s.dev_status);
+            s = Slot();
+        }
+        arena_.release();
+        for (auto& kv : tickets_) delete kv.second;
+        tickets_.clear();
+    }
+
+    int submit(const nb6_request* rq, uint64_t* ticket) {
+        std::unique_ptr<ServeReq> r(new ServeReq());
+        r->rq = *rq;
+        const int64_t ni = rq->n_i;
+        r->mi = mode_index(rq->dx_mode);
+        if (r->mi < 0) return fail(c_, NB6_ERR_ARG, "bad dx_mode %d", rq->dx_mode);
+        if (ni <= 0 || ni > INT32_MAX / 2) return fail(c_, NB6_ERR_ARG, "n_i = %lld", (long long)ni);
+        if (rq->cap < 0 || rq->cap > NB6_MAX_CAP)
+            return fail(c_, NB6_ERR_ARG, "cap = %d outside [0, %d]", rq->cap, NB6_MAX_CAP);
+        if (rq->mem_kind != NB6_MEM_HOST && rq->mem_kind != NB6_MEM_DEVICE)
+            return fail(c_, NB6_ERR_ARG, "bad mem_kind %d", rq->mem_kind);
+        if (!rq->idx_i || !rq->h2_i || !rq->dtr_i || !rq->acc || !rq->jerk || !rq->nnb ||
+            (rq->cap > 0 && !rq->list))
+            return fail(c_, NB6_ERR_ARG, "null argument");
+        if (!std::isfinite(rq->t_block)) return fail(c_, NB6_ERR_ARG, "non-finite t_block");
+        {
+            std::lock_guard<std::mutex> lk(c_->cluster_mu);
+            if (rq->cluster < 0 || rq->cluster >= kMaxClusters || !c_->clusters[rq->cluster] ||
+                c_->clusters[rq->cluster]->n == 0)
+                return fail(c_, NB6_ERR_STATE, "cluster %d is not loaded", rq->cluster);
+            r->cl = c_->clusters[rq->cluster];
+            if (rq->mem_kind == NB6_MEM_HOST) {
+                for (int64_t q = 0; q < ni; ++q) {
+                    if (rq->idx_i[q] < 0 || rq->idx_i[q] >= r->cl->n)
+                        return fail(c_, NB6_ERR_ARG, "idx_i[%lld] out of range", (long long)q);
+                    const float h2f = (float)rq->h2_i[q];
+                    if (!(h2f >= 1.17549435e-38f) || !(h2f <= 3.40282347e38f))
+                        return fail(c_, NB6_ERR_ARG, "h2_i[%lld] is not a positive normal float",
+                                    (long long)q);
+                    if (!std::isfinite(rq->dtr_i[q]))
+                        return fail(c_, NB6_ERR_ARG, "dtr_i[%lld] is not finite", (long long)q);
+                }
+            }
+            // the record stream of this mode is allocated once, outside the queue
+            if (!r->cl->rec[r->mi].p) {
+                if (r->cl->in_service)
+                    return fail(c_, NB6_ERR_STATE, "cluster %d: first use of this mode while busy",
+                                rq->cluster);
+                if (int rc = ensure(c_, r->cl->rec[r->mi], (size_t)r->cl->n * rec_size(r->mi)))
+                    return rc;
+            }
+            r->plan = make_plan(c_, r->cl->n, ni, 1);
+        }
+        r->bytes = carve(r.get(), nullptr);
+        std::unique_lock<std::mutex> lk(mu_);
+        if (r->bytes > arena_.size())
+            return fail(c_, NB6_ERR_ADMISSION,
+                        "request needs %zu bytes of scratch; the serving budget is %zu",
+                        r->bytes, arena_.size());
+        r->ticket = next_ticket_++;
+        r->t_submit = now();
+        *ticket = r->ticket;
+        tickets_[r->ticket] = r.get();
+        pending_.push_back(r.release());
+        blocked_ = false;
+        cv_sched_.notify_all();
+        return NB6_OK;
+    }
+
+    int poll(uint64_t ticket, int wait, nb6_ticket_info* info) {
+        std::unique_lock<std::mutex> lk(mu_);
+        auto it = tickets_.find(ticket);
+        if (it == tickets_.end())
+            return fail(c_, NB6_ERR_UNKNOWN_TICKET, "unknown ticket %llu",
+                        (unsigned long long)ticket);
+        ServeReq* r = it->second;
+        if (r->status == NB6_PENDING) {
+            if (!wait) return NB6_PENDING;
+            cv_polled_.wait(lk, [&] { return r->status != NB6_PENDING; });
+        }
+        if (info) {
+            info->status = r->status;
+            info->slices = r->plan.nslices;
+            info->batch_size = r->batch_size;
+            info->submit_us = r->t_submit;
+            info->admit_us = r->t_admit;
+            info->done_us = r->t_done;
+        }
+        const int st = r->status;
+        tickets_.erase(it);
+        delete r;
+        return st;
+    }
+
+  private:
+    double now() const {
+        return std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0_)
+            .count();
+    }
+
+    int free_slot() const {
+        for (int i = 0; i < kSlots; ++i)
+            if (!slots_[i].busy) return i;
+        return -1;
+    }
+
+    void finish(ServeReq* r, int status, double t) {
+        r->status = status;
+        r->t_done = t;
+        arena_.free(r->off, r->bytes);
+        std::lock_guard<std::mutex> lc(c_->cluster_mu);
+        r->cl->in_service = 0;
+    }
+
+    void sched_loop() {
+        (void)hipSetDevice(c_->device);
+        std::unique_lock<std::mutex> lk(mu_);
+        for (;;) {
+            cv_sched_.wait(lk, [&] {
+                return stop_ || (!pending_.empty() && !blocked_ && free_slot() >= 0);
+            });
+            if (stop_) break;
+            const int si = free_slot();
+            Slot& sl = slots_[si];
+            std::vector<ServeReq*> batch;
+            {
+                std::lock_guard<std::mutex> lc(c_->cluster_mu);
+                for (auto it = pending_.begin();
+                     it != pending_.end() && (int)batch.size() < kMaxBatch;) {
+                    ServeReq* r = *it;
+                    if (r->cl->in_service) {  // one request per cluster in flight
+                        ++it;
+                        continue;
+                    }
+                    size_t off;
+                    if (!arena_.alloc(r->bytes, &off)) break;  // arrival order for memory
+                    r->off = off;
+                    carve(r, arena_.base() + off);
+                    r->cl->in_service = 1;
+                    r->t_admit = now();
+                    batch.push_back(r);
+                    it = pending_.erase(it);
+                }
+            }
+            if (batch.empty()) {
+                blocked_ = true;  // until a batch finishes
+                continue;
+            }
+            for (ServeReq* r : batch) r->batch_size = (int)batch.size();
+            sl.busy = true;
+            sl.reqs = batch;
+            lk.unlock();
+            const int rc = launch(sl);
+            lk.lock();
+            if (rc != NB6_OK) {
+                const double t = now();
+                for (ServeReq* r : sl.reqs) finish(r, rc, t);
+                sl.reqs.clear();
+                sl.busy = false;
+                cv_polled_.notify_all();
+                continue;
+            }
+            inflight_.push_back(si);
+            cv_inflight_.notify_all();
+        }
+    }
+
+    void done_loop() {
+        (void)hipSetDevice(c_->device);
+        std::unique_lock<std::mutex> lk(mu_);
+        for (;;) {
+            cv_inflight_.wait(lk, [&] { return !inflight_.empty() || stop_; });
+            if (inflight_.empty()) break;  // stop_ and drained
+            const int si = inflight_.front();
+            Slot& sl = slots_[si];
+            lk.unlock();
+            const hipError_t e = hipEventSynchronize(sl.done);
+            const double t = now();
+            lk.lock();
+            inflight_.pop_front();
+            for (size_t b = 0; b < sl.reqs.size(); ++b) {
+                ServeReq* r = sl.reqs[b];
+                int st = NB6_OK;
+                if (e != hipSuccess) {
+                    st = NB6_ERR_HIP;
+                } else if (sl.host_status[b] & (ST_BAD_INDEX | ST_BAD_H2 | ST_NONFINITE)) {
+                    st = NB6_ERR_DEVICE_INPUT;
+                } else if (sl.host_status[b] & ST_OVERFLOW) {
+                    st = NB6_WARN_NB_OVERFLOW;
+                }
+                finish(r, st, t);
+            }
+            sl.reqs.clear();
+            sl.busy = false;
+            blocked_ = false;
+            cv_sched_.notify_all();
+            cv_polled_.notify_all();
+        }
+    }
+
+    // Enqueue the work of one batch on its slot's stream.  Runs on the
+    // scheduler thread, so errors are returned as codes only (the context's
+    // error text belongs to the caller's thread).
+    int launch(Slot& sl) {
+        HIP_TRY(nullptr, hipSetDevice(c_->device));
+        hipStream_t st = sl.stream;
+        std::vector<ServeReq*>& reqs = sl.reqs;
+        std::stable_sort(reqs.begin(), reqs.end(),
+                         [](const ServeReq* a, const ServeReq* b) { return a->mi < b->mi; });
+        const int nreq = (int)reqs.size();
+        long long i0 = 0, item_in_mode = 0;
+        int64_t chunk_need = 0;
+        int prev_mi = -1;
+        for (int b = 0; b < nreq; ++b) {
+            ServeReq* r = reqs[b];
+            ClusterState* cl = r->cl;
+            const int ni = (int)r->rq.n_i;
+            if (r->rq.mem_kind == NB6_MEM_HOST) {
+                HIP_TRY(nullptr, hipMemcpyAsync(r->d_idx, r->rq.idx_i, ni * sizeof(int32_t),
+                                           hipMemcpyHostToDevice, st));
+                HIP_TRY(nullptr, hipMemcpyAsync(r->d_h2, r->rq.h2_i, ni * sizeof(double),
+                                           hipMemcpyHostToDevice, st));
+                HIP_TRY(nullptr, hipMemcpyAsync(r->d_dtr, r->rq.dtr_i, ni * sizeof(double),
+                                           hipMemcpyHostToDevice, st));
+            }
+            if (r->mi != prev_mi) {
+                item_in_mode = 0;
+                prev_mi = r->mi;
+            }
+            ReqDesc& d = sl.host_desc[b];
+            std::memset(&d, 0, sizeof d);
+            const int bit = mode_bit(r->mi);
+            {
+                std::lock_guard<std::mutex> lc(c_->cluster_mu);
+                d.do_predict = !((cl->pred_valid & bit) && cl->t_pred == r->rq.t_block);
+                if (d.do_predict) {
+                    cl->pred_valid = (cl->t_pred == r->rq.t_block ? cl->pred_valid : 0) | bit;
+                    cl->t_pred = r->rq.t_block;
+                }
+            }
+            unsigned* status = sl.dev_status + b;
+            d.pred.n = cl->n;
+            d.pred.m = cl->m; d.pred.x = cl->x; d.pred.v = cl->v; d.pred.a = cl->a;
+            d.pred.jk = cl->jk; d.pred.t = cl->t;
+            d.pred.tb = r->rq.t_block;
+            d.pred.ff = r->mi == MODE_FF ? (RecFF*)cl->rec[MODE_FF].p : nullptr;
+            d.pred.f64 = r->mi == MODE_F64 ? (RecF64*)cl->rec[MODE_F64].p : nullptr;
+            d.pred.f32 = r->mi == MODE_F32 ? (RecF32*)cl->rec[MODE_F32].p : nullptr;
+            d.pred.status = status;
+            const Plan& p = r->plan;
+            d.rg.rec = cl->rec[r->mi].p;
+            d.rg.n = (int)cl->n;
+            d.rg.idx = r->d_idx; d.rg.h2 = r->d_h2; d.rg.dtr = r->d_dtr;
+            d.rg.ni = ni;
+            d.rg.slice_len = p.slice_len;
+            d.rg.nslices = p.nslices;
+            d.rg.part = r->part; d.rg.cnt = r->cnt; d.rg.lst = r->lst;
+            d.rg.caps = r->rq.cap + 1;
+            d.rg.status = status;
+            d.fin.part = r->part; d.fin.cnt = r->cnt; d.fin.lst = r->lst;
+            d.fin.nslices = p.nslices; d.fin.ni = ni; d.fin.caps = r->rq.cap + 1;
+            d.fin.n = (int)cl->n; d.fin.idx = r->d_idx; d.fin.h2 = r->d_h2;
+            d.fin.acc = r->d_acc; d.fin.jerk = r->d_jerk; d.fin.nnb = r->d_nnb;
+            d.fin.list = r->d_list; d.fin.cap = r->rq.cap; d.fin.status = status;
+            d.fin.ovf_count = r->cnt + ni; d.fin.ovf_list = r->ovf;
+            d.ov.rec = d.rg.rec; d.ov.n = d.rg.n; d.ov.idx = r->d_idx; d.ov.h2 = r->d_h2;
+            d.ov.dtr = r->d_dtr; d.ov.list = r->d_list; d.ov.cap = r->rq.cap;
+            d.ov.ovf_count = r->cnt + ni; d.ov.ovf_list = r->ovf;
+            d.mode = r->mi;
+            d.groups = (ni + 63) / 64;
+            d.item0 = item_in_mode;
+            d.i0 = i0;
+            item_in_mode += (long long)d.groups * p.nslices;
+            i0 += ni;
+            chunk_need = std::max<int64_t>(chunk_need, std::max<int64_t>(cl->n, ni + 1));
+        }
+        HIP_TRY(nullptr, hipMemcpyAsync(sl.dev_desc, sl.host_desc, nreq * sizeof(ReqDesc),
+                                   hipMemcpyHostToDevice, st));
+        HIP_TRY(nullptr, launch_zero_u32(sl.dev_status, kMaxBatch + 6, st));
+        unsigned long long* counters = (unsigned long long*)(sl.dev_status + kMaxBatch);
+        BatchArgs all{};
+        all.reqs = sl.dev_desc;
+        all.nreq = nreq;
+        all.ni_total = i0;
+        HIP_TRY(nullptr, launch_serve_prepare(
+                        all, (int)((chunk_need + PREPARE_CHUNK - 1) / PREPARE_CHUNK), st));
+        // one persistent force launch per coordinate mode present
+        const int blocks = c_->num_cu * 8;
+        for (int b = 0; b < nreq;) {
+            int e = b;
+            long long items = 0;
+            while (e < nreq && reqs[e]->mi == reqs[b]->mi) {
+                items += (long long)sl.host_desc[e].groups * reqs[e]->plan.nslices;
+                ++e;
+            }
+            BatchArgs g{};
+            g.reqs = sl.dev_desc + b;
+            g.nreq = e - b;
+            g.nitems = items;
+            g.counter = counters + reqs[b]->mi;
+            HIP_TRY(nullptr, launch_serve_regf(reqs[b]->mi, g, blocks, st));
+            b = e;
+        }
+        HIP_TRY(nullptr, launch_serve_finalize(all, st));
+        for (int b = 0; b < nreq;) {
+            int e = b;
+            while (e < nreq && reqs[e]->mi == reqs[b]->mi) ++e;
+            BatchArgs g{};
+            g.reqs = sl.dev_desc + b;
+            g.nreq = e - b;
+            HIP_TRY(nullptr, launch_serve_overflow(reqs[b]->mi, g, st));
+            b = e;
+        }
+        for (ServeReq* r : reqs) {
+            if (r->rq.mem_kind != NB6_MEM_HOST) continue;
+            const size_t ni = (size_t)r->rq.n_i;
+            HIP_TRY(nullptr, hipMemcpyAsync(r->rq.acc, r->d_acc, 3 * ni * sizeof(double),
+                                       hipMemcpyDeviceToHost, st));
+            HIP_TRY(nullptr, hipMemcpyAsync(r->rq.jerk, r->d_jerk, 3 * ni * sizeof(double),
+                                       hipMemcpyDeviceToHost, st));
+            HIP_TRY(nullptr, hipMemcpyAsync(r->rq.nnb, r->d_nnb, ni * sizeof(int32_t),
+                                       hipMemcpyDeviceToHost, st));
+            if (r->rq.cap > 0)
+                HIP_TRY(nullptr, hipMemcpyAsync(r->rq.list, r->d_list, ni * r->rq.cap * sizeof(int32_t),
+                                           hipMemcpyDeviceToHost, st));
+        }
+        HIP_TRY(nullptr, hipMemcpyAsync(sl.host_status, sl.dev_status, nreq * sizeof(unsigned),
+                                   hipMemcpyDeviceToHost, st));
+        HIP_TRY(nullptr, hipEventRecord(sl.done, st));
+        return NB6_OK;
+    }
+
+    nb6_ctx* c_;
+    std::chrono::steady_clock::time_point t0_;
+    std::mutex mu_;
+    std::condition_variable cv_sched_, cv_inflight_, cv_polled_;
+    std::deque<ServeReq*> pending_;
+    std::unordered_map<uint64_t, ServeReq*> tickets_;
+    std::deque<int> inflight_;
+    Slot slots_[kSlots];
+    Arena arena_;
+    uint64_t next_ticket_ = 1;
+    bool stop_ = false;
+    bool blocked_ = false;
+    std::thread sched_, done_;
+};
+
+void engine_shutdown(nb6_ctx* c) {
+    if (!c->engine) return;
+    c->engine->shutdown();
+    delete c->engine;
+    c->engine = nullptr;
+}
+
+}  // namespace nb6
+
+using namespace nb6;
+
+extern "C" {
+
+int nb6_submit(nb6_ctx* c, const nb6_request* req, uint64_t* ticket) {
+    if (!c || !req || !ticket) return NB6_ERR_ARG;
+    if (!c->engine) {
+        std::unique_ptr<Engine> e(new Engine(c));
+        if (int rc = e->start()) {
+            e->shutdown();
+            return rc;
+        }
+        c->engine = e.release();
+    }
+    return c->engine->submit(req, ticket);
+}
+
+int nb6_poll(nb6_ctx* c, uint64_t ticket, int wait, nb6_ticket_info* info) {
+    if (!c) return NB6_ERR_ARG;
+    if (!c->engine) return fail(c, NB6_ERR_UNKNOWN_TICKET, "no request was ever submitted");
+    return c->engine->poll(ticket, wait, info);
+}
+
+}  // extern "C"

@@ -47,7 +47,7 @@ NB6_MAX_CAP = 1023
 EXPORTED = [
     "nb6_create", "nb6_destroy", "nb6_last_error", "nb6_load_particles",
     "nb6_predict_j", "nb6_regular_force", "nb6_sync_status", "nb6_last_slices",
-    "nb6_get_predicted", "nb6_kernel_times",
+    "nb6_get_predicted", "nb6_kernel_times", "nb6_submit", "nb6_poll",
 ]
 
 NB6_OPT_TIMING = 1
@@ -57,6 +57,22 @@ class nb6_options(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int), ("slice_hint", ctypes.c_int),
                 ("hbm_budget", ctypes.c_int64), ("flags", ctypes.c_int),
                 ("ipl_hint", ctypes.c_int)]
+
+
+class nb6_request(ctypes.Structure):
+    _fields_ = [("cluster", ctypes.c_int), ("t_block", ctypes.c_double),
+                ("dx_mode", ctypes.c_int), ("n_i", ctypes.c_int64),
+                ("idx_i", ctypes.c_void_p), ("h2_i", ctypes.c_void_p),
+                ("dtr_i", ctypes.c_void_p), ("acc", ctypes.c_void_p),
+                ("jerk", ctypes.c_void_p), ("nnb", ctypes.c_void_p),
+                ("list", ctypes.c_void_p), ("cap", ctypes.c_int32),
+                ("mem_kind", ctypes.c_int)]
+
+
+class nb6_ticket_info(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("slices", ctypes.c_int),
+                ("batch_size", ctypes.c_int), ("submit_us", ctypes.c_double),
+                ("admit_us", ctypes.c_double), ("done_us", ctypes.c_double)]
 
 
 class NB6Error(RuntimeError):
@@ -91,6 +107,8 @@ def lib():
                                         vp, vp, vp, vp, ctypes.c_int32, ctypes.c_int, vp]
         L.nb6_sync_status.argtypes = [vp, vp]
         L.nb6_kernel_times.argtypes = [vp, vp, vp]
+        L.nb6_submit.argtypes = [vp, ctypes.POINTER(nb6_request), ctypes.POINTER(ctypes.c_uint64)]
+        L.nb6_poll.argtypes = [vp, ctypes.c_uint64, ctypes.c_int, ctypes.POINTER(nb6_ticket_info)]
         L.nb6_get_predicted.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp, ctypes.c_int, vp]
         for name in EXPORTED:
             if name != "nb6_last_error":
@@ -195,6 +213,28 @@ def nb6_kernel_times(ctx):
     rc = lib().nb6_kernel_times(ctx, ms.ctypes.data, counts.ctypes.data)
     check(ctx, rc)
     return ms, counts
+
+
+def nb6_submit(ctx, cluster, t_block, dx_mode, n_i, idx_i, h2_i, dtr_i, acc, jerk, nnb,
+               nblist, cap, mem_kind=NB6_MEM_HOST):
+    """Queue one request; returns (status, ticket).  The arrays must stay alive
+    until nb6_poll reports the request finished."""
+    f = np.float64
+    rq = nb6_request(cluster, float(t_block), dx_mode, n_i, _ptr(idx_i, np.int32),
+                     _ptr(h2_i, f), _ptr(dtr_i, f), _ptr(acc, f), _ptr(jerk, f),
+                     _ptr(nnb, np.int32), _ptr(nblist, np.int32), cap, mem_kind)
+    t = ctypes.c_uint64(0)
+    rc = lib().nb6_submit(ctx, ctypes.byref(rq), ctypes.byref(t))
+    return rc, t.value
+
+
+def nb6_poll(ctx, ticket, wait=0):
+    """(status, info dict or None)."""
+    info = nb6_ticket_info()
+    rc = lib().nb6_poll(ctx, ticket, wait, ctypes.byref(info))
+    if rc == NB6_PENDING or rc == NB6_ERR_UNKNOWN_TICKET:
+        return rc, None
+    return rc, {k: getattr(info, k) for k, _ in nb6_ticket_info._fields_}
 
 
 def nb6_sync_status(ctx, stream=None):

@@ -1,0 +1,241 @@
+"""GPU tests of the serving queue (nb6_submit / nb6_poll) through the C ABI.
+
+* every served result matches the FP64 oracle (same bars as the plain path);
+* a request gives bit-identical results alone and fused with others;
+* served results equal the plain call's when both use one i per lane;
+* admission: a request larger than the HBM budget is refused; requests that
+  only fit one at a time all complete;
+* overflowed lists, unknown tickets, double polls.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+from oracle.compare import compare  # noqa: E402
+from workloads import make_cluster  # noqa: E402
+
+
+def _nb6():
+    from paper_1205_1222_amd import nb6
+    return nb6
+
+
+SIZES = [2048, 3001, 4096, 6000]
+
+
+@pytest.fixture(scope="module")
+def clusters():
+    return [make_cluster(n, 500 + k, masses="imf", k_nb=24) for k, n in enumerate(SIZES)]
+
+
+def _load_all(nb6, ctx, cls):
+    for c, cl in enumerate(cls):
+        nb6.check(ctx, nb6.nb6_load_particles(ctx, c, cl.n, cl.m, cl.x, cl.v, cl.a,
+                                              cl.jerk, cl.t))
+
+
+def _requests(cls, seed=1, per_cluster=3):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for c, cl in enumerate(cls):
+        for r in range(per_cluster):
+            ni = int(rng.choice([1, 16, 64, 100, 257, 1024]))
+            idx = np.sort(rng.choice(cl.n, ni, replace=False)).astype(np.int32)
+            tb = cl.tb + r * 2.0 ** -12   # successive block times of the cluster
+            out.append((c, tb, idx))
+    return out
+
+
+class Host:
+    """Host buffers of one request (kept alive until polled)."""
+
+    def __init__(self, ni, cap):
+        self.acc = np.full((ni, 3), np.nan)
+        self.jerk = np.full((ni, 3), np.nan)
+        self.nnb = np.full(ni, -9, np.int32)
+        self.lst = np.full((ni, max(cap, 1)), -9, np.int32)
+
+
+def _submit(nb6, ctx, cl, c, tb, idx, cap, mode=1):
+    h = Host(len(idx), cap)
+    h.idx = np.ascontiguousarray(idx, np.int32)
+    h.h2 = np.ascontiguousarray(cl.h2[idx])
+    h.dtr = np.ascontiguousarray(cl.dtr[idx])
+    rc, t = nb6.nb6_submit(ctx, c, tb, mode, len(idx), h.idx, h.h2, h.dtr, h.acc, h.jerk,
+                           h.nnb, h.lst if cap > 0 else None, cap)
+    nb6.check(ctx, rc)
+    return t, h
+
+
+def test_served_results_match_oracle(clusters):
+    nb6 = _nb6()
+    ctx = nb6.nb6_create(0)
+    try:
+        _load_all(nb6, ctx, clusters)
+        cap = 256
+        subs = []
+        for c, tb, idx in _requests(clusters):
+            subs.append((c, tb, idx) + _submit(nb6, ctx, clusters[c], c, tb, idx, cap))
+        sizes = []
+        for c, tb, idx, t, h in subs:
+            rc, info = nb6.nb6_poll(ctx, t, wait=1)
+            assert rc in (nb6.NB6_OK, nb6.NB6_WARN_NB_OVERFLOW), rc
+            sizes.append(info["batch_size"])
+            assert info["submit_us"] <= info["admit_us"] <= info["done_us"]
+            cl = clusters[c]
+            xp, vp = oracle.predict(cl.x, cl.v, cl.a, cl.jerk, cl.t, tb)
+            ref = oracle.regular_force(cl.m, xp, vp, idx, cl.h2[idx], cl.dtr[idx], lcap=4096)
+            cmp_ = compare(h.acc, h.jerk, h.nnb, h.lst, cap, ref, cl.m, xp, vp, idx,
+                           cl.h2[idx], cl.dtr[idx])
+            s = cmp_.summary()
+            assert cmp_.list_mismatch == 0 and cmp_.nnb_mismatch == 0, s
+            assert s["acc_scaled_max"] <= 1e-6 and s["jerk_scaled_max"] <= 1e-6, s
+            assert s.get("acc_rel_max", 0) <= 1e-6 and s.get("jerk_rel_max", 0) <= 1e-6, s
+        print("batch sizes", sizes, flush=True)
+        assert max(sizes) > 1  # requests were fused
+    finally:
+        nb6.nb6_destroy(ctx)
+
+
+def test_alone_and_mixed_are_bit_identical(clusters):
+    nb6 = _nb6()
+    ctx = nb6.nb6_create(0)
+    try:
+        _load_all(nb6, ctx, clusters)
+        cap = 128
+        reqs = _requests(clusters, seed=7, per_cluster=2)
+        alone = []
+        for c, tb, idx in reqs:  # one at a time
+            t, h = _submit(nb6, ctx, clusters[c], c, tb, idx, cap)
+            rc, info = nb6.nb6_poll(ctx, t, wait=1)
+            assert info["batch_size"] == 1
+            alone.append(h)
+        # all at once, in reverse order, mixed with other clusters' blocks
+        mixed = [None] * len(reqs)
+        tickets = []
+        for k in reversed(range(len(reqs))):
+            c, tb, idx = reqs[k]
+            t, h = _submit(nb6, ctx, clusters[c], c, tb, idx, cap)
+            tickets.append((k, t, h))
+        fused = 0
+        for k, t, h in tickets:
+            rc, info = nb6.nb6_poll(ctx, t, wait=1)
+            fused = max(fused, info["batch_size"])
+            mixed[k] = h
+        assert fused > 1
+        for a, m in zip(alone, mixed):
+            np.testing.assert_array_equal(a.acc, m.acc)
+            np.testing.assert_array_equal(a.jerk, m.jerk)
+            np.testing.assert_array_equal(a.nnb, m.nnb)
+            for q in range(len(a.nnb)):
+                k = min(cap, a.nnb[q])
+                np.testing.assert_array_equal(a.lst[q, :k], m.lst[q, :k])
+    finally:
+        nb6.nb6_destroy(ctx)
+
+
+def test_served_equals_plain_call(clusters):
+    """One i per lane in both paths: the same slicing, hence the same bits."""
+    nb6 = _nb6()
+    ctx = nb6.nb6_create(0, ipl_hint=1)
+    try:
+        _load_all(nb6, ctx, clusters)
+        cl = clusters[2]
+        idx = np.arange(0, cl.n, 7, dtype=np.int32)
+        t, h = _submit(nb6, ctx, cl, 2, cl.tb, idx, 64)
+        rc, _ = nb6.nb6_poll(ctx, t, wait=1)
+        nb6.check(ctx, nb6.nb6_predict_j(ctx, 2, cl.tb, nb6.NB6_DX_FF))
+        acc, jerk, nnb, lst, _ = nb6.regular_force_host(ctx, 2, idx, cl.h2[idx], cl.dtr[idx],
+                                                        1, 64)
+        np.testing.assert_array_equal(acc, h.acc)
+        np.testing.assert_array_equal(jerk, h.jerk)
+        np.testing.assert_array_equal(nnb, h.nnb)
+    finally:
+        nb6.nb6_destroy(ctx)
+
+
+def test_admission_by_budget(clusters):
+    nb6 = _nb6()
+    budget = 4 << 20
+    ctx = nb6.nb6_create(0, hbm_budget=budget)
+    try:
+        _load_all(nb6, ctx, clusters)
+        cl = clusters[3]
+        # too big for the budget on its own: refused at submit
+        big = np.arange(cl.n, dtype=np.int32)
+        h = Host(len(big), 1023)
+        rc, _ = nb6.nb6_submit(ctx, 3, cl.tb, 1, len(big), big, cl.h2[big].copy(),
+                               cl.dtr[big].copy(), h.acc, h.jerk, h.nnb, h.lst, 1023)
+        assert rc == nb6.NB6_ERR_ADMISSION
+        # each fits alone (~1.5 MB) but not two at once
+        subs = []
+        for c in range(4):
+            cl = clusters[c]
+            idx = np.arange(0, 600, dtype=np.int32)
+            subs.append(_submit(nb6, ctx, cl, c, cl.tb, idx, 500))
+        for t, h in subs:
+            rc, info = nb6.nb6_poll(ctx, t, wait=1)
+            assert rc in (nb6.NB6_OK, nb6.NB6_WARN_NB_OVERFLOW)
+            assert info["batch_size"] == 1
+            assert np.all(np.isfinite(h.acc))
+    finally:
+        nb6.nb6_destroy(ctx)
+
+
+def test_overflow_unknown_and_double_poll(clusters):
+    nb6 = _nb6()
+    ctx = nb6.nb6_create(0)
+    try:
+        _load_all(nb6, ctx, clusters)
+        cl = clusters[0]
+        idx = np.array([3, 50, 900], np.int32)
+        t_full, full = _submit(nb6, ctx, cl, 0, cl.tb, idx, 256)
+        assert nb6.nb6_poll(ctx, t_full, wait=1)[0] == nb6.NB6_OK
+        t, h = _submit(nb6, ctx, cl, 0, cl.tb, idx, 2)
+        rc, _ = nb6.nb6_poll(ctx, t, wait=1)
+        assert rc == nb6.NB6_WARN_NB_OVERFLOW
+        np.testing.assert_array_equal(h.nnb, full.nnb)
+        np.testing.assert_array_equal(h.lst[:, :2], full.lst[:, :2])
+        assert nb6.nb6_poll(ctx, t, wait=0)[0] == nb6.NB6_ERR_UNKNOWN_TICKET
+        assert nb6.nb6_poll(ctx, 987654, wait=0)[0] == nb6.NB6_ERR_UNKNOWN_TICKET
+        # bad requests are refused at submit
+        rc, _ = nb6.nb6_submit(ctx, 0, cl.tb, 3, 3, idx, cl.h2[idx].copy(), cl.dtr[idx].copy(),
+                               h.acc, h.jerk, h.nnb, h.lst, 2)
+        assert rc == nb6.NB6_ERR_ARG
+        rc, _ = nb6.nb6_submit(ctx, 9, cl.tb, 1, 3, idx, cl.h2[idx].copy(), cl.dtr[idx].copy(),
+                               h.acc, h.jerk, h.nnb, h.lst, 2)
+        assert rc == nb6.NB6_ERR_STATE
+    finally:
+        nb6.nb6_destroy(ctx)
+
+
+def test_device_mode_serving(clusters):
+    import torch
+    nb6 = _nb6()
+    ctx = nb6.nb6_create(0)
+    try:
+        _load_all(nb6, ctx, clusters)
+        cl = clusters[1]
+        idx = np.arange(5, cl.n, 11, dtype=np.int32)
+        t, h = _submit(nb6, ctx, cl, 1, cl.tb, idx, 128)
+        assert nb6.nb6_poll(ctx, t, wait=1)[0] == nb6.NB6_OK
+        dev = torch.device("cuda:0")
+        ni = len(idx)
+        ti = torch.from_numpy(idx).to(dev)
+        th2 = torch.from_numpy(cl.h2[idx].copy()).to(dev)
+        tdt = torch.from_numpy(cl.dtr[idx].copy()).to(dev)
+        acc = torch.empty((ni, 3), dtype=torch.float64, device=dev)
+        jerk = torch.empty_like(acc)
+        nnb = torch.empty(ni, dtype=torch.int32, device=dev)
+        lst = torch.empty((ni, 128), dtype=torch.int32, device=dev)
+        torch.cuda.synchronize()
+        rc, t2 = nb6.nb6_submit(ctx, 1, cl.tb, 1, ni, ti, th2, tdt, acc, jerk, nnb, lst, 128,
+                                nb6.NB6_MEM_DEVICE)
+        nb6.check(ctx, rc)
+        assert nb6.nb6_poll(ctx, t2, wait=1)[0] == nb6.NB6_OK
+        np.testing.assert_array_equal(acc.cpu().numpy(), h.acc)
+        np.testing.assert_array_equal(nnb.cpu().numpy(), h.nnb)
+    finally:
+        nb6.nb6_destroy(ctx)
