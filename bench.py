@@ -73,6 +73,185 @@ def cpu_baseline(cl, idx, gpu_out, cap, target_s):
     return base, c.summary()
 
 
+def serving_leg(args, nb6, torch):
+    """Serving trace: 64 Plummer clusters (N log-uniform 4096..65536), blocks of
+    2^k random active particles, open-loop Poisson arrivals at rho times the
+    capacity of the plain form (one block per launch, FIFO on one stream).
+    Both forms serve the same arrival sequence; latency = finish - arrival."""
+    import threading
+
+    from workloads import serving_trace
+
+    t_gen = time.perf_counter()
+    tr = serving_trace(n_requests=args.serve_requests)
+    cls, reqs = tr["clusters"], tr["requests"]
+    log(f"bench: serving trace: {len(cls)} clusters, {sum(tr['sizes'])} particles, "
+        f"{len(reqs)} requests, inputs in {time.perf_counter() - t_gen:.1f} s")
+    dev = torch.device("cuda:0")
+    cap = args.serve_cap
+    mode = MODES[args.mode]
+    # block times: successive blocks of each cluster
+    seen = [0] * len(cls)
+    tbs = []
+    for c, idx in reqs:
+        tbs.append(cls[c].tb + seen[c] * 2.0 ** -12)
+        seen[c] += 1
+    # device-resident inputs of every request
+    idx_all = np.concatenate([idx for _, idx in reqs]).astype(np.int32)
+    h2_all = np.concatenate([cls[c].h2[idx] for c, idx in reqs])
+    dtr_all = np.concatenate([cls[c].dtr[idx] for c, idx in reqs])
+    off = np.concatenate([[0], np.cumsum([len(idx) for _, idx in reqs])])
+    d_idx = torch.from_numpy(idx_all).to(dev)
+    d_h2 = torch.from_numpy(h2_all).to(dev)
+    d_dtr = torch.from_numpy(dtr_all).to(dev)
+    work = np.array([len(idx) * (cls[c].n - 1) for c, idx in reqs], dtype=np.float64)
+
+    def outputs(ni):
+        return (torch.empty((ni, 3), dtype=torch.float64, device=dev),
+                torch.empty((ni, 3), dtype=torch.float64, device=dev),
+                torch.empty(ni, dtype=torch.int32, device=dev),
+                torch.empty((ni, max(cap, 1)), dtype=torch.int32, device=dev))
+
+    def load(ctx):
+        for c, cl in enumerate(cls):
+            nb6.check(ctx, nb6.nb6_load_particles(ctx, c, cl.n, cl.m, cl.x, cl.v, cl.a,
+                                                  cl.jerk, cl.t))
+
+    # ---- plain form: one block per launch, FIFO on one stream ----------------
+    pctx = nb6.nb6_create(0)
+    load(pctx)
+    stream = torch.cuda.current_stream()
+    outs = outputs(int(max(len(idx) for _, idx in reqs)))
+
+    def plain_one(k):
+        c, idx = reqs[k]
+        ni = len(idx)
+        a, j, nn, ls = outs
+        nb6.check(pctx, nb6.nb6_predict_j(pctx, c, tbs[k], mode, stream))
+        nb6.check(pctx, nb6.nb6_regular_force(
+            pctx, c, ni, d_idx[off[k]:off[k + 1]], d_h2[off[k]:off[k + 1]],
+            d_dtr[off[k]:off[k + 1]], mode, a[:ni], j[:ni], nn[:ni], ls[:ni], cap,
+            nb6.NB6_MEM_DEVICE, stream))
+        torch.cuda.synchronize()
+
+    for k in range(min(20, len(reqs))):  # warm-up (allocations)
+        plain_one(k)
+    ncal = min(len(reqs), args.serve_calibrate)
+    t0 = time.perf_counter()
+    for k in range(ncal):
+        plain_one(k)
+    s_bar = (time.perf_counter() - t0) / ncal
+    rhos = [float(x) for x in str(args.rho).split(",")]
+    log(f"bench: plain service {s_bar * 1e3:.3f} ms/block")
+
+    def wait_until(t_start, t_rel):
+        while True:
+            d = t_start + t_rel - time.perf_counter()
+            if d <= 0:
+                return
+            time.sleep(min(d, 2e-4) if d > 2e-4 else 0)
+
+    def q(a, p):
+        return round(float(np.quantile(a, p)) * 1e3, 4)
+
+    total = work.sum()
+    runs = []
+    sctx = nb6.nb6_create(0, hbm_budget=args.serve_budget_mb << 20)
+    load(sctx)
+    # warm-up: start the queue and allocate every cluster's record stream
+    warm = []
+    for c, cl in enumerate(cls):
+        o = outputs(16)
+        wi = torch.arange(16, dtype=torch.int32, device=dev)
+        rc, t = nb6.nb6_submit(sctx, c, cl.tb, mode, 16, wi, d_h2[:16], d_dtr[:16],
+                               o[0], o[1], o[2], o[3], cap, nb6.NB6_MEM_DEVICE)
+        nb6.check(sctx, rc)
+        warm.append((t, o, wi))
+    for t, _, _ in warm:
+        nb6.nb6_poll(sctx, t, 1)
+    del warm
+    for rho in rhos:
+        rate = rho / s_bar
+        rng = np.random.Generator(np.random.PCG64(12051226))
+        arrivals = np.cumsum(rng.exponential(1.0 / rate, len(reqs)))
+
+        # plain form on the same arrival sequence
+        lat_plain = np.empty(len(reqs))
+        t_start = time.perf_counter()
+        for k in range(len(reqs)):
+            wait_until(t_start, arrivals[k])
+            plain_one(k)
+            lat_plain[k] = time.perf_counter() - t_start - arrivals[k]
+        span_plain = time.perf_counter() - t_start
+
+        # serving form: continuous batching through nb6_submit / nb6_poll
+        tickets = [None] * len(reqs)
+        infos = [None] * len(reqs)
+        live = {}
+        ready = threading.Semaphore(0)
+        errors = []
+
+        def poller():
+            for k in range(len(reqs)):
+                ready.acquire()
+                rc, info = nb6.nb6_poll(sctx, tickets[k], 1)
+                if rc not in (nb6.NB6_OK, nb6.NB6_WARN_NB_OVERFLOW):
+                    errors.append((k, rc))
+                infos[k] = info
+                live.pop(k, None)
+
+        th = threading.Thread(target=poller)
+        th.start()
+        t_start = time.perf_counter()
+        sub_wall = np.empty(len(reqs))
+        for k in range(len(reqs)):
+            c, idx = reqs[k]
+            ni = len(idx)
+            o = outputs(ni)
+            live[k] = o
+            wait_until(t_start, arrivals[k])
+            sub_wall[k] = time.perf_counter() - t_start
+            rc, t = nb6.nb6_submit(sctx, c, tbs[k], mode, ni, d_idx[off[k]:off[k + 1]],
+                                   d_h2[off[k]:off[k + 1]], d_dtr[off[k]:off[k + 1]],
+                                   o[0], o[1], o[2], o[3], cap, nb6.NB6_MEM_DEVICE)
+            nb6.check(sctx, rc)
+            tickets[k] = t
+            ready.release()
+        th.join()
+        if errors:
+            raise RuntimeError(f"served requests failed: {errors[:5]}")
+        sub = np.array([i["submit_us"] for i in infos]) * 1e-6
+        done = np.array([i["done_us"] for i in infos]) * 1e-6
+        # latency from the arrival time (the submit call happens at the arrival)
+        lat_serve = done - sub + np.maximum(sub_wall - arrivals, 0.0)
+        span_serve = done.max() - sub.min() + max(0.0, sub_wall[0] - arrivals[0])
+        batch = np.array([i["batch_size"] for i in infos])
+        run = {"rho": rho, "arrival_rate_per_s": round(rate, 1),
+               "served": {"p50_ms": q(lat_serve, 0.5), "p99_ms": q(lat_serve, 0.99),
+                          "ginteractions_s": round(total / span_serve / 1e9, 3),
+                          "mean_batch": round(float(batch.mean()), 2),
+                          "max_batch": int(batch.max())},
+               "plain": {"p50_ms": q(lat_plain, 0.5), "p99_ms": q(lat_plain, 0.99),
+                         "ginteractions_s": round(total / span_plain / 1e9, 3)}}
+        log(f"bench: rho={rho}: served p50/p99 = {run['served']['p50_ms']}/"
+            f"{run['served']['p99_ms']} ms ({run['served']['ginteractions_s']} Gint/s, "
+            f"mean batch {run['served']['mean_batch']}); plain p50/p99 = "
+            f"{run['plain']['p50_ms']}/{run['plain']['p99_ms']} ms "
+            f"({run['plain']['ginteractions_s']} Gint/s)")
+        runs.append(run)
+    nb6.nb6_destroy(sctx)
+    nb6.nb6_destroy(pctx)
+    head = runs[0]
+    return {
+        "workload": "64 Plummer clusters, N log-uniform 4096..65536; blocks of 2^k random "
+                    "active particles, k uniform in 4..floor(log2 N); Poisson arrivals",
+        "requests": len(reqs), "list_cap": cap, "hbm_budget_mb": args.serve_budget_mb,
+        "plain_service_ms": round(s_bar * 1e3, 4),
+        "p50_ms": head["served"]["p50_ms"], "p99_ms": head["served"]["p99_ms"],
+        "rho": head["rho"], "runs": runs,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,6 +265,13 @@ def main():
     ap.add_argument("--slices", type=int, default=0, help="j-slices (0: auto)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=4000)
+    ap.add_argument("--serve-calibrate", type=int, default=300)
+    ap.add_argument("--serve-cap", type=int, default=128)
+    ap.add_argument("--serve-budget-mb", type=int, default=1024)
+    ap.add_argument("--rho", default="0.8,0.95,1.5",
+                    help="offered load(s) as fractions of the plain form's capacity")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -187,14 +373,17 @@ def main():
                      "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": None},
     }
+    gpu_out = (acc.cpu().numpy(), jerk.cpu().numpy(), nnb.cpu().numpy(),
+               lst[:, :args.cap].cpu().numpy())
+    nb6.nb6_destroy(ctx)
+    del acc, jerk, nnb, lst
+    if not args.no_serving:
+        out["serving"] = serving_leg(args, nb6, torch)
     if not args.no_cpu_baseline:
-        gpu_out = (acc.cpu().numpy(), jerk.cpu().numpy(), nnb.cpu().numpy(),
-                   lst[:, :args.cap].cpu().numpy())
         log("bench: timing the FP64 oracle on a sample of the block ...")
         base, accuracy = cpu_baseline(cl, idx_np, gpu_out, args.cap, args.cpu_seconds)
         out["cpu_baseline"] = base
         out["accuracy"] = accuracy
-    nb6.nb6_destroy(ctx)
     print(json.dumps(out), flush=True)
 
 

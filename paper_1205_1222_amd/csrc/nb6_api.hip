@@ -108,13 +108,50 @@ struct TimedLaunch {
     }
 };
 
-// The cluster, if loaded, and not in use by the serving queue.
+// Ownership of a cluster for the duration of one plain call.  The call's
+// stream first waits for the serving queue's last work on the cluster; at
+// release, the call's own stream work is recorded for the queue to wait on.
+class PlainClaim {
+  public:
+    PlainClaim() = default;
+    PlainClaim(const PlainClaim&) = delete;
+    PlainClaim& operator=(const PlainClaim&) = delete;
+    // NB6_OK or NB6_ERR_STATE (a serving request is in flight on it).
+    int claim(nb6_ctx* c, ClusterState* cl, hipStream_t st) {
+        c_ = c;
+        int expect = 0;
+        if (!cl->owner.compare_exchange_strong(expect, -1))
+            return fail(c, NB6_ERR_STATE, "cluster is in use by the serving queue");
+        cl_ = cl;
+        st_ = st;
+        if (cl->last_served && hipStreamWaitEvent(st, cl->last_served, 0) != hipSuccess) {
+            release();
+            return fail(c, NB6_ERR_HIP, "hipStreamWaitEvent failed");
+        }
+        return NB6_OK;
+    }
+    ~PlainClaim() { release(); }
+
+  private:
+    void release() {
+        if (!cl_) return;
+        if (!cl_->last_plain)
+            (void)hipEventCreateWithFlags(&cl_->last_plain, hipEventDisableTiming);
+        if (cl_->last_plain) (void)hipEventRecord(cl_->last_plain, st_);
+        cl_->owner.store(0);
+        cl_ = nullptr;
+        engine_kick(c_);
+    }
+    nb6_ctx* c_ = nullptr;
+    ClusterState* cl_ = nullptr;
+    hipStream_t st_ = nullptr;
+};
+
+// The cluster, if loaded.
 int get_cluster(nb6_ctx* c, int cluster, ClusterState** out) {
     if (cluster < 0 || cluster >= kMaxClusters || !c->clusters[cluster] ||
         c->clusters[cluster]->n == 0)
         return fail(c, NB6_ERR_STATE, "cluster %d is not loaded", cluster);
-    if (c->clusters[cluster]->in_service)
-        return fail(c, NB6_ERR_STATE, "cluster %d is in use by the serving queue", cluster);
     *out = c->clusters[cluster];
     return NB6_OK;
 }
@@ -178,6 +215,8 @@ int nb6_destroy(nb6_ctx* c) {
         if (!cl) continue;
         if (cl->state) (void)hipFree(cl->state);
         for (auto& r : cl->rec) release(r);
+        if (cl->last_plain) (void)hipEventDestroy(cl->last_plain);
+        if (cl->last_served) (void)hipEventDestroy(cl->last_served);
         delete cl;
     }
     for (DevBuf* b : {&c->part, &c->cnt, &c->lst, &c->ovf, &c->in_idx, &c->in_h2, &c->in_dtr,
@@ -231,8 +270,9 @@ int nb6_load_particles(nb6_ctx* c, int cluster, int64_t n, const double* m, cons
     HIP_TRY(c, hipSetDevice(c->device));
     std::lock_guard<std::mutex> lk(c->cluster_mu);
     ClusterState*& cl = c->clusters[cluster];
-    if (cl && cl->in_service)
-        return fail(c, NB6_ERR_STATE, "cluster %d is in use by the serving queue", cluster);
+    if (!cl) cl = new ClusterState();
+    PlainClaim claim;
+    if (int rc = claim.claim(c, cl, st)) return rc;
 
     if (mem_kind == NB6_MEM_HOST) {
         if (!finite_all(m, n) || !finite_all(t, n) || !finite_all(x, 3 * n) ||
@@ -243,7 +283,6 @@ int nb6_load_particles(nb6_ctx* c, int cluster, int64_t n, const double* m, cons
         mem_kind == NB6_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
 
     if (!idx) {  // full load
-        if (!cl) cl = new ClusterState();
         if (cl->n != n) {
             HIP_TRY(c, hipDeviceSynchronize());
             if (cl->state) HIP_TRY(c, hipFree(cl->state));
@@ -316,6 +355,8 @@ int nb6_predict_j(nb6_ctx* c, int cluster, double t_block, int modes, void* stre
     std::lock_guard<std::mutex> lk(c->cluster_mu);
     ClusterState* cl = nullptr;
     if (int rc = get_cluster(c, cluster, &cl)) return rc;
+    PlainClaim claim;
+    if (int rc = claim.claim(c, cl, (hipStream_t)stream)) return rc;
     if (modes == 0) modes = NB6_DX_ALL;
     if (modes & ~NB6_DX_ALL) return fail(c, NB6_ERR_ARG, "bad modes mask %d", modes);
     if (!std::isfinite(t_block)) return fail(c, NB6_ERR_ARG, "non-finite t_block");
@@ -351,6 +392,8 @@ int nb6_regular_force(nb6_ctx* c, int cluster, int64_t n_i, const int32_t* idx_i
     std::lock_guard<std::mutex> lk(c->cluster_mu);
     ClusterState* cl = nullptr;
     if (int rc = get_cluster(c, cluster, &cl)) return rc;
+    PlainClaim claim;
+    if (int rc = claim.claim(c, cl, (hipStream_t)stream)) return rc;
     const int mi = mode_index(dx_mode);
     if (mi < 0) return fail(c, NB6_ERR_ARG, "bad dx_mode %d", dx_mode);
     if (!(cl->pred_valid & dx_mode))
@@ -504,6 +547,8 @@ int nb6_get_predicted(nb6_ctx* c, int cluster, int dx_mode, double* x, double* v
     std::lock_guard<std::mutex> lk(c->cluster_mu);
     ClusterState* cl = nullptr;
     if (int rc = get_cluster(c, cluster, &cl)) return rc;
+    PlainClaim claim;
+    if (int rc = claim.claim(c, cl, (hipStream_t)stream)) return rc;
     const int mi = mode_index(dx_mode);
     if (mi < 0) return fail(c, NB6_ERR_ARG, "bad dx_mode %d", dx_mode);
     if (!(cl->pred_valid & dx_mode))

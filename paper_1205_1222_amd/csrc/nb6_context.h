@@ -6,6 +6,7 @@
 #include "../../include/nb6.h"
 #include "nb6_internal.h"
 
+#include <atomic>
 #include <cstdint>
 #include <mutex>
 #include <string>
@@ -27,7 +28,13 @@ struct ClusterState {
     DevBuf rec[3];             // j-records by mode index
     int pred_valid = 0;        // NB6_DX_* bits whose records are current
     double t_pred = 0.0;
-    int in_service = 0;        // requests of the serving queue in flight on it
+    // Owner of the cluster: 0 free, 1 a serving request in flight, -1 a plain
+    // call in progress.  Claimed with compare-and-swap from 0.
+    std::atomic<int> owner{0};
+    // Last stream work of each side on this cluster; the other side's stream
+    // waits for it before touching the cluster (created on first use).
+    hipEvent_t last_plain = nullptr;
+    hipEvent_t last_served = nullptr;
 };
 
 inline int mode_index(int dx_mode) {
@@ -87,6 +94,8 @@ void release(DevBuf& b);
 Plan make_plan(const nb6_ctx* c, int64_t n, int64_t ni, int ipl = 0);
 // Shut the serving queue down (nb6_destroy).
 void engine_shutdown(nb6_ctx* c);
+// Tell the serving queue that a cluster was released by a plain call.
+void engine_kick(nb6_ctx* c);
 
 #define HIP_TRY(ctx, call)                                                          \
     do {                                                                            \

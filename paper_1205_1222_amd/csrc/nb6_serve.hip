@@ -11,8 +11,12 @@
 //   finalize     one launch over every active particle of the batch,
 //   overflow     ordered rebuild of overflowed lists,
 // on one of kSlots streams, so up to kSlots batches run at once and requests
-// that arrive meanwhile form the next batch.  A completion thread waits for
-// each batch, stamps its requests and frees their memory and clusters.
+// that arrive meanwhile form the next batch.  A batch holds at most about
+// kBatchWork pair interactions (a larger request runs alone), and its
+// persistent grid is sized to its work and never fills more than a quarter of
+// the wave slots of the chip, so short batches run beside long ones.  A host
+// callback at the end of each batch's stream work stamps its requests and
+// frees their memory and clusters.
 //
 // A request's slicing (make_plan with one i per lane) and its summation
 // order depend only on the request, so its results are bit-identical alone
@@ -34,8 +38,9 @@ namespace nb6 {
 
 namespace {
 
-constexpr int kSlots = 3;          // batches in flight
+constexpr int kSlots = 4;          // batches in flight
 constexpr int kMaxBatch = 512;     // requests per batch
+constexpr double kBatchWork = 2.5e8;  // pair interactions per batch (~0.2 ms)
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -157,13 +162,13 @@ size_t carve(ServeReq* r, char* base) {
 
 struct Slot {
     hipStream_t stream = nullptr;
-    hipEvent_t done = nullptr;
     ReqDesc* host_desc = nullptr;        // pinned
     ReqDesc* dev_desc = nullptr;
     unsigned* host_status = nullptr;     // pinned [kMaxBatch]
     unsigned* dev_status = nullptr;      // [kMaxBatch] status words + 6 counter words
     bool busy = false;
     std::vector<ServeReq*> reqs;
+    class Engine* engine = nullptr;      // for the completion callback
 };
 
 }  // namespace
@@ -177,14 +182,13 @@ class Engine {
         if (int rc = arena_.init(c_, (size_t)c_->hbm_budget)) return rc;
         for (Slot& s : slots_) {
             HIP_TRY(c_, hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking));
-            HIP_TRY(c_, hipEventCreateWithFlags(&s.done, hipEventDisableTiming));
             HIP_TRY(c_, hipHostMalloc((void**)&s.host_desc, kMaxBatch * sizeof(ReqDesc)));
             HIP_TRY(c_, hipMalloc((void**)&s.dev_desc, kMaxBatch * sizeof(ReqDesc)));
             HIP_TRY(c_, hipHostMalloc((void**)&s.host_status, kMaxBatch * sizeof(unsigned)));
             HIP_TRY(c_, hipMalloc((void**)&s.dev_status, (kMaxBatch + 6) * sizeof(unsigned)));
         }
+        for (Slot& s : slots_) s.engine = this;
         sched_ = std::thread([this] { sched_loop(); });
-        done_ = std::thread([this] { done_loop(); });
         return NB6_OK;
     }
 
@@ -198,16 +202,21 @@ class Engine {
             }
             pending_.clear();
             cv_sched_.notify_all();
-            cv_inflight_.notify_all();
             cv_polled_.notify_all();
         }
         if (sched_.joinable()) sched_.join();
-        if (done_.joinable()) done_.join();
+        {
+            std::unique_lock<std::mutex> lk(mu_);  // batches still on the GPU
+            cv_sched_.wait(lk, [&] {
+                for (const Slot& s : slots_)
+                    if (s.busy) return false;
+                return true;
+            });
+        }
         (void)hipSetDevice(c_->device);
         for (Slot& s : slots_) {
             if (s.stream) (void)hipStreamSynchronize(s.stream);
             if (s.stream) (void)hipStreamDestroy(s.stream);
-            if (s.done) (void)hipEventDestroy(s.done);
             if (s.host_desc) (void)hipHostFree(s.host_desc);
             if (s.dev_desc) (void)hipFree(s.dev_desc);
             if (s.host_status) (void)hipHostFree(s.host_status);
@@ -252,11 +261,9 @@ class Engine {
                         return fail(c_, NB6_ERR_ARG, "dtr_i[%lld] is not finite", (long long)q);
                 }
             }
-            // the record stream of this mode is allocated once, outside the queue
+            // the record stream of this mode is allocated once, here; requests
+            // in flight on the cluster use other modes' streams
             if (!r->cl->rec[r->mi].p) {
-                if (r->cl->in_service)
-                    return fail(c_, NB6_ERR_STATE, "cluster %d: first use of this mode while busy",
-                                rq->cluster);
                 if (int rc = ensure(c_, r->cl->rec[r->mi], (size_t)r->cl->n * rec_size(r->mi)))
                     return rc;
             }
@@ -276,6 +283,13 @@ class Engine {
         blocked_ = false;
         cv_sched_.notify_all();
         return NB6_OK;
+    }
+
+    // A cluster became free outside the queue (a plain call ended).
+    void kick() {
+        std::lock_guard<std::mutex> lk(mu_);
+        blocked_ = false;
+        cv_sched_.notify_all();
     }
 
     int poll(uint64_t ticket, int wait, nb6_ticket_info* info) {
@@ -315,43 +329,53 @@ class Engine {
         return -1;
     }
 
+    // Called with mu_ held; takes no other lock (it runs in the completion
+    // callback, which must not wait for a thread that may be waiting for the
+    // GPU).
     void finish(ServeReq* r, int status, double t) {
         r->status = status;
         r->t_done = t;
         arena_.free(r->off, r->bytes);
-        std::lock_guard<std::mutex> lc(c_->cluster_mu);
-        r->cl->in_service = 0;
+        r->cl->owner.store(0);
     }
 
     void sched_loop() {
         (void)hipSetDevice(c_->device);
         std::unique_lock<std::mutex> lk(mu_);
         for (;;) {
-            cv_sched_.wait(lk, [&] {
+            // A blocked queue is retried on every submission, completion and
+            // cluster release, and at least every 2 ms.
+            cv_sched_.wait_for(lk, std::chrono::milliseconds(2), [&] {
                 return stop_ || (!pending_.empty() && !blocked_ && free_slot() >= 0);
             });
             if (stop_) break;
+            blocked_ = false;
+            if (pending_.empty() || free_slot() < 0) continue;
             const int si = free_slot();
             Slot& sl = slots_[si];
             std::vector<ServeReq*> batch;
-            {
-                std::lock_guard<std::mutex> lc(c_->cluster_mu);
-                for (auto it = pending_.begin();
-                     it != pending_.end() && (int)batch.size() < kMaxBatch;) {
-                    ServeReq* r = *it;
-                    if (r->cl->in_service) {  // one request per cluster in flight
-                        ++it;
-                        continue;
-                    }
-                    size_t off;
-                    if (!arena_.alloc(r->bytes, &off)) break;  // arrival order for memory
-                    r->off = off;
-                    carve(r, arena_.base() + off);
-                    r->cl->in_service = 1;
-                    r->t_admit = now();
-                    batch.push_back(r);
-                    it = pending_.erase(it);
+            double work = 0.0;
+            for (auto it = pending_.begin();
+                 it != pending_.end() && (int)batch.size() < kMaxBatch;) {
+                ServeReq* r = *it;
+                const double w = (double)r->rq.n_i * (double)r->cl->n;
+                if (!batch.empty() && work + w > kBatchWork) break;
+                int free_owner = 0;  // one request per cluster, no plain call on it
+                if (!r->cl->owner.compare_exchange_strong(free_owner, 1)) {
+                    ++it;
+                    continue;
                 }
+                size_t off;
+                if (!arena_.alloc(r->bytes, &off)) {  // arrival order for memory
+                    r->cl->owner.store(0);
+                    break;
+                }
+                work += w;
+                r->off = off;
+                carve(r, arena_.base() + off);
+                r->t_admit = now();
+                batch.push_back(r);
+                it = pending_.erase(it);
             }
             if (batch.empty()) {
                 blocked_ = true;  // until a batch finishes
@@ -371,42 +395,31 @@ class Engine {
                 cv_polled_.notify_all();
                 continue;
             }
-            inflight_.push_back(si);
-            cv_inflight_.notify_all();
         }
     }
 
-    void done_loop() {
-        (void)hipSetDevice(c_->device);
-        std::unique_lock<std::mutex> lk(mu_);
-        for (;;) {
-            cv_inflight_.wait(lk, [&] { return !inflight_.empty() || stop_; });
-            if (inflight_.empty()) break;  // stop_ and drained
-            const int si = inflight_.front();
-            Slot& sl = slots_[si];
-            lk.unlock();
-            const hipError_t e = hipEventSynchronize(sl.done);
-            const double t = now();
-            lk.lock();
-            inflight_.pop_front();
-            for (size_t b = 0; b < sl.reqs.size(); ++b) {
-                ServeReq* r = sl.reqs[b];
-                int st = NB6_OK;
-                if (e != hipSuccess) {
-                    st = NB6_ERR_HIP;
-                } else if (sl.host_status[b] & (ST_BAD_INDEX | ST_BAD_H2 | ST_NONFINITE)) {
-                    st = NB6_ERR_DEVICE_INPUT;
-                } else if (sl.host_status[b] & ST_OVERFLOW) {
-                    st = NB6_WARN_NB_OVERFLOW;
-                }
-                finish(r, st, t);
-            }
-            sl.reqs.clear();
-            sl.busy = false;
-            blocked_ = false;
-            cv_sched_.notify_all();
-            cv_polled_.notify_all();
+    // Host callback at the end of a batch's stream work (no HIP calls here).
+    static void on_batch_done(void* arg) {
+        Slot* sl = static_cast<Slot*>(arg);
+        sl->engine->complete(*sl);
+    }
+
+    void complete(Slot& sl) {
+        const double t = now();
+        std::lock_guard<std::mutex> lk(mu_);
+        for (size_t b = 0; b < sl.reqs.size(); ++b) {
+            int st = NB6_OK;
+            if (sl.host_status[b] & (ST_BAD_INDEX | ST_BAD_H2 | ST_NONFINITE))
+                st = NB6_ERR_DEVICE_INPUT;
+            else if (sl.host_status[b] & ST_OVERFLOW)
+                st = NB6_WARN_NB_OVERFLOW;
+            finish(sl.reqs[b], st, t);
         }
+        sl.reqs.clear();
+        sl.busy = false;
+        blocked_ = false;
+        cv_sched_.notify_all();
+        cv_polled_.notify_all();
     }
 
     // Enqueue the work of one batch on its slot's stream.  Runs on the
@@ -438,16 +451,15 @@ class Engine {
                 item_in_mode = 0;
                 prev_mi = r->mi;
             }
+            if (cl->last_plain) HIP_TRY(nullptr, hipStreamWaitEvent(st, cl->last_plain, 0));
             ReqDesc& d = sl.host_desc[b];
             std::memset(&d, 0, sizeof d);
             const int bit = mode_bit(r->mi);
-            {
-                std::lock_guard<std::mutex> lc(c_->cluster_mu);
-                d.do_predict = !((cl->pred_valid & bit) && cl->t_pred == r->rq.t_block);
-                if (d.do_predict) {
-                    cl->pred_valid = (cl->t_pred == r->rq.t_block ? cl->pred_valid : 0) | bit;
-                    cl->t_pred = r->rq.t_block;
-                }
+            // the queue owns the cluster while the request is in flight
+            d.do_predict = !((cl->pred_valid & bit) && cl->t_pred == r->rq.t_block);
+            if (d.do_predict) {
+                cl->pred_valid = (cl->t_pred == r->rq.t_block ? cl->pred_valid : 0) | bit;
+                cl->t_pred = r->rq.t_block;
             }
             unsigned* status = sl.dev_status + b;
             d.pred.n = cl->n;
@@ -495,8 +507,8 @@ class Engine {
         all.ni_total = i0;
         HIP_TRY(nullptr, launch_serve_prepare(
                         all, (int)((chunk_need + PREPARE_CHUNK - 1) / PREPARE_CHUNK), st));
-        // one persistent force launch per coordinate mode present
-        const int blocks = c_->num_cu * 8;
+        // one persistent force launch per coordinate mode present; about one
+        // work item per wave, at most 4 waves per SIMD of the chip
         for (int b = 0; b < nreq;) {
             int e = b;
             long long items = 0;
@@ -504,6 +516,7 @@ class Engine {
                 items += (long long)sl.host_desc[e].groups * reqs[e]->plan.nslices;
                 ++e;
             }
+            const int blocks = (int)std::min<long long>((long long)c_->num_cu * 4, (items + 3) / 4);
             BatchArgs g{};
             g.reqs = sl.dev_desc + b;
             g.nreq = e - b;
@@ -537,24 +550,32 @@ class Engine {
         }
         HIP_TRY(nullptr, hipMemcpyAsync(sl.host_status, sl.dev_status, nreq * sizeof(unsigned),
                                    hipMemcpyDeviceToHost, st));
-        HIP_TRY(nullptr, hipEventRecord(sl.done, st));
+        for (ServeReq* r : reqs) {  // plain calls on these clusters wait for this
+            if (!r->cl->last_served)
+                HIP_TRY(nullptr, hipEventCreateWithFlags(&r->cl->last_served, hipEventDisableTiming));
+            HIP_TRY(nullptr, hipEventRecord(r->cl->last_served, st));
+        }
+        HIP_TRY(nullptr, hipLaunchHostFunc(st, &Engine::on_batch_done, &sl));
         return NB6_OK;
     }
 
     nb6_ctx* c_;
     std::chrono::steady_clock::time_point t0_;
     std::mutex mu_;
-    std::condition_variable cv_sched_, cv_inflight_, cv_polled_;
+    std::condition_variable cv_sched_, cv_polled_;
     std::deque<ServeReq*> pending_;
     std::unordered_map<uint64_t, ServeReq*> tickets_;
-    std::deque<int> inflight_;
     Slot slots_[kSlots];
     Arena arena_;
     uint64_t next_ticket_ = 1;
     bool stop_ = false;
     bool blocked_ = false;
-    std::thread sched_, done_;
+    std::thread sched_;
 };
+
+void engine_kick(nb6_ctx* c) {
+    if (c->engine) c->engine->kick();
+}
 
 void engine_shutdown(nb6_ctx* c) {
     if (!c->engine) return;
