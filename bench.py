@@ -270,6 +270,9 @@ def main():
     ap.add_argument("--serve-calibrate", type=int, default=300)
     ap.add_argument("--serve-cap", type=int, default=128)
     ap.add_argument("--serve-budget-mb", type=int, default=1024)
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="run one device copy of this size first: the known-size kernel that "
+                         "calibrates the FETCH_SIZE/WRITE_SIZE counters")
     ap.add_argument("--rho", default="0.8,0.95,1.5",
                     help="offered load(s) as fractions of the plain form's capacity")
     args = ap.parse_args()
@@ -282,6 +285,15 @@ def main():
     import torch
     from paper_1205_1222_amd import nb6
     from workloads import config
+
+    if args.copy_mib > 0:
+        n_el = (args.copy_mib << 20) // 4
+        src = torch.ones(n_el, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"bench: copied {args.copy_mib} MiB device to device (counter calibration)")
+        del src, dst
 
     t_gen = time.perf_counter()
     cfg = config(args.config)

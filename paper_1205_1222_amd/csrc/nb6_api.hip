@@ -68,6 +68,8 @@ Plan make_plan(const nb6_ctx* c, int64_t n, int64_t ni, int ipl) {
     int64_t s = c->slice_hint > 0 ? c->slice_hint : (target + groups - 1) / groups;
     s = std::max<int64_t>(1, std::min<int64_t>(s, (n + 255) / 256));
     s = std::min<int64_t>(s, 65535);
+    // a multiple of 8 lets the force kernel keep each slice on one XCD
+    if (c->slice_hint <= 0 && s >= 8) s = s / 8 * 8;
     int64_t len = (n + s - 1) / s;
     len = (len + 3) / 4 * 4;
     p.slice_len = (int)len;
@@ -455,7 +457,8 @@ int nb6_regular_force(nb6_ctx* c, int cluster, int64_t n_i, const int32_t* idx_i
     const Plan p = make_plan(c, n, ni);
     const int caps = cap + 1;  // room for the i-particle itself
     int rc;
-    if ((rc = ensure(c, c->part, (size_t)p.nslices * NPART * ni * sizeof(double))) ||
+    const size_t ni64 = ((size_t)ni + 63) / 64 * 64;  // partials by 64-particle block
+    if ((rc = ensure(c, c->part, (size_t)p.nslices * NPART * ni64 * sizeof(double))) ||
         (rc = ensure(c, c->cnt, ((size_t)ni + 1) * sizeof(int32_t))) ||
         (rc = ensure(c, c->lst, (size_t)ni * caps * sizeof(int32_t))) ||
         (rc = ensure(c, c->ovf, (size_t)ni * sizeof(int32_t))))

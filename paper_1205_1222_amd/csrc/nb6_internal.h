@@ -53,7 +53,7 @@ struct RegfArgs {
     int            ni;
     int            slice_len; // j per slice (multiple of 4)
     int            nslices;
-    double*        part;      // [ni][nslices][NPART]
+    double*        part;      // [ceil(ni/64)][nslices][NPART][64]
     int32_t*       cnt;       // [ni] neighbours found, the i itself included (zeroed)
     int32_t*       lst;       // [ni][caps] neighbours in the order found
     int            caps;      // per-i list capacity (cap + 1)
@@ -133,14 +133,14 @@ struct ReqDesc {
     int          mode;        // MODE_*
     int          groups;      // i-groups of 64
     long long    item0;       // first force work item within its mode group
-    long long    i0;          // first particle within the batch
+    long long    blk0;        // first 64-particle block within the batch
 };
 
 struct BatchArgs {
     const ReqDesc*      reqs;      // device copy of the batch's descriptors
     int                 nreq;
     long long           nitems;    // force work items of this launch
-    long long           ni_total;  // particles of the batch
+    long long           nblk_total; // 64-particle blocks of the batch
     unsigned long long* counter;   // work-item counter (zeroed before the launch)
 };
 

@@ -184,6 +184,11 @@ __device__ __forceinline__ float checked_h2(double h2) {
     return (f >= FLT_MIN && f <= FLT_MAX) ? f : -1.0f;
 }
 
+// Index of partial sum (q, s, c) in the block layout [q/64][s][c][q%64].
+__device__ __forceinline__ size_t part_index(int q, int s, int c, int nslices) {
+    return (((size_t)(q >> 6) * nslices + s) * NPART + c) * 64 + (q & 63);
+}
+
 // Force, jerk and neighbour appends of one (i-group, j-slice) work item:
 // 64 * IPL active particles starting at group * 64 * IPL, against the
 // j-particles of slice s.
@@ -268,37 +273,54 @@ __device__ __forceinline__ void regf_item(const RegfArgs& a, const int group, co
             for (int c = 0; c < 6; ++c) sum[k][c] += (double)run[k][c];
     }
 
-    // partial sums, i-major: part[q][s][0..5]
+    // partial sums by 64-particle block: part[q / 64][s][c][q % 64], so each
+    // component of a wave's 64 particles is one contiguous 512-byte store
 #pragma unroll
     for (int k = 0; k < IPL; ++k) {
         if (q[k] < a.ni) {
-            double* p = a.part + ((size_t)q[k] * a.nslices + s) * NPART;
+            double* p = a.part + part_index(q[k], s, 0, a.nslices);
 #pragma unroll
-            for (int c = 0; c < NPART; ++c) p[c] = sum[k][c];
+            for (int c = 0; c < NPART; ++c) p[c * 64] = sum[k][c];
         }
     }
 }
 
-// One launch of one request: grid (i-groups / waves per block, slices).
-// At least 4 waves per SIMD (<= 128 VGPRs): below that the scalar-load
-// latency of the j-records is no longer hidden.
+// One launch of one request: a 1-D grid of nslices x gblocks workgroups,
+// gblocks = i-groups / waves per block.  Workgroups are handed to the 8 XCDs
+// in turn (workgroup id mod 8), so when nslices is a multiple of 8 the
+// mapping below gives every slice to one XCD: each XCD's L2 then holds the
+// j-records of its own slices only.  At least 4 waves per SIMD (<= 128
+// VGPRs): below that the scalar-load latency of the j-records is no longer
+// hidden.
 template <int MODE, int IPL>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
-regf_kernel(RegfArgs a) {
+regf_kernel(RegfArgs a, int gblocks) {
+    const int b = blockIdx.x;
+    int s, gb;
+    if ((a.nslices & 7) == 0) {
+        const int xcd = b & 7, k = b >> 3;
+        s = xcd + 8 * (k / gblocks);
+        gb = k % gblocks;
+    } else {
+        s = b / gblocks;
+        gb = b % gblocks;
+    }
     const int wpb = blockDim.x >> 6;
-    const int group = blockIdx.x * wpb + (threadIdx.x >> 6);
+    const int group = gb * wpb + (threadIdx.x >> 6);
     if (group * 64 * IPL >= a.ni) return;  // uniform across the wave
-    regf_item<MODE, IPL>(a, group, blockIdx.y);
+    regf_item<MODE, IPL>(a, group, s);
 }
 
 // ---------------------------------------------------------------------------
-// Finalize: one wavefront per i.
-//   sums  -- the wave loads i's S x 6 partials (contiguous) into LDS and
-//            lanes 0..5 add them in slice order: a fixed summation order.
-//   lists -- count <= caps: every neighbour was stored; each entry's output
-//            position is its rank among the entries (entries are distinct),
-//            less one past the i itself.  count > caps: the list overflowed
-//            and i is queued for the ordered overflow scan.
+// Finalize: one workgroup per block of 64 particles.
+//   sums  -- thread t of the first wave adds particle (blk*64 + t)'s slice
+//            partials in slice order (a fixed summation order; the loads of
+//            the wave are contiguous).
+//   lists -- each wave takes 16 of the 64 particles.  count <= caps: every
+//            neighbour was stored; an entry's output position is its rank
+//            among the entries (entries are distinct), less one past the i
+//            itself.  count > caps: the list overflowed and i is queued for
+//            the ordered overflow scan.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -306,67 +328,75 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Finalize of particle q of one request by the calling wavefront; sh_part
-// and sh_list are this wave's LDS buffers.
-__device__ __forceinline__ void finalize_item(const FinalArgs& a, const int q,
-                                              double* __restrict__ sh_part,
-                                              int32_t* __restrict__ sh_list) {
-    const int lane = threadIdx.x & 63;
+__device__ __forceinline__ bool invalid_i(const FinalArgs& a, int q) {
     const int32_t self = a.idx[q];
-    if (self < 0 || self >= a.n || checked_h2(a.h2[q]) < 0.0f) {
-        if (lane < 3) {
-            const double nan = __builtin_nan("");
-            a.acc[3 * q + lane] = nan;
-            a.jerk[3 * q + lane] = nan;
-        }
-        if (lane == 0) a.nnb[q] = -1;
-        return;
-    }
+    return self < 0 || self >= a.n || checked_h2(a.h2[q]) < 0.0f;
+}
 
-    double total = 0.0;  // lane c < 6: component c
-    const double* src = a.part + (size_t)q * a.nslices * NPART;
-    for (int s0 = 0; s0 < a.nslices; s0 += 64) {
-        const int ns = min(64, a.nslices - s0);
-        for (int e = lane; e < ns * NPART; e += 64) sh_part[e] = src[(size_t)s0 * NPART + e];
-        wave_sync();
-        if (lane < NPART)
-            for (int s = 0; s < ns; ++s) total += sh_part[s * NPART + lane];
-        wave_sync();
-    }
-    if (lane < 3) a.acc[3 * q + lane] = total;
-    else if (lane < 6) a.jerk[3 * q + lane - 3] = total;
-
-    const int count = a.cnt[q];          // neighbours found, the i itself included
-    if (lane == 0) a.nnb[q] = count - 1;
-    if (count > a.caps) {
-        if (lane == 0) {
-            atomicOr(a.status, (unsigned)ST_OVERFLOW);
-            const int slot = atomicAdd(a.ovf_count, 1);
-            a.ovf_list[slot] = q;
+// Block blk of one request; sh_list is MAX_CAPS ints per wave.
+__device__ __forceinline__ void finalize_block(const FinalArgs& a, const int blk,
+                                               int32_t (*sh_list)[MAX_CAPS]) {
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (w == 0) {
+        const int q = blk * 64 + lane;
+        if (q < a.ni) {
+            if (invalid_i(a, q)) {
+                const double nan = __builtin_nan("");
+                for (int c = 0; c < 3; ++c) {
+                    a.acc[3 * q + c] = nan;
+                    a.jerk[3 * q + c] = nan;
+                }
+                a.nnb[q] = -1;
+            } else {
+                double sum[NPART];
+#pragma unroll
+                for (int c = 0; c < NPART; ++c) sum[c] = 0.0;
+                const double* p = a.part + part_index(q, 0, 0, a.nslices);
+                for (int s = 0; s < a.nslices; ++s)
+#pragma unroll
+                    for (int c = 0; c < NPART; ++c) sum[c] += p[((size_t)s * NPART + c) * 64];
+                for (int c = 0; c < 3; ++c) {
+                    a.acc[3 * q + c] = sum[c];
+                    a.jerk[3 * q + c] = sum[3 + c];
+                }
+                a.nnb[q] = a.cnt[q] - 1;  // the i itself is among the found
+            }
         }
-        return;
     }
-    const int32_t* l = a.lst + (size_t)q * a.caps;
-    for (int e = lane; e < count; e += 64) sh_list[e] = l[e];
-    wave_sync();
-    for (int e = lane; e < count; e += 64) {
-        const int32_t v = sh_list[e];
-        if (v == self) continue;
-        int rank = 0;
-        for (int k = 0; k < count; ++k) rank += sh_list[k] < v ? 1 : 0;
-        const int pos = rank - (v > self ? 1 : 0);
-        if (pos >= 0 && pos < a.cap) a.list[(size_t)q * a.cap + pos] = v;
+    int32_t* sl = sh_list[w];
+    for (int t = 0; t < 16; ++t) {
+        const int q = blk * 64 + w * 16 + t;  // uniform across the wave
+        if (q >= a.ni) break;
+        if (invalid_i(a, q)) continue;
+        const int32_t self = a.idx[q];
+        const int count = a.cnt[q];
+        if (count > a.caps) {
+            if (lane == 0) {
+                atomicOr(a.status, (unsigned)ST_OVERFLOW);
+                const int slot = atomicAdd(a.ovf_count, 1);
+                a.ovf_list[slot] = q;
+            }
+            continue;
+        }
+        const int32_t* l = a.lst + (size_t)q * a.caps;
+        for (int e = lane; e < count; e += 64) sl[e] = l[e];
+        wave_sync();
+        for (int e = lane; e < count; e += 64) {
+            const int32_t v = sl[e];
+            if (v == self) continue;
+            int rank = 0;
+            for (int k = 0; k < count; ++k) rank += sl[k] < v ? 1 : 0;
+            const int pos = rank - (v > self ? 1 : 0);
+            if (pos >= 0 && pos < a.cap) a.list[(size_t)q * a.cap + pos] = v;
+        }
+        wave_sync();  // sl is rewritten for the next particle
     }
-    wave_sync();  // sh_list may be reused by this wave's next item
 }
 
 __global__ void __launch_bounds__(256) finalize_kernel(FinalArgs a) {
-    __shared__ double sh_part[4][NPART * 64];
     __shared__ int32_t sh_list[4][MAX_CAPS];
-    const int w = threadIdx.x >> 6;
-    const int q = blockIdx.x * 4 + w;
-    if (q >= a.ni) return;
-    finalize_item(a, q, sh_part[w], sh_list[w]);
+    finalize_block(a, blockIdx.x, sh_list);
 }
 
 // ---------------------------------------------------------------------------
@@ -481,19 +511,17 @@ serve_regf_kernel(BatchArgs b) {
 }
 
 __global__ void __launch_bounds__(256) serve_finalize_kernel(BatchArgs b) {
-    __shared__ double sh_part[4][NPART * 64];
     __shared__ int32_t sh_list[4][MAX_CAPS];
     const_ptr<ReqDesc> reqs = (const_ptr<ReqDesc>)(b.reqs);
-    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const long long gi = (long long)blockIdx.x * 4 + w;
-    if (gi >= b.ni_total) return;
-    int lo = 0, hi = b.nreq - 1;  // last request with i0 <= gi
+    const long long gb = blockIdx.x;  // 64-particle block within the batch
+    if (gb >= b.nblk_total) return;
+    int lo = 0, hi = b.nreq - 1;      // last request with blk0 <= gb
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (reqs[mid].i0 <= gi) lo = mid; else hi = mid - 1;
+        if (reqs[mid].blk0 <= gb) lo = mid; else hi = mid - 1;
     }
     const FinalArgs f = load_final_args(reqs + lo);
-    finalize_item(f, (int)(gi - reqs[lo].i0), sh_part[w], sh_list[w]);
+    finalize_block(f, (int)(gb - reqs[lo].blk0), sh_list);
 }
 
 template <int MODE>
@@ -631,9 +659,11 @@ __global__ void zero_u32_kernel(unsigned* p, int n) {
 template <int MODE, int IPL>
 static hipError_t launch_regf_t(int wpb, const RegfArgs& a, hipStream_t st) {
     const int groups = (a.ni + 64 * IPL - 1) / (64 * IPL);
-    dim3 grid((groups + wpb - 1) / wpb, a.nslices);
-    dim3 block(64 * wpb);
-    hipLaunchKernelGGL((regf_kernel<MODE, IPL>), grid, block, 0, st, a);
+    const int gblocks = (groups + wpb - 1) / wpb;
+    const long long blocks = (long long)gblocks * a.nslices;
+    if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((regf_kernel<MODE, IPL>), dim3((unsigned)blocks), dim3(64 * wpb), 0, st,
+                       a, gblocks);
     return hipGetLastError();
 }
 
@@ -653,7 +683,7 @@ hipError_t launch_regf(int mode, int ipl, int wpb, const RegfArgs& a, hipStream_
 hipError_t launch_finalize(const FinalArgs& a, hipStream_t s) {
     if (a.ni <= 0) return hipSuccess;
     if (a.caps > MAX_CAPS) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(finalize_kernel, dim3((a.ni + 3) / 4), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(finalize_kernel, dim3((a.ni + 63) / 64), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
@@ -715,8 +745,8 @@ hipError_t launch_serve_regf(int mode, const BatchArgs& b, int blocks, hipStream
 }
 
 hipError_t launch_serve_finalize(const BatchArgs& b, hipStream_t s) {
-    if (b.ni_total <= 0) return hipSuccess;
-    const dim3 grid((unsigned)((b.ni_total + 3) / 4)), block(256);
+    if (b.nblk_total <= 0) return hipSuccess;
+    const dim3 grid((unsigned)b.nblk_total), block(256);
     hipLaunchKernelGGL(serve_finalize_kernel, grid, block, 0, s, b);
     return hipGetLastError();
 }

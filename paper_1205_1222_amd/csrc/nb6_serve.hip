@@ -136,7 +136,8 @@ size_t carve(ServeReq* r, char* base) {
         off += align_up(bytes);
         return p;
     };
-    r->part = (double*)take(ni * r->plan.nslices * NPART * sizeof(double));
+    const size_t ni64 = (ni + 63) / 64 * 64;  // partials are kept by 64-particle block
+    r->part = (double*)take(ni64 * r->plan.nslices * NPART * sizeof(double));
     r->cnt = (int32_t*)take((ni + 1) * sizeof(int32_t));
     r->lst = (int32_t*)take(ni * caps * sizeof(int32_t));
     r->ovf = (int32_t*)take(ni * sizeof(int32_t));
@@ -432,7 +433,7 @@ class Engine {
         std::stable_sort(reqs.begin(), reqs.end(),
                          [](const ServeReq* a, const ServeReq* b) { return a->mi < b->mi; });
         const int nreq = (int)reqs.size();
-        long long i0 = 0, item_in_mode = 0;
+        long long blk0 = 0, item_in_mode = 0;
         int64_t chunk_need = 0;
         int prev_mi = -1;
         for (int b = 0; b < nreq; ++b) {
@@ -492,9 +493,9 @@ class Engine {
             d.mode = r->mi;
             d.groups = (ni + 63) / 64;
             d.item0 = item_in_mode;
-            d.i0 = i0;
+            d.blk0 = blk0;
             item_in_mode += (long long)d.groups * p.nslices;
-            i0 += ni;
+            blk0 += (ni + 63) / 64;
             chunk_need = std::max<int64_t>(chunk_need, std::max<int64_t>(cl->n, ni + 1));
         }
         HIP_TRY(nullptr, hipMemcpyAsync(sl.dev_desc, sl.host_desc, nreq * sizeof(ReqDesc),
@@ -504,7 +505,7 @@ class Engine {
         BatchArgs all{};
         all.reqs = sl.dev_desc;
         all.nreq = nreq;
-        all.ni_total = i0;
+        all.nblk_total = blk0;
         HIP_TRY(nullptr, launch_serve_prepare(
                         all, (int)((chunk_need + PREPARE_CHUNK - 1) / PREPARE_CHUNK), st));
         // one persistent force launch per coordinate mode present; about one

@@ -56,6 +56,24 @@ def pin_golden_forces(lib=None):
         assert list(map(int, r.nnb)) == [len(l) for l in c["lists"]], c["name"]
 
 
+def pin_pair_terms_golden(lib=None):
+    """Per-pair terms on the hand-derived two-body cases (pair i=0, j=1)."""
+    cases = {c["name"]: c for c in json.load(open(GOLDEN))["force_cases"]}
+    for name in ("two_body_static", "two_body_transverse_velocity",
+                 "two_body_radial_velocity", "velocity_criterion_off"):
+        c = cases[name]
+        rmin, dacc, djrk = oracle.pair_terms([0], [1], [c["dtr"][0]], c["m"], c["x"], c["v"],
+                                             lib=lib)
+        assert _close(dacc[0], c["acc"][0], 1e-14), (name, dacc)
+        assert _close(djrk[0], c["jerk"][0], 1e-14), (name, djrk)
+        r = np.linalg.norm(np.subtract(c["x"][1], c["x"][0]))
+        assert abs(rmin[0] - r) <= 1e-15 * r, (name, rmin)
+    # the velocity criterion's end point: |R + dt V| = |3 - 3| = 0
+    c = cases["velocity_criterion_catches_approach"]
+    rmin, _, _ = oracle.pair_terms([0], [1], [c["dtr"][0]], c["m"], c["x"], c["v"], lib=lib)
+    assert rmin[0] == 0.0
+
+
 def pin_golden_predict(lib=None):
     cases = json.load(open(GOLDEN))["predict_cases"]
     for c in cases:
@@ -234,6 +252,7 @@ def pin_scales_and_truncation(lib=None):
 
 ALL_PINS = [  # roughly cheapest first
     pin_golden_forces,
+    pin_pair_terms_golden,
     pin_golden_predict,
     pin_everything_neighbour,
     pin_scales_and_truncation,

@@ -36,6 +36,11 @@ MUTANTS = {
                               "vp[q] = v[q] + a[q] * dt + jerk[q] * dt * dt / 6.0;"),
     "predict_dt_sign": ("double dt = tb - t[k];", "double dt = t[k] - tb;"),
     "uncompensated_drop": ("a->c += (a->s - s) + t;", "a->c += 0.0;"),
+    "pair_terms_R_sign": ("R[c] = xp[3 * j + c] - xp[3 * i + c];\n            V[c] = vp[3 * j + c] - vp[3 * i + c];\n            P[c] = R[c] + dtr[p] * V[c];",
+                          "R[c] = xp[3 * i + c] - xp[3 * j + c];\n            V[c] = vp[3 * j + c] - vp[3 * i + c];\n            P[c] = R[c] + dtr[p] * V[c];"),
+    "pair_terms_jerk_sign": ("djrk[3 * p + c] = m[j] * (V[c] / r3 - 3.0 * rv * R[c] / r5);",
+                             "djrk[3 * p + c] = m[j] * (V[c] / r3 + 3.0 * rv * R[c] / r5);"),
+    "pair_terms_rmin_max": ("rmin[p] = sqrt((p2 < r2) ? p2 : r2);", "rmin[p] = sqrt((p2 < r2) ? r2 : p2);"),
 }
 
 
