@@ -252,6 +252,49 @@ def serving_leg(args, nb6, torch):
     }
 
 
+def block_sweep(args, cfg, nb6, torch, T):
+    """Force-call time for every block of the configuration (one JSON line each)."""
+    cl = cfg["cluster"]
+    n = cl.n
+    stream = torch.cuda.current_stream()
+    mode = MODES[args.mode]
+    ctx = nb6.nb6_create(0, flags=nb6.NB6_OPT_TIMING, ipl_hint=args.ipl, slice_hint=args.slices)
+    nb6.check(ctx, nb6.nb6_load_particles(ctx, 0, n, cl.m, cl.x, cl.v, cl.a, cl.jerk, cl.t))
+    nb6.check(ctx, nb6.nb6_predict_j(ctx, 0, cl.tb, mode, stream))
+    for name, idx in sorted(cfg["blocks"].items(), key=lambda kv: len(kv[1])):
+        ni = len(idx)
+        idx_d, h2_d, dtr_d = T(idx, torch.int32), T(cl.h2[idx]), T(cl.dtr[idx])
+        acc = torch.empty((ni, 3), dtype=torch.float64, device="cuda:0")
+        jerk = torch.empty_like(acc)
+        nnb = torch.empty(ni, dtype=torch.int32, device="cuda:0")
+        lst = torch.empty((ni, args.cap), dtype=torch.int32, device="cuda:0")
+        reps = max(3, min(200, int(2e11 / max(ni * n, 1))))
+
+        def call():
+            nb6.check(ctx, nb6.nb6_regular_force(ctx, 0, ni, idx_d, h2_d, dtr_d, mode, acc,
+                                                 jerk, nnb, lst, args.cap, nb6.NB6_MEM_DEVICE,
+                                                 stream))
+        call()
+        torch.cuda.synchronize()
+        nb6.nb6_kernel_times(ctx)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            call()
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / reps
+        ms, cnt = nb6.nb6_kernel_times(ctx)
+        pairs = ni * (n - 1)
+        print(json.dumps({"block": name, "N": n, "N_i": ni, "mode": args.mode,
+                          "slices": nb6.nb6_last_slices(ctx), "reps": reps,
+                          "call_us": round(wall * 1e6, 2),
+                          "force_us": round(ms[1] / cnt[1] * 1e3, 2),
+                          "finalize_us": round(ms[2] / cnt[2] * 1e3, 2),
+                          "call_gint_s": round(pairs / wall / 1e9, 3),
+                          "force_gint_s": round(pairs / (ms[1] / cnt[1] * 1e-3) / 1e9, 3)}),
+              flush=True)
+    nb6.nb6_destroy(ctx)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -270,12 +313,23 @@ def main():
     ap.add_argument("--serve-calibrate", type=int, default=300)
     ap.add_argument("--serve-cap", type=int, default=128)
     ap.add_argument("--serve-budget-mb", type=int, default=1024)
+    ap.add_argument("--block-sweep", action="store_true",
+                    help="time every block of the configuration (per-size curve) and exit")
+    ap.add_argument("--isa-rates", action="store_true",
+                    help="only run the vector-instruction issue-rate probe and exit")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="run one device copy of this size first: the known-size kernel that "
                          "calibrates the FETCH_SIZE/WRITE_SIZE counters")
     ap.add_argument("--rho", default="0.8,0.95,1.5",
                     help="offered load(s) as fractions of the plain form's capacity")
     args = ap.parse_args()
+
+    if args.isa_rates:
+        import subprocess
+        probe = os.path.join(ROOT, "paper_1205_1222_amd", "isa_rates")
+        if not os.path.exists(probe):
+            sys.exit(f"{probe} is missing: run python -m paper_1205_1222_amd.build")
+        sys.exit(subprocess.run([probe]).returncode)
 
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} is not supported: this build measures one "
@@ -306,6 +360,9 @@ def main():
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
     T = lambda a, dt=torch.float64: torch.from_numpy(np.ascontiguousarray(a)).to(dev, dt)  # noqa: E731
+    if args.block_sweep:
+        block_sweep(args, cfg, nb6, torch, T)
+        return
     m_d, x_d, v_d, a_d, j_d, t_d = (T(q) for q in (cl.m, cl.x, cl.v, cl.a, cl.jerk, cl.t))
     idx_d = T(idx_np, torch.int32)
     # corrector output of the active particles (device-resident)
