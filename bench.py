@@ -23,8 +23,11 @@ sample also gives the ``accuracy`` report of the GPU result.
 from __future__ import annotations
 
 import argparse
+import csv
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -36,6 +39,135 @@ sys.path.insert(0, ROOT)
 FLOP_PER_INTERACTION = 53
 FP32_PEAK_TFLOPS = 157.3          # 256 CU x 2.4 GHz x 256 FLOP/clk
 MODES = {"ff": 1, "fp64": 2, "fp32": 4}
+
+
+# Counter figures of the force kernel (HBM traffic, FP32 VALU instruction
+# counts) come from rocprofv3 counter runs of this script, summarised by
+# --counter-summary into COUNTER_FILE.  They are reported only while the
+# kernel sources are the ones the counters were taken from.
+KERNEL_SOURCES = ("paper_1205_1222_amd/csrc/nb6_kernels.hip",
+                  "paper_1205_1222_amd/csrc/nb6_internal.h")
+COUNTER_FILE = os.path.join("profiles", "regf_ff_plummer131072_all_counters.md")
+VALU_COUNTERS = ("SQ_INSTS_VALU", "SQ_INSTS_VALU_ADD_F32", "SQ_INSTS_VALU_MUL_F32",
+                 "SQ_INSTS_VALU_FMA_F32", "SQ_INSTS_VALU_TRANS_F32", "SQ_INSTS_SALU",
+                 "SQ_INSTS_SMEM", "SQ_WAVES")
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def _counter_rows(path, counter):
+    with open(path, newline="") as f:
+        return [(r["Kernel_Name"], float(r["Counter_Value"])) for r in csv.DictReader(f)
+                if r["Counter_Name"] == counter]
+
+
+def _is_force(name):
+    return "regf_kernel" in name or "regf_lanes_kernel" in name
+
+
+def _median(v):
+    v = sorted(v)
+    return v[len(v) // 2]
+
+
+def counter_summary(fetch_csv, write_csv, valu_csv, copy_mib, config_line, pairs):
+    """Markdown summary of the counter runs of the force kernel: per-launch HBM
+    bytes (each counter scaled by what it reads for the device copy of copy_mib
+    MiB made at the start of the same run) and FP32 VALU instruction counts."""
+    copy_bytes = copy_mib << 20
+    res = {}
+    kernel = None
+    for name, path, counter in (("read", fetch_csv, "FETCH_SIZE"),
+                                ("write", write_csv, "WRITE_SIZE")):
+        rows = _counter_rows(path, counter)
+        copies = [v for k, v in rows if "copyBuffer" in k]
+        regf = [(k, v) for k, v in rows if _is_force(k)]
+        if not copies or not regf:
+            raise SystemExit(f"{path}: no copy or force-kernel dispatch with {counter}")
+        kernel = regf[0][0]
+        factor = copy_bytes / (max(copies) * 1024.0)
+        med = _median([v for _, v in regf])
+        res[name] = {"counter": counter, "kib_per_launch": med, "copy_kib": max(copies),
+                     "factor": round(factor, 4), "bytes": int(round(med * 1024.0 * factor))}
+    valu = {}
+    if valu_csv:
+        for c in VALU_COUNTERS:
+            vals = [v for k, v in _counter_rows(valu_csv, c) if _is_force(k)]
+            if vals:
+                valu[c] = _median(vals)
+    machine = {"kernel": kernel, "source_sha256": kernel_source_hash(), "config": config_line,
+               "read_bytes": res["read"]["bytes"], "write_bytes": res["write"]["bytes"]}
+    flops = None
+    if all(c in valu for c in VALU_COUNTERS[1:5]):
+        # wave instructions x 64 lanes; an FMA counts 2, add / mul / transcendental 1
+        flops = 64.0 * (valu["SQ_INSTS_VALU_ADD_F32"] + valu["SQ_INSTS_VALU_MUL_F32"] +
+                        2.0 * valu["SQ_INSTS_VALU_FMA_F32"] + valu["SQ_INSTS_VALU_TRANS_F32"])
+        machine["fp32_flop"] = flops
+    cmd = ("python3 bench.py --steps 2 --warmup 1 --no-serving --no-cpu-baseline "
+           f"--copy-mib {copy_mib}")
+    lines = [
+        "# Counters of the force kernel, Plummer N = 131072, all 131072 active (FF)",
+        "",
+        "rocprofv3 counter runs of the benchmark (one counter group per run).  Each run "
+        f"begins with a {copy_mib} MiB device-to-device copy whose known size calibrates "
+        "the traffic counters (bytes = counter KiB x 1024 x factor).  Figures are the "
+        "median over the run's force launches.",
+        "",
+        "Commands (repo root, GPU box; then this summary from the CSV files):",
+        "",
+        f"    timeout -s KILL 120 rocprofv3 --pmc FETCH_SIZE -f csv -d gpurun_out/pmc_fetch "
+        f"-o fetch -- {cmd}",
+        f"    timeout -s KILL 120 rocprofv3 --pmc WRITE_SIZE -f csv -d gpurun_out/pmc_write "
+        f"-o write -- {cmd}",
+        f"    timeout -s KILL 120 rocprofv3 --pmc {' '.join(VALU_COUNTERS)} -f csv "
+        f"-d gpurun_out/pmc_valu -o valu -- {cmd}",
+        "    python3 bench.py --counter-summary gpurun_out/pmc_fetch/fetch_counter_collection.csv "
+        "gpurun_out/pmc_write/write_counter_collection.csv "
+        f"gpurun_out/pmc_valu/valu_counter_collection.csv --copy-mib {copy_mib}",
+        "",
+        f"Kernel: `{kernel}`; config: {config_line}; {pairs:.4g} pair interactions per launch.",
+        "",
+        "| Traffic counter | calibration copy (KiB) | factor | force kernel (KiB / launch) "
+        "| bytes / launch |",
+        "|:--|--:|--:|--:|--:|",
+    ]
+    for name in ("read", "write"):
+        r = res[name]
+        lines.append(f"| {r['counter']} | {r['copy_kib']:.0f} | {r['factor']} | "
+                     f"{r['kib_per_launch']:.0f} | {r['bytes'] / 1e6:.1f} MB |")
+    if valu:
+        lines += ["", "| VALU counter | per launch | per interaction (x64 lanes / pairs) |",
+                  "|:--|--:|--:|"]
+        for c in VALU_COUNTERS:
+            if c in valu:
+                lines.append(f"| {c} | {valu[c]:.4g} | {64.0 * valu[c] / pairs:.3f} |")
+        if flops is not None:
+            lines += ["", f"FP32 VALU FLOP per launch (FMA = 2): {flops:.4g}, "
+                          f"{flops / pairs:.2f} per interaction."]
+    lines += ["", "counter-record: " + json.dumps(machine), ""]
+    return "\n".join(lines)
+
+
+def counters_from_profile(config_line):
+    """The counter record of COUNTER_FILE when it was taken from the current
+    kernel sources and the same configuration, else None."""
+    path = os.path.join(ROOT, COUNTER_FILE)
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        m = re.search(r"^counter-record: (\{.*\})$", f.read(), re.M)
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    if rec.get("source_sha256") != kernel_source_hash() or rec.get("config") != config_line:
+        return None
+    return rec
 
 
 def log(*a):
@@ -252,47 +384,81 @@ def serving_leg(args, nb6, torch):
     }
 
 
-def block_sweep(args, cfg, nb6, torch, T):
-    """Force-call time for every block of the configuration (one JSON line each)."""
+def block_sweep(args, cfg, nb6, torch, T, lanes=0, slices=None, max_ni=None, max_reps=200):
+    """Force-call time for every block of the configuration (one JSON line each):
+    wall time per call on a context without event timing (back-to-back calls on
+    one stream, so host launch cost shows only where it exceeds the GPU time),
+    and per-kernel GPU times on a second context with event timing."""
     cl = cfg["cluster"]
     n = cl.n
     stream = torch.cuda.current_stream()
     mode = MODES[args.mode]
-    ctx = nb6.nb6_create(0, flags=nb6.NB6_OPT_TIMING, ipl_hint=args.ipl, slice_hint=args.slices)
-    nb6.check(ctx, nb6.nb6_load_particles(ctx, 0, n, cl.m, cl.x, cl.v, cl.a, cl.jerk, cl.t))
-    nb6.check(ctx, nb6.nb6_predict_j(ctx, 0, cl.tb, mode, stream))
+    slices = args.slices if slices is None else slices
+    ctxs = []
+    for flags in (0, nb6.NB6_OPT_TIMING):
+        ctx = nb6.nb6_create(0, flags=flags, ipl_hint=args.ipl, slice_hint=slices,
+                             jl_hint=lanes)
+        nb6.check(ctx, nb6.nb6_load_particles(ctx, 0, n, cl.m, cl.x, cl.v, cl.a, cl.jerk,
+                                              cl.t))
+        nb6.check(ctx, nb6.nb6_predict_j(ctx, 0, cl.tb, mode, stream))
+        ctxs.append(ctx)
     for name, idx in sorted(cfg["blocks"].items(), key=lambda kv: len(kv[1])):
         ni = len(idx)
+        if max_ni is not None and ni > max_ni:
+            continue
         idx_d, h2_d, dtr_d = T(idx, torch.int32), T(cl.h2[idx]), T(cl.dtr[idx])
         acc = torch.empty((ni, 3), dtype=torch.float64, device="cuda:0")
         jerk = torch.empty_like(acc)
         nnb = torch.empty(ni, dtype=torch.int32, device="cuda:0")
         lst = torch.empty((ni, args.cap), dtype=torch.int32, device="cuda:0")
-        reps = max(3, min(200, int(2e11 / max(ni * n, 1))))
+        reps = max(3, min(max_reps, int(2e11 / max(ni * n, 1))))
 
-        def call():
+        def call(ctx):
             nb6.check(ctx, nb6.nb6_regular_force(ctx, 0, ni, idx_d, h2_d, dtr_d, mode, acc,
                                                  jerk, nnb, lst, args.cap, nb6.NB6_MEM_DEVICE,
                                                  stream))
-        call()
-        torch.cuda.synchronize()
-        nb6.nb6_kernel_times(ctx)
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            call()
-        torch.cuda.synchronize()
-        wall = (time.perf_counter() - t0) / reps
-        ms, cnt = nb6.nb6_kernel_times(ctx)
+        out = []
+        for k, ctx in enumerate(ctxs):
+            call(ctx)
+            torch.cuda.synchronize()
+            if k == 1:
+                nb6.nb6_kernel_times(ctx)
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                call(ctx)
+            torch.cuda.synchronize()
+            out.append((time.perf_counter() - t0) / reps)
+        wall = out[0]
+        ms, cnt = nb6.nb6_kernel_times(ctxs[1])
         pairs = ni * (n - 1)
+        ipl, jl, ns, slen = nb6.nb6_last_plan(ctxs[1])
         print(json.dumps({"block": name, "N": n, "N_i": ni, "mode": args.mode,
-                          "slices": nb6.nb6_last_slices(ctx), "reps": reps,
+                          "ipl": ipl, "lanes": jl, "slices": ns, "slice_len": slen,
+                          "forced": [lanes, slices], "reps": reps,
                           "call_us": round(wall * 1e6, 2),
                           "force_us": round(ms[1] / cnt[1] * 1e3, 2),
                           "finalize_us": round(ms[2] / cnt[2] * 1e3, 2),
                           "call_gint_s": round(pairs / wall / 1e9, 3),
                           "force_gint_s": round(pairs / (ms[1] / cnt[1] * 1e-3) / 1e9, 3)}),
               flush=True)
-    nb6.nb6_destroy(ctx)
+    for ctx in ctxs:
+        nb6.nb6_destroy(ctx)
+
+
+def plan_sweep(args, cfg, nb6, torch, T):
+    """Blocks of at most 4096 under forced (lanes per i, slices) plans, beside the
+    automatic plan, to tune the plan rule."""
+    block_sweep(args, cfg, nb6, torch, T, max_ni=4096, max_reps=60)
+    for lanes in (1, 4, 16, 64):
+        for slices in (32, 64, 128, 256, 512, 1024):
+            block_sweep(args, cfg, nb6, torch, T, lanes=lanes, slices=slices, max_ni=4096,
+                        max_reps=60)
+
+
+def traffic_config(args):
+    """The configuration a traffic record belongs to."""
+    return (f"config {args.config} block {args.block} mode {args.mode} cap {args.cap} "
+            f"ipl {args.ipl} slices {args.slices} lanes {args.lanes}")
 
 
 def main():
@@ -309,20 +475,43 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=4000)
+    ap.add_argument("--serve-requests", type=int, default=20000)
     ap.add_argument("--serve-calibrate", type=int, default=300)
     ap.add_argument("--serve-cap", type=int, default=128)
-    ap.add_argument("--serve-budget-mb", type=int, default=1024)
+    ap.add_argument("--serve-budget-mb", type=int, default=256,
+                    help="serving HBM budget: above the largest request's footprint "
+                         "(~140 MB), below what the fused batches would hold unchecked")
     ap.add_argument("--block-sweep", action="store_true",
                     help="time every block of the configuration (per-size curve) and exit")
+    ap.add_argument("--plan-sweep", action="store_true",
+                    help="time blocks of <= 4096 under forced lane / slice plans and exit")
+    ap.add_argument("--lanes", type=int, default=0, help="lanes per i-particle (0: auto)")
     ap.add_argument("--isa-rates", action="store_true",
                     help="only run the vector-instruction issue-rate probe and exit")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="run one device copy of this size first: the known-size kernel that "
                          "calibrates the FETCH_SIZE/WRITE_SIZE counters")
-    ap.add_argument("--rho", default="0.8,0.95,1.5",
+    ap.add_argument("--counter-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "VALU_CSV"),
+                    help="write the force kernel's counter summary from three rocprofv3 "
+                         "counter CSV files (with --copy-mib; '-' for no VALU run) to its "
+                         "profiles/ file and exit")
+    ap.add_argument("--rho", default="0.5,0.8,0.95,1.5",
                     help="offered load(s) as fractions of the plain form's capacity")
     args = ap.parse_args()
+
+    if args.counter_summary:
+        if args.copy_mib <= 0:
+            sys.exit("--counter-summary needs --copy-mib (the calibration copy's size)")
+        from workloads import config
+        cfg = config(args.config)
+        pairs = len(cfg["blocks"][args.block]) * (cfg["cluster"].n - 1)
+        f_csv, w_csv, v_csv = args.counter_summary
+        text = counter_summary(f_csv, w_csv, None if v_csv == "-" else v_csv, args.copy_mib,
+                               traffic_config(args), pairs)
+        with open(os.path.join(ROOT, COUNTER_FILE), "w") as f:
+            f.write(text)
+        print(text)
+        return
 
     if args.isa_rates:
         import subprocess
@@ -361,7 +550,10 @@ def main():
     stream = torch.cuda.current_stream()
     T = lambda a, dt=torch.float64: torch.from_numpy(np.ascontiguousarray(a)).to(dev, dt)  # noqa: E731
     if args.block_sweep:
-        block_sweep(args, cfg, nb6, torch, T)
+        block_sweep(args, cfg, nb6, torch, T, lanes=args.lanes)
+        return
+    if args.plan_sweep:
+        plan_sweep(args, cfg, nb6, torch, T)
         return
     m_d, x_d, v_d, a_d, j_d, t_d = (T(q) for q in (cl.m, cl.x, cl.v, cl.a, cl.jerk, cl.t))
     idx_d = T(idx_np, torch.int32)
@@ -377,7 +569,7 @@ def main():
     mode = MODES[args.mode]
 
     ctx = nb6.nb6_create(0, flags=nb6.NB6_OPT_TIMING, ipl_hint=args.ipl,
-                         slice_hint=args.slices)
+                         slice_hint=args.slices, jl_hint=args.lanes)
     nb6.check(ctx, nb6.nb6_load_particles(ctx, 0, n, m_d, x_d, v_d, a_d, j_d, t_d,
                                           mem_kind=nb6.NB6_MEM_DEVICE, stream=stream))
 
@@ -442,6 +634,16 @@ def main():
                      "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": None},
     }
+    rec = counters_from_profile(traffic_config(args))
+    if rec is not None:
+        out["roofline"]["traffic"] = rec["read_bytes"] + rec["write_bytes"]
+        out["roofline"]["traffic_read"] = rec["read_bytes"]
+        out["roofline"]["traffic_write"] = rec["write_bytes"]
+        out["roofline"]["traffic_unit"] = "bytes per force launch"
+        if "fp32_flop" in rec:
+            # the second reading of the peak fraction: counted FP32 VALU work
+            out["pct_fp32_peak_counted"] = round(
+                100.0 * rec["fp32_flop"] / (regf_ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, 2)
     gpu_out = (acc.cpu().numpy(), jerk.cpu().numpy(), nnb.cpu().numpy(),
                lst[:, :args.cap].cpu().numpy())
     nb6.nb6_destroy(ctx)

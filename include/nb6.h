@@ -76,6 +76,8 @@ typedef struct nb6_options {
     int64_t hbm_budget;    /* bytes the serving queue may hold; 0: 1/4 of free */
     int     flags;         /* NB6_OPT_* bits                                  */
     int     ipl_hint;      /* 0: choose i-particles per lane; 1 or 2: force it */
+    int     jl_hint;       /* 0: choose the lanes that share one i-particle;
+                              1, 2, 4, ..., 64: force it (not with ipl_hint 2) */
 } nb6_options;
 
 /* Record HIP events around every predictor, force and finalize launch so
@@ -248,6 +250,12 @@ int nb6_poll(nb6_ctx *ctx, uint64_t ticket, int wait, nb6_ticket_info *info);
 /* Number of j-slices (the j-split across workgroups) the last force call
  * used; for diagnostics and tests. */
 int nb6_last_slices(const nb6_ctx *ctx);
+
+/* Work partition of the last force call, for diagnostics and tests:
+ * out[0] i-particles per lane, out[1] lanes per i-particle, out[2] number of
+ * j-slices, out[3] j-particles per slice (the last slice may be shorter).
+ * Errors: NB6_ERR_ARG (NULL ctx or out). */
+int nb6_last_plan(const nb6_ctx *ctx, int out[4]);
 
 #ifdef __cplusplus
 }

@@ -59,19 +59,50 @@ void release(DevBuf& b) {
 Plan make_plan(const nb6_ctx* c, int64_t n, int64_t ni, int ipl) {
     Plan p;
     p.ipl = ipl > 0 ? ipl : c->ipl_hint > 0 ? c->ipl_hint : (ni >= 16384 ? 2 : 1);
-    const int64_t groups = (ni + 64 * p.ipl - 1) / (64 * p.ipl);
+    // Slices are at least 256 j-particles long, and give each lane at least
+    // 32 of them.
+    auto max_slices = [&](int sh) {
+        const int64_t len = std::max<int64_t>(256, (int64_t)32 << sh);
+        return std::max<int64_t>(1, (n + len - 1) / len);
+    };
+    auto groups_of = [&](int sh) {
+        const int g = regf_group_size(p.ipl, sh);
+        return (ni + g - 1) / g;
+    };
+    // Lanes per i.  A block of at most 256 is latency-bound, not
+    // throughput-bound: its i share the lanes of a wavefront (64 lanes per i
+    // up to 64 i, then 32 and 16), with slices sized to balance the force
+    // kernel's dependent j-loads (slice_len / lanes / 4 per lane) against
+    // the finalize kernel's dependent partial loads (slices / 32).
+    int sh = 0;
+    bool lanes_plan = false;
+    if (p.ipl == 1) {
+        if (c->jl_hint > 0) {
+            while ((1 << sh) < c->jl_hint) ++sh;
+        } else if (ni <= 256) {
+            sh = ni <= 64 ? 6 : ni <= 128 ? 5 : 4;
+            lanes_plan = true;
+        }
+    }
+    p.jl_shift = sh;
+    const int64_t groups = groups_of(sh);
     p.wpb = (int)std::min<int64_t>(4, groups);
     // About 32 waves per SIMD over the launch (several rounds at the
-    // kernel's occupancy, so the last round's imbalance is a small part);
-    // no slice shorter than 256 j-particles.
+    // kernel's occupancy, so the last round's imbalance is a small part).
     const int64_t target = (int64_t)c->num_cu * 4 * 32;
     int64_t s = c->slice_hint > 0 ? c->slice_hint : (target + groups - 1) / groups;
-    s = std::max<int64_t>(1, std::min<int64_t>(s, (n + 255) / 256));
+    if (lanes_plan && c->slice_hint <= 0) {
+        // measured optimum about sqrt(1.5 n / lanes), taken to a power of 2
+        const double best = std::sqrt(1.5 * (double)n / (double)(1 << sh));
+        s = (int64_t)1 << (int)std::lround(std::log2(std::max(1.0, best)));
+    }
+    s = std::max<int64_t>(1, std::min<int64_t>(s, c->slice_hint > 0 ? (n + 255) / 256
+                                                                   : max_slices(sh)));
     s = std::min<int64_t>(s, 65535);
     // a multiple of 8 lets the force kernel keep each slice on one XCD
     if (c->slice_hint <= 0 && s >= 8) s = s / 8 * 8;
     int64_t len = (n + s - 1) / s;
-    len = (len + 3) / 4 * 4;
+    len = (len + VTILE - 1) / VTILE * VTILE;
     p.slice_len = (int)len;
     p.nslices = (int)((n + len - 1) / len);
     return p;
@@ -172,7 +203,9 @@ int nb6_create(nb6_ctx** out, const nb6_options* opt) {
         c->hbm_budget = opt->hbm_budget;
         c->timing = (opt->flags & NB6_OPT_TIMING) != 0;
         c->ipl_hint = opt->ipl_hint;
-        if (c->ipl_hint < 0 || c->ipl_hint > 2) {
+        c->jl_hint = opt->jl_hint;
+        if (c->ipl_hint < 0 || c->ipl_hint > 2 || c->jl_hint < 0 || c->jl_hint > 64 ||
+            (c->jl_hint & (c->jl_hint - 1)) != 0 || (c->jl_hint > 1 && c->ipl_hint == 2)) {
             delete c;
             return NB6_ERR_ARG;
         }
@@ -255,7 +288,16 @@ int nb6_kernel_times(nb6_ctx* c, double* ms, int64_t* counts) {
 
 const char* nb6_last_error(const nb6_ctx* c) { return c ? c->err.c_str() : "no context"; }
 
-int nb6_last_slices(const nb6_ctx* c) { return c ? c->last_slices : 0; }
+int nb6_last_slices(const nb6_ctx* c) { return c ? c->last_plan.nslices : 0; }
+
+int nb6_last_plan(const nb6_ctx* c, int out[4]) {
+    if (!c || !out) return NB6_ERR_ARG;
+    out[0] = c->last_plan.ipl;
+    out[1] = 1 << c->last_plan.jl_shift;
+    out[2] = c->last_plan.nslices;
+    out[3] = c->last_plan.slice_len;
+    return NB6_OK;
+}
 
 int nb6_load_particles(nb6_ctx* c, int cluster, int64_t n, const double* m, const double* x,
                        const double* v, const double* a, const double* jerk, const double* t,
@@ -290,6 +332,9 @@ int nb6_load_particles(nb6_ctx* c, int cluster, int64_t n, const double* m, cons
             if (cl->state) HIP_TRY(c, hipFree(cl->state));
             cl->state = nullptr;
             cl->n = 0;
+            // the predicted records are sized by n: reallocated on next use
+            for (DevBuf& b : cl->rec) release(b);
+            release(cl->tmax);
             if (hipMalloc(&cl->state, (size_t)14 * n * sizeof(double)) != hipSuccess) {
                 (void)hipGetLastError();
                 cl->state = nullptr;
@@ -374,6 +419,8 @@ int nb6_predict_j(nb6_ctx* c, int cluster, double t_block, int modes, void* stre
         int rc = ensure(c, cl->rec[mi], (size_t)cl->n * rec_size(mi));
         if (rc) return rc;
     }
+    if (int rc = ensure(c, cl->tmax, (size_t)vtiles(cl->n) * sizeof(float))) return rc;
+    pa.tmax = (float*)cl->tmax.p;
     pa.ff = (modes & NB6_DX_FF) ? (RecFF*)cl->rec[MODE_FF].p : nullptr;
     pa.f64 = (modes & NB6_DX_FP64) ? (RecF64*)cl->rec[MODE_F64].p : nullptr;
     pa.f32 = (modes & NB6_DX_FP32) ? (RecF32*)cl->rec[MODE_F32].p : nullptr;
@@ -475,6 +522,8 @@ int nb6_regular_force(nb6_ctx* c, int cluster, int64_t n_i, const int32_t* idx_i
     ra.ni = ni;
     ra.slice_len = p.slice_len;
     ra.nslices = p.nslices;
+    ra.jl_shift = p.jl_shift;
+    ra.tmax = (const float*)cl->tmax.p;
     ra.part = (double*)c->part.p;
     ra.cnt = d_cnt;
     ra.lst = (int32_t*)c->lst.p;
@@ -522,7 +571,7 @@ int nb6_regular_force(nb6_ctx* c, int cluster, int64_t n_i, const int32_t* idx_i
         oa.ovf_list = fa.ovf_list;
         HIP_TRY(c, launch_overflow(mi, oa, st));
     }
-    c->last_slices = p.nslices;
+    c->last_plan = p;
 
     if (mem_kind == NB6_MEM_DEVICE) return NB6_OK;
 

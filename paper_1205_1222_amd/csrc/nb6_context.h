@@ -26,6 +26,7 @@ struct ClusterState {
     double* state = nullptr;   // m[n] t[n] x[3n] v[3n] a[3n] jk[3n]
     double *m = nullptr, *t = nullptr, *x = nullptr, *v = nullptr, *a = nullptr, *jk = nullptr;
     DevBuf rec[3];             // j-records by mode index
+    DevBuf tmax;               // max vabs per tile of VTILE records (any mode)
     int pred_valid = 0;        // NB6_DX_* bits whose records are current
     double t_pred = 0.0;
     // Owner of the cluster: 0 free, 1 a serving request in flight, -1 a plain
@@ -56,7 +57,7 @@ inline size_t rec_size(int mi) {
 
 // Wave-level work partition of one force call.
 struct Plan {
-    int ipl, wpb, nslices, slice_len;
+    int ipl, jl_shift, wpb, nslices, slice_len;
 };
 
 class Engine;  // serving queue (nb6_serve.hip)
@@ -68,6 +69,7 @@ struct nb6_ctx {
     int num_cu = 256;
     int slice_hint = 0;
     int ipl_hint = 0;
+    int jl_hint = 0;
     int64_t hbm_budget = 0;
     std::vector<nb6::ClusterState*> clusters;
     nb6::DevBuf part, cnt, lst, ovf;                  // force-kernel scratch
@@ -76,7 +78,7 @@ struct nb6_ctx {
     nb6::DevBuf ld[7];                                // HOST-mode load staging
     unsigned* status = nullptr;                       // device status word
     std::string err;
-    int last_slices = 0;
+    nb6::Plan last_plan{0, 0, 0, 0, 0};
     bool timing = false;
     struct Timed { int kind; hipEvent_t a, b; };
     std::vector<Timed> timed;                         // pending event pairs

@@ -33,6 +33,12 @@ struct __attribute__((aligned(16))) RecF32 {  // plain float coordinates, 32 B
 
 enum Mode { MODE_FF = 0, MODE_F64 = 1, MODE_F32 = 2 };
 
+// j-particles per tile of the force kernel: its FP32 partial sums are folded
+// into FP64 once per tile, and the predictor records max |v| of every tile of
+// VTILE consecutive particles (the bound of the candidate pre-test).
+constexpr int VTILE = 32;
+__host__ __device__ inline long long vtiles(long long n) { return (n + VTILE - 1) / VTILE; }
+
 // Bits of the device status word.
 enum StatusBits { ST_BAD_INDEX = 1, ST_BAD_H2 = 2, ST_NONFINITE = 4, ST_OVERFLOW = 8 };
 
@@ -41,6 +47,12 @@ enum StatusBits { ST_BAD_INDEX = 1, ST_BAD_H2 = 2, ST_NONFINITE = 4, ST_OVERFLOW
 constexpr int NPART = 6;
 // Largest per-i list capacity (cap + 1 slots: the i itself is found too).
 constexpr int MAX_CAPS = 1024;
+// Particles per finalize workgroup (lists; the first ceil(ni / 64)
+// workgroups also reduce the slice partials of 64 particles each).
+constexpr int FINAL_PPB = 8;
+__host__ __device__ inline long long final_blocks(long long ni) {
+    return (ni + FINAL_PPB - 1) / FINAL_PPB;
+}
 // Workgroups of the overflow scan (each loops over the queued i).
 constexpr int OVERFLOW_BLOCKS = 64;
 
@@ -51,8 +63,10 @@ struct RegfArgs {
     const double*  h2;        // [ni]
     const double*  dtr;       // [ni]
     int            ni;
-    int            slice_len; // j per slice (multiple of 4)
+    int            slice_len; // j per slice (multiple of VTILE)
     int            nslices;
+    int            jl_shift;  // log2 of the lanes that share one i (0: one lane per i)
+    const float*   tmax;      // [vtiles(n)] max of vabs over each tile of VTILE j
     double*        part;      // [ceil(ni/64)][nslices][NPART][64]
     int32_t*       cnt;       // [ni] neighbours found, the i itself included (zeroed)
     int32_t*       lst;       // [ni][caps] neighbours in the order found
@@ -104,6 +118,7 @@ struct PredictArgs {
     RecFF*        ff;  // may be null
     RecF64*       f64; // may be null
     RecF32*       f32; // may be null
+    float*        tmax; // [vtiles(n)] max vabs per tile (always written)
     unsigned*     status;
 };
 
@@ -131,16 +146,16 @@ struct ReqDesc {
     PredictArgs  pred;        // prediction of its cluster (when do_predict)
     int          do_predict;
     int          mode;        // MODE_*
-    int          groups;      // i-groups of 64
+    int          groups;      // i-groups of 64 >> rg.jl_shift
     long long    item0;       // first force work item within its mode group
-    long long    blk0;        // first 64-particle block within the batch
+    long long    blk0;        // first finalize workgroup within the batch
 };
 
 struct BatchArgs {
     const ReqDesc*      reqs;      // device copy of the batch's descriptors
     int                 nreq;
     long long           nitems;    // force work items of this launch
-    long long           nblk_total; // 64-particle blocks of the batch
+    long long           nblk_total; // finalize workgroups of the batch
     unsigned long long* counter;   // work-item counter (zeroed before the launch)
 };
 
@@ -153,9 +168,12 @@ hipError_t launch_serve_overflow(int mode, const BatchArgs& b, hipStream_t s);
 constexpr int PREPARE_CHUNK = 1024;
 hipError_t launch_serve_prepare(const BatchArgs& b, int chunks, hipStream_t s);
 
-// i-particles per lane of the force kernel.
+// Force kernel: ipl i-particles per lane (a.jl_shift == 0), or one i per
+// 2^a.jl_shift lanes (ipl == 1).
 hipError_t launch_regf(int mode, int ipl, int waves_per_block, const RegfArgs& a,
                        hipStream_t s);
+// i-particles of one work item (one wavefront) of the force kernel.
+__host__ __device__ inline int regf_group_size(int ipl, int jl_shift) { return (64 * ipl) >> jl_shift; }
 hipError_t launch_finalize(const FinalArgs& a, hipStream_t s);
 hipError_t launch_overflow(int mode, const OverflowArgs& a, hipStream_t s);
 hipError_t launch_predict(const PredictArgs& a, hipStream_t s);

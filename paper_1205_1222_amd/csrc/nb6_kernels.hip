@@ -6,6 +6,8 @@
 //   regf_kernel       regular force, jerk and neighbour appends for one
 //                     (i-group, j-slice) pair (section 3.3 step 6 with the
 //                     velocity criterion of section 3.2).
+//   regf_lanes_kernel the same for small active blocks, with several lanes
+//                     per i splitting the slice's j.
 //   finalize_kernel   fixed-order reduction of the j-slice partial sums and
 //                     the sorted neighbour list of each i (the reduction and
 //                     list-gathering kernels of section 3.4).
@@ -13,7 +15,8 @@
 //                     capacity: the first `cap` in ascending j.
 //
 // Design:
-//   * i-particles live in VGPRs, IPL of them per lane.
+//   * i-particles live in VGPRs, IPL of them per lane (or one per 2^k lanes
+//     for small blocks).
 //   * Every lane of a wavefront reads the same j-record, so records are
 //     fetched with scalar loads into SGPRs and used directly as operands of
 //     the vector instructions: no LDS traffic and no VGPRs spent on j.
@@ -40,7 +43,7 @@
 
 namespace nb6 {
 
-constexpr int TILE = 32;    // j per FP32 tile before the FP64 fold
+constexpr int TILE = VTILE; // j per FP32 tile before the FP64 fold
 constexpr int JG = 4;       // j-records loaded together
 
 template <int MODE> struct RecOf;
@@ -109,19 +112,27 @@ __device__ __forceinline__ bool velocity_criterion(float r2, float dx, float dy,
     return fminf(r2, p2) < h2;
 }
 
+// Candidate bound (c_i + dtr_i w)^2 for an upper bound w of |v_j|.
+__device__ __forceinline__ float sq_bound(const IAux& ia, float w) {
+    const float b = fmaf(ia.dtr, w, ia.c);
+    return b * b;
+}
+
 // One i-j interaction.  run[0..2] += m r^-3 R, run[3..5] += m r^-3 (V + alpha R)
 // with alpha = -3 (R.V)/r^2, unless j is a neighbour of i, in which case j is
 // appended to i's list instead.
 //
-// The velocity criterion is evaluated only for candidate pairs,
-// r^2 < (c_i + dtr_i |v_j|)^2: since |R + dtr V| >= |R| - dtr (|v_i| + |v_j|),
-// a pair outside that radius is not a neighbour, and the 2^-16 relative
-// margin folded into c_i covers the FP32 rounding of every quantity involved,
-// so the decision equals that of the full test.  Candidates are rare, so the
-// branch is almost never taken by any lane of a wavefront.
+// The velocity criterion is evaluated only for candidate pairs, r^2 < bnd2
+// with bnd2 = (c_i + dtr_i w)^2 for some w >= |v_j| (the caller's choice:
+// |v_j| itself, or the largest |v| of j's tile): since
+// |R + dtr V| >= |R| - dtr (|v_i| + |v_j|), a pair outside that radius is not
+// a neighbour, and the 2^-16 relative margin folded into c_i covers the FP32
+// rounding of every quantity involved, so the decision equals that of the
+// full test.  Candidates are rare, so the branch is seldom taken by any lane
+// of a wavefront.
 template <int MODE>
 __device__ __forceinline__ void interact(const typename RecOf<MODE>::T& r, int j,
-                                         const IPos<MODE>& ip, const IAux& ia,
+                                         const IPos<MODE>& ip, const IAux& ia, float bnd2,
                                          float run[6], int qq, const RegfArgs& a) {
     float dx, dy, dz;
     coord_diff(r, ip, dx, dy, dz);
@@ -131,8 +142,7 @@ __device__ __forceinline__ void interact(const typename RecOf<MODE>::T& r, int j
     const float r2 = dist2(dx, dy, dz);
     const float rv = fmaf(dz, dvz, fmaf(dy, dvy, dx * dvx));
     float rinv = __builtin_amdgcn_rsqf(r2);
-    const float bnd = fmaf(ia.dtr, r.vabs, ia.c);
-    if (r2 < bnd * bnd) {
+    if (r2 < bnd2) {
         if (velocity_criterion(r2, dx, dy, dz, dvx, dvy, dvz, ia.dtr, ia.h2)) {
             const int slot = atomicAdd(a.cnt + qq, 1);
             if (slot < a.caps) a.lst[(size_t)qq * a.caps + slot] = j;
@@ -189,6 +199,38 @@ __device__ __forceinline__ size_t part_index(int q, int s, int c, int nslices) {
     return (((size_t)(q >> 6) * nslices + s) * NPART + c) * 64 + (q & 63);
 }
 
+// State of active particle q for the force kernel: position, velocity,
+// neighbour radius and the i-part of the candidate radius.  Returns the list
+// row the lane appends to (row 0 for lanes without a valid i: those never
+// append, since their h2 is -1 and their candidate radius NaN).  A bad index
+// or radius is flagged once, by the work items of slice 0.
+template <int MODE>
+__device__ __forceinline__ int load_i(const RegfArgs& a, const int q, const int s,
+                                      IPos<MODE>& ip, IAux& ia) {
+    using Rec = typename RecOf<MODE>::T;
+    bool live = q < a.ni;
+    int pi = live ? a.idx[q] : 0;
+    float h2f = live ? checked_h2(a.h2[q]) : -1.0f;
+    const float dtf = live ? (float)a.dtr[q] : 0.0f;
+    if (live) {
+        unsigned bad = 0;
+        if (pi < 0 || pi >= a.n) bad |= ST_BAD_INDEX;
+        if (h2f < 0.0f) bad |= ST_BAD_H2;
+        if (bad) {
+            if (s == 0) atomicOr(a.status, bad);
+            pi = 0;
+            h2f = -1.0f;
+            live = false;
+        }
+    }
+    const Rec* rv = static_cast<const Rec*>(a.rec);  // per-lane address
+    get_ipos(rv[pi], ip, ia);
+    ia.h2 = h2f;
+    ia.dtr = dtf;
+    ia.c = (float)((sqrt((double)h2f) + (double)dtf * (double)ia.vabs) * (1.0 + 0x1p-16));
+    return live ? q : 0;
+}
+
 // Force, jerk and neighbour appends of one (i-group, j-slice) work item:
 // 64 * IPL active particles starting at group * 64 * IPL, against the
 // j-particles of slice s.
@@ -201,35 +243,10 @@ __device__ __forceinline__ void regf_item(const RegfArgs& a, const int group, co
 
     IPos<MODE> ip[IPL];
     IAux ia[IPL];
-    int q[IPL];
-    int qq[IPL];  // list row of the lane's i (row 0 for invalid lanes, which never append)
 #pragma unroll
-    for (int k = 0; k < IPL; ++k) {
-        q[k] = ibase + k * 64 + lane;
-        bool live = q[k] < a.ni;
-        int pi = live ? a.idx[q[k]] : 0;
-        float h2f = live ? checked_h2(a.h2[q[k]]) : -1.0f;
-        const float dtf = live ? (float)a.dtr[q[k]] : 0.0f;
-        if (live) {
-            unsigned bad = 0;
-            if (pi < 0 || pi >= a.n) bad |= ST_BAD_INDEX;
-            if (h2f < 0.0f) bad |= ST_BAD_H2;
-            if (bad) {
-                if (s == 0) atomicOr(a.status, bad);
-                pi = 0;
-                h2f = -1.0f;
-                live = false;
-            }
-        }
-        const Rec* rv = static_cast<const Rec*>(a.rec);  // per-lane address
-        get_ipos(rv[pi], ip[k], ia[k]);
-        ia[k].h2 = h2f;
-        ia[k].dtr = dtf;
-        // NaN for invalid lanes (h2f = -1): never a candidate, never appends
-        ia[k].c = (float)((sqrt((double)h2f) + (double)dtf * (double)ia[k].vabs) *
-                          (1.0 + 0x1p-16));
-        qq[k] = live ? q[k] : 0;
-    }
+    for (int k = 0; k < IPL; ++k) (void)load_i<MODE>(a, ibase + k * 64 + lane, s, ip[k], ia[k]);
+    // A lane's list row is its q = ibase + k * 64 + lane, recomputed from the
+    // lane id where it is needed (lanes without a valid i never append).
 
     const int j0 = s * a.slice_len;
     const int j1 = min(j0 + a.slice_len, a.n);
@@ -240,32 +257,43 @@ __device__ __forceinline__ void regf_item(const RegfArgs& a, const int group, co
 #pragma unroll
         for (int c = 0; c < 6; ++c) sum[k][c] = 0.0;
 
-    for (int jt = j0; jt < j1; jt += TILE) {
+    const_ptr<float> tmax = (const_ptr<float>)(a.tmax);
+    for (int jt = j0; jt < j1; jt += TILE) {  // j0 is a multiple of TILE
         const int je = min(jt + TILE, j1);
         float run[IPL][6];
 #pragma unroll
         for (int k = 0; k < IPL; ++k)
 #pragma unroll
             for (int c = 0; c < 6; ++c) run[k][c] = 0.0f;
+        // candidate bound of the tile: its largest |v_j| for every j
+        const float vm = tmax[jt / TILE];
+        float bnd2[IPL];
+#pragma unroll
+        for (int k = 0; k < IPL; ++k) bnd2[k] = sq_bound(ia[k], vm);
 
-        // groups of JG records: all their scalar loads are issued before the
-        // first interaction of the group, so one load latency covers JG j.
+        // groups of G records: all their scalar loads are issued before the
+        // first interaction of the group, so one load latency covers G j.
+        // With two i per lane a group of 2 gives as many interactions per
+        // load as 4 with one, and keeps the kernel within 128 VGPRs.
+        constexpr int G = IPL == 2 ? 2 : JG;
         int j = jt;
-        for (; j + JG <= je; j += JG) {
-            Rec r[JG];
+        for (; j + G <= je; j += G) {
+            Rec r[G];
 #pragma unroll
-            for (int g = 0; g < JG; ++g) r[g] = load_rec(rec + j + g);
+            for (int g = 0; g < G; ++g) r[g] = load_rec(rec + j + g);
 #pragma unroll
-            for (int g = 0; g < JG; ++g)
+            for (int g = 0; g < G; ++g)
 #pragma unroll
                 for (int k = 0; k < IPL; ++k)
-                    interact<MODE>(r[g], j + g, ip[k], ia[k], run[k], qq[k], a);
+                    interact<MODE>(r[g], j + g, ip[k], ia[k], bnd2[k], run[k],
+                                   ibase + k * 64 + (int)__lane_id(), a);
         }
         for (; j < je; ++j) {
             const Rec r = load_rec(rec + j);
 #pragma unroll
             for (int k = 0; k < IPL; ++k)
-                interact<MODE>(r, j, ip[k], ia[k], run[k], qq[k], a);
+                interact<MODE>(r, j, ip[k], ia[k], bnd2[k], run[k],
+                               ibase + k * 64 + (int)__lane_id(), a);
         }
 #pragma unroll
         for (int k = 0; k < IPL; ++k)
@@ -277,11 +305,75 @@ __device__ __forceinline__ void regf_item(const RegfArgs& a, const int group, co
     // component of a wave's 64 particles is one contiguous 512-byte store
 #pragma unroll
     for (int k = 0; k < IPL; ++k) {
-        if (q[k] < a.ni) {
-            double* p = a.part + part_index(q[k], s, 0, a.nslices);
+        const int q = ibase + k * 64 + lane;
+        if (q < a.ni) {
+            double* p = a.part + part_index(q, s, 0, a.nslices);
 #pragma unroll
             for (int c = 0; c < NPART; ++c) p[c * 64] = sum[k][c];
         }
+    }
+}
+
+// The same work item when 2^jl_shift consecutive lanes share one i: the
+// wavefront holds 64 >> jl_shift particles starting at group * (64 >>
+// jl_shift), and lane k of an i's lanes takes the j-particles j0 + k,
+// j0 + k + 2^jl_shift, ... of the slice.  The records are vector loads (the
+// lanes read different j).  At the end, a butterfly over the i's lanes adds
+// their FP64 sums; it gives the same bits in each of those lanes, and the
+// first of them stores the partial.  Used when the active block is too small
+// to give every lane its own i and still fill the chip.
+template <int MODE>
+__device__ __forceinline__ void regf_item_lanes(const RegfArgs& a, const int group,
+                                                const int s) {
+    using Rec = typename RecOf<MODE>::T;
+    const Rec* rec = static_cast<const Rec*>(a.rec);
+    const int lane = threadIdx.x & 63;
+    const int sh = a.jl_shift;
+    const int jl = 1 << sh;
+    const int jsub = lane & (jl - 1);
+    const int q = group * (64 >> sh) + (lane >> sh);
+
+    IPos<MODE> ip;
+    IAux ia;
+    const int qq = load_i<MODE>(a, q, s, ip, ia);
+
+    const int j0 = s * a.slice_len;
+    const int j1 = min(j0 + a.slice_len, a.n);
+
+    double sum[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) sum[c] = 0.0;
+
+    for (int jt = j0; jt < j1; jt += TILE * jl) {
+        const int je = min(jt + TILE * jl, j1);
+        float run[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) run[c] = 0.0f;
+        int j = jt + jsub;
+        for (; j + (JG - 1) * jl < je; j += JG * jl) {
+            Rec r[JG];
+#pragma unroll
+            for (int g = 0; g < JG; ++g) r[g] = rec[j + g * jl];
+#pragma unroll
+            for (int g = 0; g < JG; ++g)
+                interact<MODE>(r[g], j + g * jl, ip, ia, sq_bound(ia, r[g].vabs), run, qq, a);
+        }
+        for (; j < je; j += jl) {
+            const Rec r = rec[j];
+            interact<MODE>(r, j, ip, ia, sq_bound(ia, r.vabs), run, qq, a);
+        }
+#pragma unroll
+        for (int c = 0; c < 6; ++c) sum[c] += (double)run[c];
+    }
+
+    for (int d = 1; d < jl; d <<= 1)
+#pragma unroll
+        for (int c = 0; c < 6; ++c) sum[c] += __shfl_xor(sum[c], d);
+
+    if (jsub == 0 && q < a.ni) {
+        double* p = a.part + part_index(q, s, 0, a.nslices);
+#pragma unroll
+        for (int c = 0; c < NPART; ++c) p[c * 64] = sum[c];
     }
 }
 
@@ -311,17 +403,42 @@ regf_kernel(RegfArgs a, int gblocks) {
     regf_item<MODE, IPL>(a, group, s);
 }
 
+// The force kernel for lanes that share an i (a.jl_shift > 0), with the grid
+// and XCD mapping of regf_kernel.
+template <int MODE>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+regf_lanes_kernel(RegfArgs a, int gblocks) {
+    const int b = blockIdx.x;
+    int s, gb;
+    if ((a.nslices & 7) == 0) {
+        const int xcd = b & 7, k = b >> 3;
+        s = xcd + 8 * (k / gblocks);
+        gb = k % gblocks;
+    } else {
+        s = b / gblocks;
+        gb = b % gblocks;
+    }
+    const int wpb = blockDim.x >> 6;
+    const int group = gb * wpb + (threadIdx.x >> 6);
+    if (group * (64 >> a.jl_shift) >= a.ni) return;  // uniform across the wave
+    regf_item_lanes<MODE>(a, group, s);
+}
+
 // ---------------------------------------------------------------------------
-// Finalize: one workgroup per block of 64 particles.
-//   sums  -- thread t of the first wave adds particle (blk*64 + t)'s slice
-//            partials in slice order (a fixed summation order; the loads of
-//            the wave are contiguous).
-//   lists -- each wave takes 16 of the 64 particles.  count <= caps: every
-//            neighbour was stored; an entry's output position is its rank
-//            among the entries (entries are distinct), less one past the i
+// Finalize: workgroup b of a request (4 waves) does
+//   sums  -- for b < ceil(ni / 64), the slice partials of particles
+//            64b .. 64b + 63.  The four waves split each particle's partials
+//            in runs of 8 slices and the run sums are combined in a fixed
+//            order, so the result depends on the slicing only (lane t of a
+//            wave reads particle 64b + t: contiguous loads).
+//   lists -- particles 8b .. 8b + 7, two per wave.  count <= caps: every
+//            neighbour was stored, and an entry's output position is its
+//            rank among the entries (they are distinct), less one past the i
 //            itself.  count > caps: the list overflowed and i is queued for
 //            the ordered overflow scan.
+// A request therefore takes final_blocks(ni) = ceil(ni / FINAL_PPB) workgroups.
 // ---------------------------------------------------------------------------
+
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -333,70 +450,129 @@ __device__ __forceinline__ bool invalid_i(const FinalArgs& a, int q) {
     return self < 0 || self >= a.n || checked_h2(a.h2[q]) < 0.0f;
 }
 
-// Block blk of one request; sh_list is MAX_CAPS ints per wave.
-__device__ __forceinline__ void finalize_block(const FinalArgs& a, const int blk,
-                                               int32_t (*sh_list)[MAX_CAPS]) {
+// LDS of the finalize kernels: the four waves' slice sums, and later (the
+// same bytes) one buffer of MAX_CAPS list entries per wave.
+union FinalShared {
+    double  sum[4][NPART][64];
+    int32_t list[4][MAX_CAPS];
+};
+
+// Slice sums of particles 64 blk .. 64 blk + 63, by the whole workgroup.
+__device__ __forceinline__ void finalize_sums(const FinalArgs& a, const int blk,
+                                              FinalShared& sh) {
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (w == 0) {
-        const int q = blk * 64 + lane;
-        if (q < a.ni) {
-            if (invalid_i(a, q)) {
-                const double nan = __builtin_nan("");
-                for (int c = 0; c < 3; ++c) {
-                    a.acc[3 * q + c] = nan;
-                    a.jerk[3 * q + c] = nan;
-                }
-                a.nnb[q] = -1;
-            } else {
-                double sum[NPART];
+    const int q = blk * 64 + lane;
+    double sum[NPART];
 #pragma unroll
-                for (int c = 0; c < NPART; ++c) sum[c] = 0.0;
-                const double* p = a.part + part_index(q, 0, 0, a.nslices);
-                for (int s = 0; s < a.nslices; ++s)
+    for (int c = 0; c < NPART; ++c) sum[c] = 0.0;
+    if (q < a.ni) {
+        const double* p = a.part + part_index(q, 0, 0, a.nslices);
+        for (int s0 = 8 * w; s0 < a.nslices; s0 += 32) {
+            double v[8][NPART];  // the 48 loads of a run are in flight together
 #pragma unroll
-                    for (int c = 0; c < NPART; ++c) sum[c] += p[((size_t)s * NPART + c) * 64];
-                for (int c = 0; c < 3; ++c) {
-                    a.acc[3 * q + c] = sum[c];
-                    a.jerk[3 * q + c] = sum[3 + c];
-                }
-                a.nnb[q] = a.cnt[q] - 1;  // the i itself is among the found
-            }
+            for (int u = 0; u < 8; ++u)
+#pragma unroll
+                for (int c = 0; c < NPART; ++c)
+                    v[u][c] = s0 + u < a.nslices ? p[((size_t)(s0 + u) * NPART + c) * 64] : 0.0;
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+#pragma unroll
+                for (int c = 0; c < NPART; ++c) sum[c] += v[u][c];
         }
     }
-    int32_t* sl = sh_list[w];
-    for (int t = 0; t < 16; ++t) {
-        const int q = blk * 64 + w * 16 + t;  // uniform across the wave
-        if (q >= a.ni) break;
-        if (invalid_i(a, q)) continue;
-        const int32_t self = a.idx[q];
-        const int count = a.cnt[q];
-        if (count > a.caps) {
-            if (lane == 0) {
-                atomicOr(a.status, (unsigned)ST_OVERFLOW);
-                const int slot = atomicAdd(a.ovf_count, 1);
-                a.ovf_list[slot] = q;
+#pragma unroll
+    for (int c = 0; c < NPART; ++c) sh.sum[w][c][lane] = sum[c];
+    __syncthreads();
+    if (w == 0 && q < a.ni) {
+        if (invalid_i(a, q)) {
+            const double nan = __builtin_nan("");
+            for (int c = 0; c < 3; ++c) {
+                a.acc[3 * q + c] = nan;
+                a.jerk[3 * q + c] = nan;
             }
-            continue;
+            a.nnb[q] = -1;
+        } else {
+            for (int c = 0; c < NPART; ++c) {
+                const double t = ((sh.sum[0][c][lane] + sh.sum[1][c][lane]) +
+                                  sh.sum[2][c][lane]) + sh.sum[3][c][lane];
+                if (c < 3) a.acc[3 * q + c] = t;
+                else a.jerk[3 * q + c - 3] = t;
+            }
+            a.nnb[q] = a.cnt[q] - 1;  // the i itself is among the found
         }
-        const int32_t* l = a.lst + (size_t)q * a.caps;
-        for (int e = lane; e < count; e += 64) sl[e] = l[e];
-        wave_sync();
-        for (int e = lane; e < count; e += 64) {
-            const int32_t v = sl[e];
-            if (v == self) continue;
-            int rank = 0;
-            for (int k = 0; k < count; ++k) rank += sl[k] < v ? 1 : 0;
-            const int pos = rank - (v > self ? 1 : 0);
-            if (pos >= 0 && pos < a.cap) a.list[(size_t)q * a.cap + pos] = v;
-        }
-        wave_sync();  // sl is rewritten for the next particle
     }
+    __syncthreads();  // the LDS is reused for lists
+}
+
+// Sorted list of particle q (wave-uniform) from its `count` found entries;
+// `first` holds entry `lane` when lane < min(count, caps).  sl: this wave's
+// LDS buffer, for lists longer than one wavefront.
+__device__ __forceinline__ void finalize_list(const FinalArgs& a, const int q,
+                                              const int32_t self, const int count,
+                                              const int32_t first, int32_t* sl) {
+    const int lane = threadIdx.x & 63;
+    if (count > a.caps) {
+        if (lane == 0) {
+            atomicOr(a.status, (unsigned)ST_OVERFLOW);
+            const int slot = atomicAdd(a.ovf_count, 1);
+            a.ovf_list[slot] = q;
+        }
+        return;
+    }
+    int32_t* out = a.list + (size_t)q * a.cap;
+    if (count <= 64) {
+        // one entry per lane; ranks by reading every entry across the wave
+        const int32_t v = lane < count ? first : INT32_MAX;
+        int rank = 0;
+        for (int k = 0; k < count; ++k) rank += __builtin_amdgcn_readlane(v, k) < v ? 1 : 0;
+        const int pos = rank - (v > self ? 1 : 0);
+        if (lane < count && v != self && pos < a.cap) out[pos] = v;
+        return;
+    }
+    const int32_t* l = a.lst + (size_t)q * a.caps;
+    for (int e = lane; e < count; e += 64) sl[e] = l[e];
+    wave_sync();
+    for (int e = lane; e < count; e += 64) {
+        const int32_t v = sl[e];
+        if (v == self) continue;
+        int rank = 0;
+        for (int k = 0; k < count; ++k) rank += sl[k] < v ? 1 : 0;
+        const int pos = rank - (v > self ? 1 : 0);
+        if (pos >= 0 && pos < a.cap) out[pos] = v;
+    }
+    wave_sync();  // sl is rewritten for the next particle
+}
+
+// Workgroup blk of one request's finalize.
+__device__ __forceinline__ void finalize_block(const FinalArgs& a, const int blk,
+                                               FinalShared& sh) {
+    if (blk * 64 < a.ni) finalize_sums(a, blk, sh);  // uniform across the workgroup
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    constexpr int PPW = FINAL_PPB / 4;
+    const int q0 = blk * FINAL_PPB + w * PPW;
+    // every load of the wave's particles is issued before the first sort
+    int32_t self[PPW], count[PPW], first[PPW];
+    bool ok[PPW];
+#pragma unroll
+    for (int k = 0; k < PPW; ++k) {
+        const int q = q0 + k;
+        ok[k] = q < a.ni;
+        self[k] = ok[k] ? a.idx[q] : -1;
+        const float h2f = ok[k] ? checked_h2(a.h2[q]) : -1.0f;
+        count[k] = ok[k] ? a.cnt[q] : 0;
+        first[k] = ok[k] && lane < a.caps ? a.lst[(size_t)q * a.caps + lane] : 0;
+        ok[k] = ok[k] && self[k] >= 0 && self[k] < a.n && h2f >= 0.0f;
+    }
+#pragma unroll
+    for (int k = 0; k < PPW; ++k)
+        if (ok[k]) finalize_list(a, q0 + k, self[k], count[k], first[k], sh.list[w]);
 }
 
 __global__ void __launch_bounds__(256) finalize_kernel(FinalArgs a) {
-    __shared__ int32_t sh_list[4][MAX_CAPS];
-    finalize_block(a, blockIdx.x, sh_list);
+    __shared__ FinalShared sh;
+    finalize_block(a, blockIdx.x, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -455,10 +631,18 @@ __global__ void __launch_bounds__(256) overflow_kernel(OverflowArgs a) {
 // Serving: fused launches over the requests of a batch.  The descriptors are
 // copied to the device before the launches and read with scalar loads.
 // ---------------------------------------------------------------------------
+// The copies below name every field (a struct copy out of the constant
+// address space does not compile); the sizes pin the field lists, so a field
+// added to an argument struct cannot be left out here unnoticed.
+static_assert(sizeof(RegfArgs) == 104, "load_regf_args must copy every RegfArgs field");
+static_assert(sizeof(FinalArgs) == 120, "load_final_args must copy every FinalArgs field");
+static_assert(sizeof(OverflowArgs) == 72, "load_overflow_args must copy every field");
+
 __device__ __forceinline__ RegfArgs load_regf_args(const_ptr<ReqDesc> d) {
     RegfArgs a;
     a.rec = d->rg.rec; a.n = d->rg.n; a.idx = d->rg.idx; a.h2 = d->rg.h2; a.dtr = d->rg.dtr;
     a.ni = d->rg.ni; a.slice_len = d->rg.slice_len; a.nslices = d->rg.nslices;
+    a.jl_shift = d->rg.jl_shift; a.tmax = d->rg.tmax;
     a.part = d->rg.part; a.cnt = d->rg.cnt; a.lst = d->rg.lst; a.caps = d->rg.caps;
     a.status = d->rg.status;
     return a;
@@ -506,14 +690,17 @@ serve_regf_kernel(BatchArgs b) {
         const RegfArgs a = load_regf_args(reqs + lo);
         const long long local = item - reqs[lo].item0;
         const int groups = reqs[lo].groups;
-        regf_item<MODE, 1>(a, (int)(local % groups), (int)(local / groups));
+        if (a.jl_shift > 0)
+            regf_item_lanes<MODE>(a, (int)(local % groups), (int)(local / groups));
+        else
+            regf_item<MODE, 1>(a, (int)(local % groups), (int)(local / groups));
     }
 }
 
 __global__ void __launch_bounds__(256) serve_finalize_kernel(BatchArgs b) {
-    __shared__ int32_t sh_list[4][MAX_CAPS];
+    __shared__ FinalShared sh;
     const_ptr<ReqDesc> reqs = (const_ptr<ReqDesc>)(b.reqs);
-    const long long gb = blockIdx.x;  // 64-particle block within the batch
+    const long long gb = blockIdx.x;  // finalize workgroup within the batch
     if (gb >= b.nblk_total) return;
     int lo = 0, hi = b.nreq - 1;      // last request with blk0 <= gb
     while (lo < hi) {
@@ -521,7 +708,7 @@ __global__ void __launch_bounds__(256) serve_finalize_kernel(BatchArgs b) {
         if (reqs[mid].blk0 <= gb) lo = mid; else hi = mid - 1;
     }
     const FinalArgs f = load_final_args(reqs + lo);
-    finalize_block(f, (int)(gb - reqs[lo].blk0), sh_list);
+    finalize_block(f, (int)(gb - reqs[lo].blk0), sh);
 }
 
 template <int MODE>
@@ -539,7 +726,8 @@ __global__ void __launch_bounds__(256) serve_overflow_kernel(BatchArgs b) {
 
 // Block (r, chunk): predict chunk of request r's cluster (when flagged) and
 // clear the same chunk of its counts (n_i counts and the overflow count).
-__device__ __forceinline__ void predict_one(const PredictArgs& a, int64_t k);
+__device__ __forceinline__ float predict_one(const PredictArgs& a, int64_t k);
+__device__ __forceinline__ void store_tile_max(const PredictArgs& a, int64_t k, float v);
 
 __global__ void __launch_bounds__(256) serve_prepare_kernel(BatchArgs b) {
     const ReqDesc* d = b.reqs + blockIdx.x;
@@ -547,7 +735,10 @@ __global__ void __launch_bounds__(256) serve_prepare_kernel(BatchArgs b) {
     const int64_t base = (int64_t)blockIdx.y * PREPARE_CHUNK;
     for (int64_t e = base + threadIdx.x; e < base + PREPARE_CHUNK; e += blockDim.x) {
         if (e <= ni) d->rg.cnt[e] = 0;
-        if (d->do_predict && e < d->pred.n) predict_one(d->pred, e);
+        if (d->do_predict) {  // uniform across the workgroup
+            const float v = e < d->pred.n ? predict_one(d->pred, e) : 0.0f;
+            store_tile_max(d->pred, e, v);
+        }
     }
 }
 
@@ -555,7 +746,8 @@ __global__ void __launch_bounds__(256) serve_prepare_kernel(BatchArgs b) {
 // Prediction of every j-particle to the block time (FP64 Horner form of the
 // cubic Taylor series), and the j-records of each requested mode.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void predict_one(const PredictArgs& a, const int64_t k) {
+// Predicts particle k and returns the vabs of its records.
+__device__ __forceinline__ float predict_one(const PredictArgs& a, const int64_t k) {
     const double dt = a.tb - a.t[k];
     const double h = 0.5 * dt, t3 = dt * (1.0 / 3.0);
     double xp[3], vp[3];
@@ -596,12 +788,22 @@ __device__ __forceinline__ void predict_one(const PredictArgs& a, const int64_t 
         r.vx = vf[0]; r.vy = vf[1]; r.vz = vf[2]; r.vabs = vabs;
         a.f32[k] = r;
     }
+    return vabs;
+}
+
+// Largest vabs of the VTILE consecutive particles k0 .. k0 + VTILE - 1 held by
+// lanes that are VTILE-aligned within the wavefront (v = 0 for particles past
+// the end), stored by the first of those lanes.
+__device__ __forceinline__ void store_tile_max(const PredictArgs& a, const int64_t k, float v) {
+#pragma unroll
+    for (int d = VTILE / 2; d > 0; d >>= 1) v = fmaxf(v, __shfl_xor(v, d, VTILE));
+    if (k < a.n && (k % VTILE) == 0) a.tmax[k / VTILE] = v;
 }
 
 __global__ void __launch_bounds__(256) predict_kernel(PredictArgs a) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= a.n) return;
-    predict_one(a, k);
+    const float v = k < a.n ? predict_one(a, k) : 0.0f;
+    store_tile_max(a, k, v);
 }
 
 // Subset update of the stored state: entry e goes to particle idx[e].  An
@@ -658,12 +860,19 @@ __global__ void zero_u32_kernel(unsigned* p, int n) {
 // ---------------------------------------------------------------------------
 template <int MODE, int IPL>
 static hipError_t launch_regf_t(int wpb, const RegfArgs& a, hipStream_t st) {
-    const int groups = (a.ni + 64 * IPL - 1) / (64 * IPL);
+    if (a.jl_shift < 0 || a.jl_shift > 6 || (a.jl_shift > 0 && IPL != 1))
+        return hipErrorInvalidValue;
+    const int gsize = regf_group_size(IPL, a.jl_shift);
+    const int groups = (a.ni + gsize - 1) / gsize;
     const int gblocks = (groups + wpb - 1) / wpb;
     const long long blocks = (long long)gblocks * a.nslices;
     if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((regf_kernel<MODE, IPL>), dim3((unsigned)blocks), dim3(64 * wpb), 0, st,
-                       a, gblocks);
+    if (a.jl_shift > 0)
+        hipLaunchKernelGGL((regf_lanes_kernel<MODE>), dim3((unsigned)blocks), dim3(64 * wpb), 0,
+                           st, a, gblocks);
+    else
+        hipLaunchKernelGGL((regf_kernel<MODE, IPL>), dim3((unsigned)blocks), dim3(64 * wpb), 0,
+                           st, a, gblocks);
     return hipGetLastError();
 }
 
@@ -683,7 +892,7 @@ hipError_t launch_regf(int mode, int ipl, int wpb, const RegfArgs& a, hipStream_
 hipError_t launch_finalize(const FinalArgs& a, hipStream_t s) {
     if (a.ni <= 0) return hipSuccess;
     if (a.caps > MAX_CAPS) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(finalize_kernel, dim3((a.ni + 63) / 64), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)final_blocks(a.ni)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -18,7 +18,7 @@
 // callback at the end of each batch's stream work stamps its requests and
 // frees their memory and clusters.
 //
-// A request's slicing (make_plan with one i per lane) and its summation
+// A request's slicing (make_plan without two i per lane) and its summation
 // order depend only on the request, so its results are bit-identical alone
 // and in any mix.
 #include "nb6_context.h"
@@ -268,6 +268,10 @@ class Engine {
                 if (int rc = ensure(c_, r->cl->rec[r->mi], (size_t)r->cl->n * rec_size(r->mi)))
                     return rc;
             }
+            if (!r->cl->tmax.p) {
+                if (int rc = ensure(c_, r->cl->tmax, (size_t)vtiles(r->cl->n) * sizeof(float)))
+                    return rc;
+            }
             r->plan = make_plan(c_, r->cl->n, ni, 1);
         }
         r->bytes = carve(r.get(), nullptr);
@@ -470,6 +474,7 @@ class Engine {
             d.pred.ff = r->mi == MODE_FF ? (RecFF*)cl->rec[MODE_FF].p : nullptr;
             d.pred.f64 = r->mi == MODE_F64 ? (RecF64*)cl->rec[MODE_F64].p : nullptr;
             d.pred.f32 = r->mi == MODE_F32 ? (RecF32*)cl->rec[MODE_F32].p : nullptr;
+            d.pred.tmax = (float*)cl->tmax.p;
             d.pred.status = status;
             const Plan& p = r->plan;
             d.rg.rec = cl->rec[r->mi].p;
@@ -478,6 +483,8 @@ class Engine {
             d.rg.ni = ni;
             d.rg.slice_len = p.slice_len;
             d.rg.nslices = p.nslices;
+            d.rg.jl_shift = p.jl_shift;
+            d.rg.tmax = (const float*)cl->tmax.p;
             d.rg.part = r->part; d.rg.cnt = r->cnt; d.rg.lst = r->lst;
             d.rg.caps = r->rq.cap + 1;
             d.rg.status = status;
@@ -491,11 +498,12 @@ class Engine {
             d.ov.dtr = r->d_dtr; d.ov.list = r->d_list; d.ov.cap = r->rq.cap;
             d.ov.ovf_count = r->cnt + ni; d.ov.ovf_list = r->ovf;
             d.mode = r->mi;
-            d.groups = (ni + 63) / 64;
+            const int gsize = regf_group_size(1, p.jl_shift);
+            d.groups = (ni + gsize - 1) / gsize;
             d.item0 = item_in_mode;
             d.blk0 = blk0;
             item_in_mode += (long long)d.groups * p.nslices;
-            blk0 += (ni + 63) / 64;
+            blk0 += final_blocks(ni);
             chunk_need = std::max<int64_t>(chunk_need, std::max<int64_t>(cl->n, ni + 1));
         }
         HIP_TRY(nullptr, hipMemcpyAsync(sl.dev_desc, sl.host_desc, nreq * sizeof(ReqDesc),

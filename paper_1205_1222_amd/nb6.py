@@ -47,6 +47,7 @@ NB6_MAX_CAP = 1023
 EXPORTED = [
     "nb6_create", "nb6_destroy", "nb6_last_error", "nb6_load_particles",
     "nb6_predict_j", "nb6_regular_force", "nb6_sync_status", "nb6_last_slices",
+    "nb6_last_plan",
     "nb6_get_predicted", "nb6_kernel_times", "nb6_submit", "nb6_poll",
 ]
 
@@ -56,7 +57,7 @@ NB6_OPT_TIMING = 1
 class nb6_options(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int), ("slice_hint", ctypes.c_int),
                 ("hbm_budget", ctypes.c_int64), ("flags", ctypes.c_int),
-                ("ipl_hint", ctypes.c_int)]
+                ("ipl_hint", ctypes.c_int), ("jl_hint", ctypes.c_int)]
 
 
 class nb6_request(ctypes.Structure):
@@ -100,6 +101,7 @@ def lib():
         L.nb6_last_error.argtypes = [vp]
         L.nb6_last_error.restype = ctypes.c_char_p
         L.nb6_last_slices.argtypes = [vp]
+        L.nb6_last_plan.argtypes = [vp, vp]
         L.nb6_load_particles.argtypes = [vp, ctypes.c_int, i64, vp, vp, vp, vp, vp, vp, vp,
                                          ctypes.c_int, vp]
         L.nb6_predict_j.argtypes = [vp, ctypes.c_int, ctypes.c_double, ctypes.c_int, vp]
@@ -158,9 +160,9 @@ def check(ctx, rc, allow=(NB6_OK,)):
 
 
 # ---- the C entry points ---------------------------------------------------
-def nb6_create(device=0, slice_hint=0, hbm_budget=0, flags=0, ipl_hint=0):
+def nb6_create(device=0, slice_hint=0, hbm_budget=0, flags=0, ipl_hint=0, jl_hint=0):
     h = ctypes.c_void_p()
-    opt = nb6_options(device, slice_hint, hbm_budget, flags, ipl_hint)
+    opt = nb6_options(device, slice_hint, hbm_budget, flags, ipl_hint, jl_hint)
     rc = lib().nb6_create(ctypes.byref(h), ctypes.byref(opt))
     if rc != NB6_OK:
         raise NB6Error(rc, "nb6_create failed")
@@ -177,6 +179,15 @@ def nb6_last_error(ctx):
 
 def nb6_last_slices(ctx):
     return lib().nb6_last_slices(ctx)
+
+
+def nb6_last_plan(ctx):
+    """(i per lane, lanes per i, slices, j per slice) of the last force call."""
+    out = (ctypes.c_int * 4)()
+    rc = lib().nb6_last_plan(ctx, out)
+    if rc != NB6_OK:
+        raise NB6Error(rc, "nb6_last_plan failed")
+    return tuple(out)
 
 
 def nb6_load_particles(ctx, cluster, n, m, x, v, a, jerk, t, idx=None,

@@ -147,6 +147,41 @@ def test_ragged_sizes_and_slicings(ctx):
             nb6.nb6_destroy(c2)
 
 
+def test_lanes_per_i(ctx):
+    """Small blocks give each i several lanes (j split across an i's lanes,
+    butterfly sum at the end): automatic plans for blocks of 1..300 and
+    forced lane counts on a ragged block and ragged slices."""
+    nb6 = _nb6()
+    cfg = config(2)
+    cl = cfg["cluster"]
+    load(ctx, cl)
+    rng = np.random.Generator(np.random.PCG64(11))
+    for ni in (1, 2, 3, 5, 31, 64, 100, 200, 300):
+        idx = np.sort(rng.choice(cl.n, ni, replace=False)).astype(np.int32)
+        check_mode(ctx, cl, idx, "ff", f"lanes_auto_n{ni}")
+        ipl, lanes, slices, slen = nb6.nb6_last_plan(ctx)
+        print("plan", ni, ipl, lanes, slices, slen, flush=True)
+        assert ipl == 1
+        assert lanes == (64 if ni <= 64 else 32 if ni <= 128 else 16 if ni <= 256 else 1)
+        assert slen >= 32 * lanes and slices * slen >= cl.n
+    idx = np.sort(rng.choice(cl.n, 3, replace=False)).astype(np.int32)
+    for mode in ("fp64", "fp32"):
+        check_mode(ctx, cl, idx, mode, f"lanes_auto_n3_{mode}")
+    idx = np.sort(rng.choice(cl.n, 130, replace=False)).astype(np.int32)
+    ref = oracle_ref(cl, idx)
+    for jl, hint in ((2, 0), (16, 3), (64, 0), (64, 7)):
+        c2 = nb6.nb6_create(0, jl_hint=jl, slice_hint=hint)
+        try:
+            load(c2, cl)
+            check_mode(c2, cl, idx, "ff", f"lanes_forced{jl}_s{hint}", ref=ref)
+            assert nb6.nb6_last_plan(c2)[1] == jl
+        finally:
+            nb6.nb6_destroy(c2)
+    for bad in ({"jl_hint": 3}, {"jl_hint": 128}, {"jl_hint": 4, "ipl_hint": 2}):
+        with pytest.raises(nb6.NB6Error):
+            nb6.nb6_create(0, **bad)
+
+
 def test_neighbour_overflow_and_cap(ctx):
     nb6 = _nb6()
     cfg = config(1)
