@@ -58,7 +58,9 @@ void release(DevBuf& b) {
 
 Plan make_plan(const nb6_ctx* c, int64_t n, int64_t ni, int ipl) {
     Plan p;
-    p.ipl = ipl > 0 ? ipl : c->ipl_hint > 0 ? c->ipl_hint : (ni >= 16384 ? 2 : 1);
+    // two i per lane once every lane has work for several slices' worth of
+    // j (measured: better from 4096 active particles on, at N = 2^17 and 2^20)
+    p.ipl = ipl > 0 ? ipl : c->ipl_hint > 0 ? c->ipl_hint : (ni >= 4096 ? 2 : 1);
     // Slices are at least 256 j-particles long, and give each lane at least
     // 32 of them.
     auto max_slices = [&](int sh) {
@@ -99,12 +101,15 @@ Plan make_plan(const nb6_ctx* c, int64_t n, int64_t ni, int ipl) {
     s = std::max<int64_t>(1, std::min<int64_t>(s, c->slice_hint > 0 ? (n + 255) / 256
                                                                    : max_slices(sh)));
     s = std::min<int64_t>(s, 65535);
-    // a multiple of 8 lets the force kernel keep each slice on one XCD
-    if (c->slice_hint <= 0 && s >= 8) s = s / 8 * 8;
+    // a multiple of 8 lets the force kernel keep each slice on one XCD; the
+    // count is kept even when rounding the length up to whole tiles leaves
+    // the last slices empty (their partials are zero)
+    const bool xcd_split = c->slice_hint <= 0 && s >= 8;
+    if (xcd_split) s = s / 8 * 8;
     int64_t len = (n + s - 1) / s;
     len = (len + VTILE - 1) / VTILE * VTILE;
     p.slice_len = (int)len;
-    p.nslices = (int)((n + len - 1) / len);
+    p.nslices = xcd_split ? (int)s : (int)((n + len - 1) / len);
     return p;
 }
 

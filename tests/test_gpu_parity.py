@@ -346,6 +346,41 @@ def test_config3_full_size_sampled(ctx, block):
     assert s.get("acc_rel_max", 0.0) <= 1e-6 and s.get("jerk_rel_max", 0.0) <= 1e-6, s
 
 
+@pytest.mark.parametrize("mode", ["ff", "fp64", "fp32"])
+@pytest.mark.parametrize("block", ["random4096", "all"])
+def test_config5_full_size_sampled(ctx, block, mode):
+    """N = 2^20, ~100 neighbours, in the three coordinate modes, in the launch
+    configuration the benchmark times; the oracle checks 256 sampled i."""
+    nb6 = _nb6()
+    cfg = config(5)
+    cl = cfg["cluster"]
+    idx = cfg["blocks"][block]
+    load(ctx, cl)
+    cap = 256
+    acc, jerk, nnb, lst, rc = nb6.regular_force_host(ctx, 0, idx, cl.h2[idx], cl.dtr[idx],
+                                                     MODES[mode], cap)
+    rng = np.random.Generator(np.random.PCG64(6))
+    samp = np.sort(rng.choice(len(idx), 256, replace=False))
+    xp, vp = oracle.predict(cl.x, cl.v, cl.a, cl.jerk, cl.t, cl.tb)
+    si = idx[samp]
+    ref = oracle.regular_force(cl.m, xp, vp, si, cl.h2[si], cl.dtr[si], lcap=4096)
+    c = compare(acc[samp], jerk[samp], nnb[samp], lst[samp], cap, ref, cl.m, xp, vp, si,
+                cl.h2[si], cl.dtr[si])
+    s = c.summary()
+    s["slices"] = nb6.nb6_last_slices(ctx)
+    _record(f"C5_{block}_{mode}", s)
+    del acc, jerk, nnb, lst
+    assert c.incomplete == 0
+    if mode != "fp32":
+        assert c.list_mismatch == 0 and c.nnb_mismatch == 0, c.mismatches[:10]
+    else:
+        assert c.list_mismatch <= len(si) // 100, c.mismatches[:10]
+    assert s["acc_scaled_max"] <= TOL_SCALED[mode] and s["jerk_scaled_max"] <= TOL_SCALED[mode], s
+    if TOL_REL[mode] is not None:
+        assert s.get("acc_rel_max", 0.0) <= TOL_REL[mode], s
+        assert s.get("jerk_rel_max", 0.0) <= TOL_REL[mode], s
+
+
 @pytest.mark.parametrize("n", [1024, 1500])
 def test_everything_neighbour_long_lists(ctx, n):
     """h -> infinity: every j is a neighbour.  N = 1024 fills the largest list
