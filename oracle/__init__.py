@@ -1,4 +1,5 @@
-"""FP64 CPU oracle for the Ahmad-Cohen regular force (test infrastructure).
+"""FP64 CPU oracle for the Ahmad-Cohen regular and irregular forces (test
+infrastructure).
 
 Only the test suite, the smoke check and the CPU-baseline leg of the
 benchmark may import this package.  The GPU library never does, and this
@@ -14,6 +15,8 @@ from .oracle import (  # noqa: F401
     predict,
     regular_force,
     pair_terms,
+    irregular_force,
     max_threads,
     OracleResult,
+    IrregularResult,
 )

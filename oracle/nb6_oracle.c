@@ -1,6 +1,6 @@
 /*
- * nb6_oracle.c -- FP64 CPU oracle for the regular force of the Ahmad-Cohen
- * neighbour scheme (Nitadori & Aarseth 2012, "Accelerating NBODY6 with
+ * nb6_oracle.c -- FP64 CPU oracle for the regular and irregular forces of the
+ * Ahmad-Cohen neighbour scheme (Nitadori & Aarseth 2012, "Accelerating NBODY6 with
  * Graphics Processing Units").
  *
  * TEST INFRASTRUCTURE ONLY.  This file is the reference that the GPU library
@@ -27,6 +27,11 @@
  *   - nb6o_pair_terms: the same pair quantities for an explicit list of
  *     (i, j) pairs; the tests use it to treat pairs that sit on the
  *     neighbour-radius boundary.
+ *
+ *   - nb6o_irregular_force: the irregular force and its time derivative of
+ *     section 3.3 step 4, the sums over the entries of each active
+ *     particle's neighbour list L_i (the quantity the irregular-force
+ *     library of section 3.5 returns for a list of active particles).
  *
  * Readings of the paper taken here (each is listed with its reason in the
  * design notes of the repository):
@@ -223,6 +228,87 @@ void nb6o_pair_terms(int64_t np, const int32_t *pi, const int32_t *pj,
             djrk[3 * p + c] = m[j] * (V[c] / r3 - 3.0 * rv * R[c] / r5);
         }
     }
+}
+
+/* ---------------------------------------------------------------------- */
+/* Irregular force and its derivative over neighbour lists                 */
+/* (section 3.3 step 4; the irregular-force library of section 3.5)        */
+/* ---------------------------------------------------------------------- */
+/*
+ * For each active i = idx[q] and every entry j of its list L_i:
+ *   F_I,i  = sum_{j in L_i} m_j R_ij / |R_ij|^3
+ *   dF_I,i = sum_{j in L_i} m_j (V_ij / |R_ij|^3
+ *                                - 3 (R_ij . V_ij) R_ij / |R_ij|^5)
+ * with R_ij = R_j - R_i and V_ij = V_j - V_i of the predicted state.
+ * Inputs
+ *   n, m[n], xp[n][3], vp[n][3]   predicted state of the cluster
+ *   ni, idx[ni]                   active particles (0 <= idx < n)
+ *   cnt[ni]                       entries of each list (0 <= cnt <= lcap)
+ *   list[ni][lcap]                the entries (0 <= entry < n, any order)
+ * An entry equal to i is skipped: L_i of section 3.3 step 6 never holds i,
+ * so a list that does gets no self-term.  Duplicated entries count twice.
+ * Outputs
+ *   acc[ni][3], jrk[ni][3]        F_I and dF_I
+ *   sa[ni], sj[ni]                sums of m_j / r^2 and of
+ *                                 m_j (|V| / r^3 + 3 |R.V| / r^4) over the
+ *                                 same terms (may be NULL)
+ * Returns 0, -1 for an index (idx or a list entry) outside [0, n), -3 for a
+ * count outside [0, lcap]; nothing is computed then.
+ */
+int nb6o_irregular_force(int64_t n, const double *m, const double *xp,
+                         const double *vp, int64_t ni, const int32_t *idx,
+                         const int32_t *cnt, const int32_t *list, int64_t lcap,
+                         double *acc, double *jrk, double *sa, double *sj,
+                         int nthreads)
+{
+    for (int64_t q = 0; q < ni; ++q) {
+        if (idx[q] < 0 || idx[q] >= n) return -1;
+        if (cnt[q] < 0 || cnt[q] > lcap) return -3;
+        for (int64_t e = 0; e < cnt[q]; ++e)
+            if (list[q * lcap + e] < 0 || list[q * lcap + e] >= n) return -1;
+    }
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t q = 0; q < ni; ++q) {
+        const int64_t i = idx[q];
+        nsum A[3] = {{0, 0}, {0, 0}, {0, 0}};
+        nsum J[3] = {{0, 0}, {0, 0}, {0, 0}};
+        nsum SA = {0, 0}, SJ = {0, 0};
+        for (int64_t e = 0; e < cnt[q]; ++e) {
+            const int64_t j = list[q * lcap + e];
+            if (j == i) continue;
+            const double mj = m[j];
+            double Rij[3], Vij[3];
+            for (int c = 0; c < 3; ++c) {
+                Rij[c] = xp[3 * j + c] - xp[3 * i + c];
+                Vij[c] = vp[3 * j + c] - vp[3 * i + c];
+            }
+            double d2 = Rij[0] * Rij[0] + Rij[1] * Rij[1] + Rij[2] * Rij[2];
+            double d = sqrt(d2);
+            double d3 = d2 * d;
+            double d5 = d3 * d2;
+            double rdotv = Rij[0] * Vij[0] + Rij[1] * Vij[1] + Rij[2] * Vij[2];
+            for (int c = 0; c < 3; ++c) {
+                nsum_add(&A[c], mj * Rij[c] / d3);
+                nsum_add(&J[c], mj * (Vij[c] / d3 - 3.0 * rdotv * Rij[c] / d5));
+            }
+            double vabs = sqrt(Vij[0] * Vij[0] + Vij[1] * Vij[1] + Vij[2] * Vij[2]);
+            nsum_add(&SA, mj / d2);
+            nsum_add(&SJ, mj * (vabs / d3 + 3.0 * fabs(rdotv) / (d2 * d2)));
+        }
+        for (int c = 0; c < 3; ++c) {
+            acc[3 * q + c] = nsum_get(&A[c]);
+            jrk[3 * q + c] = nsum_get(&J[c]);
+        }
+        if (sa) sa[q] = nsum_get(&SA);
+        if (sj) sj[q] = nsum_get(&SJ);
+    }
+    return 0;
 }
 
 /* Number of OpenMP threads a parallel region of this library will use. */

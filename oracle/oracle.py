@@ -58,6 +58,10 @@ def _bind(lib):
     lib.nb6o_regular_force.restype = ctypes.c_int
     lib.nb6o_pair_terms.argtypes = [i64, i32, i32, d, d, d, d, d, d, d]
     lib.nb6o_pair_terms.restype = None
+    lib.nb6o_irregular_force.argtypes = [
+        i64, d, d, d, i64, i32, i32, i32, i64, d, d, d, d, ctypes.c_int,
+    ]
+    lib.nb6o_irregular_force.restype = ctypes.c_int
     lib.nb6o_max_threads.argtypes = []
     lib.nb6o_max_threads.restype = ctypes.c_int
     return lib
@@ -152,3 +156,41 @@ def pair_terms(pi, pj, dtr, m, xp, vp, lib=None):
     lib.nb6o_pair_terms(npair, _pi(pi), _pi(pj), _pd(dtr), _pd(m), _pd(xp),
                         _pd(vp), _pd(rmin), _pd(dacc), _pd(djrk))
     return rmin, dacc, djrk
+
+
+@dataclass
+class IrregularResult:
+    acc: np.ndarray      # [ni, 3]
+    jerk: np.ndarray     # [ni, 3]
+    sa: np.ndarray       # [ni] sum of m/r^2 over the list
+    sj: np.ndarray       # [ni] jerk scale over the list
+
+
+def irregular_force(m, xp, vp, idx, lists, nthreads=0, lib=None):
+    """Irregular force and its derivative of the active set ``idx`` over the
+    neighbour lists ``lists`` (one integer sequence per active particle)."""
+    lib = lib or _load()
+    n = len(m)
+    m = _f64(m, (n,))
+    xp = _f64(xp, (n, 3))
+    vp = _f64(vp, (n, 3))
+    idx = np.ascontiguousarray(idx, dtype=np.int32)
+    ni = len(idx)
+    if len(lists) != ni:
+        raise ValueError("one list per active particle")
+    cnt = np.array([len(l) for l in lists], dtype=np.int32)
+    lcap = max(1, int(cnt.max()) if ni else 1)
+    lst = np.zeros((ni, lcap), dtype=np.int32)
+    for q, l in enumerate(lists):
+        lst[q, : len(l)] = l
+    acc = np.zeros((ni, 3))
+    jrk = np.zeros((ni, 3))
+    sa = np.zeros(ni)
+    sj = np.zeros(ni)
+    rc = lib.nb6o_irregular_force(
+        n, _pd(m), _pd(xp), _pd(vp), ni, _pi(idx), _pi(cnt), _pi(lst), lcap,
+        _pd(acc), _pd(jrk), _pd(sa), _pd(sj), int(nthreads),
+    )
+    if rc != 0:
+        raise ValueError(f"oracle rejected its input (code {rc})")
+    return IrregularResult(acc, jrk, sa, sj)

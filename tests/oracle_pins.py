@@ -1,5 +1,9 @@
 """Pins for the FP64 oracle: checks against facts the paper and mathematics fix.
 
+(The irregular-force pins at the end tie that function to the hand-derived
+golden values, to the pinned regular force through the partition of section
+3.3, to Newton's third law and to a finite-difference jerk.)
+
 Each ``pin_*`` function takes the ctypes handle of an oracle build (``None``
 for the default build) and raises ``AssertionError`` when the oracle
 disagrees with:
@@ -250,6 +254,106 @@ def pin_scales_and_truncation(lib=None):
     assert np.array_equal(short.acc, full.acc)
 
 
+# --------------------------------------------------------------------------
+# Irregular force (section 3.3 step 4)
+# --------------------------------------------------------------------------
+def pin_irregular_golden(lib=None):
+    """With every other particle listed, the irregular force is the whole sum:
+    the hand-derived values of the golden cases that have no neighbours."""
+    for c in json.load(open(GOLDEN))["force_cases"]:
+        if any(c["lists"]):
+            continue
+        m = np.array(c["m"], float)
+        xp = np.array(c["x"], float)
+        vp = np.array(c["v"], float)
+        n = len(m)
+        act = list(c["active"])
+        lists = [[j for j in range(n) if j != i] for i in act]
+        r = oracle.irregular_force(m, xp, vp, act, lists, lib=lib)
+        assert _close(r.acc, c["acc"], 1e-14), (c["name"], r.acc, c["acc"])
+        if c["jerk"] != "skip":
+            assert _close(r.jerk, c["jerk"], 1e-14), (c["name"], r.jerk, c["jerk"])
+
+
+def pin_irregular_complements_regular(lib=None):
+    """Section 3.3 splits the force: regular over the non-neighbours plus
+    irregular over the list L_i equals the regular force with no neighbour
+    at all (h -> 0), for any radius and time-step."""
+    cl = make_cluster(300, 17, masses="imf", stored_state=False, k_nb=12)
+    n = cl.n
+    idx = np.arange(0, n, 3)
+    full = oracle.regular_force(cl.m, cl.x, cl.v, idx, 1e-300, 0.0, lcap=4, lib=lib)
+    assert full.nnb.max() == 0
+    for h2, dtr in ((cl.h2[idx], cl.dtr[idx]), (cl.h2[idx] * 4.0, 0.0)):
+        reg = oracle.regular_force(cl.m, cl.x, cl.v, idx, h2, dtr, lcap=n, lib=lib)
+        assert reg.nnb.sum() > len(idx)
+        irr = oracle.irregular_force(cl.m, cl.x, cl.v, idx, reg.lists, lib=lib)
+        for a, b, full_q, sc in ((reg.acc, irr.acc, full.acc, full.sa),
+                                 (reg.jerk, irr.jerk, full.jerk, full.sj)):
+            err = np.linalg.norm(a + b - full_q, axis=1) / sc
+            assert err.max() < 1e-13, err.max()
+        # the magnitude sums split the same way
+        assert np.all(np.abs(reg.sa + irr.sa - full.sa) <= 1e-13 * full.sa)
+        assert np.all(np.abs(reg.sj + irr.sj - full.sj) <= 1e-13 * full.sj)
+
+
+def pin_irregular_momentum(lib=None):
+    """Symmetric lists (uniform h, dt_reg = 0, all active): sum m F_I = 0 and
+    sum m dF_I/dt = 0 (Newton's third law within the neighbour spheres)."""
+    cl = make_cluster(400, 23, masses="imf", stored_state=False, k_nb=10)
+    n = cl.n
+    idx = np.arange(n)
+    reg = oracle.regular_force(cl.m, cl.x, cl.v, idx, 0.2 ** 2, 0.0, lcap=n, lib=lib)
+    irr = oracle.irregular_force(cl.m, cl.x, cl.v, idx, reg.lists, lib=lib)
+    for q in (irr.acc, irr.jerk):
+        tot = (cl.m[:, None] * q).sum(0)
+        scale = (cl.m * np.linalg.norm(q, axis=1)).sum()
+        assert np.all(np.abs(tot) <= 1e-13 * scale), (tot, scale)
+
+
+def pin_irregular_fd_jerk(lib=None):
+    """dF_I/dt = d(F_I)/dt along straight-line drift with the lists held fixed."""
+    cl = make_cluster(200, 29, masses="imf", stored_state=False, k_nb=20)
+    n = cl.n
+    idx = np.arange(n)
+    z = np.zeros((n, 3))
+    reg = oracle.regular_force(cl.m, cl.x, cl.v, idx, cl.h2, 0.0, lcap=n, lib=lib)
+    base = oracle.irregular_force(cl.m, cl.x, cl.v, idx, reg.lists, lib=lib)
+    d = 1e-7
+    xp, _ = oracle.predict(cl.x, cl.v, z, z, np.zeros(n), d, lib=lib)
+    xm, _ = oracle.predict(cl.x, cl.v, z, z, np.zeros(n), -d, lib=lib)
+    ap = oracle.irregular_force(cl.m, xp, cl.v, idx, reg.lists, lib=lib).acc
+    am = oracle.irregular_force(cl.m, xm, cl.v, idx, reg.lists, lib=lib).acc
+    fd = (ap - am) / (2 * d)
+    has = base.sj > 0
+    assert has.sum() > n // 2
+    err = np.linalg.norm(fd - base.jerk, axis=1)[has] / base.sj[has]
+    assert err.max() < 1e-5, err.max()
+
+
+def pin_irregular_list_semantics(lib=None):
+    """Empty lists give zero; an entry equal to i adds nothing; the order of
+    the entries does not matter; a repeated entry counts twice."""
+    m, x, v, h2, dtr = _tiny_inputs(7, n=30)
+    n = len(m)
+    rng = np.random.default_rng(3)
+    idx = np.arange(n)
+    lists = [rng.choice([j for j in range(n) if j != i], 6, replace=False) for i in idx]
+    base = oracle.irregular_force(m, x, v, idx, lists, lib=lib)
+    assert np.all(base.sa > 0)
+    empty = oracle.irregular_force(m, x, v, idx, [[] for _ in idx], lib=lib)
+    assert np.all(empty.acc == 0) and np.all(empty.jerk == 0) and np.all(empty.sa == 0)
+    with_self = [np.concatenate([[i], l]) for i, l in zip(idx, lists)]
+    r = oracle.irregular_force(m, x, v, idx, with_self, lib=lib)
+    assert np.array_equal(r.acc, base.acc) and np.array_equal(r.jerk, base.jerk)
+    rev = oracle.irregular_force(m, x, v, idx, [l[::-1] for l in lists], lib=lib)
+    assert _close(rev.acc, base.acc, 1e-15) and _close(rev.jerk, base.jerk, 1e-15)
+    one = [l[:1] for l in lists]
+    r1 = oracle.irregular_force(m, x, v, idx, one, lib=lib)
+    r2 = oracle.irregular_force(m, x, v, idx, [np.concatenate([l, l]) for l in one], lib=lib)
+    assert _close(r2.acc, 2.0 * r1.acc, 1e-15) and _close(r2.jerk, 2.0 * r1.jerk, 1e-15)
+
+
 ALL_PINS = [  # roughly cheapest first
     pin_golden_forces,
     pin_pair_terms_golden,
@@ -261,4 +365,9 @@ ALL_PINS = [  # roughly cheapest first
     pin_momentum,
     pin_fd_jerk,
     pin_plummer_mean_field,
+    pin_irregular_golden,
+    pin_irregular_list_semantics,
+    pin_irregular_complements_regular,
+    pin_irregular_momentum,
+    pin_irregular_fd_jerk,
 ]

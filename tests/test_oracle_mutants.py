@@ -41,6 +41,22 @@ MUTANTS = {
     "pair_terms_jerk_sign": ("djrk[3 * p + c] = m[j] * (V[c] / r3 - 3.0 * rv * R[c] / r5);",
                              "djrk[3 * p + c] = m[j] * (V[c] / r3 + 3.0 * rv * R[c] / r5);"),
     "pair_terms_rmin_max": ("rmin[p] = sqrt((p2 < r2) ? p2 : r2);", "rmin[p] = sqrt((p2 < r2) ? r2 : p2);"),
+    # irregular force
+    "irr_R_sign": ("Rij[c] = xp[3 * j + c] - xp[3 * i + c];", "Rij[c] = xp[3 * i + c] - xp[3 * j + c];"),
+    "irr_V_sign": ("Vij[c] = vp[3 * j + c] - vp[3 * i + c];", "Vij[c] = vp[3 * i + c] - vp[3 * j + c];"),
+    "irr_mass_of_i": ("const double mj = m[j];", "const double mj = m[i];"),
+    "irr_drop_rv_term": ("mj * (Vij[c] / d3 - 3.0 * rdotv * Rij[c] / d5)", "mj * (Vij[c] / d3)"),
+    "irr_jerk_rv_sign": ("mj * (Vij[c] / d3 - 3.0 * rdotv * Rij[c] / d5)",
+                         "mj * (Vij[c] / d3 + 3.0 * rdotv * Rij[c] / d5)"),
+    "irr_d3_as_d2": ("double d3 = d2 * d;", "double d3 = d2;"),
+    "irr_d5_as_d4": ("double d5 = d3 * d2;", "double d5 = d2 * d2;"),
+    "irr_skip_first_entry": ("for (int64_t e = 0; e < cnt[q]; ++e) {\n            const int64_t j",
+                             "for (int64_t e = 1; e < cnt[q]; ++e) {\n            const int64_t j"),
+    "irr_last_entry_dropped": ("for (int64_t e = 0; e < cnt[q]; ++e) {\n            const int64_t j",
+                               "for (int64_t e = 0; e + 1 < cnt[q]; ++e) {\n            const int64_t j"),
+    "irr_self_not_skipped": ("const int64_t j = list[q * lcap + e];\n            if (j == i) continue;",
+                             "const int64_t j = list[q * lcap + e];"),
+    "irr_wrong_row": ("const int64_t j = list[q * lcap + e];", "const int64_t j = list[e];"),
 }
 
 
