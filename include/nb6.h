@@ -68,6 +68,10 @@ extern "C" {
 /* Largest neighbour-list capacity of nb6_regular_force. */
 #define NB6_MAX_CAP  1023
 
+/* Largest row of the neighbour lists a cluster stores for the irregular
+ * force (nb6_set_lists). */
+#define NB6_MAX_LIST_CAP  8192
+
 typedef struct nb6_ctx nb6_ctx;
 
 typedef struct nb6_options {
@@ -80,8 +84,9 @@ typedef struct nb6_options {
                               1, 2, 4, ..., 64: force it (not with ipl_hint 2) */
 } nb6_options;
 
-/* Record HIP events around every predictor, force and finalize launch so
- * that nb6_kernel_times() can report their GPU durations. */
+/* Record HIP events around every predictor, force, finalize and
+ * irregular-force launch so that nb6_kernel_times() can report their GPU
+ * durations. */
 #define NB6_OPT_TIMING 1
 
 /*
@@ -160,9 +165,9 @@ int nb6_regular_force(nb6_ctx *ctx, int cluster, int64_t n_i,
 /*
  * Wait for `stream` and return (and clear) the GPU-side validation state of
  * the context: NB6_OK, or NB6_ERR_DEVICE_INPUT when a DEVICE-mode call met
- * an out-of-range index, an h2 that is not a positive normal float, or a
- * non-finite predicted coordinate.  Results of such a call are NaN for the
- * offending i.
+ * an out-of-range index, an h2 that is not a positive normal float, a
+ * non-finite predicted coordinate, or an invalid neighbour list
+ * (nb6_set_lists).  Results of such a call are NaN for the offending i.
  */
 int nb6_sync_status(nb6_ctx *ctx, void *stream);
 
@@ -180,11 +185,54 @@ int nb6_get_predicted(nb6_ctx *ctx, int cluster, int dx_mode, double *x, double 
 /*
  * With NB6_OPT_TIMING: wait for the recorded launches and return, for the
  * launches since the previous call, ms[0] = total predictor time,
- * ms[1] = total force-kernel time, ms[2] = total finalize time, and
- * counts[0..2] = the number of launches of each.  The record is then cleared.
- * Errors: NB6_ERR_STATE when timing is off, NB6_ERR_HIP.
+ * ms[1] = total force-kernel time, ms[2] = total finalize time,
+ * ms[3] = total irregular-force time, and counts[0..3] = the number of
+ * launches of each (ms and counts hold 4 entries).  The record is then
+ * cleared.  Errors: NB6_ERR_STATE when timing is off, NB6_ERR_HIP.
  */
 int nb6_kernel_times(nb6_ctx *ctx, double *ms, int64_t *counts);
+
+/* ---- irregular force over stored neighbour lists ----------------------- */
+
+/*
+ * Replace the stored neighbour lists of particles idx_i[0..n_i) of the
+ * cluster.  The library keeps one list per particle between regular steps
+ * and the host sends a particle's list after a regular step that changed it
+ * (section 3.5; Appendix C sends each new list after the regular force of
+ * its block).  Row k of `list` holds nnb_i[k] entries, list[k*cap + e] for
+ * e < nnb_i[k]: particle indices of the cluster, in any order (the list of
+ * nb6_regular_force is ascending and can be passed as it is, with the same
+ * cap).  An entry equal to the particle itself adds nothing.
+ *   1 <= cap <= NB6_MAX_LIST_CAP; 0 <= nnb_i[k] <= cap; the idx_i distinct.
+ * A full nb6_load_particles of the cluster empties every stored list; lists
+ * never set are empty.  HOST mode checks every argument (NB6_ERR_ARG); in
+ * DEVICE mode an out-of-range particle, count or entry is reported by
+ * nb6_sync_status (NB6_ERR_DEVICE_INPUT) and that particle's list is stored
+ * empty; repeated idx_i then leave one of their lists (which is undefined).
+ * Errors: NB6_ERR_ARG, NB6_ERR_STATE, NB6_ERR_NOMEM, NB6_ERR_HIP.
+ */
+int nb6_set_lists(nb6_ctx *ctx, int cluster, int64_t n_i, const int32_t *idx_i,
+                  const int32_t *nnb_i, const int32_t *list, int32_t cap,
+                  int mem_kind, void *stream);
+
+/*
+ * Irregular force and its time derivative (section 3.3 step 4) of the
+ * active particles idx_i[0..n_i) at time t_block, over their stored lists:
+ *   acc[q]  = sum_{j in L_i} m_j R_ij / |R_ij|^3
+ *   jerk[q] = sum_{j in L_i} m_j (V_ij / |R_ij|^3 - 3 (R_ij.V_ij) R_ij / |R_ij|^5)
+ * with i = idx_i[q], R_ij = R_j - R_i and V_ij = V_j - V_i.  Every particle
+ * needed is predicted to t_block from the stored state by the cubic Taylor
+ * series (section 3.3 step 3), inside the call and independently of
+ * nb6_predict_j; all arithmetic is FP64.  acc, jerk: [n_i][3] doubles.
+ * Repeated idx_i are allowed.  An empty list gives zeros.  Out-of-range
+ * idx_i: NB6_ERR_ARG (HOST) or NaN rows and NB6_ERR_DEVICE_INPUT from
+ * nb6_sync_status (DEVICE).  Errors: NB6_ERR_ARG, NB6_ERR_STATE,
+ * NB6_ERR_NOMEM, NB6_ERR_HIP, NB6_ERR_DEVICE_INPUT (HOST: a stored list that
+ * held an invalid entry).  n_i == 0 is a no-op.
+ */
+int nb6_irregular_force(nb6_ctx *ctx, int cluster, double t_block, int64_t n_i,
+                        const int32_t *idx_i, double *acc, double *jerk,
+                        int mem_kind, void *stream);
 
 /* ---- serving: continuously batched requests ---------------------------- */
 

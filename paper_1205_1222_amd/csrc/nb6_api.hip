@@ -255,6 +255,7 @@ int nb6_destroy(nb6_ctx* c) {
         if (!cl) continue;
         if (cl->state) (void)hipFree(cl->state);
         for (auto& r : cl->rec) release(r);
+        for (DevBuf* b : {&cl->tmax, &cl->nbl, &cl->nbc}) release(*b);
         if (cl->last_plain) (void)hipEventDestroy(cl->last_plain);
         if (cl->last_served) (void)hipEventDestroy(cl->last_served);
         delete cl;
@@ -276,7 +277,7 @@ int nb6_kernel_times(nb6_ctx* c, double* ms, int64_t* counts) {
     if (!c || !ms || !counts) return NB6_ERR_ARG;
     if (!c->timing) return fail(c, NB6_ERR_STATE, "context created without NB6_OPT_TIMING");
     HIP_TRY(c, hipSetDevice(c->device));
-    for (int k = 0; k < 3; ++k) { ms[k] = 0.0; counts[k] = 0; }
+    for (int k = 0; k < 4; ++k) { ms[k] = 0.0; counts[k] = 0; }
     int rc = NB6_OK;
     for (auto& t : c->timed) {
         float e = 0.0f;
@@ -337,9 +338,11 @@ int nb6_load_particles(nb6_ctx* c, int cluster, int64_t n, const double* m, cons
             if (cl->state) HIP_TRY(c, hipFree(cl->state));
             cl->state = nullptr;
             cl->n = 0;
-            // the predicted records are sized by n: reallocated on next use
+            // the predicted records and stored lists are sized by n:
+            // reallocated on next use
             for (DevBuf& b : cl->rec) release(b);
-            release(cl->tmax);
+            for (DevBuf* b : {&cl->tmax, &cl->nbl, &cl->nbc}) release(*b);
+            cl->lcap = 0;
             if (hipMalloc(&cl->state, (size_t)14 * n * sizeof(double)) != hipSuccess) {
                 (void)hipGetLastError();
                 cl->state = nullptr;
@@ -359,6 +362,8 @@ int nb6_load_particles(nb6_ctx* c, int cluster, int64_t n, const double* m, cons
         HIP_TRY(c, hipMemcpyAsync(cl->v, v, 3 * n * sizeof(double), kind, st));
         HIP_TRY(c, hipMemcpyAsync(cl->a, a, 3 * n * sizeof(double), kind, st));
         HIP_TRY(c, hipMemcpyAsync(cl->jk, jerk, 3 * n * sizeof(double), kind, st));
+        // a full load starts every stored neighbour list empty
+        if (cl->nbc.p) HIP_TRY(c, launch_zero_u32((unsigned*)cl->nbc.p, (int)n, st));
         if (mem_kind == NB6_MEM_HOST) HIP_TRY(c, hipStreamSynchronize(st));
         cl->pred_valid = 0;
         return NB6_OK;
@@ -635,6 +640,165 @@ int nb6_get_predicted(nb6_ctx* c, int cluster, int dx_mode, double* x, double* v
     return NB6_OK;
 }
 
+// Stored lists of a cluster exist (counts zeroed) and rows hold >= cap entries.
+static int ensure_lists(nb6_ctx* c, ClusterState* cl, int cap, hipStream_t st) {
+    const int64_t n = cl->n;
+    if (!cl->nbc.p) {
+        if (int rc = ensure(c, cl->nbc, (size_t)n * sizeof(int32_t))) return rc;
+        HIP_TRY(c, launch_zero_u32((unsigned*)cl->nbc.p, (int)n, st));
+    }
+    if (cap <= cl->lcap) return NB6_OK;
+    DevBuf grown;
+    if (int rc = ensure(c, grown, (size_t)n * cap * sizeof(int32_t))) return rc;
+    if (cl->lcap > 0) {
+        HIP_TRY(c, launch_copy_rows((const int32_t*)cl->nbl.p, cl->lcap, (int32_t*)grown.p, cap,
+                                    (const int32_t*)cl->nbc.p, n, st));
+        HIP_TRY(c, hipStreamSynchronize(st));  // the old rows are freed next
+    }
+    release(cl->nbl);
+    cl->nbl = grown;
+    cl->lcap = cap;
+    return NB6_OK;
+}
+
+int nb6_set_lists(nb6_ctx* c, int cluster, int64_t n_i, const int32_t* idx_i,
+                  const int32_t* nnb_i, const int32_t* list, int32_t cap, int mem_kind,
+                  void* stream) {
+    if (!c) return NB6_ERR_ARG;
+    c->err.clear();
+    std::lock_guard<std::mutex> lk(c->cluster_mu);
+    ClusterState* cl = nullptr;
+    if (int rc = get_cluster(c, cluster, &cl)) return rc;
+    PlainClaim claim;
+    if (int rc = claim.claim(c, cl, (hipStream_t)stream)) return rc;
+    static_assert(MAX_LIST_CAP == NB6_MAX_LIST_CAP, "stored-list limits disagree");
+    if (n_i < 0 || n_i > cl->n) return fail(c, NB6_ERR_ARG, "n_i = %lld", (long long)n_i);
+    if (cap < 1 || cap > MAX_LIST_CAP)
+        return fail(c, NB6_ERR_ARG, "cap = %d outside [1, %d]", cap, MAX_LIST_CAP);
+    if (mem_kind != NB6_MEM_HOST && mem_kind != NB6_MEM_DEVICE)
+        return fail(c, NB6_ERR_ARG, "bad mem_kind %d", mem_kind);
+    if (n_i == 0) return NB6_OK;
+    if (!idx_i || !nnb_i || !list) return fail(c, NB6_ERR_ARG, "null argument");
+    HIP_TRY(c, hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t n = cl->n;
+    const int ni = (int)n_i;
+    const int32_t* d_idx = idx_i;
+    const int32_t* d_nnb = nnb_i;
+    const int32_t* d_list = list;
+    if (mem_kind == NB6_MEM_HOST) {
+        std::vector<char> seen((size_t)n, 0);
+        for (int k = 0; k < ni; ++k) {
+            const int32_t p = idx_i[k];
+            if (p < 0 || p >= n)
+                return fail(c, NB6_ERR_ARG, "idx_i[%d] = %d out of range", k, p);
+            if (seen[p]) return fail(c, NB6_ERR_ARG, "particle %d listed twice", p);
+            seen[p] = 1;
+            if (nnb_i[k] < 0 || nnb_i[k] > cap)
+                return fail(c, NB6_ERR_ARG, "nnb_i[%d] = %d outside [0, %d]", k, nnb_i[k], cap);
+            for (int e = 0; e < nnb_i[k]; ++e) {
+                const int32_t j = list[(size_t)k * cap + e];
+                if (j < 0 || j >= n)
+                    return fail(c, NB6_ERR_ARG, "list entry (%d, %d) = %d out of range", k, e, j);
+            }
+        }
+        int rc;
+        if ((rc = ensure(c, c->in_idx, ni * sizeof(int32_t))) ||
+            (rc = ensure(c, c->out_nnb, ni * sizeof(int32_t))) ||
+            (rc = ensure(c, c->out_list, (size_t)ni * cap * sizeof(int32_t))))
+            return rc;
+        HIP_TRY(c, hipMemcpyAsync(c->in_idx.p, idx_i, ni * sizeof(int32_t), hipMemcpyHostToDevice, st));
+        HIP_TRY(c, hipMemcpyAsync(c->out_nnb.p, nnb_i, ni * sizeof(int32_t), hipMemcpyHostToDevice, st));
+        HIP_TRY(c, hipMemcpyAsync(c->out_list.p, list, (size_t)ni * cap * sizeof(int32_t),
+                                  hipMemcpyHostToDevice, st));
+        d_idx = (const int32_t*)c->in_idx.p;
+        d_nnb = (const int32_t*)c->out_nnb.p;
+        d_list = (const int32_t*)c->out_list.p;
+    }
+    if (int rc = ensure_lists(c, cl, cap, st)) return rc;
+    SetListArgs sa{};
+    sa.n = n;
+    sa.idx = d_idx;
+    sa.ni = ni;
+    sa.nnb = d_nnb;
+    sa.list = d_list;
+    sa.cap = cap;
+    sa.nbl = (int32_t*)cl->nbl.p;
+    sa.nbc = (int32_t*)cl->nbc.p;
+    sa.lcap = cl->lcap;
+    sa.status = c->status;
+    HIP_TRY(c, launch_set_lists(sa, st));
+    if (mem_kind == NB6_MEM_HOST) HIP_TRY(c, hipStreamSynchronize(st));
+    return NB6_OK;
+}
+
+int nb6_irregular_force(nb6_ctx* c, int cluster, double t_block, int64_t n_i,
+                        const int32_t* idx_i, double* acc, double* jerk, int mem_kind,
+                        void* stream) {
+    if (!c) return NB6_ERR_ARG;
+    c->err.clear();
+    std::lock_guard<std::mutex> lk(c->cluster_mu);
+    ClusterState* cl = nullptr;
+    if (int rc = get_cluster(c, cluster, &cl)) return rc;
+    PlainClaim claim;
+    if (int rc = claim.claim(c, cl, (hipStream_t)stream)) return rc;
+    if (!std::isfinite(t_block)) return fail(c, NB6_ERR_ARG, "non-finite t_block");
+    if (n_i < 0 || n_i > INT32_MAX / 4) return fail(c, NB6_ERR_ARG, "n_i = %lld", (long long)n_i);
+    if (mem_kind != NB6_MEM_HOST && mem_kind != NB6_MEM_DEVICE)
+        return fail(c, NB6_ERR_ARG, "bad mem_kind %d", mem_kind);
+    if (n_i == 0) return NB6_OK;
+    if (!idx_i || !acc || !jerk) return fail(c, NB6_ERR_ARG, "null argument");
+    HIP_TRY(c, hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t n = cl->n;
+    const int ni = (int)n_i;
+    const int32_t* d_idx = idx_i;
+    double* d_acc = acc;
+    double* d_jerk = jerk;
+    if (mem_kind == NB6_MEM_HOST) {
+        for (int q = 0; q < ni; ++q)
+            if (idx_i[q] < 0 || idx_i[q] >= n)
+                return fail(c, NB6_ERR_ARG, "idx_i[%d] = %d out of range", q, idx_i[q]);
+        int rc;
+        if ((rc = ensure(c, c->in_idx, ni * sizeof(int32_t))) ||
+            (rc = ensure(c, c->out_acc, 3 * (size_t)ni * sizeof(double))) ||
+            (rc = ensure(c, c->out_jerk, 3 * (size_t)ni * sizeof(double))))
+            return rc;
+        HIP_TRY(c, hipMemcpyAsync(c->in_idx.p, idx_i, ni * sizeof(int32_t), hipMemcpyHostToDevice, st));
+        d_idx = (const int32_t*)c->in_idx.p;
+        d_acc = (double*)c->out_acc.p;
+        d_jerk = (double*)c->out_jerk.p;
+    }
+    if (int rc = ensure_lists(c, cl, 1, st)) return rc;  // no lists yet: all empty
+    IrrArgs ia{};
+    ia.n = n;
+    ia.m = cl->m; ia.t = cl->t; ia.x = cl->x; ia.v = cl->v; ia.a = cl->a; ia.jk = cl->jk;
+    ia.tb = t_block;
+    ia.idx = d_idx;
+    ia.ni = ni;
+    ia.nbl = (const int32_t*)cl->nbl.p;
+    ia.nbc = (const int32_t*)cl->nbc.p;
+    ia.lcap = cl->lcap;
+    ia.acc = d_acc;
+    ia.jerk = d_jerk;
+    ia.status = c->status;
+    {
+        TimedLaunch tl(c, 3, st);
+        HIP_TRY(c, launch_irregular(ia, st));
+        tl.done();
+    }
+    if (mem_kind == NB6_MEM_DEVICE) return NB6_OK;
+    HIP_TRY(c, hipMemcpyAsync(acc, d_acc, 3 * (size_t)ni * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(c, hipMemcpyAsync(jerk, d_jerk, 3 * (size_t)ni * sizeof(double), hipMemcpyDeviceToHost, st));
+    unsigned status[4];
+    HIP_TRY(c, hipMemcpyAsync(status, c->status, sizeof status, hipMemcpyDeviceToHost, st));
+    HIP_TRY(c, hipStreamSynchronize(st));
+    HIP_TRY(c, launch_zero_u32(c->status, 4, st));
+    if (status[0] & (ST_BAD_INDEX | ST_BAD_LIST))
+        return fail(c, NB6_ERR_DEVICE_INPUT, "GPU validation flagged 0x%x", status[0]);
+    return NB6_OK;
+}
+
 int nb6_sync_status(nb6_ctx* c, void* stream) {
     if (!c) return NB6_ERR_ARG;
     HIP_TRY(c, hipSetDevice(c->device));
@@ -644,7 +808,7 @@ int nb6_sync_status(nb6_ctx* c, void* stream) {
     HIP_TRY(c, hipStreamSynchronize(st));
     HIP_TRY(c, launch_zero_u32(c->status, 4, st));
     HIP_TRY(c, hipStreamSynchronize(st));
-    if (status[0] & (ST_BAD_INDEX | ST_BAD_H2 | ST_NONFINITE))
+    if (status[0] & (ST_BAD_INDEX | ST_BAD_H2 | ST_NONFINITE | ST_BAD_LIST))
         return fail(c, NB6_ERR_DEVICE_INPUT, "GPU validation flagged 0x%x", status[0]);
     return NB6_OK;
 }

@@ -27,6 +27,9 @@ struct ClusterState {
     double *m = nullptr, *t = nullptr, *x = nullptr, *v = nullptr, *a = nullptr, *jk = nullptr;
     DevBuf rec[3];             // j-records by mode index
     DevBuf tmax;               // max vabs per tile of VTILE records (any mode)
+    DevBuf nbl;                // stored neighbour lists [n][lcap] (irregular force)
+    DevBuf nbc;                // entries of each stored list [n]
+    int lcap = 0;
     int pred_valid = 0;        // NB6_DX_* bits whose records are current
     double t_pred = 0.0;
     // Owner of the cluster: 0 free, 1 a serving request in flight, -1 a plain
@@ -80,7 +83,7 @@ struct nb6_ctx {
     std::string err;
     nb6::Plan last_plan{0, 0, 0, 0, 0};
     bool timing = false;
-    struct Timed { int kind; hipEvent_t a, b; };
+    struct Timed { int kind; hipEvent_t a, b; };  // kind: 0 predict, 1 force, 2 finalize, 3 irregular
     std::vector<Timed> timed;                         // pending event pairs
     // Cluster states are shared with the serving queue's thread.
     std::mutex cluster_mu;

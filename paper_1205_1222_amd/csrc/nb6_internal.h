@@ -40,7 +40,21 @@ constexpr int VTILE = 32;
 __host__ __device__ inline long long vtiles(long long n) { return (n + VTILE - 1) / VTILE; }
 
 // Bits of the device status word.
-enum StatusBits { ST_BAD_INDEX = 1, ST_BAD_H2 = 2, ST_NONFINITE = 4, ST_OVERFLOW = 8 };
+enum StatusBits {
+    ST_BAD_INDEX = 1, ST_BAD_H2 = 2, ST_NONFINITE = 4, ST_OVERFLOW = 8, ST_BAD_LIST = 16
+};
+
+// Cubic Taylor prediction of one coordinate in FP64 Horner form with explicit
+// fused multiply-adds (section 3.3 step 3): h = dt/2, t3 = dt/3,
+//   xp = x + dt (v + h (a + t3 jk)),   vp = v + dt (a + h jk).
+// Every predictor of the library uses this one expression, so a particle
+// predicted to the same time gets the same bits everywhere.
+__device__ __forceinline__ void predict_coord(double dt, double h, double t3, double x,
+                                              double v, double a, double jk, double& xp,
+                                              double& vp) {
+    xp = fma(dt, fma(h, fma(t3, jk, a), v), x);
+    vp = fma(dt, fma(h, jk, a), v);
+}
 
 // Partial sums leave the force kernel as 6 FP64 components per (i, slice):
 // acc xyz, jerk xyz.
@@ -135,6 +149,51 @@ struct ScatterArgs {
     int64_t        limit; // cluster size; entries with idx outside [0, limit) are skipped
     unsigned*      status;
 };
+
+// ---------------------------------------------------------------------------
+// Irregular force over stored neighbour lists.
+// ---------------------------------------------------------------------------
+// Largest row of the stored neighbour lists.
+constexpr int MAX_LIST_CAP = 8192;
+
+struct IrrArgs {
+    int64_t        n;         // cluster size
+    const double*  m;         // stored state (structure of arrays, FP64)
+    const double*  t;
+    const double*  x;         // [n][3]
+    const double*  v;
+    const double*  a;
+    const double*  jk;
+    double         tb;        // block time
+    const int32_t* idx;       // [ni] active particles
+    int            ni;
+    const int32_t* nbl;       // [n][lcap] stored lists
+    const int32_t* nbc;       // [n] entries of each stored list
+    int            lcap;
+    double*        acc;       // [ni][3]
+    double*        jerk;      // [ni][3]
+    unsigned*      status;
+};
+
+struct SetListArgs {
+    int64_t        n;         // cluster size
+    const int32_t* idx;       // [ni] particles whose lists are replaced
+    int            ni;
+    const int32_t* nnb;       // [ni] entries of each new list
+    const int32_t* list;      // [ni][cap] the new lists
+    int            cap;
+    int32_t*       nbl;       // [n][lcap] storage
+    int32_t*       nbc;       // [n]
+    int            lcap;
+    unsigned*      status;
+};
+
+hipError_t launch_irregular(const IrrArgs& a, hipStream_t s);
+hipError_t launch_set_lists(const SetListArgs& a, hipStream_t s);
+// Copy the first cnt[p] entries of every row p from rows of src_cap entries
+// to rows of dst_cap entries (the stored lists grow).
+hipError_t launch_copy_rows(const int32_t* src, int src_cap, int32_t* dst, int dst_cap,
+                            const int32_t* cnt, int64_t n, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Serving: one descriptor per request of a fused batch.

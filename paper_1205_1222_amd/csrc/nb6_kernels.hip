@@ -754,10 +754,8 @@ __device__ __forceinline__ float predict_one(const PredictArgs& a, const int64_t
     bool finite = isfinite(dt);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        const double x = a.x[3 * k + c], v = a.v[3 * k + c];
-        const double acc = a.a[3 * k + c], jk = a.jk[3 * k + c];
-        xp[c] = fma(dt, fma(h, fma(t3, jk, acc), v), x);
-        vp[c] = fma(dt, fma(h, jk, acc), v);
+        predict_coord(dt, h, t3, a.x[3 * k + c], a.v[3 * k + c], a.a[3 * k + c],
+                      a.jk[3 * k + c], xp[c], vp[c]);
         finite = finite && isfinite(xp[c]) && isfinite(vp[c]);
     }
     const float m = (float)a.m[k];

@@ -43,12 +43,14 @@ NB6_DX_FP64 = 2
 NB6_DX_FP32 = 4
 NB6_DX_ALL = 7
 NB6_MAX_CAP = 1023
+NB6_MAX_LIST_CAP = 8192
 
 EXPORTED = [
     "nb6_create", "nb6_destroy", "nb6_last_error", "nb6_load_particles",
     "nb6_predict_j", "nb6_regular_force", "nb6_sync_status", "nb6_last_slices",
     "nb6_last_plan",
     "nb6_get_predicted", "nb6_kernel_times", "nb6_submit", "nb6_poll",
+    "nb6_set_lists", "nb6_irregular_force",
 ]
 
 NB6_OPT_TIMING = 1
@@ -112,6 +114,10 @@ def lib():
         L.nb6_submit.argtypes = [vp, ctypes.POINTER(nb6_request), ctypes.POINTER(ctypes.c_uint64)]
         L.nb6_poll.argtypes = [vp, ctypes.c_uint64, ctypes.c_int, ctypes.POINTER(nb6_ticket_info)]
         L.nb6_get_predicted.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp, ctypes.c_int, vp]
+        L.nb6_set_lists.argtypes = [vp, ctypes.c_int, i64, vp, vp, vp, ctypes.c_int32,
+                                    ctypes.c_int, vp]
+        L.nb6_irregular_force.argtypes = [vp, ctypes.c_int, ctypes.c_double, i64, vp, vp, vp,
+                                          ctypes.c_int, vp]
         for name in EXPORTED:
             if name != "nb6_last_error":
                 getattr(L, name).restype = ctypes.c_int
@@ -211,6 +217,19 @@ def nb6_regular_force(ctx, cluster, n_i, idx_i, h2_i, dtr_i, dx_mode, acc, jerk,
         _ptr(nblist, np.int32), cap, mem_kind, _stream(stream))
 
 
+def nb6_set_lists(ctx, cluster, n_i, idx_i, nnb_i, nblist, cap, mem_kind=NB6_MEM_HOST,
+                  stream=None):
+    return lib().nb6_set_lists(ctx, cluster, n_i, _ptr(idx_i, np.int32), _ptr(nnb_i, np.int32),
+                               _ptr(nblist, np.int32), cap, mem_kind, _stream(stream))
+
+
+def nb6_irregular_force(ctx, cluster, t_block, n_i, idx_i, acc, jerk, mem_kind=NB6_MEM_HOST,
+                        stream=None):
+    f = np.float64
+    return lib().nb6_irregular_force(ctx, cluster, float(t_block), n_i, _ptr(idx_i, np.int32),
+                                     _ptr(acc, f), _ptr(jerk, f), mem_kind, _stream(stream))
+
+
 def nb6_get_predicted(ctx, cluster, dx_mode, x, v, mem_kind=NB6_MEM_HOST, stream=None):
     f = np.float64
     return lib().nb6_get_predicted(ctx, cluster, dx_mode, _ptr(x, f), _ptr(v, f), mem_kind,
@@ -218,9 +237,10 @@ def nb6_get_predicted(ctx, cluster, dx_mode, x, v, mem_kind=NB6_MEM_HOST, stream
 
 
 def nb6_kernel_times(ctx):
-    """(ms[3], counts[3]) for predictor, force and finalize launches."""
-    ms = np.zeros(3)
-    counts = np.zeros(3, np.int64)
+    """(ms[4], counts[4]) for predictor, force, finalize and irregular-force
+    launches."""
+    ms = np.zeros(4)
+    counts = np.zeros(4, np.int64)
     rc = lib().nb6_kernel_times(ctx, ms.ctypes.data, counts.ctypes.data)
     check(ctx, rc)
     return ms, counts
@@ -267,3 +287,23 @@ def regular_force_host(ctx, cluster, idx_i, h2_i, dtr_i, dx_mode=NB6_DX_FF, cap=
                            nnb, lst if cap > 0 else None, cap, NB6_MEM_HOST)
     check(ctx, rc, (NB6_OK, NB6_WARN_NB_OVERFLOW))
     return acc, jerk, nnb, lst[:, :cap], rc
+
+
+def set_lists_host(ctx, cluster, idx_i, nnb_i, nblist):
+    """Host-memory nb6_set_lists: rows of ``nblist`` ([n_i, cap]) hold the first
+    ``nnb_i`` entries of each list."""
+    idx_i = np.ascontiguousarray(idx_i, dtype=np.int32)
+    nnb_i = np.ascontiguousarray(nnb_i, dtype=np.int32)
+    nblist = np.ascontiguousarray(nblist, dtype=np.int32)
+    check(ctx, nb6_set_lists(ctx, cluster, len(idx_i), idx_i, nnb_i, nblist,
+                             nblist.shape[1] if nblist.ndim == 2 else 1, NB6_MEM_HOST))
+
+
+def irregular_force_host(ctx, cluster, t_block, idx_i):
+    """Host-memory nb6_irregular_force; returns (acc, jerk)."""
+    idx_i = np.ascontiguousarray(idx_i, dtype=np.int32)
+    ni = len(idx_i)
+    acc = np.empty((ni, 3))
+    jerk = np.empty((ni, 3))
+    check(ctx, nb6_irregular_force(ctx, cluster, t_block, ni, idx_i, acc, jerk, NB6_MEM_HOST))
+    return acc, jerk
