@@ -109,7 +109,7 @@ def counter_summary(fetch_csv, write_csv, valu_csv, copy_mib, config_line, pairs
         flops = 64.0 * (valu["SQ_INSTS_VALU_ADD_F32"] + valu["SQ_INSTS_VALU_MUL_F32"] +
                         2.0 * valu["SQ_INSTS_VALU_FMA_F32"] + valu["SQ_INSTS_VALU_TRANS_F32"])
         machine["fp32_flop"] = flops
-    cmd = ("python3 bench.py --steps 2 --warmup 1 --no-serving --no-cpu-baseline "
+    cmd = ("python3 bench.py --steps 2 --warmup 1 --no-serving --no-cpu-baseline --no-irregular "
            f"--copy-mib {copy_mib}")
     lines = [
         "# Counters of the force kernel, Plummer N = 131072, all 131072 active (FF)",
@@ -384,6 +384,73 @@ def serving_leg(args, nb6, torch):
     }
 
 
+# Algorithmic bytes of the irregular force: per list entry the entry itself
+# and the stored FP64 state of j (m, t, x, v, a, jerk: 112 B); per active
+# particle its index, list count, stored state and the two output vectors.
+IRR_BYTES_PER_PAIR = 4 + 112
+IRR_BYTES_PER_I = 4 + 4 + 112 + 48
+HBM_PEAK_GBS = 8000.0
+
+
+def irregular_leg(args, nb6, torch, ctx, cl, idx_np, idx_d, nnb, lst):
+    """Irregular force (section 3.3 step 4) over the lists the last regular
+    call produced: nb6_set_lists for the block, then nb6_irregular_force of the
+    whole block and of smaller random sub-blocks; HIP-event kernel times."""
+    stream = torch.cuda.current_stream()
+    dev = idx_d.device
+    ni = len(idx_np)
+    cap = lst.shape[1]
+    cnt = torch.clamp(nnb, max=cap).contiguous()
+    nb6.nb6_kernel_times(ctx)
+    t0 = time.perf_counter()
+    nb6.check(ctx, nb6.nb6_set_lists(ctx, 0, ni, idx_d, cnt, lst, cap, nb6.NB6_MEM_DEVICE,
+                                     stream))
+    torch.cuda.synchronize()
+    set_ms = (time.perf_counter() - t0) * 1e3
+    pairs_all = int(cnt.sum().item())
+    acc = torch.empty((ni, 3), dtype=torch.float64, device=dev)
+    jerk = torch.empty_like(acc)
+    res = {"set_lists_ms": round(set_ms, 4), "list_cap": cap,
+           "mean_list": round(pairs_all / ni, 2), "blocks": []}
+    rng = np.random.Generator(np.random.PCG64(12051229))
+    cnt_h = cnt.cpu().numpy()
+    for size in sorted({1, 64, 1024, 16384, ni}):
+        if size > ni:
+            continue
+        sel = np.arange(ni) if size == ni else np.sort(rng.choice(ni, size, replace=False))
+        sub = torch.from_numpy(idx_np[sel].astype(np.int32)).to(dev)
+        pairs = int(cnt_h[sel].sum())
+        reps = max(5, min(200, int(3e7 / max(pairs, 1))))
+
+        def call():
+            nb6.check(ctx, nb6.nb6_irregular_force(ctx, 0, cl.tb, size, sub, acc[:size],
+                                                   jerk[:size], nb6.NB6_MEM_DEVICE, stream))
+        call()
+        torch.cuda.synchronize()
+        nb6.nb6_kernel_times(ctx)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            call()
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / reps
+        ms, counts = nb6.nb6_kernel_times(ctx)
+        k_ms = ms[3] / max(counts[3], 1)
+        byts = pairs * IRR_BYTES_PER_PAIR + size * IRR_BYTES_PER_I
+        res["blocks"].append({"N_i": size, "pairs": pairs, "call_us": round(wall * 1e6, 2),
+                              "kernel_us": round(k_ms * 1e3, 2),
+                              "gpairs_s": round(pairs / (k_ms * 1e-3) / 1e9, 3),
+                              "algorithmic_gb_s": round(byts / (k_ms * 1e-3) / 1e9, 1)})
+        log(f"bench: irregular N_i={size}: {pairs} pairs, kernel {k_ms * 1e3:.2f} us, "
+            f"call {wall * 1e6:.2f} us")
+    nb6.check(ctx, nb6.nb6_sync_status(ctx, stream))
+    whole = res["blocks"][-1]
+    res["roofline"] = {"bound": "hbm", "achieved": whole["algorithmic_gb_s"],
+                       "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": round(whole["algorithmic_gb_s"] / HBM_PEAK_GBS, 4),
+                       "traffic": None}
+    return res
+
+
 def block_sweep(args, cfg, nb6, torch, T, lanes=0, slices=None, max_ni=None, max_reps=200):
     """Force-call time for every block of the configuration (one JSON line each):
     wall time per call on a context without event timing (back-to-back calls on
@@ -475,6 +542,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-irregular", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=20000)
     ap.add_argument("--serve-calibrate", type=int, default=300)
     ap.add_argument("--serve-cap", type=int, default=128)
@@ -646,6 +714,8 @@ def main():
                 100.0 * rec["fp32_flop"] / (regf_ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, 2)
     gpu_out = (acc.cpu().numpy(), jerk.cpu().numpy(), nnb.cpu().numpy(),
                lst[:, :args.cap].cpu().numpy())
+    if not args.no_irregular:
+        out["irregular"] = irregular_leg(args, nb6, torch, ctx, cl, idx_np, idx_d, nnb, lst)
     nb6.nb6_destroy(ctx)
     del acc, jerk, nnb, lst
     if not args.no_serving:

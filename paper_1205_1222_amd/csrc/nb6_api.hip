@@ -329,9 +329,6 @@ int nb6_load_particles(nb6_ctx* c, int cluster, int64_t n, const double* m, cons
             !finite_all(v, 3 * n) || !finite_all(a, 3 * n) || !finite_all(jerk, 3 * n))
             return fail(c, NB6_ERR_ARG, "non-finite value in the particle state");
     }
-    const hipMemcpyKind kind =
-        mem_kind == NB6_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
-
     if (!idx) {  // full load
         if (cl->n != n) {
             HIP_TRY(c, hipDeviceSynchronize());
@@ -343,54 +340,39 @@ int nb6_load_particles(nb6_ctx* c, int cluster, int64_t n, const double* m, cons
             for (DevBuf& b : cl->rec) release(b);
             for (DevBuf* b : {&cl->tmax, &cl->nbl, &cl->nbc}) release(*b);
             cl->lcap = 0;
-            if (hipMalloc(&cl->state, (size_t)14 * n * sizeof(double)) != hipSuccess) {
+            if (hipMalloc(&cl->state, (size_t)n * sizeof(StateRec)) != hipSuccess) {
                 (void)hipGetLastError();
                 cl->state = nullptr;
                 return fail(c, NB6_ERR_NOMEM, "cluster state of %lld particles", (long long)n);
             }
             cl->n = n;
-            cl->m = cl->state;
-            cl->t = cl->m + n;
-            cl->x = cl->t + n;
-            cl->v = cl->x + 3 * n;
-            cl->a = cl->v + 3 * n;
-            cl->jk = cl->a + 3 * n;
         }
-        HIP_TRY(c, hipMemcpyAsync(cl->m, m, n * sizeof(double), kind, st));
-        HIP_TRY(c, hipMemcpyAsync(cl->t, t, n * sizeof(double), kind, st));
-        HIP_TRY(c, hipMemcpyAsync(cl->x, x, 3 * n * sizeof(double), kind, st));
-        HIP_TRY(c, hipMemcpyAsync(cl->v, v, 3 * n * sizeof(double), kind, st));
-        HIP_TRY(c, hipMemcpyAsync(cl->a, a, 3 * n * sizeof(double), kind, st));
-        HIP_TRY(c, hipMemcpyAsync(cl->jk, jerk, 3 * n * sizeof(double), kind, st));
-        // a full load starts every stored neighbour list empty
-        if (cl->nbc.p) HIP_TRY(c, launch_zero_u32((unsigned*)cl->nbc.p, (int)n, st));
-        if (mem_kind == NB6_MEM_HOST) HIP_TRY(c, hipStreamSynchronize(st));
-        cl->pred_valid = 0;
-        return NB6_OK;
+    } else {
+        if (!cl || cl->n == 0) return fail(c, NB6_ERR_STATE, "cluster %d is not loaded", cluster);
+        if (n > cl->n) return fail(c, NB6_ERR_ARG, "subset of %lld > cluster size", (long long)n);
     }
-
-    // subset update
-    if (!cl || cl->n == 0) return fail(c, NB6_ERR_STATE, "cluster %d is not loaded", cluster);
-    if (n > cl->n) return fail(c, NB6_ERR_ARG, "subset of %lld > cluster size", (long long)n);
+    // both forms pack the structure-of-arrays input into the state records
     ScatterArgs sa{};
     sa.n = n;
     sa.limit = cl->n;
     sa.status = c->status;
-    sa.dm = cl->m; sa.dt = cl->t; sa.dx = cl->x; sa.dv = cl->v; sa.da = cl->a; sa.djk = cl->jk;
+    sa.dst = cl->state;
     if (mem_kind == NB6_MEM_HOST) {
-        for (int64_t k = 0; k < n; ++k)
-            if (idx[k] < 0 || idx[k] >= cl->n)
-                return fail(c, NB6_ERR_ARG, "idx[%lld] = %d out of range", (long long)k, idx[k]);
+        if (idx)
+            for (int64_t k = 0; k < n; ++k)
+                if (idx[k] < 0 || idx[k] >= cl->n)
+                    return fail(c, NB6_ERR_ARG, "idx[%lld] = %d out of range", (long long)k,
+                                idx[k]);
         const size_t sz[7] = {n * sizeof(int32_t), n * sizeof(double), n * sizeof(double),
                               3 * n * sizeof(double), 3 * n * sizeof(double),
                               3 * n * sizeof(double), 3 * n * sizeof(double)};
         const void* src[7] = {idx, m, t, x, v, a, jerk};
-        for (int k = 0; k < 7; ++k) {
+        for (int k = idx ? 0 : 1; k < 7; ++k) {
             int rc = ensure(c, c->ld[k], sz[k]);
             if (rc) return rc;
             HIP_TRY(c, hipMemcpyAsync(c->ld[k].p, src[k], sz[k], hipMemcpyHostToDevice, st));
         }
-        sa.idx = (const int32_t*)c->ld[0].p;
+        sa.idx = idx ? (const int32_t*)c->ld[0].p : nullptr;
         sa.m = (const double*)c->ld[1].p;
         sa.t = (const double*)c->ld[2].p;
         sa.x = (const double*)c->ld[3].p;
@@ -401,6 +383,8 @@ int nb6_load_particles(nb6_ctx* c, int cluster, int64_t n, const double* m, cons
         sa.idx = idx; sa.m = m; sa.t = t; sa.x = x; sa.v = v; sa.a = a; sa.jk = jerk;
     }
     HIP_TRY(c, launch_scatter(sa, st));
+    // a full load starts every stored neighbour list empty
+    if (!idx && cl->nbc.p) HIP_TRY(c, launch_zero_u32((unsigned*)cl->nbc.p, (int)n, st));
     if (mem_kind == NB6_MEM_HOST) HIP_TRY(c, hipStreamSynchronize(st));
     cl->pred_valid = 0;
     return NB6_OK;
@@ -420,7 +404,7 @@ int nb6_predict_j(nb6_ctx* c, int cluster, double t_block, int modes, void* stre
     HIP_TRY(c, hipSetDevice(c->device));
     PredictArgs pa{};
     pa.n = cl->n;
-    pa.m = cl->m; pa.x = cl->x; pa.v = cl->v; pa.a = cl->a; pa.jk = cl->jk; pa.t = cl->t;
+    pa.st = cl->state;
     pa.tb = t_block;
     pa.status = c->status;
     const int bits[3] = {NB6_DX_FF, NB6_DX_FP64, NB6_DX_FP32};
@@ -772,7 +756,7 @@ int nb6_irregular_force(nb6_ctx* c, int cluster, double t_block, int64_t n_i,
     if (int rc = ensure_lists(c, cl, 1, st)) return rc;  // no lists yet: all empty
     IrrArgs ia{};
     ia.n = n;
-    ia.m = cl->m; ia.t = cl->t; ia.x = cl->x; ia.v = cl->v; ia.a = cl->a; ia.jk = cl->jk;
+    ia.st = cl->state;
     ia.tb = t_block;
     ia.idx = d_idx;
     ia.ni = ni;

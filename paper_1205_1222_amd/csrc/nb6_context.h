@@ -23,8 +23,7 @@ struct DevBuf {
 
 struct ClusterState {
     int64_t n = 0;
-    double* state = nullptr;   // m[n] t[n] x[3n] v[3n] a[3n] jk[3n]
-    double *m = nullptr, *t = nullptr, *x = nullptr, *v = nullptr, *a = nullptr, *jk = nullptr;
+    StateRec* state = nullptr; // [n] stored state, one record per particle
     DevBuf rec[3];             // j-records by mode index
     DevBuf tmax;               // max vabs per tile of VTILE records (any mode)
     DevBuf nbl;                // stored neighbour lists [n][lcap] (irregular force)

@@ -120,15 +120,24 @@ struct OverflowArgs {
     const int32_t* ovf_list;
 };
 
+// ---------------------------------------------------------------------------
+// Stored state of one particle: the corrected position, velocity,
+// acceleration and jerk at its own time t, and its mass -- what the
+// predictor works from (section 3.3 step 3).  One 128-byte record per
+// particle, so that the gather of one particle (the irregular force reads
+// its list's particles in arbitrary order) touches one cache line.
+// ---------------------------------------------------------------------------
+struct __attribute__((aligned(128))) StateRec {
+    double x[3], v[3], a[3], jk[3];
+    double m, t;
+    double pad[2];
+};
+static_assert(sizeof(StateRec) == 128, "one cache line per particle");
+
 struct PredictArgs {
-    int64_t       n;
-    const double* m;
-    const double* x;   // [n][3]
-    const double* v;
-    const double* a;
-    const double* jk;
-    const double* t;
-    double        tb;
+    int64_t         n;
+    const StateRec* st;  // [n]
+    double          tb;
     RecFF*        ff;  // may be null
     RecF64*       f64; // may be null
     RecF32*       f32; // may be null
@@ -138,14 +147,14 @@ struct PredictArgs {
 
 struct ScatterArgs {
     int64_t        n;     // entries
-    const int32_t* idx;   // [n] destination particle of each entry
+    const int32_t* idx;   // [n] destination particle of each entry (null: entry e -> e)
     const double*  m;     // sources, [n] and [n][3]
     const double*  x;
     const double*  v;
     const double*  a;
     const double*  jk;
     const double*  t;
-    double* dm; double* dx; double* dv; double* da; double* djk; double* dt;
+    StateRec*      dst;   // [limit] stored state
     int64_t        limit; // cluster size; entries with idx outside [0, limit) are skipped
     unsigned*      status;
 };
@@ -157,14 +166,9 @@ struct ScatterArgs {
 constexpr int MAX_LIST_CAP = 8192;
 
 struct IrrArgs {
-    int64_t        n;         // cluster size
-    const double*  m;         // stored state (structure of arrays, FP64)
-    const double*  t;
-    const double*  x;         // [n][3]
-    const double*  v;
-    const double*  a;
-    const double*  jk;
-    double         tb;        // block time
+    int64_t         n;        // cluster size
+    const StateRec* st;       // [n] stored state
+    double          tb;       // block time
     const int32_t* idx;       // [ni] active particles
     int            ni;
     const int32_t* nbl;       // [n][lcap] stored lists

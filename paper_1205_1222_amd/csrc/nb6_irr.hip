@@ -11,7 +11,7 @@
 //   set_lists_kernel   one wavefront per replaced list: copy, validate.
 //   copy_rows_kernel   re-lay the stored lists when their rows grow.
 //
-// The work per pair is a handful of gathers from the stored state and ~60
+// The work per pair is one gather of a 128-byte state record and ~60
 // FP64 operations, so the kernel is bound by the latency and bandwidth of
 // the gathers, not by arithmetic: it computes in FP64 throughout (FP64 runs
 // at the FP32 fma rate on this chip), which makes its result independent of
@@ -25,14 +25,15 @@
 namespace nb6 {
 
 // Predicted position and velocity of particle k at time tb.
-__device__ __forceinline__ void predict_particle(const IrrArgs& a, const int64_t k,
-                                                 double xp[3], double vp[3]) {
-    const double dt = a.tb - a.t[k];
+// Predicted position and velocity of particle k at time tb, and its mass.
+__device__ __forceinline__ double predict_particle(const IrrArgs& a, const int64_t k,
+                                                   double xp[3], double vp[3]) {
+    const StateRec s = a.st[k];  // one 128-byte record
+    const double dt = a.tb - s.t;
     const double h = 0.5 * dt, t3 = dt * (1.0 / 3.0);
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
-        predict_coord(dt, h, t3, a.x[3 * k + c], a.v[3 * k + c], a.a[3 * k + c],
-                      a.jk[3 * k + c], xp[c], vp[c]);
+    for (int c = 0; c < 3; ++c) predict_coord(dt, h, t3, s.x[c], s.v[c], s.a[c], s.jk[c], xp[c], vp[c]);
+    return s.m;
 }
 
 __global__ void __launch_bounds__(256) irregular_kernel(IrrArgs a) {
@@ -48,31 +49,35 @@ __global__ void __launch_bounds__(256) irregular_kernel(IrrArgs a) {
         }
         return;
     }
-    double xi[3], vi[3];
-    predict_particle(a, i, xi, vi);
-    const int cnt = a.nbc[i];
+    // the first row entry of each lane is loaded before the count is known
+    // (the row holds lcap entries), so the count, the row and the i record
+    // arrive in one memory round trip
     const int32_t* row = a.nbl + (size_t)i * a.lcap;
+    const int32_t first = lane < a.lcap ? row[lane] : 0;
+    const int cnt = a.nbc[i];
+    double xi[3], vi[3];
+    (void)predict_particle(a, i, xi, vi);
 
     double s[6];
 #pragma unroll
     for (int c = 0; c < 6; ++c) s[c] = 0.0;
     bool bad = false;
     for (int e = lane; e < cnt; e += 64) {
-        const int32_t j = row[e];
+        const int32_t j = e < 64 ? first : row[e];
         if (j == i) continue;  // no self-term
         if (j < 0 || j >= a.n) {
             bad = true;
             continue;
         }
         double xj[3], vj[3];
-        predict_particle(a, j, xj, vj);
+        const double mj = predict_particle(a, j, xj, vj);
         const double dx = xj[0] - xi[0], dy = xj[1] - xi[1], dz = xj[2] - xi[2];
         const double dvx = vj[0] - vi[0], dvy = vj[1] - vi[1], dvz = vj[2] - vi[2];
         const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
         const double rv = fma(dz, dvz, fma(dy, dvy, dx * dvx));
         const double rinv = 1.0 / sqrt(r2);
         const double rinv2 = rinv * rinv;
-        const double mr3 = (a.m[j] * rinv) * rinv2;
+        const double mr3 = (mj * rinv) * rinv2;
         const double alpha = (-3.0 * rv) * rinv2;
         s[0] = fma(mr3, dx, s[0]);
         s[1] = fma(mr3, dy, s[1]);

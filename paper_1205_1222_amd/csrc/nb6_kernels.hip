@@ -748,17 +748,17 @@ __global__ void __launch_bounds__(256) serve_prepare_kernel(BatchArgs b) {
 // ---------------------------------------------------------------------------
 // Predicts particle k and returns the vabs of its records.
 __device__ __forceinline__ float predict_one(const PredictArgs& a, const int64_t k) {
-    const double dt = a.tb - a.t[k];
+    const StateRec& s = a.st[k];
+    const double dt = a.tb - s.t;
     const double h = 0.5 * dt, t3 = dt * (1.0 / 3.0);
     double xp[3], vp[3];
     bool finite = isfinite(dt);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        predict_coord(dt, h, t3, a.x[3 * k + c], a.v[3 * k + c], a.a[3 * k + c],
-                      a.jk[3 * k + c], xp[c], vp[c]);
+        predict_coord(dt, h, t3, s.x[c], s.v[c], s.a[c], s.jk[c], xp[c], vp[c]);
         finite = finite && isfinite(xp[c]) && isfinite(vp[c]);
     }
-    const float m = (float)a.m[k];
+    const float m = (float)s.m;
     if (!finite) atomicOr(a.status, (unsigned)ST_NONFINITE);
     // upper bound of the float velocity's magnitude (rounded up by 2^-20)
     const float vf[3] = {(float)vp[0], (float)vp[1], (float)vp[2]};
@@ -804,25 +804,30 @@ __global__ void __launch_bounds__(256) predict_kernel(PredictArgs a) {
     store_tile_max(a, k, v);
 }
 
-// Subset update of the stored state: entry e goes to particle idx[e].  An
-// index outside the cluster is skipped and flagged in the status word.
+// Load or subset update of the stored state: entry e (structure-of-arrays
+// sources) becomes the record of particle idx[e], or of particle e for a full
+// load.  An index outside the cluster is skipped and flagged in the status
+// word.
 __global__ void __launch_bounds__(256) scatter_kernel(ScatterArgs a) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= a.n) return;
-    const int64_t k = a.idx[e];
+    const int64_t k = a.idx ? a.idx[e] : e;
     if (k < 0 || k >= a.limit) {
         atomicOr(a.status, (unsigned)ST_BAD_INDEX);
         return;
     }
-    a.dm[k] = a.m[e];
-    a.dt[k] = a.t[e];
+    StateRec r;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        a.dx[3 * k + c] = a.x[3 * e + c];
-        a.dv[3 * k + c] = a.v[3 * e + c];
-        a.da[3 * k + c] = a.a[3 * e + c];
-        a.djk[3 * k + c] = a.jk[3 * e + c];
+        r.x[c] = a.x[3 * e + c];
+        r.v[c] = a.v[3 * e + c];
+        r.a[c] = a.a[3 * e + c];
+        r.jk[c] = a.jk[3 * e + c];
     }
+    r.m = a.m[e];
+    r.t = a.t[e];
+    r.pad[0] = r.pad[1] = 0.0;
+    a.dst[k] = r;
 }
 
 __device__ __forceinline__ void unpack_one(const RecFF& r, double* x, double* v) {

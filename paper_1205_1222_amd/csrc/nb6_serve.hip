@@ -468,8 +468,7 @@ class Engine {
             }
             unsigned* status = sl.dev_status + b;
             d.pred.n = cl->n;
-            d.pred.m = cl->m; d.pred.x = cl->x; d.pred.v = cl->v; d.pred.a = cl->a;
-            d.pred.jk = cl->jk; d.pred.t = cl->t;
+            d.pred.st = cl->state;
             d.pred.tb = r->rq.t_block;
             d.pred.ff = r->mi == MODE_FF ? (RecFF*)cl->rec[MODE_FF].p : nullptr;
             d.pred.f64 = r->mi == MODE_F64 ? (RecF64*)cl->rec[MODE_F64].p : nullptr;
