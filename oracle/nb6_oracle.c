@@ -21,8 +21,10 @@
  *     neighbour criterion of section 3.2 (the smaller of the two end-point
  *     distances |R_ij| and |R_ij + dt_reg,i V_ij| compared with h_i), then
  *     the regular force and its time derivative of section 3.3, step 6
- *     (the F_reg and dF_reg/dt sums over non-neighbours), and the neighbour
- *     list L_i of the same step.
+ *     (the F_reg and dF_reg/dt sums over non-neighbours), the neighbour
+ *     list L_i of the same step, and optionally the regular potential (the
+ *     extra sum the appendix kernel adds under its POTENTIAL switch; section
+ *     4 quotes its accuracy for the energy check).
  *
  *   - nb6o_pair_terms: the same pair quantities for an explicit list of
  *     (i, j) pairs; the tests use it to treat pairs that sit on the
@@ -120,6 +122,9 @@ void nb6o_predict(int64_t n, const double *x, const double *v,
  *   sa[ni]       sum over non-neighbours of m_j / r^2        (may be NULL)
  *   sj[ni]       sum over non-neighbours of
  *                m_j (|V|/r^3 + 3 |R.V| / r^4)               (may be NULL)
+ *   pot[ni]      regular potential, -sum over non-neighbours of m_j / r
+ *                (the optional potential sum of the appendix kernel, with
+ *                the physical sign)                          (may be NULL)
  * Returns 0, or -1 for a bad index, -2 for h2 <= 0 (nothing is computed
  * for that i).
  */
@@ -128,7 +133,7 @@ int nb6o_regular_force(int64_t n, const double *m, const double *xp,
                        const double *h2, const double *dtr,
                        double *acc, double *jrk, int32_t *nnb,
                        int32_t *list, int64_t lcap,
-                       double *sa, double *sj, int nthreads)
+                       double *sa, double *sj, double *pot, int nthreads)
 {
     for (int64_t q = 0; q < ni; ++q) {
         if (idx[q] < 0 || idx[q] >= n) return -1;
@@ -147,7 +152,7 @@ int nb6o_regular_force(int64_t n, const double *m, const double *xp,
         const double dti = dtr[q];
         nsum A[3] = {{0, 0}, {0, 0}, {0, 0}};
         nsum J[3] = {{0, 0}, {0, 0}, {0, 0}};
-        nsum SA = {0, 0}, SJ = {0, 0};
+        nsum SA = {0, 0}, SJ = {0, 0}, PHI = {0, 0};
         int64_t count = 0;
 
         for (int64_t j = 0; j < n; ++j) {
@@ -179,6 +184,7 @@ int nb6o_regular_force(int64_t n, const double *m, const double *xp,
             double vabs = sqrt(V[0] * V[0] + V[1] * V[1] + V[2] * V[2]);
             nsum_add(&SA, m[j] / r2);
             nsum_add(&SJ, m[j] * (vabs / r3 + 3.0 * fabs(rv) / (r2 * r2)));
+            nsum_add(&PHI, -m[j] / r);
         }
         for (int c = 0; c < 3; ++c) {
             acc[3 * q + c] = nsum_get(&A[c]);
@@ -187,6 +193,7 @@ int nb6o_regular_force(int64_t n, const double *m, const double *xp,
         nnb[q] = (int32_t)count;
         if (sa) sa[q] = nsum_get(&SA);
         if (sj) sj[q] = nsum_get(&SJ);
+        if (pot) pot[q] = nsum_get(&PHI);
     }
     return 0;
 }
@@ -252,6 +259,8 @@ void nb6o_pair_terms(int64_t np, const int32_t *pi, const int32_t *pj,
  *   sa[ni], sj[ni]                sums of m_j / r^2 and of
  *                                 m_j (|V| / r^3 + 3 |R.V| / r^4) over the
  *                                 same terms (may be NULL)
+ *   pot[ni]                       irregular potential, -sum m_j / r over
+ *                                 the list (may be NULL)
  * Returns 0, -1 for an index (idx or a list entry) outside [0, n), -3 for a
  * count outside [0, lcap]; nothing is computed then.
  */
@@ -259,7 +268,7 @@ int nb6o_irregular_force(int64_t n, const double *m, const double *xp,
                          const double *vp, int64_t ni, const int32_t *idx,
                          const int32_t *cnt, const int32_t *list, int64_t lcap,
                          double *acc, double *jrk, double *sa, double *sj,
-                         int nthreads)
+                         double *pot, int nthreads)
 {
     for (int64_t q = 0; q < ni; ++q) {
         if (idx[q] < 0 || idx[q] >= n) return -1;
@@ -278,7 +287,7 @@ int nb6o_irregular_force(int64_t n, const double *m, const double *xp,
         const int64_t i = idx[q];
         nsum A[3] = {{0, 0}, {0, 0}, {0, 0}};
         nsum J[3] = {{0, 0}, {0, 0}, {0, 0}};
-        nsum SA = {0, 0}, SJ = {0, 0};
+        nsum SA = {0, 0}, SJ = {0, 0}, PHI = {0, 0};
         for (int64_t e = 0; e < cnt[q]; ++e) {
             const int64_t j = list[q * lcap + e];
             if (j == i) continue;
@@ -300,6 +309,7 @@ int nb6o_irregular_force(int64_t n, const double *m, const double *xp,
             double vabs = sqrt(Vij[0] * Vij[0] + Vij[1] * Vij[1] + Vij[2] * Vij[2]);
             nsum_add(&SA, mj / d2);
             nsum_add(&SJ, mj * (vabs / d3 + 3.0 * fabs(rdotv) / (d2 * d2)));
+            nsum_add(&PHI, -mj / d);
         }
         for (int c = 0; c < 3; ++c) {
             acc[3 * q + c] = nsum_get(&A[c]);
@@ -307,6 +317,7 @@ int nb6o_irregular_force(int64_t n, const double *m, const double *xp,
         }
         if (sa) sa[q] = nsum_get(&SA);
         if (sj) sj[q] = nsum_get(&SJ);
+        if (pot) pot[q] = nsum_get(&PHI);
     }
     return 0;
 }

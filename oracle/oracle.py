@@ -53,13 +53,13 @@ def _bind(lib):
     lib.nb6o_predict.argtypes = [i64, d, d, d, d, d, ctypes.c_double, d, d]
     lib.nb6o_predict.restype = None
     lib.nb6o_regular_force.argtypes = [
-        i64, d, d, d, i64, i32, d, d, d, d, i32, i32, i64, d, d, ctypes.c_int,
+        i64, d, d, d, i64, i32, d, d, d, d, i32, i32, i64, d, d, d, ctypes.c_int,
     ]
     lib.nb6o_regular_force.restype = ctypes.c_int
     lib.nb6o_pair_terms.argtypes = [i64, i32, i32, d, d, d, d, d, d, d]
     lib.nb6o_pair_terms.restype = None
     lib.nb6o_irregular_force.argtypes = [
-        i64, d, d, d, i64, i32, i32, i32, i64, d, d, d, d, ctypes.c_int,
+        i64, d, d, d, i64, i32, i32, i32, i64, d, d, d, d, d, ctypes.c_int,
     ]
     lib.nb6o_irregular_force.restype = ctypes.c_int
     lib.nb6o_max_threads.argtypes = []
@@ -108,6 +108,7 @@ class OracleResult:
     sa: np.ndarray       # [ni] sum of m/r^2 over non-neighbours
     sj: np.ndarray       # [ni] jerk scale
     complete: bool       # every list fitted in lcap
+    pot: np.ndarray = None  # [ni] regular potential -sum m/r over non-neighbours
 
 
 def regular_force(m, xp, vp, idx, h2, dtr, lcap=1024, nthreads=0, lib=None):
@@ -127,16 +128,17 @@ def regular_force(m, xp, vp, idx, h2, dtr, lcap=1024, nthreads=0, lib=None):
     lst = np.full((ni, max(lcap, 1)), -1, dtype=np.int32)
     sa = np.zeros(ni)
     sj = np.zeros(ni)
+    pot = np.zeros(ni)
     rc = lib.nb6o_regular_force(
         n, _pd(m), _pd(xp), _pd(vp), ni, _pi(idx), _pd(h2), _pd(dtr),
         _pd(acc), _pd(jrk), _pi(nnb), _pi(lst), int(lcap), _pd(sa), _pd(sj),
-        int(nthreads),
+        _pd(pot), int(nthreads),
     )
     if rc != 0:
         raise ValueError(f"oracle rejected its input (code {rc})")
     lists = [lst[q, : min(int(nnb[q]), lcap)].copy() for q in range(ni)]
     return OracleResult(acc, jrk, nnb, lists, sa, sj,
-                        bool(ni == 0 or nnb.max() <= lcap))
+                        bool(ni == 0 or nnb.max() <= lcap), pot)
 
 
 def pair_terms(pi, pj, dtr, m, xp, vp, lib=None):
@@ -164,6 +166,7 @@ class IrregularResult:
     jerk: np.ndarray     # [ni, 3]
     sa: np.ndarray       # [ni] sum of m/r^2 over the list
     sj: np.ndarray       # [ni] jerk scale over the list
+    pot: np.ndarray      # [ni] irregular potential -sum m/r over the list
 
 
 def irregular_force(m, xp, vp, idx, lists, nthreads=0, lib=None):
@@ -187,10 +190,11 @@ def irregular_force(m, xp, vp, idx, lists, nthreads=0, lib=None):
     jrk = np.zeros((ni, 3))
     sa = np.zeros(ni)
     sj = np.zeros(ni)
+    pot = np.zeros(ni)
     rc = lib.nb6o_irregular_force(
         n, _pd(m), _pd(xp), _pd(vp), ni, _pi(idx), _pi(cnt), _pi(lst), lcap,
-        _pd(acc), _pd(jrk), _pd(sa), _pd(sj), int(nthreads),
+        _pd(acc), _pd(jrk), _pd(sa), _pd(sj), _pd(pot), int(nthreads),
     )
     if rc != 0:
         raise ValueError(f"oracle rejected its input (code {rc})")
-    return IrregularResult(acc, jrk, sa, sj)
+    return IrregularResult(acc, jrk, sa, sj, pot)

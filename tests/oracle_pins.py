@@ -55,6 +55,7 @@ def pin_golden_forces(lib=None):
         assert _close(r.acc, c["acc"], 1e-14), (c["name"], r.acc, c["acc"])
         if c["jerk"] != "skip":
             assert _close(r.jerk, c["jerk"], 1e-14), (c["name"], r.jerk, c["jerk"])
+        assert _close(r.pot, c["pot"], 1e-14), (c["name"], r.pot, c["pot"])
         got = [list(map(int, l)) for l in r.lists]
         assert got == c["lists"], (c["name"], got, c["lists"])
         assert list(map(int, r.nnb)) == [len(l) for l in c["lists"]], c["name"]
@@ -255,6 +256,59 @@ def pin_scales_and_truncation(lib=None):
 
 
 # --------------------------------------------------------------------------
+# Potential
+# --------------------------------------------------------------------------
+def pin_potential_gradient(lib=None):
+    """The acceleration is minus the gradient of the potential at the
+    particle: central differences of phi_i in each coordinate of x_i, the
+    other particles fixed (no neighbours, so the sums cover every j)."""
+    cl = make_cluster(300, 31, masses="imf", stored_state=False, k_nb=8)
+    n = cl.n
+    base = oracle.regular_force(cl.m, cl.x, cl.v, np.arange(n), 1e-300, 0.0, lcap=4, lib=lib)
+    d = 1e-6
+    for i in range(0, n, 37):
+        g = np.zeros(3)
+        for c in range(3):
+            xp = cl.x.copy()
+            xm = cl.x.copy()
+            xp[i, c] += d
+            xm[i, c] -= d
+            pp = oracle.regular_force(cl.m, xp, cl.v, [i], 1e-300, 0.0, lcap=4, lib=lib).pot[0]
+            pm = oracle.regular_force(cl.m, xm, cl.v, [i], 1e-300, 0.0, lcap=4, lib=lib).pot[0]
+            g[c] = (pp - pm) / (2 * d)
+        err = np.linalg.norm(-g - base.acc[i]) / base.sa[i]
+        assert err < 1e-5, (i, err)
+
+
+def pin_potential_plummer(lib=None):
+    """The potential of a Plummer sphere sample follows -M (r^2 + b^2)^-1/2
+    (G = M = 1, b = 3 pi/16); without the neighbour ball of radius h the
+    regular potential lacks that ball's share, 2 pi rho h^2 for a uniform
+    ball, which is added back here."""
+    cl = make_cluster(16384, 11, masses="equal", stored_state=False, k_nb=8)
+    n = cl.n
+    idx = np.arange(0, n, 4)
+    b = 3.0 * np.pi / 16.0
+    x = cl.x[idx]
+    rad = np.sqrt((x * x).sum(1))
+    phi_mf = -1.0 / np.sqrt(rad ** 2 + b * b)
+    full = oracle.regular_force(cl.m, cl.x, cl.v, idx, 1e-300, 0.0, lcap=4, lib=lib)
+    h = 0.06
+    reg = oracle.regular_force(cl.m, cl.x, cl.v, idx, h * h, 0.0, lcap=4096, lib=lib)
+    rho = 3.0 / (4.0 * np.pi * b ** 3) * (1.0 + rad ** 2 / b ** 2) ** -2.5
+    sel = rad < 3.0
+    for got, expect in ((full.pot, phi_mf), (reg.pot, phi_mf + 2.0 * np.pi * rho * h * h)):
+        edges = np.quantile(rad[sel], np.linspace(0, 1, 9))
+        for lo, hi in zip(edges[:-1], edges[1:]):
+            s_ = sel & (rad >= lo) & (rad < hi)
+            assert abs(got[s_].mean() / expect[s_].mean() - 1.0) < 0.01, (lo, hi)
+    # virial equilibrium in Henon units: W = (1/2) sum m phi = 2 E = -1/2
+    allp = oracle.regular_force(cl.m, cl.x, cl.v, np.arange(n), 1e-300, 0.0, lcap=4, lib=lib)
+    w = 0.5 * (cl.m * allp.pot).sum()
+    assert abs(w + 0.5) < 0.02, w
+
+
+# --------------------------------------------------------------------------
 # Irregular force (section 3.3 step 4)
 # --------------------------------------------------------------------------
 def pin_irregular_golden(lib=None):
@@ -273,6 +327,7 @@ def pin_irregular_golden(lib=None):
         assert _close(r.acc, c["acc"], 1e-14), (c["name"], r.acc, c["acc"])
         if c["jerk"] != "skip":
             assert _close(r.jerk, c["jerk"], 1e-14), (c["name"], r.jerk, c["jerk"])
+        assert _close(r.pot, c["pot"], 1e-14), (c["name"], r.pot, c["pot"])
 
 
 def pin_irregular_complements_regular(lib=None):
@@ -292,9 +347,10 @@ def pin_irregular_complements_regular(lib=None):
                                  (reg.jerk, irr.jerk, full.jerk, full.sj)):
             err = np.linalg.norm(a + b - full_q, axis=1) / sc
             assert err.max() < 1e-13, err.max()
-        # the magnitude sums split the same way
+        # the magnitude sums and the potential split the same way
         assert np.all(np.abs(reg.sa + irr.sa - full.sa) <= 1e-13 * full.sa)
         assert np.all(np.abs(reg.sj + irr.sj - full.sj) <= 1e-13 * full.sj)
+        assert np.all(np.abs(reg.pot + irr.pot - full.pot) <= 1e-13 * np.abs(full.pot))
 
 
 def pin_irregular_momentum(lib=None):
@@ -365,6 +421,8 @@ ALL_PINS = [  # roughly cheapest first
     pin_momentum,
     pin_fd_jerk,
     pin_plummer_mean_field,
+    pin_potential_gradient,
+    pin_potential_plummer,
     pin_irregular_golden,
     pin_irregular_list_semantics,
     pin_irregular_complements_regular,

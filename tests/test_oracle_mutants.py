@@ -41,6 +41,14 @@ MUTANTS = {
     "pair_terms_jerk_sign": ("djrk[3 * p + c] = m[j] * (V[c] / r3 - 3.0 * rv * R[c] / r5);",
                              "djrk[3 * p + c] = m[j] * (V[c] / r3 + 3.0 * rv * R[c] / r5);"),
     "pair_terms_rmin_max": ("rmin[p] = sqrt((p2 < r2) ? p2 : r2);", "rmin[p] = sqrt((p2 < r2) ? r2 : p2);"),
+    # potential
+    "pot_sign": ("nsum_add(&PHI, -m[j] / r);", "nsum_add(&PHI, m[j] / r);"),
+    "pot_inverse_square": ("nsum_add(&PHI, -m[j] / r);", "nsum_add(&PHI, -m[j] / r2);"),
+    "pot_mass_of_i": ("nsum_add(&PHI, -m[j] / r);", "nsum_add(&PHI, -m[i] / r);"),
+    "pot_includes_neighbours": ("++count;\n                continue;",
+                                "++count;\n                nsum_add(&PHI, -m[j] / sqrt(r2));\n                continue;"),
+    "irr_pot_sign": ("nsum_add(&PHI, -mj / d);", "nsum_add(&PHI, mj / d);"),
+    "irr_pot_power": ("nsum_add(&PHI, -mj / d);", "nsum_add(&PHI, -mj / d2);"),
     # irregular force
     "irr_R_sign": ("Rij[c] = xp[3 * j + c] - xp[3 * i + c];", "Rij[c] = xp[3 * i + c] - xp[3 * j + c];"),
     "irr_V_sign": ("Vij[c] = vp[3 * j + c] - vp[3 * i + c];", "Vij[c] = vp[3 * i + c] - vp[3 * j + c];"),
