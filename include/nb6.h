@@ -149,6 +149,11 @@ int nb6_predict_j(nb6_ctx *ctx, int cluster, double t_block, int modes,
  *          count, self excluded), list[n_i][cap] (the first min(nnb, cap)
  *          neighbours in ascending cluster index; entries past that are
  *          left unspecified).  list may be NULL when cap == 0.
+ *          pot[n_i] (may be NULL): the regular potential
+ *          -sum m_j / |R_ij| over the same non-neighbour terms (the optional
+ *          potential sum of the paper's kernel, Appendix B; section 4 quotes
+ *          its use in the energy check).  Asking for it adds one FP32 add
+ *          per pair and one partial-sum component.
  * The neighbour decision and the force arithmetic are done in FP32 (the
  * coordinate difference per dx_mode), the sums are compensated, and the
  * outputs are double.
@@ -159,8 +164,8 @@ int nb6_predict_j(nb6_ctx *ctx, int cluster, double t_block, int modes,
 int nb6_regular_force(nb6_ctx *ctx, int cluster, int64_t n_i,
                       const int32_t *idx_i, const double *h2_i,
                       const double *dtr_i, int dx_mode, double *acc,
-                      double *jerk, int32_t *nnb, int32_t *list, int32_t cap,
-                      int mem_kind, void *stream);
+                      double *jerk, double *pot, int32_t *nnb, int32_t *list,
+                      int32_t cap, int mem_kind, void *stream);
 
 /*
  * Wait for `stream` and return (and clear) the GPU-side validation state of
@@ -223,7 +228,8 @@ int nb6_set_lists(nb6_ctx *ctx, int cluster, int64_t n_i, const int32_t *idx_i,
  * with i = idx_i[q], R_ij = R_j - R_i and V_ij = V_j - V_i.  Every particle
  * needed is predicted to t_block from the stored state by the cubic Taylor
  * series (section 3.3 step 3), inside the call and independently of
- * nb6_predict_j; all arithmetic is FP64.  acc, jerk: [n_i][3] doubles.
+ * nb6_predict_j; all arithmetic is FP64.  acc, jerk: [n_i][3] doubles;
+ * pot[n_i] (may be NULL): the irregular potential -sum_{j in L_i} m_j / |R_ij|.
  * Repeated idx_i are allowed.  An empty list gives zeros.  Out-of-range
  * idx_i: NB6_ERR_ARG (HOST) or NaN rows and NB6_ERR_DEVICE_INPUT from
  * nb6_sync_status (DEVICE).  Errors: NB6_ERR_ARG, NB6_ERR_STATE,
@@ -232,7 +238,7 @@ int nb6_set_lists(nb6_ctx *ctx, int cluster, int64_t n_i, const int32_t *idx_i,
  */
 int nb6_irregular_force(nb6_ctx *ctx, int cluster, double t_block, int64_t n_i,
                         const int32_t *idx_i, double *acc, double *jerk,
-                        int mem_kind, void *stream);
+                        double *pot, int mem_kind, void *stream);
 
 /* ---- serving: continuously batched requests ---------------------------- */
 

@@ -261,7 +261,7 @@ int nb6_destroy(nb6_ctx* c) {
         delete cl;
     }
     for (DevBuf* b : {&c->part, &c->cnt, &c->lst, &c->ovf, &c->in_idx, &c->in_h2, &c->in_dtr,
-                      &c->out_acc, &c->out_jerk, &c->out_nnb, &c->out_list})
+                      &c->out_acc, &c->out_jerk, &c->out_pot, &c->out_nnb, &c->out_list})
         release(*b);
     for (auto& b : c->ld) release(b);
     if (c->status) (void)hipFree(c->status);
@@ -428,8 +428,8 @@ int nb6_predict_j(nb6_ctx* c, int cluster, double t_block, int modes, void* stre
 
 int nb6_regular_force(nb6_ctx* c, int cluster, int64_t n_i, const int32_t* idx_i,
                       const double* h2_i, const double* dtr_i, int dx_mode, double* acc,
-                      double* jerk, int32_t* nnb, int32_t* list, int32_t cap, int mem_kind,
-                      void* stream) {
+                      double* jerk, double* pot, int32_t* nnb, int32_t* list, int32_t cap,
+                      int mem_kind, void* stream) {
     if (!c) return NB6_ERR_ARG;
     c->err.clear();
     std::lock_guard<std::mutex> lk(c->cluster_mu);
@@ -461,6 +461,7 @@ int nb6_regular_force(nb6_ctx* c, int cluster, int64_t n_i, const int32_t* idx_i
     const double* d_dtr = dtr_i;
     double* d_acc = acc;
     double* d_jerk = jerk;
+    double* d_pot = pot;
     int32_t* d_nnb = nnb;
     int32_t* d_list = list;
     if (mem_kind == NB6_MEM_HOST) {
@@ -481,7 +482,8 @@ int nb6_regular_force(nb6_ctx* c, int cluster, int64_t n_i, const int32_t* idx_i
             (rc = ensure(c, c->out_acc, 3 * ni * sizeof(double))) ||
             (rc = ensure(c, c->out_jerk, 3 * ni * sizeof(double))) ||
             (rc = ensure(c, c->out_nnb, ni * sizeof(int32_t))) ||
-            (rc = ensure(c, c->out_list, std::max<size_t>(1, (size_t)ni * cap) * sizeof(int32_t))))
+            (rc = ensure(c, c->out_list, std::max<size_t>(1, (size_t)ni * cap) * sizeof(int32_t))) ||
+            (pot && (rc = ensure(c, c->out_pot, ni * sizeof(double)))))
             return rc;
         HIP_TRY(c, hipMemcpyAsync(c->in_idx.p, idx_i, ni * sizeof(int32_t), hipMemcpyHostToDevice, st));
         HIP_TRY(c, hipMemcpyAsync(c->in_h2.p, h2_i, ni * sizeof(double), hipMemcpyHostToDevice, st));
@@ -493,13 +495,15 @@ int nb6_regular_force(nb6_ctx* c, int cluster, int64_t n_i, const int32_t* idx_i
         d_jerk = (double*)c->out_jerk.p;
         d_nnb = (int32_t*)c->out_nnb.p;
         d_list = (int32_t*)c->out_list.p;
+        if (pot) d_pot = (double*)c->out_pot.p;
     }
 
     const Plan p = make_plan(c, n, ni);
+    const int npart = pot ? NPART_POT : NPART;
     const int caps = cap + 1;  // room for the i-particle itself
     int rc;
     const size_t ni64 = ((size_t)ni + 63) / 64 * 64;  // partials by 64-particle block
-    if ((rc = ensure(c, c->part, (size_t)p.nslices * NPART * ni64 * sizeof(double))) ||
+    if ((rc = ensure(c, c->part, (size_t)p.nslices * npart * ni64 * sizeof(double))) ||
         (rc = ensure(c, c->cnt, ((size_t)ni + 1) * sizeof(int32_t))) ||
         (rc = ensure(c, c->lst, (size_t)ni * caps * sizeof(int32_t))) ||
         (rc = ensure(c, c->ovf, (size_t)ni * sizeof(int32_t))))
@@ -525,7 +529,7 @@ int nb6_regular_force(nb6_ctx* c, int cluster, int64_t n_i, const int32_t* idx_i
     ra.status = c->status;
     {
         TimedLaunch tl(c, 1, st);
-        HIP_TRY(c, launch_regf(mi, p.ipl, p.wpb, ra, st));
+        HIP_TRY(c, launch_regf(mi, p.ipl, p.wpb, pot != nullptr, ra, st));
         tl.done();
     }
 
@@ -541,6 +545,7 @@ int nb6_regular_force(nb6_ctx* c, int cluster, int64_t n_i, const int32_t* idx_i
     fa.h2 = d_h2;
     fa.acc = d_acc;
     fa.jerk = d_jerk;
+    fa.pot = pot ? d_pot : nullptr;
     fa.nnb = d_nnb;
     fa.list = d_list;
     fa.cap = cap;
@@ -572,6 +577,8 @@ int nb6_regular_force(nb6_ctx* c, int cluster, int64_t n_i, const int32_t* idx_i
     HIP_TRY(c, hipMemcpyAsync(acc, d_acc, 3 * ni * sizeof(double), hipMemcpyDeviceToHost, st));
     HIP_TRY(c, hipMemcpyAsync(jerk, d_jerk, 3 * ni * sizeof(double), hipMemcpyDeviceToHost, st));
     HIP_TRY(c, hipMemcpyAsync(nnb, d_nnb, ni * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    if (pot)
+        HIP_TRY(c, hipMemcpyAsync(pot, d_pot, ni * sizeof(double), hipMemcpyDeviceToHost, st));
     if (cap > 0)
         HIP_TRY(c, hipMemcpyAsync(list, d_list, (size_t)ni * cap * sizeof(int32_t),
                                   hipMemcpyDeviceToHost, st));
@@ -717,8 +724,8 @@ int nb6_set_lists(nb6_ctx* c, int cluster, int64_t n_i, const int32_t* idx_i,
 }
 
 int nb6_irregular_force(nb6_ctx* c, int cluster, double t_block, int64_t n_i,
-                        const int32_t* idx_i, double* acc, double* jerk, int mem_kind,
-                        void* stream) {
+                        const int32_t* idx_i, double* acc, double* jerk, double* pot,
+                        int mem_kind, void* stream) {
     if (!c) return NB6_ERR_ARG;
     c->err.clear();
     std::lock_guard<std::mutex> lk(c->cluster_mu);
@@ -739,6 +746,7 @@ int nb6_irregular_force(nb6_ctx* c, int cluster, double t_block, int64_t n_i,
     const int32_t* d_idx = idx_i;
     double* d_acc = acc;
     double* d_jerk = jerk;
+    double* d_pot = pot;
     if (mem_kind == NB6_MEM_HOST) {
         for (int q = 0; q < ni; ++q)
             if (idx_i[q] < 0 || idx_i[q] >= n)
@@ -746,12 +754,14 @@ int nb6_irregular_force(nb6_ctx* c, int cluster, double t_block, int64_t n_i,
         int rc;
         if ((rc = ensure(c, c->in_idx, ni * sizeof(int32_t))) ||
             (rc = ensure(c, c->out_acc, 3 * (size_t)ni * sizeof(double))) ||
-            (rc = ensure(c, c->out_jerk, 3 * (size_t)ni * sizeof(double))))
+            (rc = ensure(c, c->out_jerk, 3 * (size_t)ni * sizeof(double))) ||
+            (pot && (rc = ensure(c, c->out_pot, ni * sizeof(double)))))
             return rc;
         HIP_TRY(c, hipMemcpyAsync(c->in_idx.p, idx_i, ni * sizeof(int32_t), hipMemcpyHostToDevice, st));
         d_idx = (const int32_t*)c->in_idx.p;
         d_acc = (double*)c->out_acc.p;
         d_jerk = (double*)c->out_jerk.p;
+        if (pot) d_pot = (double*)c->out_pot.p;
     }
     if (int rc = ensure_lists(c, cl, 1, st)) return rc;  // no lists yet: all empty
     IrrArgs ia{};
@@ -765,6 +775,7 @@ int nb6_irregular_force(nb6_ctx* c, int cluster, double t_block, int64_t n_i,
     ia.lcap = cl->lcap;
     ia.acc = d_acc;
     ia.jerk = d_jerk;
+    ia.pot = pot ? d_pot : nullptr;
     ia.status = c->status;
     {
         TimedLaunch tl(c, 3, st);
@@ -774,6 +785,8 @@ int nb6_irregular_force(nb6_ctx* c, int cluster, double t_block, int64_t n_i,
     if (mem_kind == NB6_MEM_DEVICE) return NB6_OK;
     HIP_TRY(c, hipMemcpyAsync(acc, d_acc, 3 * (size_t)ni * sizeof(double), hipMemcpyDeviceToHost, st));
     HIP_TRY(c, hipMemcpyAsync(jerk, d_jerk, 3 * (size_t)ni * sizeof(double), hipMemcpyDeviceToHost, st));
+    if (pot)
+        HIP_TRY(c, hipMemcpyAsync(pot, d_pot, ni * sizeof(double), hipMemcpyDeviceToHost, st));
     unsigned status[4];
     HIP_TRY(c, hipMemcpyAsync(status, c->status, sizeof status, hipMemcpyDeviceToHost, st));
     HIP_TRY(c, hipStreamSynchronize(st));

@@ -76,7 +76,7 @@ struct nb6_ctx {
     std::vector<nb6::ClusterState*> clusters;
     nb6::DevBuf part, cnt, lst, ovf;                  // force-kernel scratch
     nb6::DevBuf in_idx, in_h2, in_dtr;                // HOST-mode inputs
-    nb6::DevBuf out_acc, out_jerk, out_nnb, out_list; // HOST-mode outputs
+    nb6::DevBuf out_acc, out_jerk, out_pot, out_nnb, out_list;  // HOST-mode outputs
     nb6::DevBuf ld[7];                                // HOST-mode load staging
     unsigned* status = nullptr;                       // device status word
     std::string err;

@@ -57,8 +57,10 @@ __device__ __forceinline__ void predict_coord(double dt, double h, double t3, do
 }
 
 // Partial sums leave the force kernel as 6 FP64 components per (i, slice):
-// acc xyz, jerk xyz.
+// acc xyz, jerk xyz; 7 when the potential is asked for (the sum of m / r over
+// the non-neighbours last).
 constexpr int NPART = 6;
+constexpr int NPART_POT = 7;
 // Largest per-i list capacity (cap + 1 slots: the i itself is found too).
 constexpr int MAX_CAPS = 1024;
 // Particles per finalize workgroup (lists; the first ceil(ni / 64)
@@ -81,7 +83,7 @@ struct RegfArgs {
     int            nslices;
     int            jl_shift;  // log2 of the lanes that share one i (0: one lane per i)
     const float*   tmax;      // [vtiles(n)] max of vabs over each tile of VTILE j
-    double*        part;      // [ceil(ni/64)][nslices][NPART][64]
+    double*        part;      // [ceil(ni/64)][nslices][NPART or NPART_POT][64]
     int32_t*       cnt;       // [ni] neighbours found, the i itself included (zeroed)
     int32_t*       lst;       // [ni][caps] neighbours in the order found
     int            caps;      // per-i list capacity (cap + 1)
@@ -100,6 +102,7 @@ struct FinalArgs {
     const double*  h2;
     double*        acc;       // [ni][3]
     double*        jerk;      // [ni][3]
+    double*        pot;       // [ni] or null (then the partials have NPART components)
     int32_t*       nnb;       // [ni]
     int32_t*       list;      // [ni][cap]
     int            cap;
@@ -176,6 +179,7 @@ struct IrrArgs {
     int            lcap;
     double*        acc;       // [ni][3]
     double*        jerk;      // [ni][3]
+    double*        pot;       // [ni] or null
     unsigned*      status;
 };
 
@@ -233,7 +237,7 @@ hipError_t launch_serve_prepare(const BatchArgs& b, int chunks, hipStream_t s);
 
 // Force kernel: ipl i-particles per lane (a.jl_shift == 0), or one i per
 // 2^a.jl_shift lanes (ipl == 1).
-hipError_t launch_regf(int mode, int ipl, int waves_per_block, const RegfArgs& a,
+hipError_t launch_regf(int mode, int ipl, int waves_per_block, bool pot, const RegfArgs& a,
                        hipStream_t s);
 // i-particles of one work item (one wavefront) of the force kernel.
 __host__ __device__ inline int regf_group_size(int ipl, int jl_shift) { return (64 * ipl) >> jl_shift; }

@@ -46,6 +46,7 @@ __global__ void __launch_bounds__(256) irregular_kernel(IrrArgs a) {
             atomicOr(a.status, (unsigned)ST_BAD_INDEX);
             const double nan = __builtin_nan("");
             for (int c = 0; c < 3; ++c) a.acc[3 * q + c] = a.jerk[3 * q + c] = nan;
+            if (a.pot) a.pot[q] = nan;
         }
         return;
     }
@@ -58,9 +59,9 @@ __global__ void __launch_bounds__(256) irregular_kernel(IrrArgs a) {
     double xi[3], vi[3];
     (void)predict_particle(a, i, xi, vi);
 
-    double s[6];
+    double s[7];  // acc, jerk, sum of m / r
 #pragma unroll
-    for (int c = 0; c < 6; ++c) s[c] = 0.0;
+    for (int c = 0; c < 7; ++c) s[c] = 0.0;
     bool bad = false;
     for (int e = lane; e < cnt; e += 64) {
         const int32_t j = e < 64 ? first : row[e];
@@ -77,7 +78,9 @@ __global__ void __launch_bounds__(256) irregular_kernel(IrrArgs a) {
         const double rv = fma(dz, dvz, fma(dy, dvy, dx * dvx));
         const double rinv = 1.0 / sqrt(r2);
         const double rinv2 = rinv * rinv;
-        const double mr3 = (mj * rinv) * rinv2;
+        const double mr = mj * rinv;
+        const double mr3 = mr * rinv2;
+        s[6] += mr;
         const double alpha = (-3.0 * rv) * rinv2;
         s[0] = fma(mr3, dx, s[0]);
         s[1] = fma(mr3, dy, s[1]);
@@ -89,7 +92,7 @@ __global__ void __launch_bounds__(256) irregular_kernel(IrrArgs a) {
     // butterfly over the wavefront: every lane ends with the same bits
     for (int d = 32; d > 0; d >>= 1)
 #pragma unroll
-        for (int c = 0; c < 6; ++c) s[c] += __shfl_xor(s[c], d);
+        for (int c = 0; c < 7; ++c) s[c] += __shfl_xor(s[c], d);
     const bool any_bad = __ballot(bad) != 0;
     if (lane == 0) {
         if (any_bad) atomicOr(a.status, (unsigned)ST_BAD_LIST);
@@ -97,6 +100,7 @@ __global__ void __launch_bounds__(256) irregular_kernel(IrrArgs a) {
             a.acc[3 * q + c] = s[c];
             a.jerk[3 * q + c] = s[3 + c];
         }
+        if (a.pot) a.pot[q] = -s[6];
     }
 }
 

@@ -119,8 +119,9 @@ __device__ __forceinline__ float sq_bound(const IAux& ia, float w) {
 }
 
 // One i-j interaction.  run[0..2] += m r^-3 R, run[3..5] += m r^-3 (V + alpha R)
-// with alpha = -3 (R.V)/r^2, unless j is a neighbour of i, in which case j is
-// appended to i's list instead.
+// with alpha = -3 (R.V)/r^2 and, when NP == 7, run[6] += m / r (the potential
+// sum), unless j is a neighbour of i, in which case j is appended to i's list
+// instead.
 //
 // The velocity criterion is evaluated only for candidate pairs, r^2 < bnd2
 // with bnd2 = (c_i + dtr_i w)^2 for some w >= |v_j| (the caller's choice:
@@ -130,10 +131,10 @@ __device__ __forceinline__ float sq_bound(const IAux& ia, float w) {
 // rounding of every quantity involved, so the decision equals that of the
 // full test.  Candidates are rare, so the branch is seldom taken by any lane
 // of a wavefront.
-template <int MODE>
+template <int MODE, int NP>
 __device__ __forceinline__ void interact(const typename RecOf<MODE>::T& r, int j,
                                          const IPos<MODE>& ip, const IAux& ia, float bnd2,
-                                         float run[6], int qq, const RegfArgs& a) {
+                                         float run[NP], int qq, const RegfArgs& a) {
     float dx, dy, dz;
     coord_diff(r, ip, dx, dy, dz);
     const float dvx = r.vx - ia.vx;
@@ -150,8 +151,10 @@ __device__ __forceinline__ void interact(const typename RecOf<MODE>::T& r, int j
         }
     }
     const float rinv2 = rinv * rinv;
-    const float mr3 = (r.m * rinv) * rinv2;
+    const float mr = r.m * rinv;
+    const float mr3 = mr * rinv2;
     const float alpha = (-3.0f * rv) * rinv2;
+    if constexpr (NP == 7) run[6] += mr;
     run[0] = fmaf(mr3, dx, run[0]);
     run[1] = fmaf(mr3, dy, run[1]);
     run[2] = fmaf(mr3, dz, run[2]);
@@ -194,9 +197,10 @@ __device__ __forceinline__ float checked_h2(double h2) {
     return (f >= FLT_MIN && f <= FLT_MAX) ? f : -1.0f;
 }
 
-// Index of partial sum (q, s, c) in the block layout [q/64][s][c][q%64].
-__device__ __forceinline__ size_t part_index(int q, int s, int c, int nslices) {
-    return (((size_t)(q >> 6) * nslices + s) * NPART + c) * 64 + (q & 63);
+// Index of partial sum (q, s, c) in the block layout [q/64][s][c][q%64] of
+// np components per (particle, slice).
+__device__ __forceinline__ size_t part_index(int q, int s, int c, int nslices, int np) {
+    return (((size_t)(q >> 6) * nslices + s) * np + c) * 64 + (q & 63);
 }
 
 // State of active particle q for the force kernel: position, velocity,
@@ -234,7 +238,7 @@ __device__ __forceinline__ int load_i(const RegfArgs& a, const int q, const int 
 // Force, jerk and neighbour appends of one (i-group, j-slice) work item:
 // 64 * IPL active particles starting at group * 64 * IPL, against the
 // j-particles of slice s.
-template <int MODE, int IPL>
+template <int MODE, int IPL, int NP>
 __device__ __forceinline__ void regf_item(const RegfArgs& a, const int group, const int s) {
     using Rec = typename RecOf<MODE>::T;
     const_ptr<Rec> rec = (const_ptr<Rec>)(a.rec);
@@ -251,20 +255,20 @@ __device__ __forceinline__ void regf_item(const RegfArgs& a, const int group, co
     const int j0 = s * a.slice_len;
     const int j1 = min(j0 + a.slice_len, a.n);
 
-    double sum[IPL][6];
+    double sum[IPL][NP];
 #pragma unroll
     for (int k = 0; k < IPL; ++k)
 #pragma unroll
-        for (int c = 0; c < 6; ++c) sum[k][c] = 0.0;
+        for (int c = 0; c < NP; ++c) sum[k][c] = 0.0;
 
     const_ptr<float> tmax = (const_ptr<float>)(a.tmax);
     for (int jt = j0; jt < j1; jt += TILE) {  // j0 is a multiple of TILE
         const int je = min(jt + TILE, j1);
-        float run[IPL][6];
+        float run[IPL][NP];
 #pragma unroll
         for (int k = 0; k < IPL; ++k)
 #pragma unroll
-            for (int c = 0; c < 6; ++c) run[k][c] = 0.0f;
+            for (int c = 0; c < NP; ++c) run[k][c] = 0.0f;
         // candidate bound of the tile: its largest |v_j| for every j
         const float vm = tmax[jt / TILE];
         float bnd2[IPL];
@@ -285,20 +289,20 @@ __device__ __forceinline__ void regf_item(const RegfArgs& a, const int group, co
             for (int g = 0; g < G; ++g)
 #pragma unroll
                 for (int k = 0; k < IPL; ++k)
-                    interact<MODE>(r[g], j + g, ip[k], ia[k], bnd2[k], run[k],
+                    interact<MODE, NP>(r[g], j + g, ip[k], ia[k], bnd2[k], run[k],
                                    ibase + k * 64 + (int)__lane_id(), a);
         }
         for (; j < je; ++j) {
             const Rec r = load_rec(rec + j);
 #pragma unroll
             for (int k = 0; k < IPL; ++k)
-                interact<MODE>(r, j, ip[k], ia[k], bnd2[k], run[k],
+                interact<MODE, NP>(r, j, ip[k], ia[k], bnd2[k], run[k],
                                ibase + k * 64 + (int)__lane_id(), a);
         }
 #pragma unroll
         for (int k = 0; k < IPL; ++k)
 #pragma unroll
-            for (int c = 0; c < 6; ++c) sum[k][c] += (double)run[k][c];
+            for (int c = 0; c < NP; ++c) sum[k][c] += (double)run[k][c];
     }
 
     // partial sums by 64-particle block: part[q / 64][s][c][q % 64], so each
@@ -307,9 +311,9 @@ __device__ __forceinline__ void regf_item(const RegfArgs& a, const int group, co
     for (int k = 0; k < IPL; ++k) {
         const int q = ibase + k * 64 + lane;
         if (q < a.ni) {
-            double* p = a.part + part_index(q, s, 0, a.nslices);
+            double* p = a.part + part_index(q, s, 0, a.nslices, NP);
 #pragma unroll
-            for (int c = 0; c < NPART; ++c) p[c * 64] = sum[k][c];
+            for (int c = 0; c < NP; ++c) p[c * 64] = sum[k][c];
         }
     }
 }
@@ -322,7 +326,7 @@ __device__ __forceinline__ void regf_item(const RegfArgs& a, const int group, co
 // their FP64 sums; it gives the same bits in each of those lanes, and the
 // first of them stores the partial.  Used when the active block is too small
 // to give every lane its own i and still fill the chip.
-template <int MODE>
+template <int MODE, int NP>
 __device__ __forceinline__ void regf_item_lanes(const RegfArgs& a, const int group,
                                                 const int s) {
     using Rec = typename RecOf<MODE>::T;
@@ -340,15 +344,15 @@ __device__ __forceinline__ void regf_item_lanes(const RegfArgs& a, const int gro
     const int j0 = s * a.slice_len;
     const int j1 = min(j0 + a.slice_len, a.n);
 
-    double sum[6];
+    double sum[NP];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) sum[c] = 0.0;
+    for (int c = 0; c < NP; ++c) sum[c] = 0.0;
 
     for (int jt = j0; jt < j1; jt += TILE * jl) {
         const int je = min(jt + TILE * jl, j1);
-        float run[6];
+        float run[NP];
 #pragma unroll
-        for (int c = 0; c < 6; ++c) run[c] = 0.0f;
+        for (int c = 0; c < NP; ++c) run[c] = 0.0f;
         int j = jt + jsub;
         for (; j + (JG - 1) * jl < je; j += JG * jl) {
             Rec r[JG];
@@ -356,24 +360,24 @@ __device__ __forceinline__ void regf_item_lanes(const RegfArgs& a, const int gro
             for (int g = 0; g < JG; ++g) r[g] = rec[j + g * jl];
 #pragma unroll
             for (int g = 0; g < JG; ++g)
-                interact<MODE>(r[g], j + g * jl, ip, ia, sq_bound(ia, r[g].vabs), run, qq, a);
+                interact<MODE, NP>(r[g], j + g * jl, ip, ia, sq_bound(ia, r[g].vabs), run, qq, a);
         }
         for (; j < je; j += jl) {
             const Rec r = rec[j];
-            interact<MODE>(r, j, ip, ia, sq_bound(ia, r.vabs), run, qq, a);
+            interact<MODE, NP>(r, j, ip, ia, sq_bound(ia, r.vabs), run, qq, a);
         }
 #pragma unroll
-        for (int c = 0; c < 6; ++c) sum[c] += (double)run[c];
+        for (int c = 0; c < NP; ++c) sum[c] += (double)run[c];
     }
 
     for (int d = 1; d < jl; d <<= 1)
 #pragma unroll
-        for (int c = 0; c < 6; ++c) sum[c] += __shfl_xor(sum[c], d);
+        for (int c = 0; c < NP; ++c) sum[c] += __shfl_xor(sum[c], d);
 
     if (jsub == 0 && q < a.ni) {
-        double* p = a.part + part_index(q, s, 0, a.nslices);
+        double* p = a.part + part_index(q, s, 0, a.nslices, NP);
 #pragma unroll
-        for (int c = 0; c < NPART; ++c) p[c * 64] = sum[c];
+        for (int c = 0; c < NP; ++c) p[c * 64] = sum[c];
     }
 }
 
@@ -384,7 +388,7 @@ __device__ __forceinline__ void regf_item_lanes(const RegfArgs& a, const int gro
 // j-records of its own slices only.  At least 4 waves per SIMD (<= 128
 // VGPRs): below that the scalar-load latency of the j-records is no longer
 // hidden.
-template <int MODE, int IPL>
+template <int MODE, int IPL, int NP>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
 regf_kernel(RegfArgs a, int gblocks) {
     const int b = blockIdx.x;
@@ -400,12 +404,12 @@ regf_kernel(RegfArgs a, int gblocks) {
     const int wpb = blockDim.x >> 6;
     const int group = gb * wpb + (threadIdx.x >> 6);
     if (group * 64 * IPL >= a.ni) return;  // uniform across the wave
-    regf_item<MODE, IPL>(a, group, s);
+    regf_item<MODE, IPL, NP>(a, group, s);
 }
 
 // The force kernel for lanes that share an i (a.jl_shift > 0), with the grid
 // and XCD mapping of regf_kernel.
-template <int MODE>
+template <int MODE, int NP>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
 regf_lanes_kernel(RegfArgs a, int gblocks) {
     const int b = blockIdx.x;
@@ -421,7 +425,7 @@ regf_lanes_kernel(RegfArgs a, int gblocks) {
     const int wpb = blockDim.x >> 6;
     const int group = gb * wpb + (threadIdx.x >> 6);
     if (group * (64 >> a.jl_shift) >= a.ni) return;  // uniform across the wave
-    regf_item_lanes<MODE>(a, group, s);
+    regf_item_lanes<MODE, NP>(a, group, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -453,36 +457,38 @@ __device__ __forceinline__ bool invalid_i(const FinalArgs& a, int q) {
 // LDS of the finalize kernels: the four waves' slice sums, and later (the
 // same bytes) one buffer of MAX_CAPS list entries per wave.
 union FinalShared {
-    double  sum[4][NPART][64];
+    double  sum[4][NPART_POT][64];
     int32_t list[4][MAX_CAPS];
 };
 
-// Slice sums of particles 64 blk .. 64 blk + 63, by the whole workgroup.
+// Slice sums of particles 64 blk .. 64 blk + 63, by the whole workgroup
+// (NP partial components: acc, jerk and, for 7, the potential sum).
+template <int NP>
 __device__ __forceinline__ void finalize_sums(const FinalArgs& a, const int blk,
                                               FinalShared& sh) {
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int q = blk * 64 + lane;
-    double sum[NPART];
+    double sum[NP];
 #pragma unroll
-    for (int c = 0; c < NPART; ++c) sum[c] = 0.0;
+    for (int c = 0; c < NP; ++c) sum[c] = 0.0;
     if (q < a.ni) {
-        const double* p = a.part + part_index(q, 0, 0, a.nslices);
+        const double* p = a.part + part_index(q, 0, 0, a.nslices, NP);
         for (int s0 = 8 * w; s0 < a.nslices; s0 += 32) {
-            double v[8][NPART];  // the 48 loads of a run are in flight together
+            double v[8][NP];  // the 48 loads of a run are in flight together
 #pragma unroll
             for (int u = 0; u < 8; ++u)
 #pragma unroll
-                for (int c = 0; c < NPART; ++c)
-                    v[u][c] = s0 + u < a.nslices ? p[((size_t)(s0 + u) * NPART + c) * 64] : 0.0;
+                for (int c = 0; c < NP; ++c)
+                    v[u][c] = s0 + u < a.nslices ? p[((size_t)(s0 + u) * NP + c) * 64] : 0.0;
 #pragma unroll
             for (int u = 0; u < 8; ++u)
 #pragma unroll
-                for (int c = 0; c < NPART; ++c) sum[c] += v[u][c];
+                for (int c = 0; c < NP; ++c) sum[c] += v[u][c];
         }
     }
 #pragma unroll
-    for (int c = 0; c < NPART; ++c) sh.sum[w][c][lane] = sum[c];
+    for (int c = 0; c < NP; ++c) sh.sum[w][c][lane] = sum[c];
     __syncthreads();
     if (w == 0 && q < a.ni) {
         if (invalid_i(a, q)) {
@@ -491,13 +497,15 @@ __device__ __forceinline__ void finalize_sums(const FinalArgs& a, const int blk,
                 a.acc[3 * q + c] = nan;
                 a.jerk[3 * q + c] = nan;
             }
+            if (NP == 7) a.pot[q] = nan;
             a.nnb[q] = -1;
         } else {
-            for (int c = 0; c < NPART; ++c) {
+            for (int c = 0; c < NP; ++c) {
                 const double t = ((sh.sum[0][c][lane] + sh.sum[1][c][lane]) +
                                   sh.sum[2][c][lane]) + sh.sum[3][c][lane];
                 if (c < 3) a.acc[3 * q + c] = t;
-                else a.jerk[3 * q + c - 3] = t;
+                else if (c < 6) a.jerk[3 * q + c - 3] = t;
+                else a.pot[q] = -t;  // the potential is minus the sum of m / r
             }
             a.nnb[q] = a.cnt[q] - 1;  // the i itself is among the found
         }
@@ -545,9 +553,10 @@ __device__ __forceinline__ void finalize_list(const FinalArgs& a, const int q,
 }
 
 // Workgroup blk of one request's finalize.
+template <int NP>
 __device__ __forceinline__ void finalize_block(const FinalArgs& a, const int blk,
                                                FinalShared& sh) {
-    if (blk * 64 < a.ni) finalize_sums(a, blk, sh);  // uniform across the workgroup
+    if (blk * 64 < a.ni) finalize_sums<NP>(a, blk, sh);  // uniform across the workgroup
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     constexpr int PPW = FINAL_PPB / 4;
@@ -570,9 +579,10 @@ __device__ __forceinline__ void finalize_block(const FinalArgs& a, const int blk
         if (ok[k]) finalize_list(a, q0 + k, self[k], count[k], first[k], sh.list[w]);
 }
 
+template <int NP>
 __global__ void __launch_bounds__(256) finalize_kernel(FinalArgs a) {
     __shared__ FinalShared sh;
-    finalize_block(a, blockIdx.x, sh);
+    finalize_block<NP>(a, blockIdx.x, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -635,7 +645,7 @@ __global__ void __launch_bounds__(256) overflow_kernel(OverflowArgs a) {
 // address space does not compile); the sizes pin the field lists, so a field
 // added to an argument struct cannot be left out here unnoticed.
 static_assert(sizeof(RegfArgs) == 104, "load_regf_args must copy every RegfArgs field");
-static_assert(sizeof(FinalArgs) == 120, "load_final_args must copy every FinalArgs field");
+static_assert(sizeof(FinalArgs) == 128, "load_final_args must copy every FinalArgs field");
 static_assert(sizeof(OverflowArgs) == 72, "load_overflow_args must copy every field");
 
 __device__ __forceinline__ RegfArgs load_regf_args(const_ptr<ReqDesc> d) {
@@ -651,7 +661,8 @@ __device__ __forceinline__ FinalArgs load_final_args(const_ptr<ReqDesc> d) {
     FinalArgs f;
     f.part = d->fin.part; f.cnt = d->fin.cnt; f.lst = d->fin.lst; f.nslices = d->fin.nslices;
     f.ni = d->fin.ni; f.caps = d->fin.caps; f.n = d->fin.n; f.idx = d->fin.idx; f.h2 = d->fin.h2;
-    f.acc = d->fin.acc; f.jerk = d->fin.jerk; f.nnb = d->fin.nnb; f.list = d->fin.list;
+    f.acc = d->fin.acc; f.jerk = d->fin.jerk; f.pot = d->fin.pot; f.nnb = d->fin.nnb;
+    f.list = d->fin.list;
     f.cap = d->fin.cap; f.status = d->fin.status; f.ovf_count = d->fin.ovf_count;
     f.ovf_list = d->fin.ovf_list;
     return f;
@@ -691,9 +702,9 @@ serve_regf_kernel(BatchArgs b) {
         const long long local = item - reqs[lo].item0;
         const int groups = reqs[lo].groups;
         if (a.jl_shift > 0)
-            regf_item_lanes<MODE>(a, (int)(local % groups), (int)(local / groups));
+            regf_item_lanes<MODE, NPART>(a, (int)(local % groups), (int)(local / groups));
         else
-            regf_item<MODE, 1>(a, (int)(local % groups), (int)(local / groups));
+            regf_item<MODE, 1, NPART>(a, (int)(local % groups), (int)(local / groups));
     }
 }
 
@@ -708,7 +719,7 @@ __global__ void __launch_bounds__(256) serve_finalize_kernel(BatchArgs b) {
         if (reqs[mid].blk0 <= gb) lo = mid; else hi = mid - 1;
     }
     const FinalArgs f = load_final_args(reqs + lo);
-    finalize_block(f, (int)(gb - reqs[lo].blk0), sh);
+    finalize_block<NPART>(f, (int)(gb - reqs[lo].blk0), sh);
 }
 
 template <int MODE>
@@ -861,7 +872,7 @@ __global__ void zero_u32_kernel(unsigned* p, int n) {
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
-template <int MODE, int IPL>
+template <int MODE, int IPL, int NP>
 static hipError_t launch_regf_t(int wpb, const RegfArgs& a, hipStream_t st) {
     if (a.jl_shift < 0 || a.jl_shift > 6 || (a.jl_shift > 0 && IPL != 1))
         return hipErrorInvalidValue;
@@ -871,23 +882,28 @@ static hipError_t launch_regf_t(int wpb, const RegfArgs& a, hipStream_t st) {
     const long long blocks = (long long)gblocks * a.nslices;
     if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
     if (a.jl_shift > 0)
-        hipLaunchKernelGGL((regf_lanes_kernel<MODE>), dim3((unsigned)blocks), dim3(64 * wpb), 0,
-                           st, a, gblocks);
+        hipLaunchKernelGGL((regf_lanes_kernel<MODE, NP>), dim3((unsigned)blocks), dim3(64 * wpb),
+                           0, st, a, gblocks);
     else
-        hipLaunchKernelGGL((regf_kernel<MODE, IPL>), dim3((unsigned)blocks), dim3(64 * wpb), 0,
-                           st, a, gblocks);
+        hipLaunchKernelGGL((regf_kernel<MODE, IPL, NP>), dim3((unsigned)blocks), dim3(64 * wpb),
+                           0, st, a, gblocks);
     return hipGetLastError();
 }
 
-hipError_t launch_regf(int mode, int ipl, int wpb, const RegfArgs& a, hipStream_t s) {
+hipError_t launch_regf(int mode, int ipl, int wpb, bool pot, const RegfArgs& a,
+                       hipStream_t s) {
     if (wpb < 1 || wpb > 4) return hipErrorInvalidValue;
-    switch (mode * 4 + ipl) {
-        case MODE_FF * 4 + 1:  return launch_regf_t<MODE_FF, 1>(wpb, a, s);
-        case MODE_FF * 4 + 2:  return launch_regf_t<MODE_FF, 2>(wpb, a, s);
-        case MODE_F64 * 4 + 1: return launch_regf_t<MODE_F64, 1>(wpb, a, s);
-        case MODE_F64 * 4 + 2: return launch_regf_t<MODE_F64, 2>(wpb, a, s);
-        case MODE_F32 * 4 + 1: return launch_regf_t<MODE_F32, 1>(wpb, a, s);
-        case MODE_F32 * 4 + 2: return launch_regf_t<MODE_F32, 2>(wpb, a, s);
+    switch ((mode * 4 + ipl) * 2 + (pot ? 1 : 0)) {
+#define NB6_REGF_CASE(M, I)                                                                   \
+        case (M * 4 + I) * 2: return launch_regf_t<M, I, NPART>(wpb, a, s);                  \
+        case (M * 4 + I) * 2 + 1: return launch_regf_t<M, I, NPART_POT>(wpb, a, s);
+        NB6_REGF_CASE(MODE_FF, 1)
+        NB6_REGF_CASE(MODE_FF, 2)
+        NB6_REGF_CASE(MODE_F64, 1)
+        NB6_REGF_CASE(MODE_F64, 2)
+        NB6_REGF_CASE(MODE_F32, 1)
+        NB6_REGF_CASE(MODE_F32, 2)
+#undef NB6_REGF_CASE
         default: return hipErrorInvalidValue;
     }
 }
@@ -895,7 +911,11 @@ hipError_t launch_regf(int mode, int ipl, int wpb, const RegfArgs& a, hipStream_
 hipError_t launch_finalize(const FinalArgs& a, hipStream_t s) {
     if (a.ni <= 0) return hipSuccess;
     if (a.caps > MAX_CAPS) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)final_blocks(a.ni)), dim3(256), 0, s, a);
+    const dim3 grid((unsigned)final_blocks(a.ni)), block(256);
+    if (a.pot)
+        hipLaunchKernelGGL(finalize_kernel<NPART_POT>, grid, block, 0, s, a);
+    else
+        hipLaunchKernelGGL(finalize_kernel<NPART>, grid, block, 0, s, a);
     return hipGetLastError();
 }
 

@@ -108,7 +108,7 @@ def lib():
                                          ctypes.c_int, vp]
         L.nb6_predict_j.argtypes = [vp, ctypes.c_int, ctypes.c_double, ctypes.c_int, vp]
         L.nb6_regular_force.argtypes = [vp, ctypes.c_int, i64, vp, vp, vp, ctypes.c_int,
-                                        vp, vp, vp, vp, ctypes.c_int32, ctypes.c_int, vp]
+                                        vp, vp, vp, vp, vp, ctypes.c_int32, ctypes.c_int, vp]
         L.nb6_sync_status.argtypes = [vp, vp]
         L.nb6_kernel_times.argtypes = [vp, vp, vp]
         L.nb6_submit.argtypes = [vp, ctypes.POINTER(nb6_request), ctypes.POINTER(ctypes.c_uint64)]
@@ -117,7 +117,7 @@ def lib():
         L.nb6_set_lists.argtypes = [vp, ctypes.c_int, i64, vp, vp, vp, ctypes.c_int32,
                                     ctypes.c_int, vp]
         L.nb6_irregular_force.argtypes = [vp, ctypes.c_int, ctypes.c_double, i64, vp, vp, vp,
-                                          ctypes.c_int, vp]
+                                          vp, ctypes.c_int, vp]
         for name in EXPORTED:
             if name != "nb6_last_error":
                 getattr(L, name).restype = ctypes.c_int
@@ -209,11 +209,13 @@ def nb6_predict_j(ctx, cluster, t_block, modes=0, stream=None):
 
 
 def nb6_regular_force(ctx, cluster, n_i, idx_i, h2_i, dtr_i, dx_mode, acc, jerk,
-                      nnb, nblist, cap, mem_kind=NB6_MEM_HOST, stream=None):
+                      nnb, nblist, cap, mem_kind=NB6_MEM_HOST, stream=None, pot=None):
+    """The C entry point; ``pot`` (optional) is its potential output, which the
+    C signature takes after ``jerk``."""
     f = np.float64
     return lib().nb6_regular_force(
         ctx, cluster, n_i, _ptr(idx_i, np.int32), _ptr(h2_i, f), _ptr(dtr_i, f),
-        dx_mode, _ptr(acc, f), _ptr(jerk, f), _ptr(nnb, np.int32),
+        dx_mode, _ptr(acc, f), _ptr(jerk, f), _ptr(pot, f), _ptr(nnb, np.int32),
         _ptr(nblist, np.int32), cap, mem_kind, _stream(stream))
 
 
@@ -224,10 +226,11 @@ def nb6_set_lists(ctx, cluster, n_i, idx_i, nnb_i, nblist, cap, mem_kind=NB6_MEM
 
 
 def nb6_irregular_force(ctx, cluster, t_block, n_i, idx_i, acc, jerk, mem_kind=NB6_MEM_HOST,
-                        stream=None):
+                        stream=None, pot=None):
     f = np.float64
     return lib().nb6_irregular_force(ctx, cluster, float(t_block), n_i, _ptr(idx_i, np.int32),
-                                     _ptr(acc, f), _ptr(jerk, f), mem_kind, _stream(stream))
+                                     _ptr(acc, f), _ptr(jerk, f), _ptr(pot, f), mem_kind,
+                                     _stream(stream))
 
 
 def nb6_get_predicted(ctx, cluster, dx_mode, x, v, mem_kind=NB6_MEM_HOST, stream=None):
@@ -273,8 +276,10 @@ def nb6_sync_status(ctx, stream=None):
 
 
 # ---- convenience: allocate outputs, raise on errors ------------------------
-def regular_force_host(ctx, cluster, idx_i, h2_i, dtr_i, dx_mode=NB6_DX_FF, cap=256):
-    """Host-memory call; returns (acc, jerk, nnb, lists, status)."""
+def regular_force_host(ctx, cluster, idx_i, h2_i, dtr_i, dx_mode=NB6_DX_FF, cap=256,
+                       with_pot=False):
+    """Host-memory call; returns (acc, jerk, nnb, lists, status), and the
+    potential as a sixth item when ``with_pot``."""
     idx_i = np.ascontiguousarray(idx_i, dtype=np.int32)
     ni = len(idx_i)
     h2_i = np.ascontiguousarray(np.broadcast_to(h2_i, (ni,)), dtype=np.float64)
@@ -283,9 +288,12 @@ def regular_force_host(ctx, cluster, idx_i, h2_i, dtr_i, dx_mode=NB6_DX_FF, cap=
     jerk = np.empty((ni, 3))
     nnb = np.empty(ni, np.int32)
     lst = np.empty((ni, max(cap, 1)), np.int32)
+    pot = np.empty(ni) if with_pot else None
     rc = nb6_regular_force(ctx, cluster, ni, idx_i, h2_i, dtr_i, dx_mode, acc, jerk,
-                           nnb, lst if cap > 0 else None, cap, NB6_MEM_HOST)
+                           nnb, lst if cap > 0 else None, cap, NB6_MEM_HOST, pot=pot)
     check(ctx, rc, (NB6_OK, NB6_WARN_NB_OVERFLOW))
+    if with_pot:
+        return acc, jerk, nnb, lst[:, :cap], rc, pot
     return acc, jerk, nnb, lst[:, :cap], rc
 
 
@@ -299,11 +307,14 @@ def set_lists_host(ctx, cluster, idx_i, nnb_i, nblist):
                              nblist.shape[1] if nblist.ndim == 2 else 1, NB6_MEM_HOST))
 
 
-def irregular_force_host(ctx, cluster, t_block, idx_i):
-    """Host-memory nb6_irregular_force; returns (acc, jerk)."""
+def irregular_force_host(ctx, cluster, t_block, idx_i, with_pot=False):
+    """Host-memory nb6_irregular_force; returns (acc, jerk), and the potential
+    as a third item when ``with_pot``."""
     idx_i = np.ascontiguousarray(idx_i, dtype=np.int32)
     ni = len(idx_i)
     acc = np.empty((ni, 3))
     jerk = np.empty((ni, 3))
-    check(ctx, nb6_irregular_force(ctx, cluster, t_block, ni, idx_i, acc, jerk, NB6_MEM_HOST))
-    return acc, jerk
+    pot = np.empty(ni) if with_pot else None
+    check(ctx, nb6_irregular_force(ctx, cluster, t_block, ni, idx_i, acc, jerk, NB6_MEM_HOST,
+                                   pot=pot))
+    return (acc, jerk, pot) if with_pot else (acc, jerk)

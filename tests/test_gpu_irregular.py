@@ -66,11 +66,16 @@ def test_irregular_matches_oracle(ctx, cfg_id):
     load(ctx, cl)
     _, _, nnb, lst = regular_lists(ctx, cl, idx)
     nb6.set_lists_host(ctx, 0, idx, nnb, lst)
-    acc, jerk = nb6.irregular_force_host(ctx, 0, cl.tb, idx)
+    acc, jerk, pot = nb6.irregular_force_host(ctx, 0, cl.tb, idx, with_pot=True)
     xp, vp = oracle.predict(cl.x, cl.v, cl.a, cl.jerk, cl.t, cl.tb)
     lists = [lst[q, :nnb[q]] for q in range(len(idx))]
     ref = oracle.irregular_force(cl.m, xp, vp, idx, lists)
     check_irr(acc, jerk, ref, f"C{cfg_id}")
+    has = ref.pot != 0
+    assert np.all(pot[~has] == 0)
+    assert np.max(np.abs(pot[has] - ref.pot[has]) / np.abs(ref.pot[has])) <= TOL
+    acc0, jerk0 = nb6.irregular_force_host(ctx, 0, cl.tb, idx)
+    assert np.array_equal(acc0, acc) and np.array_equal(jerk0, jerk)
     # another block time: the library predicts every needed particle itself
     tb2 = cl.tb + 2.0 ** -10
     acc2, jerk2 = nb6.irregular_force_host(ctx, 0, tb2, idx)
@@ -95,6 +100,30 @@ def test_regular_plus_irregular_is_the_full_force(ctx):
     ej = np.linalg.norm(rjerk + ijerk - full.jerk, axis=1) / full.sj
     print("partition scaled err", ea.max(), ej.max(), flush=True)
     assert ea.max() <= 1e-6 and ej.max() <= 1e-6
+
+
+def test_potential_energy(ctx):
+    """W = (1/2) sum m_i (phi_reg,i + phi_irr,i) over a whole cluster from the
+    GPU's two potentials, against the oracle's full potential: the energy
+    check of section 4 (it quotes 1e-8 for the GPU's potential; here the
+    FP32 regular sum, compensated by the FP64 tile folds)."""
+    nb6 = _nb6()
+    cl = make_cluster(4096, 53, masses="imf", k_nb=40)
+    idx = np.arange(cl.n, dtype=np.int32)
+    load(ctx, cl)
+    _, _, nnb, lst, _, preg = nb6.regular_force_host(ctx, 0, idx, cl.h2, cl.dtr,
+                                                     nb6.NB6_DX_FF, 512, with_pot=True)
+    assert nnb.max() <= 512
+    nb6.set_lists_host(ctx, 0, idx, nnb, lst)
+    _, _, pirr = nb6.irregular_force_host(ctx, 0, cl.tb, idx, with_pot=True)
+    xp, vp = oracle.predict(cl.x, cl.v, cl.a, cl.jerk, cl.t, cl.tb)
+    full = oracle.regular_force(cl.m, xp, vp, idx, 1e-300, 0.0, lcap=4)
+    w_gpu = 0.5 * np.sum(cl.m * (preg + pirr))
+    w_ref = 0.5 * np.sum(cl.m * full.pot)
+    print("W gpu %.15g oracle %.15g rel %.3g" % (w_gpu, w_ref, abs(w_gpu / w_ref - 1)), flush=True)
+    assert abs(w_gpu / w_ref - 1.0) <= 1e-7
+    per = np.abs(preg + pirr - full.pot) / np.abs(full.pot)
+    assert per.max() <= 1e-6, per.max()
 
 
 def test_config3_full_size_device_chain(ctx):

@@ -381,6 +381,39 @@ def test_config5_full_size_sampled(ctx, block, mode):
         assert s.get("jerk_rel_max", 0.0) <= TOL_REL[mode], s
 
 
+@pytest.mark.parametrize("mode", ["ff", "fp64", "fp32"])
+def test_potential(ctx, mode):
+    """The optional regular potential (-sum m/r over the non-neighbours) against
+    the oracle, on a one-lane-per-i block, a small lanes-per-i block and C3's
+    binaries; asking for it leaves acc, jerk and the lists bit-identical."""
+    nb6 = _nb6()
+    tol = {"ff": 1e-6, "fp64": 1e-6, "fp32": 1e-5}[mode]
+    cases = [(config(2)["cluster"], config(2)["blocks"]["random1024"]),
+             (config(2)["cluster"], config(2)["blocks"]["random1024"][:37])]
+    if mode == "ff":
+        c3 = config(3)
+        cases.append((c3["cluster"], c3["blocks"]["pow2_12"]))
+    for cl, idx in cases:
+        load(ctx, cl)
+        a0, j0, n0, l0, _ = nb6.regular_force_host(ctx, 0, idx, cl.h2[idx], cl.dtr[idx],
+                                                   MODES[mode], 256)
+        a1, j1, n1, l1, _, pot = nb6.regular_force_host(ctx, 0, idx, cl.h2[idx], cl.dtr[idx],
+                                                        MODES[mode], 256, with_pot=True)
+        assert np.array_equal(a0, a1) and np.array_equal(j0, j1) and np.array_equal(n0, n1)
+        for q in range(len(idx)):
+            k = min(n0[q], 256)
+            assert np.array_equal(l0[q, :k], l1[q, :k])
+        rng = np.random.Generator(np.random.PCG64(13))
+        samp = np.sort(rng.choice(len(idx), min(128, len(idx)), replace=False))
+        xp, vp = oracle.predict(cl.x, cl.v, cl.a, cl.jerk, cl.t, cl.tb)
+        si = idx[samp]
+        ref = oracle.regular_force(cl.m, xp, vp, si, cl.h2[si], cl.dtr[si], lcap=4096)
+        ok = n0[samp] == ref.nnb  # boundary pairs move a term between the two sums
+        rel = np.abs(pot[samp] - ref.pot) / np.abs(ref.pot)
+        print(mode, len(idx), "pot rel err max %.3g" % rel[ok].max(), flush=True)
+        assert ok.mean() > 0.98 and rel[ok].max() <= tol, rel[ok].max()
+
+
 @pytest.mark.parametrize("n", [1024, 1500])
 def test_everything_neighbour_long_lists(ctx, n):
     """h -> infinity: every j is a neighbour.  N = 1024 fills the largest list
