@@ -110,6 +110,7 @@ def counter_summary(fetch_csv, write_csv, valu_csv, copy_mib, config_line, pairs
                         2.0 * valu["SQ_INSTS_VALU_FMA_F32"] + valu["SQ_INSTS_VALU_TRANS_F32"])
         machine["fp32_flop"] = flops
     cmd = ("python3 bench.py --steps 2 --warmup 1 --no-serving --no-cpu-baseline --no-irregular "
+           "--no-potential "
            f"--copy-mib {copy_mib}")
     lines = [
         "# Counters of the force kernel, Plummer N = 131072, all 131072 active (FF)",
@@ -451,6 +452,38 @@ def irregular_leg(args, nb6, torch, ctx, cl, idx_np, idx_d, nnb, lst):
     return res
 
 
+def potential_leg(args, nb6, torch, ctx, idx_d, h2_d, dtr_d, ni, mode, regf_ms, pairs):
+    """The same force call with the optional potential output: force-kernel
+    time against the call without it (one FP32 add per pair and a seventh
+    partial component)."""
+    stream = torch.cuda.current_stream()
+    dev = idx_d.device
+    acc = torch.empty((ni, 3), dtype=torch.float64, device=dev)
+    jerk = torch.empty_like(acc)
+    pot = torch.empty(ni, dtype=torch.float64, device=dev)
+    nnb = torch.empty(ni, dtype=torch.int32, device=dev)
+    lst = torch.empty((ni, max(args.cap, 1)), dtype=torch.int32, device=dev)
+
+    def call():
+        nb6.check(ctx, nb6.nb6_regular_force(ctx, 0, ni, idx_d, h2_d, dtr_d, mode, acc, jerk,
+                                             nnb, lst, args.cap, nb6.NB6_MEM_DEVICE, stream,
+                                             pot=pot))
+    call()
+    torch.cuda.synchronize()
+    nb6.nb6_kernel_times(ctx)
+    reps = max(3, min(20, int(args.steps)))
+    for _ in range(reps):
+        call()
+    torch.cuda.synchronize()
+    ms, cnt = nb6.nb6_kernel_times(ctx)
+    k_ms = ms[1] / max(cnt[1], 1)
+    log(f"bench: regular force with potential: kernel {k_ms:.4f} ms vs {regf_ms:.4f} ms")
+    return {"kernel_ms": round(k_ms, 5), "kernel_ms_without": round(regf_ms, 5),
+            "overhead_pct": round(100.0 * (k_ms / regf_ms - 1.0), 2),
+            "kernel_ginteractions_s": round(pairs / (k_ms * 1e-3) / 1e9, 3),
+            "finalize_ms": round(ms[2] / max(cnt[2], 1), 5)}
+
+
 def block_sweep(args, cfg, nb6, torch, T, lanes=0, slices=None, max_ni=None, max_reps=200):
     """Force-call time for every block of the configuration (one JSON line each):
     wall time per call on a context without event timing (back-to-back calls on
@@ -543,6 +576,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-irregular", action="store_true")
+    ap.add_argument("--no-potential", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=20000)
     ap.add_argument("--serve-calibrate", type=int, default=300)
     ap.add_argument("--serve-cap", type=int, default=128)
@@ -714,6 +748,9 @@ def main():
                 100.0 * rec["fp32_flop"] / (regf_ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, 2)
     gpu_out = (acc.cpu().numpy(), jerk.cpu().numpy(), nnb.cpu().numpy(),
                lst[:, :args.cap].cpu().numpy())
+    if not args.no_potential:
+        out["potential"] = potential_leg(args, nb6, torch, ctx, idx_d, h2_d, dtr_d, ni, mode,
+                                         regf_ms, pairs)
     if not args.no_irregular:
         out["irregular"] = irregular_leg(args, nb6, torch, ctx, cl, idx_np, idx_d, nnb, lst)
     nb6.nb6_destroy(ctx)
