@@ -199,10 +199,21 @@ def cpu_baseline(cl, idx, gpu_out, cap, target_s):
     acc, jerk, nnb, lst = gpu_out
     c = compare(acc[samp], jerk[samp], nnb[samp], lst[samp], cap, ref, cl.m, xp, vp, si,
                 cl.h2[si], cl.dtr[si])
+    cores = oracle.max_threads()
+    # the same oracle on one core, on a smaller sample (then all cores again)
+    n1 = max(1, min(len(idx), int(ns * 2.0 / max(dt * cores, 1e-6))))
+    s1 = idx[np.sort(order[:n1])]
+    t0 = time.perf_counter()
+    oracle.regular_force(cl.m, xp, vp, s1, cl.h2[s1], cl.dtr[s1], lcap=4096, nthreads=1)
+    dt1 = time.perf_counter() - t0
+    oracle.regular_force(cl.m, xp, vp, s1[:1], cl.h2[s1[:1]], cl.dtr[s1[:1]], lcap=4096,
+                         nthreads=cores)
     base = {"value": pairs / dt / 1e9, "unit": "Ginteractions/s",
-            "cores": oracle.max_threads(), "kind": "oracle",
+            "cores": cores, "kind": "oracle",
             "sample": f"{ns} of the {len(idx)} active i against all {cl.n} j "
-                      f"({pairs:.3g} pairs, {dt:.1f} s, FP64 C with OpenMP)"}
+                      f"({pairs:.3g} pairs, {dt:.1f} s, FP64 C with OpenMP)",
+            "single_core_value": n1 * (cl.n - 1) / dt1 / 1e9,
+            "single_core_sample": f"{n1} i ({dt1:.1f} s, one thread)"}
     return base, c.summary()
 
 
