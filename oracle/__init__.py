@@ -16,7 +16,9 @@ from .oracle import (  # noqa: F401
     regular_force,
     pair_terms,
     irregular_force,
+    regular_correct,
     max_threads,
     OracleResult,
     IrregularResult,
+    CorrectResult,
 )

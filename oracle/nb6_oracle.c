@@ -30,6 +30,11 @@
  *     (i, j) pairs; the tests use it to treat pairs that sit on the
  *     neighbour-radius boundary.
  *
+ *   - nb6o_regular_correct: the regular corrector of a block -- the
+ *     neighbour-change correction of the regular force difference (section
+ *     3.6), the derivatives of the regular force by Hermite interpolation,
+ *     the next regular step and the new neighbour radius (equation 1).
+ *
  *   - nb6o_irregular_force: the irregular force and its time derivative of
  *     section 3.3 step 4, the sums over the entries of each active
  *     particle's neighbour list L_i (the quantity the irregular-force
@@ -318,6 +323,96 @@ int nb6o_irregular_force(int64_t n, const double *m, const double *xp,
         if (sa) sa[q] = nsum_get(&SA);
         if (sj) sj[q] = nsum_get(&SJ);
         if (pot) pot[q] = nsum_get(&PHI);
+    }
+    return 0;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Regular corrector of a block (section 3.3 step 7, section 3.6, eq. 1)    */
+/* ---------------------------------------------------------------------- */
+/*
+ * For each particle q of a block that reached its regular time t:
+ *   h = t - t_old[q] (> 0), the length of its last regular step;
+ *   the regular force change over the step with the neighbour set held
+ *   fixed, section 3.6: the raw change plus the change of the irregular force
+ *   at t from the old to the new list,
+ *     dF  = (F_new - F_old)   + (G_new - G_old)
+ *     dFd = (Fd_new - Fd_old) + (Gd_new - Gd_old)
+ *   (F, Fd: regular force and derivative, at t_old for "old" and at t for
+ *   "new"; G, Gd: irregular force and derivative at t with the old and the
+ *   new list);
+ *   the cubic through (F_old, Fd_old) at t_old and (F_old + dF, Fd_old + dFd)
+ *   at t -- the fourth-order Hermite scheme (Makino & Aarseth 1992, which
+ *   section 2 cites for the neighbour-change corrections) -- gives
+ *     F2(t_old) = (6 dF - h (6 Fd_old + 2 dFd)) / h^2
+ *     F3        = (-12 dF + 6 h (2 Fd_old + dFd)) / h^3
+ *     F2(t)     = F2(t_old) + h F3;
+ *   the next regular step: the standard criterion on the regular force at t,
+ *     dt_est = sqrt(eta (|F_new| |F2(t)| + |Fd_new|^2)
+ *                       / (|Fd_new| |F3| + |F2(t)|^2)),
+ *   taken down to the largest power of two that is <= min(dt_est, 2 h,
+ *   dt_max) and divides t (block steps stay commensurate with the block
+ *   time, section 3.3 step 2), and not below dt_min;
+ *   the new neighbour radius, equation (1):
+ *     h_new = h_old f,  f = (n_p / n_nb)^(1/3) limited to [f_lo, f_hi],
+ *     f = f_hi when the new list is empty (section 2: the empty case is
+ *     catered for; the limits stand for its boundary modifications).
+ * Arrays: t_old, h_old, n_p, dt_new, h_new [n]; nnb [n]; all vectors [n][3].
+ * dt_min, dt_max: powers of two, dt_min <= dt_max; 0 < f_lo <= f_hi.
+ * Returns 0, -1 for a bad parameter, -4 when some h <= 0 (nothing computed).
+ */
+static double pow2_floor_dividing(double limit, double t, double dt_min, double dt_max)
+{
+    double d = dt_max;
+    while (d > dt_min && (d > limit || fmod(t, d) != 0.0)) d *= 0.5;
+    return d;
+}
+
+static double norm3(const double *x)
+{
+    return sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+}
+
+int nb6o_regular_correct(int64_t n, double t, const double *t_old,
+                         const double *f_old, const double *fd_old,
+                         const double *f_new, const double *fd_new,
+                         const double *g_old, const double *gd_old,
+                         const double *g_new, const double *gd_new,
+                         const double *h_old, const int32_t *nnb, const double *n_p,
+                         double eta, double dt_min, double dt_max, double f_lo,
+                         double f_hi, double *df, double *dfd, double *f2,
+                         double *f3, double *dt_new, double *h_new)
+{
+    int e_min, e_max;
+    if (!(eta > 0.0) || !(dt_min > 0.0) || !(dt_max >= dt_min) ||
+        frexp(dt_min, &e_min) != 0.5 || frexp(dt_max, &e_max) != 0.5 ||
+        !(f_lo > 0.0) || !(f_hi >= f_lo))
+        return -1;
+    for (int64_t q = 0; q < n; ++q)
+        if (!(t - t_old[q] > 0.0)) return -4;
+    for (int64_t q = 0; q < n; ++q) {
+        const double h = t - t_old[q];
+        double F2[3], F3[3];
+        for (int c = 0; c < 3; ++c) {
+            const int64_t k = 3 * q + c;
+            const double dF = (f_new[k] - f_old[k]) + (g_new[k] - g_old[k]);
+            const double dFd = (fd_new[k] - fd_old[k]) + (gd_new[k] - gd_old[k]);
+            const double f2_old = (6.0 * dF - h * (6.0 * fd_old[k] + 2.0 * dFd)) / (h * h);
+            F3[c] = (-12.0 * dF + 6.0 * h * (2.0 * fd_old[k] + dFd)) / (h * h * h);
+            F2[c] = f2_old + h * F3[c];
+            df[k] = dF;
+            dfd[k] = dFd;
+            f2[k] = F2[c];
+            f3[k] = F3[c];
+        }
+        const double a = norm3(f_new + 3 * q), ad = norm3(fd_new + 3 * q);
+        const double a2 = norm3(F2), a3 = norm3(F3);
+        const double est = sqrt(eta * (a * a2 + ad * ad) / (ad * a3 + a2 * a2));
+        const double lim = fmin(fmin(est, 2.0 * h), dt_max);
+        dt_new[q] = pow2_floor_dividing(lim, t, dt_min, dt_max);
+        double f = f_hi;
+        if (nnb[q] > 0) f = fmin(fmax(cbrt(n_p[q] / (double)nnb[q]), f_lo), f_hi);
+        h_new[q] = h_old[q] * f;
     }
     return 0;
 }

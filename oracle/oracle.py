@@ -62,6 +62,12 @@ def _bind(lib):
         i64, d, d, d, i64, i32, i32, i32, i64, d, d, d, d, d, ctypes.c_int,
     ]
     lib.nb6o_irregular_force.restype = ctypes.c_int
+    lib.nb6o_regular_correct.argtypes = [
+        i64, ctypes.c_double, d, d, d, d, d, d, d, d, d, d, i32, d,
+        ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+        ctypes.c_double, d, d, d, d, d, d,
+    ]
+    lib.nb6o_regular_correct.restype = ctypes.c_int
     lib.nb6o_max_threads.argtypes = []
     lib.nb6o_max_threads.restype = ctypes.c_int
     return lib
@@ -198,3 +204,35 @@ def irregular_force(m, xp, vp, idx, lists, nthreads=0, lib=None):
     if rc != 0:
         raise ValueError(f"oracle rejected its input (code {rc})")
     return IrregularResult(acc, jrk, sa, sj, pot)
+
+
+@dataclass
+class CorrectResult:
+    df: np.ndarray       # [n, 3] regular force change over the step, fixed neighbour set
+    dfd: np.ndarray      # [n, 3] the same for the derivative
+    f2: np.ndarray       # [n, 3] second derivative of the regular force at t
+    f3: np.ndarray       # [n, 3] third derivative
+    dt_new: np.ndarray   # [n] next regular step
+    h_new: np.ndarray    # [n] new neighbour radius
+
+
+def regular_correct(t, t_old, f_old, fd_old, f_new, fd_new, g_old, gd_old, g_new, gd_new,
+                    h_old, nnb, n_p, eta=0.02, dt_min=2.0 ** -20, dt_max=1.0,
+                    f_lo=0.5, f_hi=1.25, lib=None):
+    """Regular corrector of a block (see ``nb6o_regular_correct``)."""
+    lib = lib or _load()
+    t_old = _f64(np.atleast_1d(t_old))
+    n = len(t_old)
+    vecs = [_f64(q, (n, 3)) for q in (f_old, fd_old, f_new, fd_new, g_old, gd_old, g_new,
+                                       gd_new)]
+    h_old = _f64(np.broadcast_to(h_old, (n,)), (n,))
+    n_p = _f64(np.broadcast_to(n_p, (n,)), (n,))
+    nnb = np.ascontiguousarray(np.broadcast_to(nnb, (n,)), dtype=np.int32)
+    out = [np.zeros((n, 3)) for _ in range(4)] + [np.zeros(n), np.zeros(n)]
+    rc = lib.nb6o_regular_correct(
+        n, float(t), _pd(t_old), *[_pd(v) for v in vecs], _pd(h_old), _pi(nnb), _pd(n_p),
+        float(eta), float(dt_min), float(dt_max), float(f_lo), float(f_hi),
+        *[_pd(o) for o in out])
+    if rc != 0:
+        raise ValueError(f"oracle rejected its input (code {rc})")
+    return CorrectResult(*out)

@@ -410,6 +410,98 @@ def pin_irregular_list_semantics(lib=None):
     assert _close(r2.acc, 2.0 * r1.acc, 1e-15) and _close(r2.jerk, 2.0 * r1.jerk, 1e-15)
 
 
+# --------------------------------------------------------------------------
+# Regular corrector (section 3.3 step 7, section 3.6, equation 1)
+# --------------------------------------------------------------------------
+def _cubic_block(rng, n, h):
+    """A regular force that is an exact cubic in time: returns the corrector
+    inputs of one step of length h and the exact F2(t), F3."""
+    c = rng.normal(size=(4, n, 3))
+    c[3] *= 10.0
+    f_old, fd_old = c[0], c[1]
+    f_new = c[0] + c[1] * h + c[2] * h * h / 2.0 + c[3] * h ** 3 / 6.0
+    fd_new = c[1] + c[2] * h + c[3] * h * h / 2.0
+    return f_old, fd_old, f_new, fd_new, c[2] + c[3] * h, c[3]
+
+
+def pin_corrector_hermite_cubic(lib=None):
+    """Hermite interpolation is exact for a cubic force: F2 at the new time
+    and F3 come back to rounding, and with no list change dF = F_new - F_old."""
+    rng = np.random.default_rng(41)
+    n, t, h = 64, 1.0, 2.0 ** -5
+    f_old, fd_old, f_new, fd_new, f2, f3 = _cubic_block(rng, n, h)
+    z = np.zeros((n, 3))
+    g = rng.normal(size=(n, 3))
+    r = oracle.regular_correct(t, np.full(n, t - h), f_old, fd_old, f_new, fd_new, g, z, g, z,
+                               0.1, 40, 40, lib=lib)
+    assert _close(r.df, f_new - f_old, 1e-15) and _close(r.dfd, fd_new - fd_old, 1e-15)
+    assert np.max(np.abs(r.f2 - f2) / (1.0 + np.abs(f2))) < 1e-9
+    assert np.max(np.abs(r.f3 - f3) / (1.0 + np.abs(f3))) < 1e-9
+
+
+def pin_corrector_list_change(lib=None):
+    """Section 3.6: a term that moves between the regular and the irregular
+    force at the new time changes nothing -- the regular change is taken over
+    a fixed neighbour set."""
+    rng = np.random.default_rng(43)
+    n, t, h = 64, 0.75, 2.0 ** -6
+    f_old, fd_old, f_new, fd_new, _, _ = _cubic_block(rng, n, h)
+    g_old, gd_old = rng.normal(size=(2, n, 3))
+    x, xd = rng.normal(size=(2, n, 3))
+    base = oracle.regular_correct(t, np.full(n, t - h), f_old, fd_old, f_new, fd_new,
+                                  g_old, gd_old, g_old, gd_old, 0.1, 40, 40, lib=lib)
+    moved = oracle.regular_correct(t, np.full(n, t - h), f_old, fd_old, f_new + x, fd_new + xd,
+                                   g_old, gd_old, g_old - x, gd_old - xd, 0.1, 40, 40, lib=lib)
+    # (rounding of the moved term, ~1e-16, reaches F3 amplified by 12 / h^3)
+    for a, b, tol in ((base.df, moved.df, 1e-14), (base.dfd, moved.dfd, 1e-14),
+                      (base.f2, moved.f2, 1e-8), (base.f3, moved.f3, 1e-8)):
+        assert np.max(np.abs(a - b) / (1.0 + np.abs(a))) < tol
+    # and the raw difference without the correction would not agree
+    raw = oracle.regular_correct(t, np.full(n, t - h), f_old, fd_old, f_new + x, fd_new + xd,
+                                 g_old, gd_old, g_old, gd_old, 0.1, 40, 40, lib=lib)
+    assert np.max(np.abs(raw.f3 - base.f3)) > 1.0
+
+
+def pin_corrector_step(lib=None):
+    """The step criterion on a harmonic force F = A cos(w t) is sqrt(eta)/w;
+    the step is the largest power of two below it, at most twice the last
+    step, and dividing the block time."""
+    eta = 0.02
+    for w, h, t, expect in ((100.0, 2.0 ** -10, 1.0, 2.0 ** -10),      # criterion
+                            (1.0, 2.0 ** -6, 1.0, 2.0 ** -5),          # doubling limit
+                            (1.0, 2.0 ** -6, 3.0 * 2.0 ** -6, 2.0 ** -6),  # commensurate
+                            (1.0e4, 2.0 ** -14, 1.0, 2.0 ** -16)):     # dt_min
+        a = np.array([[0.3, -0.4, 1.2]])
+        f = lambda s: a * np.cos(w * s)              # noqa: E731
+        fd = lambda s: -a * w * np.sin(w * s)        # noqa: E731
+        r = oracle.regular_correct(t, [t - h], f(t - h), fd(t - h), f(t), fd(t),
+                                   np.zeros((1, 3)), np.zeros((1, 3)), np.zeros((1, 3)),
+                                   np.zeros((1, 3)), 0.1, 40, 40, eta=eta,
+                                   dt_min=2.0 ** -16, lib=lib)
+        assert r.dt_new[0] == expect, (w, h, t, r.dt_new[0], expect)
+    # the criterion itself, where the Hermite derivatives are accurate
+    w, h, t = 3.0, 2.0 ** -14, 0.5
+    a = np.array([[1.0, 2.0, -0.5]])
+    r = oracle.regular_correct(t, [t - h], a * np.cos(w * (t - h)), -a * w * np.sin(w * (t - h)),
+                               a * np.cos(w * t), -a * w * np.sin(w * t), np.zeros((1, 3)),
+                               np.zeros((1, 3)), np.zeros((1, 3)), np.zeros((1, 3)),
+                               0.1, 40, 40, eta=eta, dt_min=2.0 ** -30, lib=lib)
+    f2_exact = -w * w * a * np.cos(w * t)
+    assert np.max(np.abs(r.f2 - f2_exact)) < 1e-6 * w * w
+
+
+def pin_corrector_radius(lib=None):
+    """Equation (1): h_new = h_old (n_p / n)^(1/3), within the limits."""
+    z = np.zeros((5, 3))
+    h_old = np.array([0.1, 0.1, 0.2, 0.3, 0.4])
+    nnb = np.array([50, 50, 8, 0, 27])
+    n_p = np.array([50.0, 400.0, 1.0, 50.0, 64.0])
+    r = oracle.regular_correct(1.0, np.full(5, 0.5), z, z, z, z, z, z, z, z, h_old, nnb, n_p,
+                               f_lo=0.25, f_hi=1.5, lib=lib)
+    expect = h_old * np.array([1.0, 1.5, 0.5, 1.5, 4.0 / 3.0])
+    assert _close(r.h_new, expect, 1e-15), (r.h_new, expect)
+
+
 ALL_PINS = [  # roughly cheapest first
     pin_golden_forces,
     pin_pair_terms_golden,
@@ -421,6 +513,10 @@ ALL_PINS = [  # roughly cheapest first
     pin_momentum,
     pin_fd_jerk,
     pin_plummer_mean_field,
+    pin_corrector_hermite_cubic,
+    pin_corrector_list_change,
+    pin_corrector_step,
+    pin_corrector_radius,
     pin_potential_gradient,
     pin_potential_plummer,
     pin_irregular_golden,

@@ -41,6 +41,22 @@ MUTANTS = {
     "pair_terms_jerk_sign": ("djrk[3 * p + c] = m[j] * (V[c] / r3 - 3.0 * rv * R[c] / r5);",
                              "djrk[3 * p + c] = m[j] * (V[c] / r3 + 3.0 * rv * R[c] / r5);"),
     "pair_terms_rmin_max": ("rmin[p] = sqrt((p2 < r2) ? p2 : r2);", "rmin[p] = sqrt((p2 < r2) ? r2 : p2);"),
+    # regular corrector
+    "corr_no_list_correction": ("const double dF = (f_new[k] - f_old[k]) + (g_new[k] - g_old[k]);",
+                                "const double dF = (f_new[k] - f_old[k]);"),
+    "corr_list_correction_sign": ("const double dF = (f_new[k] - f_old[k]) + (g_new[k] - g_old[k]);",
+                                  "const double dF = (f_new[k] - f_old[k]) - (g_new[k] - g_old[k]);"),
+    "corr_f3_factor": ("F3[c] = (-12.0 * dF + 6.0 * h * (2.0 * fd_old[k] + dFd)) / (h * h * h);",
+                       "F3[c] = (-12.0 * dF + 6.0 * h * (1.0 * fd_old[k] + dFd)) / (h * h * h);"),
+    "corr_f2_at_old_time": ("F2[c] = f2_old + h * F3[c];", "F2[c] = f2_old;"),
+    "corr_no_doubling_limit": ("const double lim = fmin(fmin(est, 2.0 * h), dt_max);",
+                               "const double lim = fmin(est, dt_max);"),
+    "corr_not_commensurate": ("while (d > dt_min && (d > limit || fmod(t, d) != 0.0)) d *= 0.5;",
+                              "while (d > dt_min && d > limit) d *= 0.5;"),
+    "corr_eta_squared": ("sqrt(eta * (a * a2 + ad * ad)", "sqrt(eta * eta * (a * a2 + ad * ad)"),
+    "corr_radius_inverse": ("cbrt(n_p[q] / (double)nnb[q])", "cbrt((double)nnb[q] / n_p[q])"),
+    "corr_radius_no_limit": ("f = fmin(fmax(cbrt(n_p[q] / (double)nnb[q]), f_lo), f_hi);",
+                             "f = cbrt(n_p[q] / (double)nnb[q]);"),
     # potential
     "pot_sign": ("nsum_add(&PHI, -m[j] / r);", "nsum_add(&PHI, m[j] / r);"),
     "pot_inverse_square": ("nsum_add(&PHI, -m[j] / r);", "nsum_add(&PHI, -m[j] / r2);"),
