@@ -240,6 +240,63 @@ int nb6_irregular_force(nb6_ctx *ctx, int cluster, double t_block, int64_t n_i,
                         const int32_t *idx_i, double *acc, double *jerk,
                         double *pot, int mem_kind, void *stream);
 
+/* ---- regular corrector of a block -------------------------------------- */
+
+/* Parameters of nb6_regular_correct. */
+typedef struct nb6_corr_params {
+    double eta;     /* accuracy parameter of the step criterion (> 0; the
+                       paper's runs use 0.02)                                 */
+    double dt_min;  /* smallest regular step, a power of two                  */
+    double dt_max;  /* largest regular step, a power of two >= dt_min         */
+    double f_lo;    /* limits of the radius factor of equation (1):           */
+    double f_hi;    /*   0 < f_lo <= f_hi; f_hi is also used for empty lists  */
+} nb6_corr_params;
+
+/* One block of particles that reached their regular time t.  Vectors are
+ * [n_i][3] doubles, scalars [n_i]; "old" regular values are those of the
+ * previous regular step at t_old with the old list, "new" ones those of
+ * the force call at t with the new list; the irregular values g are both at
+ * t, with the old and with the new list (nb6_irregular_force before and
+ * after nb6_set_lists). */
+typedef struct nb6_corr_block {
+    int64_t        n_i;
+    double         t;
+    const double  *t_old;
+    const double  *f_old, *fd_old;   /* regular force and derivative at t_old */
+    const double  *f_new, *fd_new;   /* regular force and derivative at t     */
+    const double  *g_old, *gd_old;   /* irregular, at t, old list             */
+    const double  *g_new, *gd_new;   /* irregular, at t, new list             */
+    const double  *h_old;            /* neighbour radius of the new list      */
+    const int32_t *nnb;              /* size of the new list                  */
+    const double  *n_p;              /* neighbour number aimed at (eq. 1)     */
+    double        *df, *dfd;         /* out: regular change, fixed list       */
+    double        *f2, *f3;          /* out: 2nd derivative at t, 3rd         */
+    double        *dt_new, *h_new;   /* out: next regular step, new radius    */
+} nb6_corr_block;
+
+/*
+ * The regular corrector of a block (section 3.3 step 7):
+ *   dF = (f_new - f_old) + (g_new - g_old), and dFd likewise: the regular
+ *   force change over the step with the neighbour set held fixed (section
+ *   3.6: the irregular-force change at t from the old to the new list);
+ *   with h = t - t_old, the cubic through (f_old, fd_old) at t_old and
+ *   (f_old + dF, fd_old + dFd) at t (fourth-order Hermite, Makino & Aarseth
+ *   1992) gives f3 = (-12 dF + 6 h (2 fd_old + dFd)) / h^3 and
+ *   f2 = (6 dF - h (6 fd_old + 2 dFd)) / h^2 + h f3 (the new-time value);
+ *   dt_new: the step criterion sqrt(eta (|F||F2| + |Fd|^2) / (|Fd||F3| +
+ *   |F2|^2)) on the new-time values, taken down to the largest power of two
+ *   that is at most 2 h and dt_max and divides t, and at least dt_min;
+ *   h_new = h_old (n_p / nnb)^(1/3) (equation 1), the factor limited to
+ *   [f_lo, f_hi], f_hi when nnb == 0.
+ * FP64 throughout.  Every pointer of *blk lives in mem_kind memory.
+ * Errors: NB6_ERR_ARG (parameters; HOST mode: some t_old >= t, or
+ * non-finite), NB6_ERR_NOMEM, NB6_ERR_HIP.  In DEVICE mode a particle with
+ * t_old >= t gets NaN outputs and nb6_sync_status reports
+ * NB6_ERR_DEVICE_INPUT.  n_i == 0 is a no-op.
+ */
+int nb6_regular_correct(nb6_ctx *ctx, const nb6_corr_block *blk,
+                        const nb6_corr_params *params, int mem_kind, void *stream);
+
 /* ---- serving: continuously batched requests ---------------------------- */
 
 /*

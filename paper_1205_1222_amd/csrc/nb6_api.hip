@@ -261,7 +261,8 @@ int nb6_destroy(nb6_ctx* c) {
         delete cl;
     }
     for (DevBuf* b : {&c->part, &c->cnt, &c->lst, &c->ovf, &c->in_idx, &c->in_h2, &c->in_dtr,
-                      &c->out_acc, &c->out_jerk, &c->out_pot, &c->out_nnb, &c->out_list})
+                      &c->out_acc, &c->out_jerk, &c->out_pot, &c->out_nnb, &c->out_list,
+                      &c->corr})
         release(*b);
     for (auto& b : c->ld) release(b);
     if (c->status) (void)hipFree(c->status);
@@ -796,6 +797,91 @@ int nb6_irregular_force(nb6_ctx* c, int cluster, double t_block, int64_t n_i,
     return NB6_OK;
 }
 
+int nb6_regular_correct(nb6_ctx* c, const nb6_corr_block* b, const nb6_corr_params* par,
+                        int mem_kind, void* stream) {
+    if (!c) return NB6_ERR_ARG;
+    c->err.clear();
+    if (!b || !par) return fail(c, NB6_ERR_ARG, "null block or parameters");
+    int e_min = 0, e_max = 0;
+    if (!(par->eta > 0.0) || !(par->dt_min > 0.0) || !(par->dt_max >= par->dt_min) ||
+        std::frexp(par->dt_min, &e_min) != 0.5 || std::frexp(par->dt_max, &e_max) != 0.5 ||
+        !(par->f_lo > 0.0) || !(par->f_hi >= par->f_lo) || !std::isfinite(par->f_hi) ||
+        !std::isfinite(par->eta))
+        return fail(c, NB6_ERR_ARG, "bad corrector parameters");
+    if (!std::isfinite(b->t)) return fail(c, NB6_ERR_ARG, "non-finite t");
+    if (b->n_i < 0 || b->n_i > INT32_MAX) return fail(c, NB6_ERR_ARG, "n_i = %lld", (long long)b->n_i);
+    if (mem_kind != NB6_MEM_HOST && mem_kind != NB6_MEM_DEVICE)
+        return fail(c, NB6_ERR_ARG, "bad mem_kind %d", mem_kind);
+    const int64_t n = b->n_i;
+    if (n == 0) return NB6_OK;
+    const double* vin[8] = {b->f_old, b->fd_old, b->f_new, b->fd_new,
+                            b->g_old, b->gd_old, b->g_new, b->gd_new};
+    double* vout[4] = {b->df, b->dfd, b->f2, b->f3};
+    if (!b->t_old || !b->h_old || !b->nnb || !b->n_p || !b->dt_new || !b->h_new)
+        return fail(c, NB6_ERR_ARG, "null array in the block");
+    for (const double* p : vin) if (!p) return fail(c, NB6_ERR_ARG, "null array in the block");
+    for (double* p : vout) if (!p) return fail(c, NB6_ERR_ARG, "null array in the block");
+    std::lock_guard<std::mutex> lk(c->cluster_mu);
+    HIP_TRY(c, hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)stream;
+    CorrArgs a{};
+    a.n = n;
+    a.t = b->t;
+    a.eta = par->eta; a.dt_min = par->dt_min; a.dt_max = par->dt_max;
+    a.f_lo = par->f_lo; a.f_hi = par->f_hi;
+    a.status = c->status;
+    const size_t v3 = 3 * (size_t)n * sizeof(double), s1 = (size_t)n * sizeof(double);
+    if (mem_kind == NB6_MEM_HOST) {
+        for (int64_t q = 0; q < n; ++q)
+            if (!(b->t - b->t_old[q] > 0.0) || !std::isfinite(b->t_old[q]))
+                return fail(c, NB6_ERR_ARG, "t_old[%lld] is not before t", (long long)q);
+        // one staging buffer: 8 input vectors, t_old, h_old, n_p, nnb, then the outputs
+        const size_t total = 8 * v3 + 3 * s1 + (size_t)n * sizeof(int32_t) + 4 * v3 + 2 * s1;
+        if (int rc = ensure(c, c->corr, total)) return rc;
+        char* p = (char*)c->corr.p;
+        const double* dv[8];
+        for (int k = 0; k < 8; ++k) {
+            HIP_TRY(c, hipMemcpyAsync(p, vin[k], v3, hipMemcpyHostToDevice, st));
+            dv[k] = (const double*)p;
+            p += v3;
+        }
+        const double* sin3[3] = {b->t_old, b->h_old, b->n_p};
+        const double* ds[3];
+        for (int k = 0; k < 3; ++k) {
+            HIP_TRY(c, hipMemcpyAsync(p, sin3[k], s1, hipMemcpyHostToDevice, st));
+            ds[k] = (const double*)p;
+            p += s1;
+        }
+        HIP_TRY(c, hipMemcpyAsync(p, b->nnb, n * sizeof(int32_t), hipMemcpyHostToDevice, st));
+        a.nnb = (const int32_t*)p;
+        p += (size_t)n * sizeof(int32_t);
+        p = (char*)(((uintptr_t)p + 7) & ~(uintptr_t)7);
+        double* dout[6];
+        for (int k = 0; k < 4; ++k) { dout[k] = (double*)p; p += v3; }
+        for (int k = 4; k < 6; ++k) { dout[k] = (double*)p; p += s1; }
+        a.f_old = dv[0]; a.fd_old = dv[1]; a.f_new = dv[2]; a.fd_new = dv[3];
+        a.g_old = dv[4]; a.gd_old = dv[5]; a.g_new = dv[6]; a.gd_new = dv[7];
+        a.t_old = ds[0]; a.h_old = ds[1]; a.n_p = ds[2];
+        a.df = dout[0]; a.dfd = dout[1]; a.f2 = dout[2]; a.f3 = dout[3];
+        a.dt_new = dout[4]; a.h_new = dout[5];
+        HIP_TRY(c, launch_correct(a, st));
+        for (int k = 0; k < 4; ++k)
+            HIP_TRY(c, hipMemcpyAsync(vout[k], dout[k], v3, hipMemcpyDeviceToHost, st));
+        HIP_TRY(c, hipMemcpyAsync(b->dt_new, dout[4], s1, hipMemcpyDeviceToHost, st));
+        HIP_TRY(c, hipMemcpyAsync(b->h_new, dout[5], s1, hipMemcpyDeviceToHost, st));
+        HIP_TRY(c, hipStreamSynchronize(st));
+        return NB6_OK;
+    }
+    a.t_old = b->t_old;
+    a.f_old = b->f_old; a.fd_old = b->fd_old; a.f_new = b->f_new; a.fd_new = b->fd_new;
+    a.g_old = b->g_old; a.gd_old = b->gd_old; a.g_new = b->g_new; a.gd_new = b->gd_new;
+    a.h_old = b->h_old; a.nnb = b->nnb; a.n_p = b->n_p;
+    a.df = b->df; a.dfd = b->dfd; a.f2 = b->f2; a.f3 = b->f3;
+    a.dt_new = b->dt_new; a.h_new = b->h_new;
+    HIP_TRY(c, launch_correct(a, st));
+    return NB6_OK;
+}
+
 int nb6_sync_status(nb6_ctx* c, void* stream) {
     if (!c) return NB6_ERR_ARG;
     HIP_TRY(c, hipSetDevice(c->device));
@@ -805,7 +891,7 @@ int nb6_sync_status(nb6_ctx* c, void* stream) {
     HIP_TRY(c, hipStreamSynchronize(st));
     HIP_TRY(c, launch_zero_u32(c->status, 4, st));
     HIP_TRY(c, hipStreamSynchronize(st));
-    if (status[0] & (ST_BAD_INDEX | ST_BAD_H2 | ST_NONFINITE | ST_BAD_LIST))
+    if (status[0] & (ST_BAD_INDEX | ST_BAD_H2 | ST_NONFINITE | ST_BAD_LIST | ST_BAD_STEP))
         return fail(c, NB6_ERR_DEVICE_INPUT, "GPU validation flagged 0x%x", status[0]);
     return NB6_OK;
 }

@@ -78,6 +78,7 @@ struct nb6_ctx {
     nb6::DevBuf in_idx, in_h2, in_dtr;                // HOST-mode inputs
     nb6::DevBuf out_acc, out_jerk, out_pot, out_nnb, out_list;  // HOST-mode outputs
     nb6::DevBuf ld[7];                                // HOST-mode load staging
+    nb6::DevBuf corr;                                 // HOST-mode corrector staging
     unsigned* status = nullptr;                       // device status word
     std::string err;
     nb6::Plan last_plan{0, 0, 0, 0, 0};

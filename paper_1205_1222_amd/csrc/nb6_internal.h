@@ -41,7 +41,8 @@ __host__ __device__ inline long long vtiles(long long n) { return (n + VTILE - 1
 
 // Bits of the device status word.
 enum StatusBits {
-    ST_BAD_INDEX = 1, ST_BAD_H2 = 2, ST_NONFINITE = 4, ST_OVERFLOW = 8, ST_BAD_LIST = 16
+    ST_BAD_INDEX = 1, ST_BAD_H2 = 2, ST_NONFINITE = 4, ST_OVERFLOW = 8, ST_BAD_LIST = 16,
+    ST_BAD_STEP = 32
 };
 
 // Cubic Taylor prediction of one coordinate in FP64 Horner form with explicit
@@ -202,6 +203,27 @@ hipError_t launch_set_lists(const SetListArgs& a, hipStream_t s);
 // to rows of dst_cap entries (the stored lists grow).
 hipError_t launch_copy_rows(const int32_t* src, int src_cap, int32_t* dst, int dst_cap,
                             const int32_t* cnt, int64_t n, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Regular corrector of a block (elementwise, FP64).
+// ---------------------------------------------------------------------------
+struct CorrArgs {
+    int64_t        n;
+    double         t;
+    const double*  t_old;                       // [n]
+    const double*  f_old; const double* fd_old; // [n][3]
+    const double*  f_new; const double* fd_new;
+    const double*  g_old; const double* gd_old;
+    const double*  g_new; const double* gd_new;
+    const double*  h_old;                       // [n]
+    const int32_t* nnb;                         // [n]
+    const double*  n_p;                         // [n]
+    double eta, dt_min, dt_max, f_lo, f_hi;
+    double* df; double* dfd; double* f2; double* f3;  // [n][3]
+    double* dt_new; double* h_new;                     // [n]
+    unsigned*      status;
+};
+hipError_t launch_correct(const CorrArgs& a, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Serving: one descriptor per request of a fused batch.

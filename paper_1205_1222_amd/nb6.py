@@ -50,7 +50,7 @@ EXPORTED = [
     "nb6_predict_j", "nb6_regular_force", "nb6_sync_status", "nb6_last_slices",
     "nb6_last_plan",
     "nb6_get_predicted", "nb6_kernel_times", "nb6_submit", "nb6_poll",
-    "nb6_set_lists", "nb6_irregular_force",
+    "nb6_set_lists", "nb6_irregular_force", "nb6_regular_correct",
 ]
 
 NB6_OPT_TIMING = 1
@@ -76,6 +76,19 @@ class nb6_ticket_info(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("slices", ctypes.c_int),
                 ("batch_size", ctypes.c_int), ("submit_us", ctypes.c_double),
                 ("admit_us", ctypes.c_double), ("done_us", ctypes.c_double)]
+
+
+class nb6_corr_params(ctypes.Structure):
+    _fields_ = [("eta", ctypes.c_double), ("dt_min", ctypes.c_double),
+                ("dt_max", ctypes.c_double), ("f_lo", ctypes.c_double),
+                ("f_hi", ctypes.c_double)]
+
+
+class nb6_corr_block(ctypes.Structure):
+    _fields_ = [("n_i", ctypes.c_int64), ("t", ctypes.c_double)] + [
+        (name, ctypes.c_void_p) for name in (
+            "t_old", "f_old", "fd_old", "f_new", "fd_new", "g_old", "gd_old", "g_new",
+            "gd_new", "h_old", "nnb", "n_p", "df", "dfd", "f2", "f3", "dt_new", "h_new")]
 
 
 class NB6Error(RuntimeError):
@@ -116,6 +129,8 @@ def lib():
         L.nb6_get_predicted.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp, ctypes.c_int, vp]
         L.nb6_set_lists.argtypes = [vp, ctypes.c_int, i64, vp, vp, vp, ctypes.c_int32,
                                     ctypes.c_int, vp]
+        L.nb6_regular_correct.argtypes = [vp, ctypes.POINTER(nb6_corr_block),
+                                          ctypes.POINTER(nb6_corr_params), ctypes.c_int, vp]
         L.nb6_irregular_force.argtypes = [vp, ctypes.c_int, ctypes.c_double, i64, vp, vp, vp,
                                           vp, ctypes.c_int, vp]
         for name in EXPORTED:
@@ -318,3 +333,35 @@ def irregular_force_host(ctx, cluster, t_block, idx_i, with_pot=False):
     check(ctx, nb6_irregular_force(ctx, cluster, t_block, ni, idx_i, acc, jerk, NB6_MEM_HOST,
                                    pot=pot))
     return (acc, jerk, pot) if with_pot else (acc, jerk)
+
+
+def nb6_regular_correct(ctx, n_i, t, arrays, params, mem_kind=NB6_MEM_HOST, stream=None):
+    """``arrays``: dict of the nb6_corr_block arrays by field name (inputs and
+    outputs); ``params``: (eta, dt_min, dt_max, f_lo, f_hi)."""
+    f = np.float64
+    blk = nb6_corr_block(n_i, float(t))
+    for name, _ in nb6_corr_block._fields_[2:]:
+        setattr(blk, name, _ptr(arrays[name], np.int32 if name == "nnb" else f))
+    par = nb6_corr_params(*[float(x) for x in params])
+    return lib().nb6_regular_correct(ctx, ctypes.byref(blk), ctypes.byref(par), mem_kind,
+                                     _stream(stream))
+
+
+def regular_correct_host(ctx, t, t_old, f_old, fd_old, f_new, fd_new, g_old, gd_old, g_new,
+                         gd_new, h_old, nnb, n_p, eta=0.02, dt_min=2.0 ** -20, dt_max=1.0,
+                         f_lo=0.5, f_hi=1.25):
+    """Host-memory nb6_regular_correct; returns a dict of the outputs."""
+    t_old = np.ascontiguousarray(np.atleast_1d(t_old), dtype=np.float64)
+    n = len(t_old)
+    arrays = {"t_old": t_old}
+    for name, a in (("f_old", f_old), ("fd_old", fd_old), ("f_new", f_new), ("fd_new", fd_new),
+                    ("g_old", g_old), ("gd_old", gd_old), ("g_new", g_new), ("gd_new", gd_new)):
+        arrays[name] = np.ascontiguousarray(np.reshape(a, (n, 3)), dtype=np.float64)
+    arrays["h_old"] = np.ascontiguousarray(np.broadcast_to(h_old, (n,)), dtype=np.float64)
+    arrays["n_p"] = np.ascontiguousarray(np.broadcast_to(n_p, (n,)), dtype=np.float64)
+    arrays["nnb"] = np.ascontiguousarray(np.broadcast_to(nnb, (n,)), dtype=np.int32)
+    out = {k: np.empty((n, 3)) for k in ("df", "dfd", "f2", "f3")}
+    out.update({k: np.empty(n) for k in ("dt_new", "h_new")})
+    arrays.update(out)
+    check(ctx, nb6_regular_correct(ctx, n, t, arrays, (eta, dt_min, dt_max, f_lo, f_hi)))
+    return out
