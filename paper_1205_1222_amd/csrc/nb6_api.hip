@@ -260,7 +260,7 @@ int nb6_destroy(nb6_ctx* c) {
         if (cl->last_served) (void)hipEventDestroy(cl->last_served);
         delete cl;
     }
-    for (DevBuf* b : {&c->part, &c->cnt, &c->lst, &c->ovf, &c->in_idx, &c->in_h2, &c->in_dtr,
+    for (DevBuf* b : {&c->part, &c->cnt, &c->lst, &c->in_idx, &c->in_h2, &c->in_dtr,
                       &c->out_acc, &c->out_jerk, &c->out_pot, &c->out_nnb, &c->out_list,
                       &c->corr})
         release(*b);
@@ -504,13 +504,16 @@ int nb6_regular_force(nb6_ctx* c, int cluster, int64_t n_i, const int32_t* idx_i
     const int caps = cap + 1;  // room for the i-particle itself
     int rc;
     const size_t ni64 = ((size_t)ni + 63) / 64 * 64;  // partials by 64-particle block
+    const size_t cnt_cap_before = c->cnt.cap;  // a reallocation changes the capacity
     if ((rc = ensure(c, c->part, (size_t)p.nslices * npart * ni64 * sizeof(double))) ||
-        (rc = ensure(c, c->cnt, ((size_t)ni + 1) * sizeof(int32_t))) ||
-        (rc = ensure(c, c->lst, (size_t)ni * caps * sizeof(int32_t))) ||
-        (rc = ensure(c, c->ovf, (size_t)ni * sizeof(int32_t))))
+        (rc = ensure(c, c->cnt, (size_t)ni * sizeof(int32_t))) ||
+        (rc = ensure(c, c->lst, (size_t)ni * caps * sizeof(int32_t))))
         return rc;
-    int32_t* d_cnt = (int32_t*)c->cnt.p;      // [ni] counts, then the overflow count
-    HIP_TRY(c, launch_zero_u32((unsigned*)d_cnt, ni + 1, st));
+    int32_t* d_cnt = (int32_t*)c->cnt.p;  // [ni] counts: zero between calls
+    if (c->cnt_dirty || c->cnt.cap != cnt_cap_before) {
+        HIP_TRY(c, launch_zero_u32((unsigned*)d_cnt, (int)(c->cnt.cap / sizeof(int32_t)), st));
+        c->cnt_dirty = false;
+    }
 
     RegfArgs ra{};
     ra.rec = cl->rec[mi].p;
@@ -528,6 +531,8 @@ int nb6_regular_force(nb6_ctx* c, int cluster, int64_t n_i, const int32_t* idx_i
     ra.lst = (int32_t*)c->lst.p;
     ra.caps = caps;
     ra.status = c->status;
+    // the finalize resets the counts; until it is launched they are dirty
+    c->cnt_dirty = true;
     {
         TimedLaunch tl(c, 1, st);
         HIP_TRY(c, launch_regf(mi, p.ipl, p.wpb, pot != nullptr, ra, st));
@@ -551,26 +556,15 @@ int nb6_regular_force(nb6_ctx* c, int cluster, int64_t n_i, const int32_t* idx_i
     fa.list = d_list;
     fa.cap = cap;
     fa.status = c->status;
-    fa.ovf_count = d_cnt + ni;
-    fa.ovf_list = (int32_t*)c->ovf.p;
+    fa.rec = ra.rec;
+    fa.dtr = d_dtr;
+    fa.mode = mi;
     {
         TimedLaunch tl(c, 2, st);
         HIP_TRY(c, launch_finalize(fa, st));
         tl.done();
     }
-    if (cap > 0) {
-        OverflowArgs oa{};
-        oa.rec = ra.rec;
-        oa.n = (int)n;
-        oa.idx = d_idx;
-        oa.h2 = d_h2;
-        oa.dtr = d_dtr;
-        oa.list = d_list;
-        oa.cap = cap;
-        oa.ovf_count = fa.ovf_count;
-        oa.ovf_list = fa.ovf_list;
-        HIP_TRY(c, launch_overflow(mi, oa, st));
-    }
+    c->cnt_dirty = false;
     c->last_plan = p;
 
     if (mem_kind == NB6_MEM_DEVICE) return NB6_OK;

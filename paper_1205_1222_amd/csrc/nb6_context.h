@@ -74,7 +74,8 @@ struct nb6_ctx {
     int jl_hint = 0;
     int64_t hbm_budget = 0;
     std::vector<nb6::ClusterState*> clusters;
-    nb6::DevBuf part, cnt, lst, ovf;                  // force-kernel scratch
+    nb6::DevBuf part, cnt, lst;                       // force-kernel scratch
+    bool cnt_dirty = true;  // cnt must be zeroed before the next force launch
     nb6::DevBuf in_idx, in_h2, in_dtr;                // HOST-mode inputs
     nb6::DevBuf out_acc, out_jerk, out_pot, out_nnb, out_list;  // HOST-mode outputs
     nb6::DevBuf ld[7];                                // HOST-mode load staging

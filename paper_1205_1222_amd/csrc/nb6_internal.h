@@ -64,14 +64,18 @@ constexpr int NPART = 6;
 constexpr int NPART_POT = 7;
 // Largest per-i list capacity (cap + 1 slots: the i itself is found too).
 constexpr int MAX_CAPS = 1024;
-// Particles per finalize workgroup (lists; the first ceil(ni / 64)
-// workgroups also reduce the slice partials of 64 particles each).
+// Particles per finalize workgroup for the lists; the first np ceil(ni / 64)
+// workgroups also reduce one component of the slice partials of 64
+// particles each.
 constexpr int FINAL_PPB = 8;
-__host__ __device__ inline long long final_blocks(long long ni) {
+__host__ __device__ inline long long final_list_blocks(long long ni) {
     return (ni + FINAL_PPB - 1) / FINAL_PPB;
 }
-// Workgroups of the overflow scan (each loops over the queued i).
-constexpr int OVERFLOW_BLOCKS = 64;
+__host__ __device__ inline long long final_blocks(long long ni, int np) {
+    const long long sums = np * ((ni + 63) / 64);
+    const long long lists = final_list_blocks(ni);
+    return sums > lists ? sums : lists;
+}
 
 struct RegfArgs {
     const void*    rec;       // records of the cluster (mode dependent)
@@ -85,7 +89,8 @@ struct RegfArgs {
     int            jl_shift;  // log2 of the lanes that share one i (0: one lane per i)
     const float*   tmax;      // [vtiles(n)] max of vabs over each tile of VTILE j
     double*        part;      // [ceil(ni/64)][nslices][NPART or NPART_POT][64]
-    int32_t*       cnt;       // [ni] neighbours found, the i itself included (zeroed)
+    int32_t*       cnt;       // [ni] neighbours found, the i itself included (zero on
+                              // entry; the finalize leaves it zero again)
     int32_t*       lst;       // [ni][caps] neighbours in the order found
     int            caps;      // per-i list capacity (cap + 1)
     unsigned*      status;    // device status word
@@ -93,7 +98,7 @@ struct RegfArgs {
 
 struct FinalArgs {
     const double*  part;
-    const int32_t* cnt;
+    int32_t*       cnt;       // read, then reset to zero
     const int32_t* lst;
     int            nslices;
     int            ni;
@@ -108,20 +113,11 @@ struct FinalArgs {
     int32_t*       list;      // [ni][cap]
     int            cap;
     unsigned*      status;
-    int32_t*       ovf_count; // number of queued overflowed i (zeroed)
-    int32_t*       ovf_list;  // [ni] queued i
-};
-
-struct OverflowArgs {
+    // the ordered rescan of an overflowed list: the force call's records,
+    // their coordinate mode (MODE_*) and the i's dtr
     const void*    rec;
-    int            n;
-    const int32_t* idx;
-    const double*  h2;
     const double*  dtr;
-    int32_t*       list;      // [ni][cap]
-    int            cap;
-    const int32_t* ovf_count;
-    const int32_t* ovf_list;
+    int            mode;
 };
 
 // ---------------------------------------------------------------------------
@@ -231,7 +227,6 @@ hipError_t launch_correct(const CorrArgs& a, hipStream_t s);
 struct ReqDesc {
     RegfArgs     rg;          // force work of the request
     FinalArgs    fin;         // its reduction and lists
-    OverflowArgs ov;          // its overflow scan
     PredictArgs  pred;        // prediction of its cluster (when do_predict)
     int          do_predict;
     int          mode;        // MODE_*
@@ -251,7 +246,6 @@ struct BatchArgs {
 // Persistent fused force kernel over requests [reqs, reqs + nreq) of one mode.
 hipError_t launch_serve_regf(int mode, const BatchArgs& b, int blocks, hipStream_t s);
 hipError_t launch_serve_finalize(const BatchArgs& b, hipStream_t s);
-hipError_t launch_serve_overflow(int mode, const BatchArgs& b, hipStream_t s);
 // Predictions and count resets of every request of the batch, in one launch
 // of (requests x chunks) blocks; a chunk covers PREPARE_CHUNK particles.
 constexpr int PREPARE_CHUNK = 1024;
@@ -264,7 +258,6 @@ hipError_t launch_regf(int mode, int ipl, int waves_per_block, bool pot, const R
 // i-particles of one work item (one wavefront) of the force kernel.
 __host__ __device__ inline int regf_group_size(int ipl, int jl_shift) { return (64 * ipl) >> jl_shift; }
 hipError_t launch_finalize(const FinalArgs& a, hipStream_t s);
-hipError_t launch_overflow(int mode, const OverflowArgs& a, hipStream_t s);
 hipError_t launch_predict(const PredictArgs& a, hipStream_t s);
 hipError_t launch_scatter(const ScatterArgs& a, hipStream_t s);
 // Widen the j-records of one mode to double position and velocity arrays.

@@ -10,9 +10,9 @@
 //                     per i splitting the slice's j.
 //   finalize_kernel   fixed-order reduction of the j-slice partial sums and
 //                     the sorted neighbour list of each i (the reduction and
-//                     list-gathering kernels of section 3.4).
-//   overflow_kernel   exact list of an i whose neighbours outnumber the list
-//                     capacity: the first `cap` in ascending j.
+//                     list-gathering kernels of section 3.4); the exact list
+//                     of an i whose neighbours outnumber the list capacity
+//                     (the first `cap` in ascending j) by an ordered rescan.
 //
 // Design:
 //   * i-particles live in VGPRs, IPL of them per lane (or one per 2^k lanes
@@ -33,12 +33,16 @@
 //     reservation; the finalize kernel sorts each list.  A list that
 //     overflows its capacity is rebuilt by an ordered scan, so the result is
 //     always the first `cap` neighbours in ascending j.
+//   * A call is two launches, force and finalize: the finalize leaves the
+//     per-i counters at zero for the next call, and rescans overflowed lists
+//     itself.
 #include "nb6_internal.h"
 
 #include <float.h>
 
-// No implicit fused multiply-adds: the force kernel and the overflow scan
-// must take bit-identical neighbour decisions, so every fma is explicit.
+// No implicit fused multiply-adds: the force kernel and the ordered rescan of
+// an overflowed list must take bit-identical neighbour decisions, so every
+// fma is explicit.
 #pragma clang fp contract(off)
 
 namespace nb6 {
@@ -101,7 +105,8 @@ __device__ __forceinline__ float dist2(float dx, float dy, float dz) {
 
 // The neighbour criterion of section 3.2 on FP32 differences:
 // min(|R|^2, |R + dtr V|^2) < h^2.  Used verbatim by the force kernel (for
-// candidates) and by the overflow scan, so both take the same decisions.
+// candidates) and by the ordered rescan of an overflowed list, so both take
+// the same decisions.
 __device__ __forceinline__ bool velocity_criterion(float r2, float dx, float dy, float dz,
                                                    float dvx, float dvy, float dvz,
                                                    float dtr, float h2) {
@@ -430,17 +435,19 @@ regf_lanes_kernel(RegfArgs a, int gblocks) {
 
 // ---------------------------------------------------------------------------
 // Finalize: workgroup b of a request (4 waves) does
-//   sums  -- for b < ceil(ni / 64), the slice partials of particles
-//            64b .. 64b + 63.  The four waves split each particle's partials
+//   sums  -- for b < NP ceil(ni / 64), component b / ceil(ni / 64) of the
+//            slice partials of particles 64 m .. 64 m + 63, m = b mod
+//            ceil(ni / 64).  The four waves split each particle's partials
 //            in runs of 8 slices and the run sums are combined in a fixed
 //            order, so the result depends on the slicing only (lane t of a
-//            wave reads particle 64b + t: contiguous loads).
-//   lists -- particles 8b .. 8b + 7, two per wave.  count <= caps: every
-//            neighbour was stored, and an entry's output position is its
-//            rank among the entries (they are distinct), less one past the i
-//            itself.  count > caps: the list overflowed and i is queued for
-//            the ordered overflow scan.
-// A request therefore takes final_blocks(ni) = ceil(ni / FINAL_PPB) workgroups.
+//            wave reads particle 64 m + t: contiguous loads).
+//   lists -- particles 8b .. 8b + 7, two per wave: the neighbour count, and
+//            the counter reset to zero for the next call.  count <= caps:
+//            every neighbour was stored, and an entry's output position is
+//            its rank among the entries (they are distinct), less one past
+//            the i itself.  count > caps: the list overflowed and the wave
+//            rebuilds it by an ordered rescan of every j.
+// A request therefore takes final_blocks(ni, NP) workgroups.
 // ---------------------------------------------------------------------------
 
 __device__ __forceinline__ void wave_sync() {
@@ -454,63 +461,101 @@ __device__ __forceinline__ bool invalid_i(const FinalArgs& a, int q) {
     return self < 0 || self >= a.n || checked_h2(a.h2[q]) < 0.0f;
 }
 
-// LDS of the finalize kernels: the four waves' slice sums, and later (the
-// same bytes) one buffer of MAX_CAPS list entries per wave.
+// LDS of the finalize kernels: the four waves' slice sums of one component,
+// and later (the same bytes) one buffer of MAX_CAPS list entries per wave.
 union FinalShared {
-    double  sum[4][NPART_POT][64];
+    double  sum[4][64];
     int32_t list[4][MAX_CAPS];
 };
 
-// Slice sums of particles 64 blk .. 64 blk + 63, by the whole workgroup
-// (NP partial components: acc, jerk and, for 7, the potential sum).
+// Slice sums of component c of particles 64 blk .. 64 blk + 63, by the whole
+// workgroup (NP partial components: acc, jerk and, for 7, the potential sum).
+// Wave w adds the runs of 8 slices that start at 8 w, 8 w + 32, ... in slice
+// order, and the four run sums are added in wave order: the result depends on
+// the slicing only.  Four runs are loaded before the first of their adds.
 template <int NP>
-__device__ __forceinline__ void finalize_sums(const FinalArgs& a, const int blk,
+__device__ __forceinline__ void finalize_sums(const FinalArgs& a, const int blk, const int c,
                                               FinalShared& sh) {
+    constexpr int RUNS = 4;
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int q = blk * 64 + lane;
-    double sum[NP];
-#pragma unroll
-    for (int c = 0; c < NP; ++c) sum[c] = 0.0;
+    double sum = 0.0;
     if (q < a.ni) {
-        const double* p = a.part + part_index(q, 0, 0, a.nslices, NP);
-        for (int s0 = 8 * w; s0 < a.nslices; s0 += 32) {
-            double v[8][NP];  // the 48 loads of a run are in flight together
+        const double* p = a.part + part_index(q, 0, c, a.nslices, NP);
+        for (int s0 = 8 * w; s0 < a.nslices; s0 += 32 * RUNS) {
+            double v[RUNS][8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u)
+            for (int r = 0; r < RUNS; ++r)
 #pragma unroll
-                for (int c = 0; c < NP; ++c)
-                    v[u][c] = s0 + u < a.nslices ? p[((size_t)(s0 + u) * NP + c) * 64] : 0.0;
+                for (int u = 0; u < 8; ++u) {
+                    const int sl = s0 + 32 * r + u;
+                    v[r][u] = sl < a.nslices ? p[(size_t)sl * NP * 64] : 0.0;
+                }
 #pragma unroll
-            for (int u = 0; u < 8; ++u)
+            for (int r = 0; r < RUNS; ++r)
+                if (s0 + 32 * r < a.nslices)
 #pragma unroll
-                for (int c = 0; c < NP; ++c) sum[c] += v[u][c];
+                    for (int u = 0; u < 8; ++u) sum += v[r][u];
         }
     }
-#pragma unroll
-    for (int c = 0; c < NP; ++c) sh.sum[w][c][lane] = sum[c];
+    sh.sum[w][lane] = sum;
     __syncthreads();
     if (w == 0 && q < a.ni) {
         if (invalid_i(a, q)) {
             const double nan = __builtin_nan("");
-            for (int c = 0; c < 3; ++c) {
-                a.acc[3 * q + c] = nan;
-                a.jerk[3 * q + c] = nan;
-            }
-            if (NP == 7) a.pot[q] = nan;
-            a.nnb[q] = -1;
+            if (c < 3) a.acc[3 * q + c] = nan;
+            else if (c < 6) a.jerk[3 * q + c - 3] = nan;
+            else a.pot[q] = nan;
         } else {
-            for (int c = 0; c < NP; ++c) {
-                const double t = ((sh.sum[0][c][lane] + sh.sum[1][c][lane]) +
-                                  sh.sum[2][c][lane]) + sh.sum[3][c][lane];
-                if (c < 3) a.acc[3 * q + c] = t;
-                else if (c < 6) a.jerk[3 * q + c - 3] = t;
-                else a.pot[q] = -t;  // the potential is minus the sum of m / r
-            }
-            a.nnb[q] = a.cnt[q] - 1;  // the i itself is among the found
+            const double t = ((sh.sum[0][lane] + sh.sum[1][lane]) + sh.sum[2][lane]) +
+                             sh.sum[3][lane];
+            if (c < 3) a.acc[3 * q + c] = t;
+            else if (c < 6) a.jerk[3 * q + c - 3] = t;
+            else a.pot[q] = -t;  // the potential is minus the sum of m / r
         }
     }
     __syncthreads();  // the LDS is reused for lists
+}
+
+// Ordered rescan of particle q (wave-uniform, valid), whose neighbours
+// outnumber its list capacity: every j in ascending order under the force
+// kernel's neighbour test (the velocity criterion alone decides the same as
+// the kernel's candidate bound followed by it), keeping the first cap.
+// Four records per lane are in flight per step.
+template <int MODE>
+__device__ __forceinline__ void rescan_list(const FinalArgs& a, const int q, const int32_t self) {
+    using Rec = typename RecOf<MODE>::T;
+    const Rec* rec = static_cast<const Rec*>(a.rec);
+    const int lane = threadIdx.x & 63;
+    IPos<MODE> ip;
+    IAux ia;
+    get_ipos(rec[self], ip, ia);
+    const float h2f = checked_h2(a.h2[q]);
+    const float dtf = (float)a.dtr[q];
+    int32_t* out = a.list + (size_t)q * a.cap;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    int found = 0;  // wave-uniform
+    for (int j0 = 0; j0 < a.n && found < a.cap; j0 += 4 * 64) {
+        bool nb[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int j = j0 + 64 * u + lane;
+            const Rec r = rec[min(j, a.n - 1)];  // clamped: in bounds for every lane
+            float dx, dy, dz;
+            coord_diff(r, ip, dx, dy, dz);
+            nb[u] = j < a.n && j != self &&
+                    velocity_criterion(dist2(dx, dy, dz), dx, dy, dz, r.vx - ia.vx,
+                                       r.vy - ia.vy, r.vz - ia.vz, dtf, h2f);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const unsigned long long m = __ballot(nb[u]);
+            const int pos = found + __popcll(m & below);
+            if (nb[u] && pos < a.cap) out[pos] = j0 + 64 * u + lane;
+            found += __popcll(m);
+        }
+    }
 }
 
 // Sorted list of particle q (wave-uniform) from its `count` found entries;
@@ -521,10 +566,11 @@ __device__ __forceinline__ void finalize_list(const FinalArgs& a, const int q,
                                               const int32_t first, int32_t* sl) {
     const int lane = threadIdx.x & 63;
     if (count > a.caps) {
-        if (lane == 0) {
-            atomicOr(a.status, (unsigned)ST_OVERFLOW);
-            const int slot = atomicAdd(a.ovf_count, 1);
-            a.ovf_list[slot] = q;
+        if (lane == 0) atomicOr(a.status, (unsigned)ST_OVERFLOW);
+        switch (a.mode) {  // uniform
+            case MODE_FF: rescan_list<MODE_FF>(a, q, self); break;
+            case MODE_F64: rescan_list<MODE_F64>(a, q, self); break;
+            default: rescan_list<MODE_F32>(a, q, self); break;
         }
         return;
     }
@@ -556,24 +602,34 @@ __device__ __forceinline__ void finalize_list(const FinalArgs& a, const int q,
 template <int NP>
 __device__ __forceinline__ void finalize_block(const FinalArgs& a, const int blk,
                                                FinalShared& sh) {
-    if (blk * 64 < a.ni) finalize_sums<NP>(a, blk, sh);  // uniform across the workgroup
+    const int nb64 = (a.ni + 63) >> 6;
+    if (blk < NP * nb64) finalize_sums<NP>(a, blk % nb64, blk / nb64, sh);  // uniform
+    if (blk >= final_list_blocks(a.ni)) return;
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     constexpr int PPW = FINAL_PPB / 4;
     const int q0 = blk * FINAL_PPB + w * PPW;
     // every load of the wave's particles is issued before the first sort
     int32_t self[PPW], count[PPW], first[PPW];
-    bool ok[PPW];
+    bool live[PPW], ok[PPW];
 #pragma unroll
     for (int k = 0; k < PPW; ++k) {
         const int q = q0 + k;
-        ok[k] = q < a.ni;
-        self[k] = ok[k] ? a.idx[q] : -1;
-        const float h2f = ok[k] ? checked_h2(a.h2[q]) : -1.0f;
-        count[k] = ok[k] ? a.cnt[q] : 0;
-        first[k] = ok[k] && lane < a.caps ? a.lst[(size_t)q * a.caps + lane] : 0;
-        ok[k] = ok[k] && self[k] >= 0 && self[k] < a.n && h2f >= 0.0f;
+        live[k] = q < a.ni;
+        self[k] = live[k] ? a.idx[q] : -1;
+        const float h2f = live[k] ? checked_h2(a.h2[q]) : -1.0f;
+        count[k] = live[k] ? a.cnt[q] : 0;
+        first[k] = live[k] && lane < a.caps ? a.lst[(size_t)q * a.caps + lane] : 0;
+        ok[k] = live[k] && self[k] >= 0 && self[k] < a.n && h2f >= 0.0f;
     }
+    // the count is read: reset it for the next call, and store the number of
+    // neighbours (the i itself is among the found; -1 marks an invalid i)
+#pragma unroll
+    for (int k = 0; k < PPW; ++k)
+        if (live[k] && lane == 0) {
+            a.cnt[q0 + k] = 0;
+            a.nnb[q0 + k] = ok[k] ? count[k] - 1 : -1;
+        }
 #pragma unroll
     for (int k = 0; k < PPW; ++k)
         if (ok[k]) finalize_list(a, q0 + k, self[k], count[k], first[k], sh.list[w]);
@@ -586,58 +642,6 @@ __global__ void __launch_bounds__(256) finalize_kernel(FinalArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Overflowed lists: one workgroup per queued i scans all j in ascending
-// order with the force kernel's neighbour test and keeps the first `cap`.
-// ---------------------------------------------------------------------------
-// Ordered scan for queued particle q, by the whole calling workgroup.
-template <int MODE>
-__device__ __forceinline__ void overflow_item(const OverflowArgs& a, const int q,
-                                              int* __restrict__ sh_wave) {
-    using Rec = typename RecOf<MODE>::T;
-    const Rec* rec = static_cast<const Rec*>(a.rec);
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int w = tid >> 6;
-    const int32_t self = a.idx[q];
-    IPos<MODE> ip;
-    IAux ia;
-    get_ipos(rec[self], ip, ia);
-    const float h2f = checked_h2(a.h2[q]);
-    const float dtf = (float)a.dtr[q];
-    int out = 0;  // identical in every thread
-    for (int j0 = 0; j0 < a.n && out < a.cap; j0 += 256) {
-        const int j = j0 + tid;
-        bool nb = false;
-        if (j < a.n && j != self) {
-            const Rec r = rec[j];
-            float dx, dy, dz;
-            coord_diff(r, ip, dx, dy, dz);
-            const float r2 = dist2(dx, dy, dz);
-            nb = velocity_criterion(r2, dx, dy, dz, r.vx - ia.vx, r.vy - ia.vy,
-                                    r.vz - ia.vz, dtf, h2f);
-        }
-        const unsigned long long m = __ballot(nb);
-        if (lane == 0) sh_wave[w] = __popcll(m);
-        __syncthreads();
-        int base = out;
-        for (int v = 0; v < w; ++v) base += sh_wave[v];
-        const int off = __popcll(m & ((1ull << lane) - 1ull));
-        if (nb && base + off < a.cap) a.list[(size_t)q * a.cap + base + off] = j;
-        const int found = sh_wave[0] + sh_wave[1] + sh_wave[2] + sh_wave[3];
-        __syncthreads();
-        out += found;
-    }
-}
-
-template <int MODE>
-__global__ void __launch_bounds__(256) overflow_kernel(OverflowArgs a) {
-    __shared__ int sh_wave[4];
-    const int nq = *a.ovf_count;
-    for (int item = blockIdx.x; item < nq; item += gridDim.x)
-        overflow_item<MODE>(a, a.ovf_list[item], sh_wave);
-}
-
-// ---------------------------------------------------------------------------
 // Serving: fused launches over the requests of a batch.  The descriptors are
 // copied to the device before the launches and read with scalar loads.
 // ---------------------------------------------------------------------------
@@ -645,8 +649,7 @@ __global__ void __launch_bounds__(256) overflow_kernel(OverflowArgs a) {
 // address space does not compile); the sizes pin the field lists, so a field
 // added to an argument struct cannot be left out here unnoticed.
 static_assert(sizeof(RegfArgs) == 104, "load_regf_args must copy every RegfArgs field");
-static_assert(sizeof(FinalArgs) == 128, "load_final_args must copy every FinalArgs field");
-static_assert(sizeof(OverflowArgs) == 72, "load_overflow_args must copy every field");
+static_assert(sizeof(FinalArgs) == 136, "load_final_args must copy every FinalArgs field");
 
 __device__ __forceinline__ RegfArgs load_regf_args(const_ptr<ReqDesc> d) {
     RegfArgs a;
@@ -663,16 +666,9 @@ __device__ __forceinline__ FinalArgs load_final_args(const_ptr<ReqDesc> d) {
     f.ni = d->fin.ni; f.caps = d->fin.caps; f.n = d->fin.n; f.idx = d->fin.idx; f.h2 = d->fin.h2;
     f.acc = d->fin.acc; f.jerk = d->fin.jerk; f.pot = d->fin.pot; f.nnb = d->fin.nnb;
     f.list = d->fin.list;
-    f.cap = d->fin.cap; f.status = d->fin.status; f.ovf_count = d->fin.ovf_count;
-    f.ovf_list = d->fin.ovf_list;
+    f.cap = d->fin.cap; f.status = d->fin.status;
+    f.rec = d->fin.rec; f.dtr = d->fin.dtr; f.mode = d->fin.mode;
     return f;
-}
-__device__ __forceinline__ OverflowArgs load_overflow_args(const_ptr<ReqDesc> d) {
-    OverflowArgs o;
-    o.rec = d->ov.rec; o.n = d->ov.n; o.idx = d->ov.idx; o.h2 = d->ov.h2; o.dtr = d->ov.dtr;
-    o.list = d->ov.list; o.cap = d->ov.cap; o.ovf_count = d->ov.ovf_count;
-    o.ovf_list = d->ov.ovf_list;
-    return o;
 }
 
 __device__ __forceinline__ long long uniform_ll(long long v) {
@@ -722,21 +718,9 @@ __global__ void __launch_bounds__(256) serve_finalize_kernel(BatchArgs b) {
     finalize_block<NPART>(f, (int)(gb - reqs[lo].blk0), sh);
 }
 
-template <int MODE>
-__global__ void __launch_bounds__(256) serve_overflow_kernel(BatchArgs b) {
-    __shared__ int sh_wave[4];
-    const_ptr<ReqDesc> reqs = (const_ptr<ReqDesc>)(b.reqs);
-    for (int r = 0; r < b.nreq; ++r) {
-        if (reqs[r].fin.cap <= 0) continue;
-        const OverflowArgs o = load_overflow_args(reqs + r);
-        const int nq = *o.ovf_count;
-        for (int item = blockIdx.x; item < nq; item += gridDim.x)
-            overflow_item<MODE>(o, o.ovf_list[item], sh_wave);
-    }
-}
 
 // Block (r, chunk): predict chunk of request r's cluster (when flagged) and
-// clear the same chunk of its counts (n_i counts and the overflow count).
+// clear the same chunk of its n_i neighbour counts.
 __device__ __forceinline__ float predict_one(const PredictArgs& a, int64_t k);
 __device__ __forceinline__ void store_tile_max(const PredictArgs& a, int64_t k, float v);
 
@@ -745,7 +729,7 @@ __global__ void __launch_bounds__(256) serve_prepare_kernel(BatchArgs b) {
     const int ni = d->rg.ni;
     const int64_t base = (int64_t)blockIdx.y * PREPARE_CHUNK;
     for (int64_t e = base + threadIdx.x; e < base + PREPARE_CHUNK; e += blockDim.x) {
-        if (e <= ni) d->rg.cnt[e] = 0;
+        if (e < ni) d->rg.cnt[e] = 0;
         if (d->do_predict) {  // uniform across the workgroup
             const float v = e < d->pred.n ? predict_one(d->pred, e) : 0.0f;
             store_tile_max(d->pred, e, v);
@@ -911,7 +895,7 @@ hipError_t launch_regf(int mode, int ipl, int wpb, bool pot, const RegfArgs& a,
 hipError_t launch_finalize(const FinalArgs& a, hipStream_t s) {
     if (a.ni <= 0) return hipSuccess;
     if (a.caps > MAX_CAPS) return hipErrorInvalidValue;
-    const dim3 grid((unsigned)final_blocks(a.ni)), block(256);
+    const dim3 grid((unsigned)final_blocks(a.ni, a.pot ? NPART_POT : NPART)), block(256);
     if (a.pot)
         hipLaunchKernelGGL(finalize_kernel<NPART_POT>, grid, block, 0, s, a);
     else
@@ -919,16 +903,6 @@ hipError_t launch_finalize(const FinalArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_overflow(int mode, const OverflowArgs& a, hipStream_t s) {
-    const dim3 grid(OVERFLOW_BLOCKS), block(256);
-    switch (mode) {
-        case MODE_FF: hipLaunchKernelGGL(overflow_kernel<MODE_FF>, grid, block, 0, s, a); break;
-        case MODE_F64: hipLaunchKernelGGL(overflow_kernel<MODE_F64>, grid, block, 0, s, a); break;
-        case MODE_F32: hipLaunchKernelGGL(overflow_kernel<MODE_F32>, grid, block, 0, s, a); break;
-        default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
 
 hipError_t launch_predict(const PredictArgs& a, hipStream_t s) {
     if (a.n <= 0) return hipSuccess;
@@ -983,17 +957,6 @@ hipError_t launch_serve_finalize(const BatchArgs& b, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_serve_overflow(int mode, const BatchArgs& b, hipStream_t s) {
-    if (b.nreq <= 0) return hipSuccess;
-    const dim3 grid(OVERFLOW_BLOCKS), block(256);
-    switch (mode) {
-        case MODE_FF: hipLaunchKernelGGL(serve_overflow_kernel<MODE_FF>, grid, block, 0, s, b); break;
-        case MODE_F64: hipLaunchKernelGGL(serve_overflow_kernel<MODE_F64>, grid, block, 0, s, b); break;
-        case MODE_F32: hipLaunchKernelGGL(serve_overflow_kernel<MODE_F32>, grid, block, 0, s, b); break;
-        default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
 
 hipError_t launch_serve_prepare(const BatchArgs& b, int chunks, hipStream_t s) {
     if (b.nreq <= 0 || chunks <= 0) return hipSuccess;

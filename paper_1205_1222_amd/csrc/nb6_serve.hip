@@ -8,8 +8,8 @@
 //                its neighbour counts (one launch for the batch),
 //   force        one persistent launch per coordinate mode: wavefronts take
 //                (request, i-group, j-slice) items from an atomic counter,
-//   finalize     one launch over every active particle of the batch,
-//   overflow     ordered rebuild of overflowed lists,
+//   finalize     one launch over every active particle of the batch (sums,
+//                sorted lists, ordered rebuild of overflowed lists),
 // on one of kSlots streams, so up to kSlots batches run at once and requests
 // that arrive meanwhile form the next batch.  A batch holds at most about
 // kBatchWork pair interactions (a larger request runs alone), and its
@@ -115,9 +115,8 @@ struct ServeReq {
     double t_submit = 0, t_admit = 0, t_done = 0;
     // scratch carved from the arena
     double* part = nullptr;
-    int32_t* cnt = nullptr;   // [ni] + overflow count
+    int32_t* cnt = nullptr;   // [ni]
     int32_t* lst = nullptr;
-    int32_t* ovf = nullptr;
     int32_t* d_idx = nullptr;
     double* d_h2 = nullptr;
     double* d_dtr = nullptr;
@@ -138,9 +137,8 @@ size_t carve(ServeReq* r, char* base) {
     };
     const size_t ni64 = (ni + 63) / 64 * 64;  // partials are kept by 64-particle block
     r->part = (double*)take(ni64 * r->plan.nslices * NPART * sizeof(double));
-    r->cnt = (int32_t*)take((ni + 1) * sizeof(int32_t));
+    r->cnt = (int32_t*)take(ni * sizeof(int32_t));
     r->lst = (int32_t*)take(ni * caps * sizeof(int32_t));
-    r->ovf = (int32_t*)take(ni * sizeof(int32_t));
     if (r->rq.mem_kind == NB6_MEM_HOST) {
         r->d_idx = (int32_t*)take(ni * sizeof(int32_t));
         r->d_h2 = (double*)take(ni * sizeof(double));
@@ -492,17 +490,14 @@ class Engine {
             d.fin.n = (int)cl->n; d.fin.idx = r->d_idx; d.fin.h2 = r->d_h2;
             d.fin.acc = r->d_acc; d.fin.jerk = r->d_jerk; d.fin.nnb = r->d_nnb;
             d.fin.list = r->d_list; d.fin.cap = r->rq.cap; d.fin.status = status;
-            d.fin.ovf_count = r->cnt + ni; d.fin.ovf_list = r->ovf;
-            d.ov.rec = d.rg.rec; d.ov.n = d.rg.n; d.ov.idx = r->d_idx; d.ov.h2 = r->d_h2;
-            d.ov.dtr = r->d_dtr; d.ov.list = r->d_list; d.ov.cap = r->rq.cap;
-            d.ov.ovf_count = r->cnt + ni; d.ov.ovf_list = r->ovf;
+            d.fin.rec = d.rg.rec; d.fin.dtr = r->d_dtr; d.fin.mode = r->mi;
             d.mode = r->mi;
             const int gsize = regf_group_size(1, p.jl_shift);
             d.groups = (ni + gsize - 1) / gsize;
             d.item0 = item_in_mode;
             d.blk0 = blk0;
             item_in_mode += (long long)d.groups * p.nslices;
-            blk0 += final_blocks(ni);
+            blk0 += final_blocks(ni, NPART);
             chunk_need = std::max<int64_t>(chunk_need, std::max<int64_t>(cl->n, ni + 1));
         }
         HIP_TRY(nullptr, hipMemcpyAsync(sl.dev_desc, sl.host_desc, nreq * sizeof(ReqDesc),
@@ -534,15 +529,6 @@ class Engine {
             b = e;
         }
         HIP_TRY(nullptr, launch_serve_finalize(all, st));
-        for (int b = 0; b < nreq;) {
-            int e = b;
-            while (e < nreq && reqs[e]->mi == reqs[b]->mi) ++e;
-            BatchArgs g{};
-            g.reqs = sl.dev_desc + b;
-            g.nreq = e - b;
-            HIP_TRY(nullptr, launch_serve_overflow(reqs[b]->mi, g, st));
-            b = e;
-        }
         for (ServeReq* r : reqs) {
             if (r->rq.mem_kind != NB6_MEM_HOST) continue;
             const size_t ni = (size_t)r->rq.n_i;

@@ -433,3 +433,58 @@ def test_everything_neighbour_long_lists(ctx, n):
         np.testing.assert_array_equal(lst[q, :min(cap, n - 1)], want)
     with pytest.raises(Exception):
         nb6.regular_force_host(ctx, 0, idx, 1e30, cl.dtr[idx], 1, cap + 1)
+
+
+@pytest.mark.parametrize("mode", ["ff", "fp64", "fp32"])
+def test_overflow_rescan_every_mode(ctx, mode):
+    """A list capacity below the neighbour count: the finalize rebuilds such a
+    list by an ordered rescan in the call's own coordinate mode, which must
+    give the first cap entries of the full list and the true count."""
+    nb6 = _nb6()
+    cfg = config(1)
+    cl = cfg["cluster"]
+    idx = cfg["blocks"]["all"][:300]
+    load(ctx, cl)
+    full = nb6.regular_force_host(ctx, 0, idx, cl.h2[idx], cl.dtr[idx], MODES[mode], 256)
+    assert full[4] == nb6.NB6_OK
+    for cap in (1, 5):
+        acc, jerk, nnb, lst, rc = nb6.regular_force_host(ctx, 0, idx, cl.h2[idx], cl.dtr[idx],
+                                                         MODES[mode], cap)
+        assert rc == nb6.NB6_WARN_NB_OVERFLOW
+        assert np.any(full[2] > cap)
+        np.testing.assert_array_equal(nnb, full[2])
+        np.testing.assert_array_equal(acc, full[0])
+        np.testing.assert_array_equal(jerk, full[1])
+        for q in range(len(idx)):
+            k = min(cap, nnb[q])
+            np.testing.assert_array_equal(lst[q, :k], full[3][q, :k])
+
+
+def test_counts_reset_between_calls(ctx):
+    """The per-i neighbour counters are zeroed once and reset by every call's
+    finalize: calls of growing and shrinking size, with overflowing and
+    complete lists, on one context give the same bits as on fresh contexts."""
+    nb6 = _nb6()
+    cfg = config(1)
+    cl = cfg["cluster"]
+    order = cfg["blocks"]["all"]
+    load(ctx, cl)
+    plan = [(1, 64), (300, 2), (64, 64), (1024, 64), (5, 0), (1024, 3), (700, 64)]
+    got = []
+    for ni, cap in plan:
+        idx = order[:ni]
+        got.append(nb6.regular_force_host(ctx, 0, idx, cl.h2[idx], cl.dtr[idx], 1, cap))
+    for (ni, cap), g in zip(plan, got):
+        fresh = nb6.nb6_create(0)
+        try:
+            load(fresh, cl)
+            idx = order[:ni]
+            w = nb6.regular_force_host(fresh, 0, idx, cl.h2[idx], cl.dtr[idx], 1, cap)
+        finally:
+            nb6.nb6_destroy(fresh)
+        for a, b in zip(g[:3], w[:3]):
+            np.testing.assert_array_equal(a, b)
+        for q in range(ni):  # slots past a row's count are not written
+            k = min(cap, g[2][q])
+            np.testing.assert_array_equal(g[3][q, :k], w[3][q, :k])
+        assert g[4] == w[4]
