@@ -365,6 +365,7 @@ def serving_leg(args, nb6, torch):
         if errors:
             raise RuntimeError(f"served requests failed: {errors[:5]}")
         sub = np.array([i["submit_us"] for i in infos]) * 1e-6
+        admit = np.array([i["admit_us"] for i in infos]) * 1e-6
         done = np.array([i["done_us"] for i in infos]) * 1e-6
         # latency from the arrival time (the submit call happens at the arrival)
         lat_serve = done - sub + np.maximum(sub_wall - arrivals, 0.0)
@@ -374,12 +375,16 @@ def serving_leg(args, nb6, torch):
                "served": {"p50_ms": q(lat_serve, 0.5), "p99_ms": q(lat_serve, 0.99),
                           "ginteractions_s": round(total / span_serve / 1e9, 3),
                           "mean_batch": round(float(batch.mean()), 2),
-                          "max_batch": int(batch.max())},
+                          "max_batch": int(batch.max()),
+                          # submit -> admission, and admission -> completion
+                          "queue_p50_ms": q(admit - sub, 0.5),
+                          "exec_p50_ms": q(done - admit, 0.5)},
                "plain": {"p50_ms": q(lat_plain, 0.5), "p99_ms": q(lat_plain, 0.99),
                          "ginteractions_s": round(total / span_plain / 1e9, 3)}}
         log(f"bench: rho={rho}: served p50/p99 = {run['served']['p50_ms']}/"
             f"{run['served']['p99_ms']} ms ({run['served']['ginteractions_s']} Gint/s, "
-            f"mean batch {run['served']['mean_batch']}); plain p50/p99 = "
+            f"mean batch {run['served']['mean_batch']}, queue/exec p50 "
+            f"{run['served']['queue_p50_ms']}/{run['served']['exec_p50_ms']} ms); plain p50/p99 = "
             f"{run['plain']['p50_ms']}/{run['plain']['p99_ms']} ms "
             f"({run['plain']['ginteractions_s']} Gint/s)")
         runs.append(run)
@@ -407,7 +412,9 @@ HBM_PEAK_GBS = 8000.0
 def irregular_leg(args, nb6, torch, ctx, cl, idx_np, idx_d, nnb, lst):
     """Irregular force (section 3.3 step 4) over the lists the last regular
     call produced: nb6_set_lists for the block, then nb6_irregular_force of the
-    whole block and of smaller random sub-blocks; HIP-event kernel times."""
+    whole block and of smaller random sub-blocks.  Kernel times from HIP
+    events on the (timing) context ``ctx``; wall time per call, back to back,
+    on a second context without event timing holding the same state."""
     stream = torch.cuda.current_stream()
     dev = idx_d.device
     ni = len(idx_np)
@@ -419,6 +426,11 @@ def irregular_leg(args, nb6, torch, ctx, cl, idx_np, idx_d, nnb, lst):
                                      stream))
     torch.cuda.synchronize()
     set_ms = (time.perf_counter() - t0) * 1e3
+    wctx = nb6.nb6_create(0)
+    nb6.check(wctx, nb6.nb6_load_particles(wctx, 0, cl.n, cl.m, cl.x, cl.v, cl.a, cl.jerk,
+                                           cl.t))
+    nb6.check(wctx, nb6.nb6_set_lists(wctx, 0, ni, idx_d, cnt, lst, cap, nb6.NB6_MEM_DEVICE,
+                                      stream))
     pairs_all = int(cnt.sum().item())
     acc = torch.empty((ni, 3), dtype=torch.float64, device=dev)
     jerk = torch.empty_like(acc)
@@ -434,15 +446,19 @@ def irregular_leg(args, nb6, torch, ctx, cl, idx_np, idx_d, nnb, lst):
         pairs = int(cnt_h[sel].sum())
         reps = max(5, min(200, int(3e7 / max(pairs, 1))))
 
-        def call():
-            nb6.check(ctx, nb6.nb6_irregular_force(ctx, 0, cl.tb, size, sub, acc[:size],
-                                                   jerk[:size], nb6.NB6_MEM_DEVICE, stream))
-        call()
+        def call(c):
+            nb6.check(c, nb6.nb6_irregular_force(c, 0, cl.tb, size, sub, acc[:size],
+                                                 jerk[:size], nb6.NB6_MEM_DEVICE, stream))
+        for c in (ctx, wctx):
+            call(c)
         torch.cuda.synchronize()
         nb6.nb6_kernel_times(ctx)
+        for _ in range(reps):
+            call(ctx)
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(reps):
-            call()
+            call(wctx)
         torch.cuda.synchronize()
         wall = (time.perf_counter() - t0) / reps
         ms, counts = nb6.nb6_kernel_times(ctx)
@@ -455,6 +471,8 @@ def irregular_leg(args, nb6, torch, ctx, cl, idx_np, idx_d, nnb, lst):
         log(f"bench: irregular N_i={size}: {pairs} pairs, kernel {k_ms * 1e3:.2f} us, "
             f"call {wall * 1e6:.2f} us")
     nb6.check(ctx, nb6.nb6_sync_status(ctx, stream))
+    nb6.check(wctx, nb6.nb6_sync_status(wctx, stream))
+    nb6.nb6_destroy(wctx)
     whole = res["blocks"][-1]
     res["roofline"] = {"bound": "hbm", "achieved": whole["algorithmic_gb_s"],
                        "peak": HBM_PEAK_GBS, "unit": "GB/s",

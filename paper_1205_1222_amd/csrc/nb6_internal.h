@@ -230,7 +230,8 @@ struct ReqDesc {
     PredictArgs  pred;        // prediction of its cluster (when do_predict)
     int          do_predict;
     int          mode;        // MODE_*
-    int          groups;      // i-groups of 64 >> rg.jl_shift
+    int          groups;      // i-groups of regf_group_size(ipl, rg.jl_shift)
+    int          ipl;         // i-particles per lane (1 or 2; 1 when rg.jl_shift > 0)
     long long    item0;       // first force work item within its mode group
     long long    blk0;        // first finalize workgroup within the batch
 };
@@ -248,7 +249,7 @@ hipError_t launch_serve_regf(int mode, const BatchArgs& b, int blocks, hipStream
 hipError_t launch_serve_finalize(const BatchArgs& b, hipStream_t s);
 // Predictions and count resets of every request of the batch, in one launch
 // of (requests x chunks) blocks; a chunk covers PREPARE_CHUNK particles.
-constexpr int PREPARE_CHUNK = 1024;
+constexpr int PREPARE_CHUNK = 256;  // one particle per thread
 hipError_t launch_serve_prepare(const BatchArgs& b, int chunks, hipStream_t s);
 
 // Force kernel: ipl i-particles per lane (a.jl_shift == 0), or one i per

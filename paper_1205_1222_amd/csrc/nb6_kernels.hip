@@ -677,18 +677,21 @@ __device__ __forceinline__ long long uniform_ll(long long v) {
     return (long long)(((unsigned long long)hi << 32) | lo);
 }
 
-// Persistent: every wavefront takes work items (request, i-group, j-slice)
-// from the batch counter until none is left.  An item's result depends only
-// on its request, so a request gives the same bits alone or in any batch.
+// Persistent: wavefront w of the launch takes work item (request, i-group,
+// j-slice) w first, then, while the launch has fewer wavefronts W than
+// items, items W + t for tickets t = 0, 1, ... drawn from the batch counter
+// after each item.  A launch with a wavefront per item draws no ticket.  An
+// item's result depends only on its request, so a request gives the same
+// bits alone or in any batch.
 template <int MODE>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
 serve_regf_kernel(BatchArgs b) {
     const_ptr<ReqDesc> reqs = (const_ptr<ReqDesc>)(b.reqs);
-    for (;;) {
-        unsigned long long got = 0;
-        if ((threadIdx.x & 63) == 0) got = atomicAdd(b.counter, 1ull);
-        const long long item = uniform_ll((long long)got);
-        if (item >= b.nitems) break;
+    const int wpb = blockDim.x >> 6;
+    const long long waves = (long long)gridDim.x * wpb;
+    long long item = (long long)blockIdx.x * wpb +
+                     __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    while (item < b.nitems) {
         int lo = 0, hi = b.nreq - 1;  // last request with item0 <= item
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
@@ -697,10 +700,17 @@ serve_regf_kernel(BatchArgs b) {
         const RegfArgs a = load_regf_args(reqs + lo);
         const long long local = item - reqs[lo].item0;
         const int groups = reqs[lo].groups;
+        const int g = (int)(local % groups), s = (int)(local / groups);
         if (a.jl_shift > 0)
-            regf_item_lanes<MODE, NPART>(a, (int)(local % groups), (int)(local / groups));
+            regf_item_lanes<MODE, NPART>(a, g, s);
+        else if (reqs[lo].ipl == 2)
+            regf_item<MODE, 2, NPART>(a, g, s);
         else
-            regf_item<MODE, 1, NPART>(a, (int)(local % groups), (int)(local / groups));
+            regf_item<MODE, 1, NPART>(a, g, s);
+        if (waves >= b.nitems) break;  // uniform: no item beyond the first
+        unsigned long long got = 0;
+        if ((threadIdx.x & 63) == 0) got = atomicAdd(b.counter, 1ull);
+        item = waves + uniform_ll((long long)got);
     }
 }
 

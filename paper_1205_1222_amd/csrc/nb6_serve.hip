@@ -15,12 +15,13 @@
 // kBatchWork pair interactions (a larger request runs alone), and its
 // persistent grid is sized to its work and never fills more than a quarter of
 // the wave slots of the chip, so short batches run beside long ones.  A host
-// callback at the end of each batch's stream work stamps its requests and
-// frees their memory and clusters.
+// completion thread watches each batch's end-of-work event (spinning on it
+// while batches are in flight), then stamps the batch's requests and frees
+// their memory and clusters.
 //
-// A request's slicing (make_plan without two i per lane) and its summation
-// order depend only on the request, so its results are bit-identical alone
-// and in any mix.
+// A request's plan (make_plan: the rule of a plain call on the same context)
+// and its summation order depend only on the request, so its results are
+// bit-identical alone, in any mix, and to the plain call.
 #include "nb6_context.h"
 
 #include <algorithm>
@@ -43,7 +44,16 @@ constexpr int kMaxBatch = 512;     // requests per batch
 constexpr double kBatchWork = 2.5e8;  // pair interactions per batch (~0.2 ms)
 constexpr size_t kAlign = 256;
 
-size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+constexpr size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// What a batch uploads ahead of its descriptors, zeroed on the host: the
+// persistent kernels' work-item counters (one per coordinate mode) and the
+// requests' status words.  Header and descriptors go up in one copy.
+struct BatchHeader {
+    unsigned long long counters[4];
+    unsigned status[kMaxBatch];
+};
+constexpr size_t kHeaderBytes = align_up(sizeof(BatchHeader));
 
 // First-fit allocator over one device arena, coalescing on free.
 class Arena {
@@ -161,14 +171,19 @@ size_t carve(ServeReq* r, char* base) {
 
 struct Slot {
     hipStream_t stream = nullptr;
-    ReqDesc* host_desc = nullptr;        // pinned
-    ReqDesc* dev_desc = nullptr;
-    unsigned* host_status = nullptr;     // pinned [kMaxBatch]
-    unsigned* dev_status = nullptr;      // [kMaxBatch] status words + 6 counter words
-    bool busy = false;
+    hipEvent_t done = nullptr;           // recorded after the batch's last work
+    char* host_blob = nullptr;           // pinned: BatchHeader, then kMaxBatch ReqDesc
+    char* dev_blob = nullptr;            // its device copy
+    bool busy = false;                   // holds a batch
+    bool launched = false;               // its work is enqueued; `done` is pending
     std::vector<ServeReq*> reqs;
-    class Engine* engine = nullptr;      // for the completion callback
+
+    BatchHeader* host_hdr() const { return reinterpret_cast<BatchHeader*>(host_blob); }
+    BatchHeader* dev_hdr() const { return reinterpret_cast<BatchHeader*>(dev_blob); }
+    ReqDesc* host_desc() const { return reinterpret_cast<ReqDesc*>(host_blob + kHeaderBytes); }
+    ReqDesc* dev_desc() const { return reinterpret_cast<ReqDesc*>(dev_blob + kHeaderBytes); }
 };
+constexpr size_t kBlobBytes = kHeaderBytes + kMaxBatch * sizeof(ReqDesc);
 
 }  // namespace
 
@@ -181,13 +196,12 @@ class Engine {
         if (int rc = arena_.init(c_, (size_t)c_->hbm_budget)) return rc;
         for (Slot& s : slots_) {
             HIP_TRY(c_, hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking));
-            HIP_TRY(c_, hipHostMalloc((void**)&s.host_desc, kMaxBatch * sizeof(ReqDesc)));
-            HIP_TRY(c_, hipMalloc((void**)&s.dev_desc, kMaxBatch * sizeof(ReqDesc)));
-            HIP_TRY(c_, hipHostMalloc((void**)&s.host_status, kMaxBatch * sizeof(unsigned)));
-            HIP_TRY(c_, hipMalloc((void**)&s.dev_status, (kMaxBatch + 6) * sizeof(unsigned)));
+            HIP_TRY(c_, hipEventCreateWithFlags(&s.done, hipEventDisableTiming));
+            HIP_TRY(c_, hipHostMalloc((void**)&s.host_blob, kBlobBytes));
+            HIP_TRY(c_, hipMalloc((void**)&s.dev_blob, kBlobBytes));
         }
-        for (Slot& s : slots_) s.engine = this;
         sched_ = std::thread([this] { sched_loop(); });
+        done_ = std::thread([this] { done_loop(); });
         return NB6_OK;
     }
 
@@ -206,20 +220,23 @@ class Engine {
         if (sched_.joinable()) sched_.join();
         {
             std::unique_lock<std::mutex> lk(mu_);  // batches still on the GPU
-            cv_sched_.wait(lk, [&] {
-                for (const Slot& s : slots_)
-                    if (s.busy) return false;
-                return true;
-            });
+            if (done_.joinable())
+                cv_sched_.wait(lk, [&] {
+                    for (const Slot& s : slots_)
+                        if (s.busy) return false;
+                    return true;
+                });
+            stop_done_ = true;
+            cv_done_.notify_all();
         }
+        if (done_.joinable()) done_.join();
         (void)hipSetDevice(c_->device);
         for (Slot& s : slots_) {
             if (s.stream) (void)hipStreamSynchronize(s.stream);
             if (s.stream) (void)hipStreamDestroy(s.stream);
-            if (s.host_desc) (void)hipHostFree(s.host_desc);
-            if (s.dev_desc) (void)hipFree(s.dev_desc);
-            if (s.host_status) (void)hipHostFree(s.host_status);
-            if (s.dev_status) (void)hipFree(s.dev_status);
+            if (s.done) (void)hipEventDestroy(s.done);
+            if (s.host_blob) (void)hipHostFree(s.host_blob);
+            if (s.dev_blob) (void)hipFree(s.dev_blob);
             s = Slot();
         }
         arena_.release();
@@ -270,7 +287,7 @@ class Engine {
                 if (int rc = ensure(c_, r->cl->tmax, (size_t)vtiles(r->cl->n) * sizeof(float)))
                     return rc;
             }
-            r->plan = make_plan(c_, r->cl->n, ni, 1);
+            r->plan = make_plan(c_, r->cl->n, ni);
         }
         r->bytes = carve(r.get(), nullptr);
         std::unique_lock<std::mutex> lk(mu_);
@@ -398,23 +415,68 @@ class Engine {
                 cv_polled_.notify_all();
                 continue;
             }
+            sl.launched = true;
+            cv_done_.notify_all();
         }
     }
 
-    // Host callback at the end of a batch's stream work (no HIP calls here).
-    static void on_batch_done(void* arg) {
-        Slot* sl = static_cast<Slot*>(arg);
-        sl->engine->complete(*sl);
+    // Completion: while any batch is in flight, query the slots' end events
+    // in a loop (the lock is dropped around the queries); when none is, sleep
+    // until the scheduler launches one.  A spinning waiter sees the end of a
+    // batch within a few microseconds, where a stream callback takes tens.
+    void done_loop() {
+        (void)hipSetDevice(c_->device);
+        std::unique_lock<std::mutex> lk(mu_);
+        for (;;) {
+            cv_done_.wait(lk, [&] { return stop_done_ || any_launched(); });
+            if (!any_launched()) {
+                if (stop_done_) break;
+                continue;
+            }
+            Slot* cand[kSlots];
+            int nc = 0;
+            for (Slot& s : slots_)
+                if (s.launched) cand[nc++] = &s;
+            lk.unlock();
+            Slot* ready = nullptr;
+            hipError_t err = hipSuccess;
+            for (;;) {
+                for (int i = 0; i < nc && !ready; ++i) {
+                    const hipError_t e = hipEventQuery(cand[i]->done);
+                    if (e != hipErrorNotReady) {
+                        ready = cand[i];
+                        err = e;
+                    }
+                }
+                if (ready) break;
+                std::this_thread::yield();
+                if (nc < kSlots) break;  // look for slots launched meanwhile
+            }
+            lk.lock();
+            if (ready) {
+                ready->launched = false;
+                complete(*ready, err);
+            }
+        }
     }
 
-    void complete(Slot& sl) {
+    bool any_launched() const {
+        for (const Slot& s : slots_)
+            if (s.launched) return true;
+        return false;
+    }
+
+    // Called with mu_ held, after the batch's stream work has ended.
+    void complete(Slot& sl, hipError_t err) {
         const double t = now();
-        std::lock_guard<std::mutex> lk(mu_);
+        const unsigned* status = sl.host_hdr()->status;
         for (size_t b = 0; b < sl.reqs.size(); ++b) {
             int st = NB6_OK;
-            if (sl.host_status[b] & (ST_BAD_INDEX | ST_BAD_H2 | ST_NONFINITE))
+            if (err != hipSuccess)
+                st = NB6_ERR_HIP;
+            else if (status[b] & (ST_BAD_INDEX | ST_BAD_H2 | ST_NONFINITE))
                 st = NB6_ERR_DEVICE_INPUT;
-            else if (sl.host_status[b] & ST_OVERFLOW)
+            else if (status[b] & ST_OVERFLOW)
                 st = NB6_WARN_NB_OVERFLOW;
             finish(sl.reqs[b], st, t);
         }
@@ -455,7 +517,7 @@ class Engine {
                 prev_mi = r->mi;
             }
             if (cl->last_plain) HIP_TRY(nullptr, hipStreamWaitEvent(st, cl->last_plain, 0));
-            ReqDesc& d = sl.host_desc[b];
+            ReqDesc& d = sl.host_desc()[b];
             std::memset(&d, 0, sizeof d);
             const int bit = mode_bit(r->mi);
             // the queue owns the cluster while the request is in flight
@@ -464,7 +526,7 @@ class Engine {
                 cl->pred_valid = (cl->t_pred == r->rq.t_block ? cl->pred_valid : 0) | bit;
                 cl->t_pred = r->rq.t_block;
             }
-            unsigned* status = sl.dev_status + b;
+            unsigned* status = sl.dev_hdr()->status + b;
             d.pred.n = cl->n;
             d.pred.st = cl->state;
             d.pred.tb = r->rq.t_block;
@@ -492,20 +554,22 @@ class Engine {
             d.fin.list = r->d_list; d.fin.cap = r->rq.cap; d.fin.status = status;
             d.fin.rec = d.rg.rec; d.fin.dtr = r->d_dtr; d.fin.mode = r->mi;
             d.mode = r->mi;
-            const int gsize = regf_group_size(1, p.jl_shift);
+            const int gsize = regf_group_size(p.ipl, p.jl_shift);
             d.groups = (ni + gsize - 1) / gsize;
+            d.ipl = p.ipl;
             d.item0 = item_in_mode;
             d.blk0 = blk0;
             item_in_mode += (long long)d.groups * p.nslices;
             blk0 += final_blocks(ni, NPART);
-            chunk_need = std::max<int64_t>(chunk_need, std::max<int64_t>(cl->n, ni + 1));
+            chunk_need = std::max<int64_t>(chunk_need, std::max<int64_t>(cl->n, ni));
         }
-        HIP_TRY(nullptr, hipMemcpyAsync(sl.dev_desc, sl.host_desc, nreq * sizeof(ReqDesc),
+        std::memset(sl.host_hdr(), 0, sizeof(BatchHeader));
+        HIP_TRY(nullptr, hipMemcpyAsync(sl.dev_blob, sl.host_blob,
+                                   kHeaderBytes + nreq * sizeof(ReqDesc),
                                    hipMemcpyHostToDevice, st));
-        HIP_TRY(nullptr, launch_zero_u32(sl.dev_status, kMaxBatch + 6, st));
-        unsigned long long* counters = (unsigned long long*)(sl.dev_status + kMaxBatch);
+        unsigned long long* counters = sl.dev_hdr()->counters;
         BatchArgs all{};
-        all.reqs = sl.dev_desc;
+        all.reqs = sl.dev_desc();
         all.nreq = nreq;
         all.nblk_total = blk0;
         HIP_TRY(nullptr, launch_serve_prepare(
@@ -516,12 +580,12 @@ class Engine {
             int e = b;
             long long items = 0;
             while (e < nreq && reqs[e]->mi == reqs[b]->mi) {
-                items += (long long)sl.host_desc[e].groups * reqs[e]->plan.nslices;
+                items += (long long)sl.host_desc()[e].groups * reqs[e]->plan.nslices;
                 ++e;
             }
             const int blocks = (int)std::min<long long>((long long)c_->num_cu * 4, (items + 3) / 4);
             BatchArgs g{};
-            g.reqs = sl.dev_desc + b;
+            g.reqs = sl.dev_desc() + b;
             g.nreq = e - b;
             g.nitems = items;
             g.counter = counters + reqs[b]->mi;
@@ -542,14 +606,14 @@ class Engine {
                 HIP_TRY(nullptr, hipMemcpyAsync(r->rq.list, r->d_list, ni * r->rq.cap * sizeof(int32_t),
                                            hipMemcpyDeviceToHost, st));
         }
-        HIP_TRY(nullptr, hipMemcpyAsync(sl.host_status, sl.dev_status, nreq * sizeof(unsigned),
-                                   hipMemcpyDeviceToHost, st));
+        HIP_TRY(nullptr, hipMemcpyAsync(sl.host_hdr()->status, sl.dev_hdr()->status,
+                                   nreq * sizeof(unsigned), hipMemcpyDeviceToHost, st));
         for (ServeReq* r : reqs) {  // plain calls on these clusters wait for this
             if (!r->cl->last_served)
                 HIP_TRY(nullptr, hipEventCreateWithFlags(&r->cl->last_served, hipEventDisableTiming));
             HIP_TRY(nullptr, hipEventRecord(r->cl->last_served, st));
         }
-        HIP_TRY(nullptr, hipLaunchHostFunc(st, &Engine::on_batch_done, &sl));
+        HIP_TRY(nullptr, hipEventRecord(sl.done, st));
         return NB6_OK;
     }
 
@@ -563,8 +627,10 @@ class Engine {
     Arena arena_;
     uint64_t next_ticket_ = 1;
     bool stop_ = false;
+    bool stop_done_ = false;
     bool blocked_ = false;
-    std::thread sched_;
+    std::condition_variable cv_done_;
+    std::thread sched_, done_;
 };
 
 void engine_kick(nb6_ctx* c) {

@@ -488,3 +488,56 @@ def test_counts_reset_between_calls(ctx):
             k = min(cap, g[2][q])
             np.testing.assert_array_equal(g[3][q, :k], w[3][q, :k])
         assert g[4] == w[4]
+
+
+def test_tiny_clusters_and_repeated_indices(ctx):
+    """Degenerate inputs: a one-particle cluster (no j other than i: zero force,
+    empty list), a two-body pair against its closed form, and an active block
+    that names the same particle more than once (independent, identical
+    rows)."""
+    from workloads.clusters import Cluster
+    nb6 = _nb6()
+    z3 = np.zeros((1, 3))
+    one = Cluster(m=np.array([0.5]), x=np.array([[0.3, -0.2, 0.1]]), v=np.array([[0.1, 0, 0]]),
+                  a=z3, jerk=z3, t=np.zeros(1), tb=0.0, h2=np.array([0.01]),
+                  dtr=np.array([0.0]))
+    for mode in MODES.values():
+        load(ctx, one)
+        nb6.check(ctx, nb6.nb6_predict_j(ctx, 0, one.tb, mode))
+        acc, jerk, nnb, lst, rc = nb6.regular_force_host(ctx, 0, np.zeros(1, np.int32),
+                                                         one.h2, one.dtr, mode, 4)
+        assert rc == nb6.NB6_OK
+        assert np.all(acc == 0.0) and np.all(jerk == 0.0) and nnb[0] == 0
+    # two bodies 1.5 apart with radius 0.1: each feels the other's full force
+    m = np.array([0.25, 0.75])
+    x = np.array([[0.0, 0.0, 0.0], [1.5, 0.0, 0.0]])
+    v = np.array([[0.0, 0.1, 0.0], [0.0, -0.2, 0.05]])
+    two = Cluster(m=m, x=x, v=v, a=np.zeros((2, 3)), jerk=np.zeros((2, 3)), t=np.zeros(2),
+                  tb=0.0, h2=np.full(2, 0.01), dtr=np.zeros(2))
+    load(ctx, two)
+    R = x[1] - x[0]
+    V = v[1] - v[0]
+    r = np.linalg.norm(R)
+    want_a = m[1] * R / r ** 3
+    want_j = m[1] * (V / r ** 3 - 3.0 * np.dot(R, V) * R / r ** 5)
+    for name, mode in MODES.items():
+        nb6.check(ctx, nb6.nb6_predict_j(ctx, 0, two.tb, mode))
+        acc, jerk, nnb, lst, rc = nb6.regular_force_host(
+            ctx, 0, np.array([0, 1], np.int32), two.h2, two.dtr, mode, 4)
+        assert np.all(nnb == 0)
+        tol = 1e-6 if name != "fp32" else 1e-5
+        np.testing.assert_allclose(acc[0], want_a, rtol=tol, atol=tol * np.abs(want_a).max())
+        np.testing.assert_allclose(jerk[0], want_j, rtol=tol, atol=tol * np.abs(want_j).max())
+        np.testing.assert_allclose(m[0] * acc[0], -m[1] * acc[1], rtol=tol)
+    # the same particle several times in one block
+    cfg = config(1)
+    cl = cfg["cluster"]
+    load(ctx, cl)
+    idx = np.array([5, 900, 5, 0, 900, 5, 1023], np.int32)
+    xp, vp, ref = oracle_ref(cl, idx)
+    acc, jerk, nnb, lst = check_mode(ctx, cl, idx, "ff", "repeated_indices", ref=(xp, vp, ref))
+    for a_, b_ in ((0, 2), (0, 5), (1, 4)):
+        np.testing.assert_array_equal(acc[a_], acc[b_])
+        np.testing.assert_array_equal(jerk[a_], jerk[b_])
+        assert nnb[a_] == nnb[b_]
+        np.testing.assert_array_equal(lst[a_, :nnb[a_]], lst[b_, :nnb[b_]])

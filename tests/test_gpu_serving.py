@@ -136,22 +136,31 @@ def test_alone_and_mixed_are_bit_identical(clusters):
         nb6.nb6_destroy(ctx)
 
 
-def test_served_equals_plain_call(clusters):
-    """One i per lane in both paths: the same slicing, hence the same bits."""
+@pytest.mark.parametrize("hint,c,step,ni_max", [(1, 2, 7, None), (0, 3, 1, 4500),
+                                                (0, 1, 1, 2000), (0, 0, 1, 20)])
+def test_served_equals_plain_call(clusters, hint, c, step, ni_max):
+    """A served request takes the plan a plain call on the same context takes
+    (one i per lane, lanes per i for small blocks, two i per lane from 4096
+    on), hence the same bits."""
     nb6 = _nb6()
-    ctx = nb6.nb6_create(0, ipl_hint=1)
+    ctx = nb6.nb6_create(0, ipl_hint=hint)
     try:
         _load_all(nb6, ctx, clusters)
-        cl = clusters[2]
-        idx = np.arange(0, cl.n, 7, dtype=np.int32)
-        t, h = _submit(nb6, ctx, cl, 2, cl.tb, idx, 64)
+        cl = clusters[c]
+        idx = np.arange(0, cl.n, step, dtype=np.int32)[:ni_max]
+        t, h = _submit(nb6, ctx, cl, c, cl.tb, idx, 64)
         rc, _ = nb6.nb6_poll(ctx, t, wait=1)
-        nb6.check(ctx, nb6.nb6_predict_j(ctx, 2, cl.tb, nb6.NB6_DX_FF))
-        acc, jerk, nnb, lst, _ = nb6.regular_force_host(ctx, 2, idx, cl.h2[idx], cl.dtr[idx],
+        assert rc in (nb6.NB6_OK, nb6.NB6_WARN_NB_OVERFLOW)
+        nb6.check(ctx, nb6.nb6_predict_j(ctx, c, cl.tb, nb6.NB6_DX_FF))
+        acc, jerk, nnb, lst, _ = nb6.regular_force_host(ctx, c, idx, cl.h2[idx], cl.dtr[idx],
                                                         1, 64)
+        print("plan", len(idx), nb6.nb6_last_plan(ctx), flush=True)
         np.testing.assert_array_equal(acc, h.acc)
         np.testing.assert_array_equal(jerk, h.jerk)
         np.testing.assert_array_equal(nnb, h.nnb)
+        for q in range(len(idx)):
+            k = min(64, nnb[q])
+            np.testing.assert_array_equal(lst[q, :k], h.lst[q, :k])
     finally:
         nb6.nb6_destroy(ctx)
 
