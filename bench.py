@@ -558,6 +558,19 @@ def block_sweep(args, cfg, nb6, torch, T, lanes=0, slices=None, max_ni=None, max
             torch.cuda.synchronize()
             out.append((time.perf_counter() - t0) / reps)
         wall = out[0]
+        # the same call with host arrays in and out (copies and synchronisation
+        # included), as a host program without device buffers would make it
+        h_idx, h_h2, h_dtr = idx.astype(np.int32), cl.h2[idx].copy(), cl.dtr[idx].copy()
+        h_out = (np.empty((ni, 3)), np.empty((ni, 3)), np.empty(ni, np.int32),
+                 np.empty((ni, args.cap), np.int32))
+        host_reps = max(3, reps // 4)
+        for k in range(host_reps + 1):
+            if k == 1:
+                t0 = time.perf_counter()
+            nb6.check(ctxs[0], nb6.nb6_regular_force(
+                ctxs[0], 0, ni, h_idx, h_h2, h_dtr, mode, *h_out, args.cap, nb6.NB6_MEM_HOST),
+                (nb6.NB6_OK, nb6.NB6_WARN_NB_OVERFLOW))
+        host_wall = (time.perf_counter() - t0) / host_reps
         ms, cnt = nb6.nb6_kernel_times(ctxs[1])
         pairs = ni * (n - 1)
         ipl, jl, ns, slen = nb6.nb6_last_plan(ctxs[1])
@@ -565,6 +578,7 @@ def block_sweep(args, cfg, nb6, torch, T, lanes=0, slices=None, max_ni=None, max
                           "ipl": ipl, "lanes": jl, "slices": ns, "slice_len": slen,
                           "forced": [lanes, slices], "reps": reps,
                           "call_us": round(wall * 1e6, 2),
+                          "host_call_us": round(host_wall * 1e6, 2),
                           "force_us": round(ms[1] / cnt[1] * 1e3, 2),
                           "finalize_us": round(ms[2] / cnt[2] * 1e3, 2),
                           "call_gint_s": round(pairs / wall / 1e9, 3),
@@ -626,7 +640,7 @@ def main():
                     help="write the force kernel's counter summary from three rocprofv3 "
                          "counter CSV files (with --copy-mib; '-' for no VALU run) to its "
                          "profiles/ file and exit")
-    ap.add_argument("--rho", default="0.5,0.8,0.95,1.5",
+    ap.add_argument("--rho", default="0.5,0.8,0.95,1.5,2.5",
                     help="offered load(s) as fractions of the plain form's capacity")
     args = ap.parse_args()
 

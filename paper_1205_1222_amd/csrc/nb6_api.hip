@@ -56,6 +56,21 @@ void release(DevBuf& b) {
     b.cap = 0;
 }
 
+int ensure_pinned(nb6_ctx* c, PinBuf& b, size_t bytes) {
+    if (bytes <= b.cap) return NB6_OK;
+    const size_t want = std::max(bytes, b.cap + b.cap / 2);
+    if (b.p) HIP_TRY(c, hipHostFree(b.p));
+    b.p = nullptr;
+    b.cap = 0;
+    if (hipHostMalloc((void**)&b.p, want) != hipSuccess) {
+        (void)hipGetLastError();
+        b.p = nullptr;
+        return fail(c, NB6_ERR_NOMEM, "pinned host allocation of %zu bytes failed", want);
+    }
+    b.cap = want;
+    return NB6_OK;
+}
+
 Plan make_plan(const nb6_ctx* c, int64_t n, int64_t ni, int ipl) {
     Plan p;
     // two i per lane once every lane has work for several slices' worth of
@@ -260,10 +275,9 @@ int nb6_destroy(nb6_ctx* c) {
         if (cl->last_served) (void)hipEventDestroy(cl->last_served);
         delete cl;
     }
-    for (DevBuf* b : {&c->part, &c->cnt, &c->lst, &c->in_idx, &c->in_h2, &c->in_dtr,
-                      &c->out_acc, &c->out_jerk, &c->out_pot, &c->out_nnb, &c->out_list,
-                      &c->corr})
+    for (DevBuf* b : {&c->part, &c->cnt, &c->lst, &c->io, &c->out_list, &c->corr})
         release(*b);
+    if (c->pin.p) (void)hipHostFree(c->pin.p);
     for (auto& b : c->ld) release(b);
     if (c->status) (void)hipFree(c->status);
     for (auto& t : c->timed) {
@@ -465,6 +479,11 @@ int nb6_regular_force(nb6_ctx* c, int cluster, int64_t n_i, const int32_t* idx_i
     double* d_pot = pot;
     int32_t* d_nnb = nnb;
     int32_t* d_list = list;
+    struct {
+        Stage lay;
+        size_t idx, h2, dtr, in_end, acc, jerk, pot, nnb, list, out_end, status;
+        bool list_staged;
+    } hs{};
     if (mem_kind == NB6_MEM_HOST) {
         for (int q = 0; q < ni; ++q) {
             if (idx_i[q] < 0 || idx_i[q] >= n)
@@ -476,27 +495,39 @@ int nb6_regular_force(nb6_ctx* c, int cluster, int64_t n_i, const int32_t* idx_i
             if (!std::isfinite(dtr_i[q]))
                 return fail(c, NB6_ERR_ARG, "dtr_i[%d] is not finite", q);
         }
+        // inputs go up in one copy from the pinned buffer; the outputs (and
+        // lists up to kStageListMax bytes) come back in one copy into it
+        const size_t list_bytes = (size_t)ni * cap * sizeof(int32_t);
+        hs.list_staged = cap > 0 && list_bytes <= kStageListMax;
+        hs.idx = hs.lay.add(ni * sizeof(int32_t));
+        hs.h2 = hs.lay.add(ni * sizeof(double));
+        hs.dtr = hs.lay.add(ni * sizeof(double));
+        hs.in_end = hs.lay.end;
+        hs.acc = hs.lay.add(3 * ni * sizeof(double));
+        hs.jerk = hs.lay.add(3 * ni * sizeof(double));
+        hs.pot = pot ? hs.lay.add(ni * sizeof(double)) : 0;
+        hs.nnb = hs.lay.add(ni * sizeof(int32_t));
+        hs.list = hs.list_staged ? hs.lay.add(list_bytes) : 0;
+        hs.out_end = hs.lay.end;
+        hs.status = hs.lay.add(4 * sizeof(unsigned));
         int rc;
-        if ((rc = ensure(c, c->in_idx, ni * sizeof(int32_t))) ||
-            (rc = ensure(c, c->in_h2, ni * sizeof(double))) ||
-            (rc = ensure(c, c->in_dtr, ni * sizeof(double))) ||
-            (rc = ensure(c, c->out_acc, 3 * ni * sizeof(double))) ||
-            (rc = ensure(c, c->out_jerk, 3 * ni * sizeof(double))) ||
-            (rc = ensure(c, c->out_nnb, ni * sizeof(int32_t))) ||
-            (rc = ensure(c, c->out_list, std::max<size_t>(1, (size_t)ni * cap) * sizeof(int32_t))) ||
-            (pot && (rc = ensure(c, c->out_pot, ni * sizeof(double)))))
+        if ((rc = ensure(c, c->io, hs.lay.end)) || (rc = ensure_pinned(c, c->pin, hs.lay.end)) ||
+            (cap > 0 && !hs.list_staged && (rc = ensure(c, c->out_list, list_bytes))))
             return rc;
-        HIP_TRY(c, hipMemcpyAsync(c->in_idx.p, idx_i, ni * sizeof(int32_t), hipMemcpyHostToDevice, st));
-        HIP_TRY(c, hipMemcpyAsync(c->in_h2.p, h2_i, ni * sizeof(double), hipMemcpyHostToDevice, st));
-        HIP_TRY(c, hipMemcpyAsync(c->in_dtr.p, dtr_i, ni * sizeof(double), hipMemcpyHostToDevice, st));
-        d_idx = (const int32_t*)c->in_idx.p;
-        d_h2 = (const double*)c->in_h2.p;
-        d_dtr = (const double*)c->in_dtr.p;
-        d_acc = (double*)c->out_acc.p;
-        d_jerk = (double*)c->out_jerk.p;
-        d_nnb = (int32_t*)c->out_nnb.p;
-        d_list = (int32_t*)c->out_list.p;
-        if (pot) d_pot = (double*)c->out_pot.p;
+        char* pin = c->pin.p;
+        char* dev = (char*)c->io.p;
+        std::memcpy(pin + hs.idx, idx_i, ni * sizeof(int32_t));
+        std::memcpy(pin + hs.h2, h2_i, ni * sizeof(double));
+        std::memcpy(pin + hs.dtr, dtr_i, ni * sizeof(double));
+        HIP_TRY(c, hipMemcpyAsync(dev, pin, hs.in_end, hipMemcpyHostToDevice, st));
+        d_idx = (const int32_t*)(dev + hs.idx);
+        d_h2 = (const double*)(dev + hs.h2);
+        d_dtr = (const double*)(dev + hs.dtr);
+        d_acc = (double*)(dev + hs.acc);
+        d_jerk = (double*)(dev + hs.jerk);
+        d_nnb = (int32_t*)(dev + hs.nnb);
+        d_list = hs.list_staged ? (int32_t*)(dev + hs.list) : (int32_t*)c->out_list.p;
+        if (pot) d_pot = (double*)(dev + hs.pot);
     }
 
     const Plan p = make_plan(c, n, ni);
@@ -569,18 +600,23 @@ int nb6_regular_force(nb6_ctx* c, int cluster, int64_t n_i, const int32_t* idx_i
 
     if (mem_kind == NB6_MEM_DEVICE) return NB6_OK;
 
-    HIP_TRY(c, hipMemcpyAsync(acc, d_acc, 3 * ni * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIP_TRY(c, hipMemcpyAsync(jerk, d_jerk, 3 * ni * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIP_TRY(c, hipMemcpyAsync(nnb, d_nnb, ni * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    if (pot)
-        HIP_TRY(c, hipMemcpyAsync(pot, d_pot, ni * sizeof(double), hipMemcpyDeviceToHost, st));
-    if (cap > 0)
+    char* pin = c->pin.p;
+    HIP_TRY(c, hipMemcpyAsync(pin + hs.in_end, (char*)c->io.p + hs.in_end, hs.out_end - hs.in_end,
+                              hipMemcpyDeviceToHost, st));
+    if (cap > 0 && !hs.list_staged)
         HIP_TRY(c, hipMemcpyAsync(list, d_list, (size_t)ni * cap * sizeof(int32_t),
                                   hipMemcpyDeviceToHost, st));
-    unsigned status[4];
-    HIP_TRY(c, hipMemcpyAsync(status, c->status, sizeof status, hipMemcpyDeviceToHost, st));
+    HIP_TRY(c, hipMemcpyAsync(pin + hs.status, c->status, 4 * sizeof(unsigned),
+                              hipMemcpyDeviceToHost, st));
     HIP_TRY(c, hipStreamSynchronize(st));
     HIP_TRY(c, launch_zero_u32(c->status, 4, st));
+    std::memcpy(acc, pin + hs.acc, 3 * ni * sizeof(double));
+    std::memcpy(jerk, pin + hs.jerk, 3 * ni * sizeof(double));
+    std::memcpy(nnb, pin + hs.nnb, ni * sizeof(int32_t));
+    if (pot) std::memcpy(pot, pin + hs.pot, ni * sizeof(double));
+    if (hs.list_staged) std::memcpy(list, pin + hs.list, (size_t)ni * cap * sizeof(int32_t));
+    unsigned status[4];
+    std::memcpy(status, pin + hs.status, sizeof status);
     if (status[0] & (ST_BAD_INDEX | ST_BAD_H2 | ST_NONFINITE))
         return fail(c, NB6_ERR_DEVICE_INPUT, "GPU validation flagged 0x%x", status[0]);
     for (int q = 0; q < ni; ++q)
@@ -609,13 +645,12 @@ int nb6_get_predicted(nb6_ctx* c, int cluster, int dx_mode, double* x, double* v
     const int64_t n = cl->n;
     double* dx = x;
     double* dv = v;
-    if (mem_kind == NB6_MEM_HOST) {
-        int rc;
-        if ((rc = ensure(c, c->out_acc, 3 * n * sizeof(double))) ||
-            (rc = ensure(c, c->out_jerk, 3 * n * sizeof(double))))
-            return rc;
-        dx = (double*)c->out_acc.p;
-        dv = (double*)c->out_jerk.p;
+    if (mem_kind == NB6_MEM_HOST) {  // a diagnostic read: through device scratch
+        Stage lay;
+        const size_t o_v = (lay.add(3 * n * sizeof(double)), lay.add(3 * n * sizeof(double)));
+        if (int rc = ensure(c, c->io, lay.end)) return rc;
+        dx = (double*)c->io.p;
+        dv = (double*)((char*)c->io.p + o_v);
     }
     HIP_TRY(c, launch_unpack(mi, cl->rec[mi].p, n, dx, dv, st));
     if (mem_kind == NB6_MEM_HOST) {
@@ -688,18 +723,29 @@ int nb6_set_lists(nb6_ctx* c, int cluster, int64_t n_i, const int32_t* idx_i,
                     return fail(c, NB6_ERR_ARG, "list entry (%d, %d) = %d out of range", k, e, j);
             }
         }
+        // indices and counts go up through the pinned buffer in one copy,
+        // with the lists when they are small
+        const size_t list_bytes = (size_t)ni * cap * sizeof(int32_t);
+        const bool staged = list_bytes <= kStageListMax;
+        Stage lay;
+        const size_t o_idx = lay.add(ni * sizeof(int32_t));
+        const size_t o_nnb = lay.add(ni * sizeof(int32_t));
+        const size_t o_list = staged ? lay.add(list_bytes) : 0;
         int rc;
-        if ((rc = ensure(c, c->in_idx, ni * sizeof(int32_t))) ||
-            (rc = ensure(c, c->out_nnb, ni * sizeof(int32_t))) ||
-            (rc = ensure(c, c->out_list, (size_t)ni * cap * sizeof(int32_t))))
+        if ((rc = ensure(c, c->io, lay.end)) || (rc = ensure_pinned(c, c->pin, lay.end)) ||
+            (!staged && (rc = ensure(c, c->out_list, list_bytes))))
             return rc;
-        HIP_TRY(c, hipMemcpyAsync(c->in_idx.p, idx_i, ni * sizeof(int32_t), hipMemcpyHostToDevice, st));
-        HIP_TRY(c, hipMemcpyAsync(c->out_nnb.p, nnb_i, ni * sizeof(int32_t), hipMemcpyHostToDevice, st));
-        HIP_TRY(c, hipMemcpyAsync(c->out_list.p, list, (size_t)ni * cap * sizeof(int32_t),
-                                  hipMemcpyHostToDevice, st));
-        d_idx = (const int32_t*)c->in_idx.p;
-        d_nnb = (const int32_t*)c->out_nnb.p;
-        d_list = (const int32_t*)c->out_list.p;
+        char* pin = c->pin.p;
+        char* dev = (char*)c->io.p;
+        std::memcpy(pin + o_idx, idx_i, ni * sizeof(int32_t));
+        std::memcpy(pin + o_nnb, nnb_i, ni * sizeof(int32_t));
+        if (staged) std::memcpy(pin + o_list, list, list_bytes);
+        HIP_TRY(c, hipMemcpyAsync(dev, pin, lay.end, hipMemcpyHostToDevice, st));
+        if (!staged)
+            HIP_TRY(c, hipMemcpyAsync(c->out_list.p, list, list_bytes, hipMemcpyHostToDevice, st));
+        d_idx = (const int32_t*)(dev + o_idx);
+        d_nnb = (const int32_t*)(dev + o_nnb);
+        d_list = staged ? (const int32_t*)(dev + o_list) : (const int32_t*)c->out_list.p;
     }
     if (int rc = ensure_lists(c, cl, cap, st)) return rc;
     SetListArgs sa{};
@@ -742,21 +788,29 @@ int nb6_irregular_force(nb6_ctx* c, int cluster, double t_block, int64_t n_i,
     double* d_acc = acc;
     double* d_jerk = jerk;
     double* d_pot = pot;
+    Stage lay;
+    size_t o_idx = 0, o_acc = 0, o_jerk = 0, o_pot = 0, o_status = 0;
     if (mem_kind == NB6_MEM_HOST) {
         for (int q = 0; q < ni; ++q)
             if (idx_i[q] < 0 || idx_i[q] >= n)
                 return fail(c, NB6_ERR_ARG, "idx_i[%d] = %d out of range", q, idx_i[q]);
+        // the indices go up, and the outputs come back, through the pinned
+        // buffer, one copy each way
+        o_idx = lay.add(ni * sizeof(int32_t));
+        o_acc = lay.add(3 * (size_t)ni * sizeof(double));
+        o_jerk = lay.add(3 * (size_t)ni * sizeof(double));
+        o_pot = pot ? lay.add(ni * sizeof(double)) : 0;
+        o_status = lay.add(4 * sizeof(unsigned));
         int rc;
-        if ((rc = ensure(c, c->in_idx, ni * sizeof(int32_t))) ||
-            (rc = ensure(c, c->out_acc, 3 * (size_t)ni * sizeof(double))) ||
-            (rc = ensure(c, c->out_jerk, 3 * (size_t)ni * sizeof(double))) ||
-            (pot && (rc = ensure(c, c->out_pot, ni * sizeof(double)))))
+        if ((rc = ensure(c, c->io, lay.end)) || (rc = ensure_pinned(c, c->pin, lay.end)))
             return rc;
-        HIP_TRY(c, hipMemcpyAsync(c->in_idx.p, idx_i, ni * sizeof(int32_t), hipMemcpyHostToDevice, st));
-        d_idx = (const int32_t*)c->in_idx.p;
-        d_acc = (double*)c->out_acc.p;
-        d_jerk = (double*)c->out_jerk.p;
-        if (pot) d_pot = (double*)c->out_pot.p;
+        char* dev = (char*)c->io.p;
+        std::memcpy(c->pin.p + o_idx, idx_i, ni * sizeof(int32_t));
+        HIP_TRY(c, hipMemcpyAsync(dev, c->pin.p, o_acc, hipMemcpyHostToDevice, st));
+        d_idx = (const int32_t*)(dev + o_idx);
+        d_acc = (double*)(dev + o_acc);
+        d_jerk = (double*)(dev + o_jerk);
+        if (pot) d_pot = (double*)(dev + o_pot);
     }
     if (int rc = ensure_lists(c, cl, 1, st)) return rc;  // no lists yet: all empty
     IrrArgs ia{};
@@ -778,14 +832,18 @@ int nb6_irregular_force(nb6_ctx* c, int cluster, double t_block, int64_t n_i,
         tl.done();
     }
     if (mem_kind == NB6_MEM_DEVICE) return NB6_OK;
-    HIP_TRY(c, hipMemcpyAsync(acc, d_acc, 3 * (size_t)ni * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIP_TRY(c, hipMemcpyAsync(jerk, d_jerk, 3 * (size_t)ni * sizeof(double), hipMemcpyDeviceToHost, st));
-    if (pot)
-        HIP_TRY(c, hipMemcpyAsync(pot, d_pot, ni * sizeof(double), hipMemcpyDeviceToHost, st));
-    unsigned status[4];
-    HIP_TRY(c, hipMemcpyAsync(status, c->status, sizeof status, hipMemcpyDeviceToHost, st));
+    char* pin = c->pin.p;
+    HIP_TRY(c, hipMemcpyAsync(pin + o_acc, (char*)c->io.p + o_acc, o_status - o_acc,
+                              hipMemcpyDeviceToHost, st));
+    HIP_TRY(c, hipMemcpyAsync(pin + o_status, c->status, 4 * sizeof(unsigned),
+                              hipMemcpyDeviceToHost, st));
     HIP_TRY(c, hipStreamSynchronize(st));
     HIP_TRY(c, launch_zero_u32(c->status, 4, st));
+    std::memcpy(acc, pin + o_acc, 3 * (size_t)ni * sizeof(double));
+    std::memcpy(jerk, pin + o_jerk, 3 * (size_t)ni * sizeof(double));
+    if (pot) std::memcpy(pot, pin + o_pot, ni * sizeof(double));
+    unsigned status[4];
+    std::memcpy(status, pin + o_status, sizeof status);
     if (status[0] & (ST_BAD_INDEX | ST_BAD_LIST))
         return fail(c, NB6_ERR_DEVICE_INPUT, "GPU validation flagged 0x%x", status[0]);
     return NB6_OK;

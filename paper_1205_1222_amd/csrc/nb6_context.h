@@ -21,6 +21,28 @@ struct DevBuf {
     size_t cap = 0;
 };
 
+// Pinned host memory (hipHostMalloc).
+struct PinBuf {
+    char* p = nullptr;
+    size_t cap = 0;
+};
+
+// Byte layout of the arrays one HOST-mode call stages: each array starts on a
+// 256-byte boundary; the same offsets serve the pinned buffer and its device
+// mirror.
+struct Stage {
+    size_t end = 0;
+    size_t add(size_t bytes) {
+        const size_t o = end;
+        end = (end + bytes + 255) / 256 * 256;
+        return o;
+    }
+};
+// Lists of a HOST-mode call above this size are copied to the caller's array
+// directly rather than through the pinned buffer (which would add a second
+// host-side pass over them).
+constexpr size_t kStageListMax = size_t(1) << 20;
+
 struct ClusterState {
     int64_t n = 0;
     StateRec* state = nullptr; // [n] stored state, one record per particle
@@ -76,8 +98,9 @@ struct nb6_ctx {
     std::vector<nb6::ClusterState*> clusters;
     nb6::DevBuf part, cnt, lst;                       // force-kernel scratch
     bool cnt_dirty = true;  // cnt must be zeroed before the next force launch
-    nb6::DevBuf in_idx, in_h2, in_dtr;                // HOST-mode inputs
-    nb6::DevBuf out_acc, out_jerk, out_pot, out_nnb, out_list;  // HOST-mode outputs
+    nb6::DevBuf io;                                   // HOST-mode staged inputs and outputs
+    nb6::DevBuf out_list;                             // HOST-mode lists too big to stage
+    nb6::PinBuf pin;                                  // pinned mirror of `io`
     nb6::DevBuf ld[7];                                // HOST-mode load staging
     nb6::DevBuf corr;                                 // HOST-mode corrector staging
     unsigned* status = nullptr;                       // device status word
@@ -96,6 +119,8 @@ namespace nb6 {
 int fail(nb6_ctx* c, int code, const char* fmt, ...);
 int ensure(nb6_ctx* c, DevBuf& b, size_t bytes);
 void release(DevBuf& b);
+// Grow the pinned buffer to at least `bytes` (nothing may be pending on it).
+int ensure_pinned(nb6_ctx* c, PinBuf& b, size_t bytes);
 // ipl: 0 = the context's choice (its hint, else by n_i).
 Plan make_plan(const nb6_ctx* c, int64_t n, int64_t ni, int ipl = 0);
 // Shut the serving queue down (nb6_destroy).
