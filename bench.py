@@ -791,6 +791,9 @@ def main():
                 100.0 * rec["fp32_flop"] / (regf_ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, 2)
     gpu_out = (acc.cpu().numpy(), jerk.cpu().numpy(), nnb.cpu().numpy(),
                lst[:, :args.cap].cpu().numpy())
+    out["lists"] = {"cap": args.cap, "mean": round(float(gpu_out[2].mean()), 2),
+                    "max": int(gpu_out[2].max()),
+                    "overflowed": int((gpu_out[2] > args.cap).sum())}
     if not args.no_potential:
         out["potential"] = potential_leg(args, nb6, torch, ctx, idx_d, h2_d, dtr_d, ni, mode,
                                          regf_ms, pairs)

@@ -73,9 +73,10 @@ int ensure_pinned(nb6_ctx* c, PinBuf& b, size_t bytes) {
 
 Plan make_plan(const nb6_ctx* c, int64_t n, int64_t ni, int ipl) {
     Plan p;
-    // two i per lane once every lane has work for several slices' worth of
-    // j (measured: better from 4096 active particles on, at N = 2^17 and 2^20)
-    p.ipl = ipl > 0 ? ipl : c->ipl_hint > 0 ? c->ipl_hint : (ni >= 4096 ? 2 : 1);
+    // One i per lane unless asked for two: the one-i kernel holds 74 VGPRs
+    // against 106, hence more waves per SIMD, and measured faster at every
+    // block size from 512 to 2^20 active particles (at N = 2^17 and 2^20).
+    p.ipl = ipl > 0 ? ipl : c->ipl_hint > 0 ? c->ipl_hint : 1;
     // Slices are at least 256 j-particles long, and give each lane at least
     // 32 of them.
     auto max_slices = [&](int sh) {
@@ -104,10 +105,12 @@ Plan make_plan(const nb6_ctx* c, int64_t n, int64_t ni, int ipl) {
     p.jl_shift = sh;
     const int64_t groups = groups_of(sh);
     p.wpb = (int)std::min<int64_t>(4, groups);
-    // About 32 waves per SIMD over the launch (several rounds at the
-    // kernel's occupancy, so the last round's imbalance is a small part).
-    const int64_t target = (int64_t)c->num_cu * 4 * 32;
-    int64_t s = c->slice_hint > 0 ? c->slice_hint : (target + groups - 1) / groups;
+    // About 64 waves per SIMD over the launch, and slices of at most 16384
+    // j: many rounds at the kernel's occupancy, so the last round's
+    // imbalance is a small part (measured optimum at N_i = 2^12 .. 2^20).
+    const int64_t target = (int64_t)c->num_cu * 4 * 64;
+    int64_t s = c->slice_hint > 0 ? c->slice_hint
+                                  : std::max((target + groups - 1) / groups, (n + 16383) / 16384);
     if (lanes_plan && c->slice_hint <= 0) {
         // measured optimum about sqrt(1.5 n / lanes), taken to a power of 2
         const double best = std::sqrt(1.5 * (double)n / (double)(1 << sh));

@@ -149,6 +149,10 @@ __device__ __forceinline__ void interact(const typename RecOf<MODE>::T& r, int j
     const float rv = fmaf(dz, dvz, fmaf(dy, dvy, dx * dvx));
     float rinv = __builtin_amdgcn_rsqf(r2);
     if (r2 < bnd2) {
+        // Keeps the criterion behind the branch: without it the compiler may
+        // compute it for every pair and merge the two tests (8 more vector
+        // instructions per interaction).  Emits no instruction.
+        __asm__ volatile("");
         if (velocity_criterion(r2, dx, dy, dz, dvx, dvy, dvz, ia.dtr, ia.h2)) {
             const int slot = atomicAdd(a.cnt + qq, 1);
             if (slot < a.caps) a.lst[(size_t)qq * a.caps + slot] = j;
@@ -537,16 +541,21 @@ __device__ __forceinline__ void rescan_list(const FinalArgs& a, const int q, con
     const unsigned long long below = (1ull << lane) - 1ull;
     int found = 0;  // wave-uniform
     for (int j0 = 0; j0 < a.n && found < a.cap; j0 += 4 * 64) {
+        // the four records first (clamped indices: in bounds for every lane),
+        // then the tests without short-circuit evaluation, so that the loads
+        // are not moved into branches and issued one after another
+        Rec r[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) r[u] = rec[min(j0 + 64 * u + lane, a.n - 1)];
         bool nb[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int j = j0 + 64 * u + lane;
-            const Rec r = rec[min(j, a.n - 1)];  // clamped: in bounds for every lane
             float dx, dy, dz;
-            coord_diff(r, ip, dx, dy, dz);
-            nb[u] = j < a.n && j != self &&
-                    velocity_criterion(dist2(dx, dy, dz), dx, dy, dz, r.vx - ia.vx,
-                                       r.vy - ia.vy, r.vz - ia.vz, dtf, h2f);
+            coord_diff(r[u], ip, dx, dy, dz);
+            const bool hit = velocity_criterion(dist2(dx, dy, dz), dx, dy, dz, r[u].vx - ia.vx,
+                                                r[u].vy - ia.vy, r[u].vz - ia.vz, dtf, h2f);
+            nb[u] = (j < a.n) & (j != self) & hit;
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {

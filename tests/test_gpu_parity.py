@@ -541,3 +541,34 @@ def test_tiny_clusters_and_repeated_indices(ctx):
         np.testing.assert_array_equal(jerk[a_], jerk[b_])
         assert nnb[a_] == nnb[b_]
         np.testing.assert_array_equal(lst[a_, :nnb[a_]], lst[b_, :nnb[b_]])
+
+
+@pytest.mark.parametrize("mode", ["ff", "fp64", "fp32"])
+def test_two_i_per_lane(mode):
+    """The two-i-per-lane force kernel (a context option; the default plan
+    takes one): oracle parity on a ragged random block and a whole cluster,
+    and the same bits as one i per lane under the same slicing."""
+    nb6 = _nb6()
+    cfg = config(2)
+    cl = cfg["cluster"]
+    idx = cfg["blocks"]["random1024"][:1000]
+    ref = oracle_ref(cl, idx)
+    got = {}
+    for ipl in (2, 1):
+        c = nb6.nb6_create(0, ipl_hint=ipl, slice_hint=24)
+        try:
+            load(c, cl)
+            got[ipl] = check_mode(c, cl, idx, mode, f"ipl{ipl}_C2_{mode}", ref=ref)
+            assert nb6.nb6_last_plan(c)[0] == ipl
+        finally:
+            nb6.nb6_destroy(c)
+    for a, b in zip(got[1][:3], got[2][:3]):
+        np.testing.assert_array_equal(a, b)
+    c = nb6.nb6_create(0, ipl_hint=2)
+    try:
+        cfg1 = config(1)
+        cl1 = cfg1["cluster"]
+        load(c, cl1)
+        check_mode(c, cl1, cfg1["blocks"]["all"], mode, f"ipl2_C1_{mode}")
+    finally:
+        nb6.nb6_destroy(c)

@@ -137,11 +137,12 @@ def test_alone_and_mixed_are_bit_identical(clusters):
 
 
 @pytest.mark.parametrize("hint,c,step,ni_max", [(1, 2, 7, None), (0, 3, 1, 4500),
-                                                (0, 1, 1, 2000), (0, 0, 1, 20)])
+                                                (2, 3, 1, 4500), (0, 1, 1, 2000),
+                                                (0, 0, 1, 20)])
 def test_served_equals_plain_call(clusters, hint, c, step, ni_max):
     """A served request takes the plan a plain call on the same context takes
-    (one i per lane, lanes per i for small blocks, two i per lane from 4096
-    on), hence the same bits."""
+    (one i per lane, or two when the context asks for it; lanes per i for
+    small blocks), hence the same bits."""
     nb6 = _nb6()
     ctx = nb6.nb6_create(0, ipl_hint=hint)
     try:
