@@ -19,6 +19,12 @@ loop, rsqrt counted once) over its measured launch time, against the
 MI355X FP32 vector peak.  ``cpu_baseline`` is the FP64 oracle timed on the
 host cores for a bounded sample of the same block; its output for that
 sample also gives the ``accuracy`` report of the GPU result.
+
+Records beside the headline (each can be switched off): ``potential`` (the
+same call with the potential output), ``irregular`` (the irregular force
+over the lists the call returned, per block size), ``corrector`` (the
+regular corrector per block size), ``serving`` (a trace of many clusters'
+blocks served through nb6_submit / nb6_poll against one block per launch).
 """
 from __future__ import annotations
 
@@ -481,6 +487,69 @@ def irregular_leg(args, nb6, torch, ctx, cl, idx_np, idx_d, nnb, lst):
     return res
 
 
+# Algorithmic bytes of the regular corrector per particle: t_old, eight
+# [3]-vectors of force values, h_old, nnb, n_p in; four [3]-vectors, dt_new
+# and h_new out.
+CORR_BYTES_PER_I = 8 + 8 * 24 + 8 + 4 + 8 + 4 * 24 + 16
+
+
+def corrector_leg(args, nb6, torch, cl, nnb):
+    """Regular corrector (section 3.3 step 7) of blocks of the configuration:
+    device arrays, synthetic force values of the right magnitudes, the step
+    of each particle its own regular step; back-to-back calls timed with
+    events on the library's stream.  HBM-bound: roofline against 8 TB/s."""
+    stream = torch.cuda.current_stream()
+    dev = torch.device("cuda:0")
+    n_all = len(nnb)
+    rng = np.random.Generator(np.random.PCG64(12051230))
+    t = 1.0
+    vec = lambda scale: torch.from_numpy(rng.normal(0.0, scale, (n_all, 3))).to(dev)
+    arrays = {"t_old": torch.from_numpy(t - cl.dtr[:n_all]).to(dev),
+              "f_old": vec(1.0), "fd_old": vec(10.0), "f_new": vec(1.0), "fd_new": vec(10.0),
+              "g_old": vec(0.1), "gd_old": vec(1.0), "g_new": vec(0.1), "gd_new": vec(1.0),
+              "h_old": torch.from_numpy(np.sqrt(cl.h2[:n_all])).to(dev),
+              "nnb": nnb.to(torch.int32).contiguous(),
+              "n_p": torch.full((n_all,), 50.0, dtype=torch.float64, device=dev)}
+    for k in ("df", "dfd", "f2", "f3"):
+        arrays[k] = torch.empty((n_all, 3), dtype=torch.float64, device=dev)
+    for k in ("dt_new", "h_new"):
+        arrays[k] = torch.empty(n_all, dtype=torch.float64, device=dev)
+    ctx = nb6.nb6_create(0)
+    params = (0.02, 2.0 ** -20, 1.0, 0.5, 1.25)
+    res = {"bytes_per_particle": CORR_BYTES_PER_I, "blocks": []}
+    for size in sorted({1, 1024, 16384, n_all}):
+        if size > n_all:
+            continue
+        sub = {k: v[:size] for k, v in arrays.items()}
+
+        def call():
+            nb6.check(ctx, nb6.nb6_regular_correct(ctx, size, t, sub, params,
+                                                   nb6.NB6_MEM_DEVICE, stream))
+        call()
+        torch.cuda.synchronize()
+        reps = max(20, min(2000, int(2e8 / (size * CORR_BYTES_PER_I))))
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            call()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / reps
+        gbs = size * CORR_BYTES_PER_I / (us * 1e-6) / 1e9
+        res["blocks"].append({"N_i": size, "call_us": round(us, 2),
+                              "algorithmic_gb_s": round(gbs, 1)})
+        log(f"bench: corrector N_i={size}: {us:.2f} us per call, {gbs:.1f} GB/s algorithmic")
+    nb6.check(ctx, nb6.nb6_sync_status(ctx, stream))
+    nb6.nb6_destroy(ctx)
+    whole = res["blocks"][-1]
+    res["roofline"] = {"bound": "hbm", "achieved": whole["algorithmic_gb_s"],
+                       "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": round(whole["algorithmic_gb_s"] / HBM_PEAK_GBS, 4),
+                       "traffic": None}
+    return res
+
+
 def potential_leg(args, nb6, torch, ctx, idx_d, h2_d, dtr_d, ni, mode, regf_ms, pairs):
     """The same force call with the optional potential output: force-kernel
     time against the call without it (one FP32 add per pair and a seventh
@@ -620,6 +689,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-irregular", action="store_true")
     ap.add_argument("--no-potential", action="store_true")
+    ap.add_argument("--no-corrector", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=20000)
     ap.add_argument("--serve-calibrate", type=int, default=300)
     ap.add_argument("--serve-cap", type=int, default=128)
@@ -799,6 +869,8 @@ def main():
                                          regf_ms, pairs)
     if not args.no_irregular:
         out["irregular"] = irregular_leg(args, nb6, torch, ctx, cl, idx_np, idx_d, nnb, lst)
+    if not args.no_corrector:
+        out["corrector"] = corrector_leg(args, nb6, torch, cl, nnb)
     nb6.nb6_destroy(ctx)
     del acc, jerk, nnb, lst
     if not args.no_serving:
