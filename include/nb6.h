@@ -155,8 +155,10 @@ int nb6_predict_j(nb6_ctx *ctx, int cluster, double t_block, int modes,
  *          its use in the energy check).  Asking for it adds one FP32 add
  *          per pair and one partial-sum component.
  * The neighbour decision and the force arithmetic are done in FP32 (the
- * coordinate difference per dx_mode), the sums are compensated, and the
- * outputs are double.
+ * coordinate difference per dx_mode); the terms are summed in FP32 over
+ * tiles of 32 j and the tile sums in FP64, and the outputs are double.
+ * HOST mode copies only the first min(nnb, cap) entries of each list row
+ * into `list`.
  * Returns NB6_OK, or NB6_WARN_NB_OVERFLOW (HOST mode only) when some nnb
  * exceeds cap.  Errors: NB6_ERR_ARG, NB6_ERR_STATE, NB6_ERR_NOMEM,
  * NB6_ERR_HIP.  n_i == 0 is a no-op.

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 using namespace nb6;
@@ -444,6 +445,47 @@ int nb6_predict_j(nb6_ctx* c, int cluster, double t_block, int modes, void* stre
     return NB6_OK;
 }
 
+// The lists of a HOST-mode call too big to stage with the other outputs:
+// only the first min(nnb, cap) entries of each row cross PCIe.  The row
+// offsets come from the counts already on the host; a kernel packs the rows
+// into one array, one copy brings it into the pinned buffer, and host threads
+// place each row in the caller's array (entries past a row's count are left
+// as they were).
+static int copy_lists_out(nb6_ctx* c, const int32_t* d_list, const int32_t* nnb, int ni,
+                          int cap, int32_t* list, hipStream_t st) {
+    Stage lay;
+    const size_t o_off = lay.add(((size_t)ni + 1) * sizeof(int64_t));
+    std::vector<int64_t> off((size_t)ni + 1);
+    off[0] = 0;
+    for (int q = 0; q < ni; ++q) off[q + 1] = off[q] + std::min(std::max(nnb[q], 0), cap);
+    const int64_t total = off[ni];
+    const size_t o_pack = lay.add((size_t)total * sizeof(int32_t));
+    if (int rc = ensure(c, c->io, lay.end)) return rc;
+    if (int rc = ensure_pinned(c, c->pin, lay.end)) return rc;
+    char* pin = c->pin.p;
+    char* dev = (char*)c->io.p;
+    std::memcpy(pin + o_off, off.data(), ((size_t)ni + 1) * sizeof(int64_t));
+    HIP_TRY(c, hipMemcpyAsync(dev + o_off, pin + o_off, ((size_t)ni + 1) * sizeof(int64_t),
+                              hipMemcpyHostToDevice, st));
+    HIP_TRY(c, launch_pack_rows(d_list, cap, (const int64_t*)(dev + o_off), ni,
+                                (int32_t*)(dev + o_pack), st));
+    HIP_TRY(c, hipMemcpyAsync(pin + o_pack, dev + o_pack, (size_t)total * sizeof(int32_t),
+                              hipMemcpyDeviceToHost, st));
+    HIP_TRY(c, hipStreamSynchronize(st));
+    const int32_t* packed = (const int32_t*)(pin + o_pack);
+    auto place = [&](int q0, int q1) {
+        for (int q = q0; q < q1; ++q)
+            std::copy(packed + off[q], packed + off[q + 1], list + (size_t)q * cap);
+    };
+    const int nt = (int)std::min<int64_t>(8, std::max<int64_t>(1, total >> 18));
+    std::vector<std::thread> helpers;
+    for (int t = 1; t < nt; ++t)
+        helpers.emplace_back(place, (int)((int64_t)ni * t / nt), (int)((int64_t)ni * (t + 1) / nt));
+    place(0, (int)((int64_t)ni / nt));
+    for (auto& h : helpers) h.join();
+    return NB6_OK;
+}
+
 int nb6_regular_force(nb6_ctx* c, int cluster, int64_t n_i, const int32_t* idx_i,
                       const double* h2_i, const double* dtr_i, int dx_mode, double* acc,
                       double* jerk, double* pot, int32_t* nnb, int32_t* list, int32_t cap,
@@ -606,9 +648,6 @@ int nb6_regular_force(nb6_ctx* c, int cluster, int64_t n_i, const int32_t* idx_i
     char* pin = c->pin.p;
     HIP_TRY(c, hipMemcpyAsync(pin + hs.in_end, (char*)c->io.p + hs.in_end, hs.out_end - hs.in_end,
                               hipMemcpyDeviceToHost, st));
-    if (cap > 0 && !hs.list_staged)
-        HIP_TRY(c, hipMemcpyAsync(list, d_list, (size_t)ni * cap * sizeof(int32_t),
-                                  hipMemcpyDeviceToHost, st));
     HIP_TRY(c, hipMemcpyAsync(pin + hs.status, c->status, 4 * sizeof(unsigned),
                               hipMemcpyDeviceToHost, st));
     HIP_TRY(c, hipStreamSynchronize(st));
@@ -620,6 +659,9 @@ int nb6_regular_force(nb6_ctx* c, int cluster, int64_t n_i, const int32_t* idx_i
     if (hs.list_staged) std::memcpy(list, pin + hs.list, (size_t)ni * cap * sizeof(int32_t));
     unsigned status[4];
     std::memcpy(status, pin + hs.status, sizeof status);
+    if (cap > 0 && !hs.list_staged) {
+        if (int rc = copy_lists_out(c, d_list, nnb, ni, cap, list, st)) return rc;
+    }
     if (status[0] & (ST_BAD_INDEX | ST_BAD_H2 | ST_NONFINITE))
         return fail(c, NB6_ERR_DEVICE_INPUT, "GPU validation flagged 0x%x", status[0]);
     for (int q = 0; q < ni; ++q)

@@ -199,6 +199,10 @@ hipError_t launch_set_lists(const SetListArgs& a, hipStream_t s);
 // to rows of dst_cap entries (the stored lists grow).
 hipError_t launch_copy_rows(const int32_t* src, int src_cap, int32_t* dst, int dst_cap,
                             const int32_t* cnt, int64_t n, hipStream_t s);
+// Pack rows: entries [0, off[q+1] - off[q]) of row q of `list` (rows of cap
+// entries) to out[off[q] ...], for q < n.
+hipError_t launch_pack_rows(const int32_t* list, int cap, const int64_t* off, int64_t n,
+                            int32_t* out, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Regular corrector of a block (elementwise, FP64).

@@ -406,6 +406,7 @@ class Engine {
             sl.reqs = batch;
             lk.unlock();
             const int rc = launch(sl);
+            if (rc != NB6_OK) (void)hipStreamSynchronize(sl.stream);  // work enqueued so far
             lk.lock();
             if (rc != NB6_OK) {
                 const double t = now();
