@@ -79,7 +79,8 @@ typedef struct nb6_options {
     int     slice_hint;    /* 0: choose the j-split per call; >0: force it    */
     int64_t hbm_budget;    /* bytes the serving queue may hold; 0: 1/4 of free */
     int     flags;         /* NB6_OPT_* bits                                  */
-    int     ipl_hint;      /* 0: choose i-particles per lane; 1 or 2: force it */
+    int     ipl_hint;      /* i-particles per lane: 0 or 1 one (the default:
+                              measured faster at every block size), 2 two   */
     int     jl_hint;       /* 0: choose the lanes that share one i-particle;
                               1, 2, 4, ..., 64: force it (not with ipl_hint 2) */
 } nb6_options;

@@ -349,9 +349,8 @@ class Engine {
         return -1;
     }
 
-    // Called with mu_ held; takes no other lock (it runs in the completion
-    // callback, which must not wait for a thread that may be waiting for the
-    // GPU).
+    // Called with mu_ held; takes no other lock and makes no HIP call (the
+    // completion thread runs it while the scheduler may be enqueueing).
     void finish(ServeReq* r, int status, double t) {
         r->status = status;
         r->t_done = t;
