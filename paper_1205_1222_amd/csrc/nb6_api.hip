@@ -213,6 +213,44 @@ int get_cluster(nb6_ctx* c, int cluster, ClusterState** out) {
     return NB6_OK;
 }
 
+// Row offsets of lists holding min(count, cap) entries per row.
+static std::vector<int64_t> row_offsets(const int32_t* count, int n, int cap) {
+    std::vector<int64_t> off((size_t)n + 1);
+    off[0] = 0;
+    for (int q = 0; q < n; ++q) off[q + 1] = off[q] + std::min(std::max(count[q], 0), cap);
+    return off;
+}
+
+// body(q0, q1) over the rows [0, n) on up to 8 host threads (one per 2^18
+// entries moved).
+template <typename F>
+static void for_rows(int n, int64_t entries, F body) {
+    const int nt = (int)std::min<int64_t>(8, std::max<int64_t>(1, entries >> 18));
+    std::vector<std::thread> helpers;
+    for (int t = 1; t < nt; ++t)
+        helpers.emplace_back(body, (int)((int64_t)n * t / nt), (int)((int64_t)n * (t + 1) / nt));
+    body(0, (int)((int64_t)n / nt));
+    for (auto& h : helpers) h.join();
+}
+
+// Row-major [n][cap] rows to a packed array (row q at off[q]), and back.
+static void pack_rows_host(const std::vector<int64_t>& off, int n, int cap,
+                           const int32_t* rows, int32_t* packed) {
+    for_rows(n, off[n], [&](int q0, int q1) {
+        for (int q = q0; q < q1; ++q) {
+            const int32_t* r = rows + (size_t)q * cap;
+            std::copy(r, r + (off[q + 1] - off[q]), packed + off[q]);
+        }
+    });
+}
+static void unpack_rows_host(const std::vector<int64_t>& off, int n, int cap,
+                             const int32_t* packed, int32_t* rows) {
+    for_rows(n, off[n], [&](int q0, int q1) {
+        for (int q = q0; q < q1; ++q)
+            std::copy(packed + off[q], packed + off[q + 1], rows + (size_t)q * cap);
+    });
+}
+
 }  // namespace
 
 extern "C" {
@@ -279,7 +317,7 @@ int nb6_destroy(nb6_ctx* c) {
         if (cl->last_served) (void)hipEventDestroy(cl->last_served);
         delete cl;
     }
-    for (DevBuf* b : {&c->part, &c->cnt, &c->lst, &c->io, &c->out_list, &c->corr})
+    for (DevBuf* b : {&c->part, &c->cnt, &c->lst, &c->io, &c->out_list})
         release(*b);
     if (c->pin.p) (void)hipHostFree(c->pin.p);
     for (auto& b : c->ld) release(b);
@@ -455,9 +493,7 @@ static int copy_lists_out(nb6_ctx* c, const int32_t* d_list, const int32_t* nnb,
                           int cap, int32_t* list, hipStream_t st) {
     Stage lay;
     const size_t o_off = lay.add(((size_t)ni + 1) * sizeof(int64_t));
-    std::vector<int64_t> off((size_t)ni + 1);
-    off[0] = 0;
-    for (int q = 0; q < ni; ++q) off[q + 1] = off[q] + std::min(std::max(nnb[q], 0), cap);
+    const std::vector<int64_t> off = row_offsets(nnb, ni, cap);
     const int64_t total = off[ni];
     const size_t o_pack = lay.add((size_t)total * sizeof(int32_t));
     if (int rc = ensure(c, c->io, lay.end)) return rc;
@@ -472,17 +508,7 @@ static int copy_lists_out(nb6_ctx* c, const int32_t* d_list, const int32_t* nnb,
     HIP_TRY(c, hipMemcpyAsync(pin + o_pack, dev + o_pack, (size_t)total * sizeof(int32_t),
                               hipMemcpyDeviceToHost, st));
     HIP_TRY(c, hipStreamSynchronize(st));
-    const int32_t* packed = (const int32_t*)(pin + o_pack);
-    auto place = [&](int q0, int q1) {
-        for (int q = q0; q < q1; ++q)
-            std::copy(packed + off[q], packed + off[q + 1], list + (size_t)q * cap);
-    };
-    const int nt = (int)std::min<int64_t>(8, std::max<int64_t>(1, total >> 18));
-    std::vector<std::thread> helpers;
-    for (int t = 1; t < nt; ++t)
-        helpers.emplace_back(place, (int)((int64_t)ni * t / nt), (int)((int64_t)ni * (t + 1) / nt));
-    place(0, (int)((int64_t)ni / nt));
-    for (auto& h : helpers) h.join();
+    unpack_rows_host(off, ni, cap, (const int32_t*)(pin + o_pack), list);
     return NB6_OK;
 }
 
@@ -768,14 +794,19 @@ int nb6_set_lists(nb6_ctx* c, int cluster, int64_t n_i, const int32_t* idx_i,
                     return fail(c, NB6_ERR_ARG, "list entry (%d, %d) = %d out of range", k, e, j);
             }
         }
-        // indices and counts go up through the pinned buffer in one copy,
-        // with the lists when they are small
+        // indices, counts and lists go up through the pinned buffer in one
+        // copy: small lists as they are, larger ones packed to their rows'
+        // used entries (a kernel then puts the rows back in place)
         const size_t list_bytes = (size_t)ni * cap * sizeof(int32_t);
         const bool staged = list_bytes <= kStageListMax;
+        std::vector<int64_t> off;
+        if (!staged) off = row_offsets(nnb_i, ni, cap);
         Stage lay;
         const size_t o_idx = lay.add(ni * sizeof(int32_t));
         const size_t o_nnb = lay.add(ni * sizeof(int32_t));
-        const size_t o_list = staged ? lay.add(list_bytes) : 0;
+        const size_t o_off = staged ? 0 : lay.add(((size_t)ni + 1) * sizeof(int64_t));
+        const size_t o_list =
+            lay.add(staged ? list_bytes : (size_t)off[ni] * sizeof(int32_t));
         int rc;
         if ((rc = ensure(c, c->io, lay.end)) || (rc = ensure_pinned(c, c->pin, lay.end)) ||
             (!staged && (rc = ensure(c, c->out_list, list_bytes))))
@@ -784,10 +815,17 @@ int nb6_set_lists(nb6_ctx* c, int cluster, int64_t n_i, const int32_t* idx_i,
         char* dev = (char*)c->io.p;
         std::memcpy(pin + o_idx, idx_i, ni * sizeof(int32_t));
         std::memcpy(pin + o_nnb, nnb_i, ni * sizeof(int32_t));
-        if (staged) std::memcpy(pin + o_list, list, list_bytes);
+        if (staged) {
+            std::memcpy(pin + o_list, list, list_bytes);
+        } else {
+            std::memcpy(pin + o_off, off.data(), ((size_t)ni + 1) * sizeof(int64_t));
+            pack_rows_host(off, ni, cap, list, (int32_t*)(pin + o_list));
+        }
         HIP_TRY(c, hipMemcpyAsync(dev, pin, lay.end, hipMemcpyHostToDevice, st));
         if (!staged)
-            HIP_TRY(c, hipMemcpyAsync(c->out_list.p, list, list_bytes, hipMemcpyHostToDevice, st));
+            HIP_TRY(c, launch_unpack_rows((const int32_t*)(dev + o_list),
+                                          (const int64_t*)(dev + o_off), ni,
+                                          (int32_t*)c->out_list.p, cap, st));
         d_idx = (const int32_t*)(dev + o_idx);
         d_nnb = (const int32_t*)(dev + o_nnb);
         d_list = staged ? (const int32_t*)(dev + o_list) : (const int32_t*)c->out_list.p;
@@ -932,41 +970,43 @@ int nb6_regular_correct(nb6_ctx* c, const nb6_corr_block* b, const nb6_corr_para
         for (int64_t q = 0; q < n; ++q)
             if (!(b->t - b->t_old[q] > 0.0) || !std::isfinite(b->t_old[q]))
                 return fail(c, NB6_ERR_ARG, "t_old[%lld] is not before t", (long long)q);
-        // one staging buffer: 8 input vectors, t_old, h_old, n_p, nnb, then the outputs
-        const size_t total = 8 * v3 + 3 * s1 + (size_t)n * sizeof(int32_t) + 4 * v3 + 2 * s1;
-        if (int rc = ensure(c, c->corr, total)) return rc;
-        char* p = (char*)c->corr.p;
-        const double* dv[8];
-        for (int k = 0; k < 8; ++k) {
-            HIP_TRY(c, hipMemcpyAsync(p, vin[k], v3, hipMemcpyHostToDevice, st));
-            dv[k] = (const double*)p;
-            p += v3;
-        }
+        // the inputs go up in one copy from the pinned buffer and the
+        // outputs come back in one copy into it; the device mirror has the
+        // same layout
+        Stage lay;
+        size_t o_vin[8], o_sin[3], o_vout[4], o_sout[2];
+        for (auto& o : o_vin) o = lay.add(v3);
+        for (auto& o : o_sin) o = lay.add(s1);
+        const size_t o_nnb = lay.add((size_t)n * sizeof(int32_t));
+        const size_t in_end = lay.end;
+        for (auto& o : o_vout) o = lay.add(v3);
+        for (auto& o : o_sout) o = lay.add(s1);
+        if (int rc = ensure(c, c->io, lay.end)) return rc;
+        if (int rc = ensure_pinned(c, c->pin, lay.end)) return rc;
+        char* pin = c->pin.p;
+        char* dev = (char*)c->io.p;
         const double* sin3[3] = {b->t_old, b->h_old, b->n_p};
-        const double* ds[3];
-        for (int k = 0; k < 3; ++k) {
-            HIP_TRY(c, hipMemcpyAsync(p, sin3[k], s1, hipMemcpyHostToDevice, st));
-            ds[k] = (const double*)p;
-            p += s1;
-        }
-        HIP_TRY(c, hipMemcpyAsync(p, b->nnb, n * sizeof(int32_t), hipMemcpyHostToDevice, st));
-        a.nnb = (const int32_t*)p;
-        p += (size_t)n * sizeof(int32_t);
-        p = (char*)(((uintptr_t)p + 7) & ~(uintptr_t)7);
-        double* dout[6];
-        for (int k = 0; k < 4; ++k) { dout[k] = (double*)p; p += v3; }
-        for (int k = 4; k < 6; ++k) { dout[k] = (double*)p; p += s1; }
-        a.f_old = dv[0]; a.fd_old = dv[1]; a.f_new = dv[2]; a.fd_new = dv[3];
-        a.g_old = dv[4]; a.gd_old = dv[5]; a.g_new = dv[6]; a.gd_new = dv[7];
-        a.t_old = ds[0]; a.h_old = ds[1]; a.n_p = ds[2];
-        a.df = dout[0]; a.dfd = dout[1]; a.f2 = dout[2]; a.f3 = dout[3];
-        a.dt_new = dout[4]; a.h_new = dout[5];
+        for (int k = 0; k < 8; ++k) std::memcpy(pin + o_vin[k], vin[k], v3);
+        for (int k = 0; k < 3; ++k) std::memcpy(pin + o_sin[k], sin3[k], s1);
+        std::memcpy(pin + o_nnb, b->nnb, (size_t)n * sizeof(int32_t));
+        HIP_TRY(c, hipMemcpyAsync(dev, pin, in_end, hipMemcpyHostToDevice, st));
+        auto dvec = [&](size_t o) { return (double*)(dev + o); };
+        a.f_old = dvec(o_vin[0]); a.fd_old = dvec(o_vin[1]);
+        a.f_new = dvec(o_vin[2]); a.fd_new = dvec(o_vin[3]);
+        a.g_old = dvec(o_vin[4]); a.gd_old = dvec(o_vin[5]);
+        a.g_new = dvec(o_vin[6]); a.gd_new = dvec(o_vin[7]);
+        a.t_old = dvec(o_sin[0]); a.h_old = dvec(o_sin[1]); a.n_p = dvec(o_sin[2]);
+        a.nnb = (const int32_t*)(dev + o_nnb);
+        a.df = dvec(o_vout[0]); a.dfd = dvec(o_vout[1]);
+        a.f2 = dvec(o_vout[2]); a.f3 = dvec(o_vout[3]);
+        a.dt_new = dvec(o_sout[0]); a.h_new = dvec(o_sout[1]);
         HIP_TRY(c, launch_correct(a, st));
-        for (int k = 0; k < 4; ++k)
-            HIP_TRY(c, hipMemcpyAsync(vout[k], dout[k], v3, hipMemcpyDeviceToHost, st));
-        HIP_TRY(c, hipMemcpyAsync(b->dt_new, dout[4], s1, hipMemcpyDeviceToHost, st));
-        HIP_TRY(c, hipMemcpyAsync(b->h_new, dout[5], s1, hipMemcpyDeviceToHost, st));
+        HIP_TRY(c, hipMemcpyAsync(pin + in_end, dev + in_end, lay.end - in_end,
+                                  hipMemcpyDeviceToHost, st));
         HIP_TRY(c, hipStreamSynchronize(st));
+        for (int k = 0; k < 4; ++k) std::memcpy(vout[k], pin + o_vout[k], v3);
+        std::memcpy(b->dt_new, pin + o_sout[0], s1);
+        std::memcpy(b->h_new, pin + o_sout[1], s1);
         return NB6_OK;
     }
     a.t_old = b->t_old;

@@ -102,7 +102,6 @@ struct nb6_ctx {
     nb6::DevBuf out_list;                             // HOST-mode lists too big to stage
     nb6::PinBuf pin;                                  // pinned mirror of `io`
     nb6::DevBuf ld[7];                                // HOST-mode load staging
-    nb6::DevBuf corr;                                 // HOST-mode corrector staging
     unsigned* status = nullptr;                       // device status word
     std::string err;
     nb6::Plan last_plan{0, 0, 0, 0, 0};

@@ -203,6 +203,10 @@ hipError_t launch_copy_rows(const int32_t* src, int src_cap, int32_t* dst, int d
 // entries) to out[off[q] ...], for q < n.
 hipError_t launch_pack_rows(const int32_t* list, int cap, const int64_t* off, int64_t n,
                             int32_t* out, hipStream_t s);
+// The inverse: packed[off[q] ...] to the first off[q+1] - off[q] entries of
+// row q of `list`.
+hipError_t launch_unpack_rows(const int32_t* packed, const int64_t* off, int64_t n,
+                              int32_t* list, int cap, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Regular corrector of a block (elementwise, FP64).

@@ -10,8 +10,8 @@
 //                      gives the sums.
 //   set_lists_kernel   one wavefront per replaced list: copy, validate.
 //   copy_rows_kernel   re-lay the stored lists when their rows grow.
-//   pack_rows_kernel   pack the used part of each list row into one array
-//                      (host-array calls copy only that over PCIe).
+//   pack_rows_kernel   pack the used part of each list row into one array,
+//   unpack_rows_kernel and back (host-array calls move only that over PCIe).
 //
 // The work per pair is one gather of a 128-byte state record and ~60
 // FP64 operations, so the kernel is bound by the latency and bandwidth of
@@ -153,6 +153,17 @@ __global__ void __launch_bounds__(256) pack_rows_kernel(const int32_t* list, int
     for (int e = threadIdx.x & 63; e < cnt; e += 64) out[o + e] = row[e];
 }
 
+__global__ void __launch_bounds__(256) unpack_rows_kernel(const int32_t* packed,
+                                                         const int64_t* off, int64_t n,
+                                                         int32_t* list, int cap) {
+    const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (q >= n) return;
+    const int64_t o = off[q];
+    const int cnt = (int)(off[q + 1] - o);
+    int32_t* row = list + q * cap;
+    for (int e = threadIdx.x & 63; e < cnt; e += 64) row[e] = packed[o + e];
+}
+
 hipError_t launch_irregular(const IrrArgs& a, hipStream_t s) {
     if (a.ni <= 0) return hipSuccess;
     hipLaunchKernelGGL(irregular_kernel, dim3((unsigned)((a.ni + 3) / 4)), dim3(256), 0, s, a);
@@ -181,6 +192,14 @@ hipError_t launch_pack_rows(const int32_t* list, int cap, const int64_t* off, in
     if (n <= 0 || cap <= 0) return hipSuccess;
     hipLaunchKernelGGL(pack_rows_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, list, cap,
                        off, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_unpack_rows(const int32_t* packed, const int64_t* off, int64_t n,
+                              int32_t* list, int cap, hipStream_t s) {
+    if (n <= 0 || cap <= 0) return hipSuccess;
+    hipLaunchKernelGGL(unpack_rows_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, packed,
+                       off, n, list, cap);
     return hipGetLastError();
 }
 

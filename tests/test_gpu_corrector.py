@@ -141,3 +141,34 @@ def test_corrector_errors(ctx):
     assert nb6.nb6_sync_status(ctx, st) == nb6.NB6_ERR_DEVICE_INPUT
     dt_new = arrays["dt_new"].cpu().numpy()
     assert np.isfinite(dt_new[0]) and np.isnan(dt_new[1])
+
+
+def test_host_and_device_arrays_agree(ctx):
+    """The corrector with host arrays (one pinned copy each way) and with
+    device arrays gives the same bits, on a block large enough for several
+    workgroups and a ragged tail."""
+    import torch
+    nb6 = _nb6()
+    rng = np.random.default_rng(67)
+    n = 70001
+    t = 1.0
+    h = 2.0 ** -rng.integers(3, 12, n)
+    vec = lambda s: rng.normal(scale=s, size=(n, 3))  # noqa: E731
+    arrays = {"t_old": t - h, "f_old": vec(1.0), "fd_old": vec(5.0), "f_new": vec(1.0),
+              "fd_new": vec(5.0), "g_old": vec(10.0), "gd_old": vec(50.0), "g_new": vec(10.0),
+              "gd_new": vec(50.0), "h_old": rng.uniform(0.01, 0.1, n),
+              "nnb": rng.integers(0, 120, n).astype(np.int32), "n_p": rng.uniform(20, 80, n)}
+    host = nb6.regular_correct_host(ctx, t, *[arrays[k] for k in (
+        "t_old", "f_old", "fd_old", "f_new", "fd_new", "g_old", "gd_old", "g_new", "gd_new",
+        "h_old", "nnb", "n_p")], **PAR)
+    dev = {k: torch.from_numpy(np.ascontiguousarray(v)).to("cuda:0") for k, v in arrays.items()}
+    for k in ("df", "dfd", "f2", "f3"):
+        dev[k] = torch.empty((n, 3), dtype=torch.float64, device="cuda:0")
+    for k in ("dt_new", "h_new"):
+        dev[k] = torch.empty(n, dtype=torch.float64, device="cuda:0")
+    par = (PAR["eta"], PAR["dt_min"], PAR["dt_max"], PAR["f_lo"], PAR["f_hi"])
+    nb6.check(ctx, nb6.nb6_regular_correct(ctx, n, t, dev, par, nb6.NB6_MEM_DEVICE))
+    torch.cuda.synchronize()
+    nb6.check(ctx, nb6.nb6_sync_status(ctx))
+    for k in ("df", "dfd", "f2", "f3", "dt_new", "h_new"):
+        np.testing.assert_array_equal(host[k], dev[k].cpu().numpy(), err_msg=k)

@@ -250,3 +250,49 @@ def test_errors(ctx):
     assert nb6.nb6_sync_status(ctx, st) == nb6.NB6_ERR_DEVICE_INPUT
     o = out.cpu().numpy()
     assert np.all(np.isfinite(o[0])) and np.all(np.isnan(o[1]))
+
+
+def test_large_host_lists_packed(ctx):
+    """Lists above 1 MB go up packed from host arrays (rows cut to their
+    counts, put back in place on the GPU): the irregular force over them
+    equals the one over the same lists set from device arrays, and the
+    oracle's; the regular call's host-array lists come back packed too and
+    equal its device-array lists."""
+    import torch
+    nb6 = _nb6()
+    cfg = config(2)
+    cl = cfg["cluster"]
+    idx = np.arange(cl.n, dtype=np.int32)[:12000]
+    load(ctx, cl)
+    cap = 256
+    _, _, nnb, lst = regular_lists(ctx, cl, idx, cap=cap)
+    assert len(idx) * cap * 4 > (1 << 20)
+    d_idx = torch.from_numpy(idx).to("cuda:0")
+    d_out = (torch.empty((len(idx), 3), dtype=torch.float64, device="cuda:0"),
+             torch.empty((len(idx), 3), dtype=torch.float64, device="cuda:0"),
+             torch.empty(len(idx), dtype=torch.int32, device="cuda:0"),
+             torch.empty((len(idx), cap), dtype=torch.int32, device="cuda:0"))
+    nb6.check(ctx, nb6.nb6_regular_force(ctx, 0, len(idx), d_idx,
+                                         torch.from_numpy(cl.h2[idx]).to("cuda:0"),
+                                         torch.from_numpy(cl.dtr[idx]).to("cuda:0"),
+                                         nb6.NB6_DX_FF, *d_out, cap, nb6.NB6_MEM_DEVICE))
+    torch.cuda.synchronize()
+    d_nnb = d_out[2].cpu().numpy()
+    d_lst = d_out[3].cpu().numpy()
+    np.testing.assert_array_equal(d_nnb, nnb)
+    for q in range(len(idx)):
+        np.testing.assert_array_equal(d_lst[q, :nnb[q]], lst[q, :nnb[q]])
+    # lists set from host arrays (packed) and from device arrays
+    nb6.set_lists_host(ctx, 0, idx, nnb, lst)
+    acc_h, jerk_h = nb6.irregular_force_host(ctx, 0, cl.tb, idx)
+    nb6.check(ctx, nb6.nb6_set_lists(ctx, 0, len(idx), d_idx, d_out[2], d_out[3], cap,
+                                     nb6.NB6_MEM_DEVICE))
+    torch.cuda.synchronize()
+    nb6.check(ctx, nb6.nb6_sync_status(ctx))
+    acc_d, jerk_d = nb6.irregular_force_host(ctx, 0, cl.tb, idx)
+    np.testing.assert_array_equal(acc_h, acc_d)
+    np.testing.assert_array_equal(jerk_h, jerk_d)
+    xp, vp = oracle.predict(cl.x, cl.v, cl.a, cl.jerk, cl.t, cl.tb)
+    sub = np.arange(0, len(idx), 97)
+    ref = oracle.irregular_force(cl.m, xp, vp, idx[sub], [lst[q, :nnb[q]] for q in sub])
+    check_irr(acc_h[sub], jerk_h[sub], ref, "packed_lists")
