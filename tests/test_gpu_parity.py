@@ -572,3 +572,27 @@ def test_two_i_per_lane(mode):
         check_mode(c, cl1, cfg1["blocks"]["all"], mode, f"ipl2_C1_{mode}")
     finally:
         nb6.nb6_destroy(c)
+
+
+def test_nonfinite_device_state_is_reported(ctx):
+    """A non-finite coordinate loaded from device arrays (no host check) is
+    caught by the predictor: nb6_sync_status reports NB6_ERR_DEVICE_INPUT
+    once, and a clean reload makes the cluster usable again."""
+    import torch
+    nb6 = _nb6()
+    cfg = config(1)
+    cl = cfg["cluster"]
+    dev = torch.device("cuda:0")
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
+    xb = cl.x.copy()
+    xb[4, 1] = np.nan
+    s = torch.cuda.current_stream()
+    nb6.check(ctx, nb6.nb6_load_particles(ctx, 0, cl.n, T(cl.m), T(xb), T(cl.v), T(cl.a),
+                                          T(cl.jerk), T(cl.t), mem_kind=nb6.NB6_MEM_DEVICE,
+                                          stream=s))
+    nb6.check(ctx, nb6.nb6_predict_j(ctx, 0, cl.tb, 0, s))
+    assert nb6.nb6_sync_status(ctx, s) == nb6.NB6_ERR_DEVICE_INPUT
+    assert nb6.nb6_sync_status(ctx, s) == nb6.NB6_OK
+    load(ctx, cl)
+    idx = cfg["blocks"]["all"][:64]
+    check_mode(ctx, cl, idx, "ff", "reload_after_nonfinite")
