@@ -341,8 +341,9 @@ typedef struct nb6_ticket_info {
  * (slice partials, lists, staging; the request's "footprint") fits the
  * context's HBM budget (nb6_options.hbm_budget) and no other request of the
  * same cluster is in flight; it fuses every admitted request into one
- * persistent launch (up to three launches in flight), so requests that
- * arrive while others run are served as memory and launch slots free up.
+ * batch of persistent launches (up to four batches in flight, each on a
+ * stream of its own), so requests that arrive while others run are served
+ * as memory and batch slots free up.
  * A request's result does not depend on the other requests it is fused with.
  * There is no paper counterpart: the paper keeps two GPUs busy by running
  * two simulations at once (section 4); this queue serves many.

@@ -352,6 +352,10 @@ class Engine {
     // Called with mu_ held; takes no other lock and makes no HIP call (the
     // completion thread runs it while the scheduler may be enqueueing).
     void finish(ServeReq* r, int status, double t) {
+        // A batch that failed may have marked records current that it never
+        // wrote: its clusters predict again on their next use.
+        if (status < 0 && status != NB6_ERR_DEVICE_INPUT)
+            r->cl->pred_valid = 0;
         r->status = status;
         r->t_done = t;
         arena_.free(r->off, r->bytes);
