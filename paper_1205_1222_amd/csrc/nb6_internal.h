@@ -239,8 +239,7 @@ struct ReqDesc {
     int          do_predict;
     int          mode;        // MODE_*
     int          groups;      // i-groups of regf_group_size(ipl, rg.jl_shift)
-    int          ipl;         // i-particles per lane (1 or 2; 1 when rg.jl_shift > 0)
-    long long    item0;       // first force work item within its mode group
+    long long    item0;       // first force work item within its launch
     long long    blk0;        // first finalize workgroup within the batch
 };
 
@@ -252,8 +251,14 @@ struct BatchArgs {
     unsigned long long* counter;   // work-item counter (zeroed before the launch)
 };
 
-// Persistent fused force kernel over requests [reqs, reqs + nreq) of one mode.
-hipError_t launch_serve_regf(int mode, const BatchArgs& b, int blocks, hipStream_t s);
+// Work-partition classes of a served request, one persistent launch each:
+// one i per lane, lanes sharing an i (jl_shift > 0), two i per lane.
+enum { SERVE_ONE_I = 0, SERVE_LANES = 1, SERVE_TWO_I = 2, SERVE_CLASSES = 3 };
+// Persistent fused force kernel over requests [reqs, reqs + nreq) of one
+// mode and one class.
+hipError_t launch_serve_regf(int mode, int cls, const BatchArgs& b, int blocks, hipStream_t s);
+// Workgroups of that launch that fit one compute unit at once.
+hipError_t serve_regf_blocks_per_cu(int mode, int cls, int* blocks);
 hipError_t launch_serve_finalize(const BatchArgs& b, hipStream_t s);
 // Predictions and count resets of every request of the batch, in one launch
 // of (requests x chunks) blocks; a chunk covers PREPARE_CHUNK particles.

@@ -691,8 +691,10 @@ __device__ __forceinline__ long long uniform_ll(long long v) {
 // items, items W + t for tickets t = 0, 1, ... drawn from the batch counter
 // after each item.  A launch with a wavefront per item draws no ticket.  An
 // item's result depends only on its request, so a request gives the same
-// bits alone or in any batch.
-template <int MODE>
+// bits alone or in any batch.  Each work-partition class of request
+// (SERVE_ONE_I, SERVE_LANES, SERVE_TWO_I) gets a launch of its own, so the
+// one-i kernel keeps the registers, hence the occupancy, of the plain one.
+template <int MODE, int CLASS>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
 serve_regf_kernel(BatchArgs b) {
     const_ptr<ReqDesc> reqs = (const_ptr<ReqDesc>)(b.reqs);
@@ -710,10 +712,10 @@ serve_regf_kernel(BatchArgs b) {
         const long long local = item - reqs[lo].item0;
         const int groups = reqs[lo].groups;
         const int g = (int)(local % groups), s = (int)(local / groups);
-        if (a.jl_shift > 0)
-            regf_item_lanes<MODE, NPART>(a, g, s);
-        else if (reqs[lo].ipl == 2)
+        if (CLASS == SERVE_TWO_I)
             regf_item<MODE, 2, NPART>(a, g, s);
+        else if (CLASS == SERVE_LANES)
+            regf_item_lanes<MODE, NPART>(a, g, s);
         else
             regf_item<MODE, 1, NPART>(a, g, s);
         if (waves >= b.nitems) break;  // uniform: no item beyond the first
@@ -957,16 +959,38 @@ hipError_t launch_unpack(int mode, const void* rec, int64_t n, double* x, double
     return hipGetLastError();
 }
 
-hipError_t launch_serve_regf(int mode, const BatchArgs& b, int blocks, hipStream_t s) {
-    if (b.nitems <= 0) return hipSuccess;
-    const dim3 grid(blocks), block(256);
-    switch (mode) {
-        case MODE_FF: hipLaunchKernelGGL(serve_regf_kernel<MODE_FF>, grid, block, 0, s, b); break;
-        case MODE_F64: hipLaunchKernelGGL(serve_regf_kernel<MODE_F64>, grid, block, 0, s, b); break;
-        case MODE_F32: hipLaunchKernelGGL(serve_regf_kernel<MODE_F32>, grid, block, 0, s, b); break;
-        default: return hipErrorInvalidValue;
+template <int MODE>
+static const void* serve_regf_fn_mode(int cls) {
+    switch (cls) {
+        case SERVE_ONE_I: return (const void*)serve_regf_kernel<MODE, SERVE_ONE_I>;
+        case SERVE_LANES: return (const void*)serve_regf_kernel<MODE, SERVE_LANES>;
+        case SERVE_TWO_I: return (const void*)serve_regf_kernel<MODE, SERVE_TWO_I>;
+        default: return nullptr;
     }
-    return hipGetLastError();
+}
+
+static const void* serve_regf_fn(int mode, int cls) {
+    switch (mode) {
+        case MODE_FF: return serve_regf_fn_mode<MODE_FF>(cls);
+        case MODE_F64: return serve_regf_fn_mode<MODE_F64>(cls);
+        case MODE_F32: return serve_regf_fn_mode<MODE_F32>(cls);
+        default: return nullptr;
+    }
+}
+
+hipError_t serve_regf_blocks_per_cu(int mode, int cls, int* blocks) {
+    const void* fn = serve_regf_fn(mode, cls);
+    if (!fn) return hipErrorInvalidValue;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, fn, 256, 0);
+}
+
+hipError_t launch_serve_regf(int mode, int cls, const BatchArgs& b, int blocks,
+                             hipStream_t s) {
+    if (b.nitems <= 0) return hipSuccess;
+    const void* fn = serve_regf_fn(mode, cls);
+    if (!fn) return hipErrorInvalidValue;
+    void* args[] = {const_cast<BatchArgs*>(&b)};
+    return hipLaunchKernel(fn, dim3(blocks), dim3(256), args, 0, s);
 }
 
 hipError_t launch_serve_finalize(const BatchArgs& b, hipStream_t s) {

@@ -12,9 +12,10 @@
 //                sorted lists, ordered rebuild of overflowed lists),
 // on one of kSlots streams, so up to kSlots batches run at once and requests
 // that arrive meanwhile form the next batch.  A batch holds at most about
-// kBatchWork pair interactions (a larger request runs alone), and its
-// persistent grid is sized to its work and never fills more than a quarter of
-// the wave slots of the chip, so short batches run beside long ones.  A host
+// kBatchWork pair interactions (a larger request runs alone), and each
+// persistent grid is sized to its work (a wave per item, at most what the chip
+// holds at the kernel's occupancy), so short batches start beside long ones
+// as their waves retire.  A host
 // completion thread watches each batch's end-of-work event (spinning on it
 // while batches are in flight), then stamps the batch's requests and frees
 // their memory and clusters.
@@ -46,11 +47,16 @@ constexpr size_t kAlign = 256;
 
 constexpr size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
+int serve_class(const Plan& p) {
+    return p.jl_shift > 0 ? SERVE_LANES : p.ipl == 2 ? SERVE_TWO_I : SERVE_ONE_I;
+}
+
 // What a batch uploads ahead of its descriptors, zeroed on the host: the
-// persistent kernels' work-item counters (one per coordinate mode) and the
-// requests' status words.  Header and descriptors go up in one copy.
+// persistent kernels' work-item counters (one per coordinate mode and
+// i-per-lane class) and the requests' status words.  Header and descriptors
+// go up in one copy.
 struct BatchHeader {
-    unsigned long long counters[4];
+    unsigned long long counters[3 * SERVE_CLASSES];
     unsigned status[kMaxBatch];
 };
 constexpr size_t kHeaderBytes = align_up(sizeof(BatchHeader));
@@ -193,6 +199,11 @@ class Engine {
 
     int start() {
         HIP_TRY(c_, hipSetDevice(c_->device));
+        for (int m = 0; m < 3; ++m)
+            for (int k = 0; k < SERVE_CLASSES; ++k) {
+                HIP_TRY(c_, serve_regf_blocks_per_cu(m, k, &blocks_per_cu_[m][k]));
+                blocks_per_cu_[m][k] = std::max(1, blocks_per_cu_[m][k]);
+            }
         if (int rc = arena_.init(c_, (size_t)c_->hbm_budget)) return rc;
         for (Slot& s : slots_) {
             HIP_TRY(c_, hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking));
@@ -498,12 +509,17 @@ class Engine {
         HIP_TRY(nullptr, hipSetDevice(c_->device));
         hipStream_t st = sl.stream;
         std::vector<ServeReq*>& reqs = sl.reqs;
-        std::stable_sort(reqs.begin(), reqs.end(),
-                         [](const ServeReq* a, const ServeReq* b) { return a->mi < b->mi; });
+        // one persistent launch per (mode, work-partition class) present
+        auto launch_class = [](const ServeReq* r) {
+            return r->mi * SERVE_CLASSES + serve_class(r->plan);
+        };
+        std::stable_sort(reqs.begin(), reqs.end(), [&](const ServeReq* a, const ServeReq* b) {
+            return launch_class(a) < launch_class(b);
+        });
         const int nreq = (int)reqs.size();
         long long blk0 = 0, item_in_mode = 0;
         int64_t chunk_need = 0;
-        int prev_mi = -1;
+        int prev_class = -1;
         for (int b = 0; b < nreq; ++b) {
             ServeReq* r = reqs[b];
             ClusterState* cl = r->cl;
@@ -516,9 +532,9 @@ class Engine {
                 HIP_TRY(nullptr, hipMemcpyAsync(r->d_dtr, r->rq.dtr_i, ni * sizeof(double),
                                            hipMemcpyHostToDevice, st));
             }
-            if (r->mi != prev_mi) {
+            if (launch_class(r) != prev_class) {
                 item_in_mode = 0;
-                prev_mi = r->mi;
+                prev_class = launch_class(r);
             }
             if (cl->last_plain) HIP_TRY(nullptr, hipStreamWaitEvent(st, cl->last_plain, 0));
             ReqDesc& d = sl.host_desc()[b];
@@ -560,7 +576,6 @@ class Engine {
             d.mode = r->mi;
             const int gsize = regf_group_size(p.ipl, p.jl_shift);
             d.groups = (ni + gsize - 1) / gsize;
-            d.ipl = p.ipl;
             d.item0 = item_in_mode;
             d.blk0 = blk0;
             item_in_mode += (long long)d.groups * p.nslices;
@@ -578,22 +593,25 @@ class Engine {
         all.nblk_total = blk0;
         HIP_TRY(nullptr, launch_serve_prepare(
                         all, (int)((chunk_need + PREPARE_CHUNK - 1) / PREPARE_CHUNK), st));
-        // one persistent force launch per coordinate mode present; about one
-        // work item per wave, at most 4 waves per SIMD of the chip
+        // one persistent force launch per class present: a wave per work item
+        // up to the number of waves the chip holds at the kernel's occupancy
         for (int b = 0; b < nreq;) {
             int e = b;
             long long items = 0;
-            while (e < nreq && reqs[e]->mi == reqs[b]->mi) {
+            const int cls = launch_class(reqs[b]);
+            while (e < nreq && launch_class(reqs[e]) == cls) {
                 items += (long long)sl.host_desc()[e].groups * reqs[e]->plan.nslices;
                 ++e;
             }
-            const int blocks = (int)std::min<long long>((long long)c_->num_cu * 4, (items + 3) / 4);
+            const int mi = reqs[b]->mi, k = serve_class(reqs[b]->plan);
+            const long long fit = (long long)c_->num_cu * blocks_per_cu_[mi][k];
+            const int blocks = (int)std::min<long long>(fit, (items + 3) / 4);
             BatchArgs g{};
             g.reqs = sl.dev_desc() + b;
             g.nreq = e - b;
             g.nitems = items;
-            g.counter = counters + reqs[b]->mi;
-            HIP_TRY(nullptr, launch_serve_regf(reqs[b]->mi, g, blocks, st));
+            g.counter = counters + cls;
+            HIP_TRY(nullptr, launch_serve_regf(mi, k, g, blocks, st));
             b = e;
         }
         HIP_TRY(nullptr, launch_serve_finalize(all, st));
@@ -628,6 +646,7 @@ class Engine {
     std::deque<ServeReq*> pending_;
     std::unordered_map<uint64_t, ServeReq*> tickets_;
     Slot slots_[kSlots];
+    int blocks_per_cu_[3][SERVE_CLASSES] = {};  // resident workgroups per CU, per launch
     Arena arena_;
     uint64_t next_ticket_ = 1;
     bool stop_ = false;

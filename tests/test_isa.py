@@ -8,7 +8,8 @@ three properties of every force-kernel instantiation are checked:
   and the criterion's v_min_f32 (merged, they cost 8 more vector
   instructions on every pair);
 * no VGPR or SGPR is spilled and no scratch memory is used;
-* the one-i-per-lane kernel fits 6 waves per SIMD (at most 80 VGPRs).
+* the one-i-per-lane kernels, plain and served, fit 6 waves per SIMD (at
+  most 80 VGPRs).
 
 No GPU is needed: hipcc cross-compiles for gfx950.
 """
@@ -58,8 +59,8 @@ def _meta(asm, name, key):
 def test_every_force_kernel_is_present(asm):
     names = _kernels(asm)
     # 3 coordinate modes x {one-i, two-i, lanes} x {with, without potential}
-    # plus the 3 serving kernels
-    assert len(names) == 21, names
+    # plus the serving kernels: 3 coordinate modes x {one-i, lanes, two-i}
+    assert len(names) == 27, names
 
 
 def test_criterion_stays_behind_its_branch(asm):
@@ -80,5 +81,5 @@ def test_no_spills_and_no_scratch(asm):
 
 def test_one_i_kernel_occupancy(asm):
     for name in _kernels(asm):
-        if re.search(r"regf_kernelILi\dELi1ELi6E", name):
+        if re.search(r"(?<!serve_)regf_kernelILi\dELi1ELi6E|serve_regf_kernelILi\dELi0E", name):
             assert _meta(asm, name, "vgpr_count") <= 80, name
