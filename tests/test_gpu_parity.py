@@ -124,6 +124,22 @@ def test_config2_random_block(ctx, mode):
     check_mode(ctx, cl, idx, mode, f"C2_random1024_{mode}")
 
 
+@pytest.mark.parametrize("mode,offset", [("ff", (3.0, -2.0, 1.5)),
+                                         ("ff", (1000.0, -500.0, 250.0)),
+                                         ("fp64", (1000.0, -500.0, 250.0))])
+def test_offset_cluster(ctx, mode, offset):
+    """A cluster far from the coordinate origin keeps the FF and FP64 bars:
+    both form every coordinate difference from the full-precision positions.
+    Differences of FP32 positions (the high parts alone) would be off by
+    ~3e-5 of the force at the larger offset."""
+    import dataclasses
+    base = make_cluster(4096, 91, masses="imf", k_nb=32)
+    cl = dataclasses.replace(base, x=base.x + np.array(offset))
+    load(ctx, cl)
+    idx = np.arange(0, cl.n, 3, dtype=np.int32)
+    check_mode(ctx, cl, idx, mode, f"offset{int(offset[0])}_{mode}")
+
+
 def test_ragged_sizes_and_slicings(ctx):
     nb6 = _nb6()
     cl = make_cluster(1003, 77, masses="imf", k_nb=20)
