@@ -23,8 +23,10 @@ sample also gives the ``accuracy`` report of the GPU result.
 Records beside the headline (each can be switched off): ``potential`` (the
 same call with the potential output), ``irregular`` (the irregular force
 over the lists the call returned, per block size), ``corrector`` (the
-regular corrector per block size), ``serving`` (a trace of many clusters'
-blocks served through nb6_submit / nb6_poll against one block per launch).
+regular corrector per block size), ``modes`` (the other two coordinate
+modes on the same block: rate, and accuracy on the same oracle rows),
+``serving`` (a trace of many clusters' blocks served through nb6_submit /
+nb6_poll against one block per launch).
 """
 from __future__ import annotations
 
@@ -181,8 +183,9 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(cl, idx, gpu_out, cap, target_s):
-    """Time the oracle on a sample of the block; compare the GPU rows."""
+def cpu_baseline(cl, idx, gpu_outs, cap, target_s):
+    """Time the oracle on a sample of the block; compare the GPU rows of each
+    coordinate mode in gpu_outs (name -> outputs) with it."""
     import oracle
     from oracle.compare import compare
 
@@ -202,9 +205,10 @@ def cpu_baseline(cl, idx, gpu_out, cap, target_s):
     ref = oracle.regular_force(cl.m, xp, vp, si, cl.h2[si], cl.dtr[si], lcap=4096)
     dt = time.perf_counter() - t0
     pairs = ns * (cl.n - 1)
-    acc, jerk, nnb, lst = gpu_out
-    c = compare(acc[samp], jerk[samp], nnb[samp], lst[samp], cap, ref, cl.m, xp, vp, si,
-                cl.h2[si], cl.dtr[si])
+    summaries = {}
+    for name, (acc, jerk, nnb, lst) in gpu_outs.items():
+        summaries[name] = compare(acc[samp], jerk[samp], nnb[samp], lst[samp], cap, ref, cl.m,
+                                  xp, vp, si, cl.h2[si], cl.dtr[si]).summary()
     cores = oracle.max_threads()
     # the same oracle on one core, on a smaller sample (then all cores again)
     n1 = max(1, min(len(idx), int(ns * 2.0 / max(dt * cores, 1e-6))))
@@ -220,7 +224,7 @@ def cpu_baseline(cl, idx, gpu_out, cap, target_s):
                       f"({pairs:.3g} pairs, {dt:.1f} s, FP64 C with OpenMP)",
             "single_core_value": n1 * (cl.n - 1) / dt1 / 1e9,
             "single_core_sample": f"{n1} i ({dt1:.1f} s, one thread)"}
-    return base, c.summary()
+    return base, summaries
 
 
 def serving_leg(args, nb6, torch):
@@ -690,6 +694,8 @@ def main():
     ap.add_argument("--no-irregular", action="store_true")
     ap.add_argument("--no-potential", action="store_true")
     ap.add_argument("--no-corrector", action="store_true")
+    ap.add_argument("--no-modes", action="store_true",
+                    help="skip the other coordinate modes' rate and accuracy")
     ap.add_argument("--serve-requests", type=int, default=20000)
     ap.add_argument("--serve-calibrate", type=int, default=300)
     ap.add_argument("--serve-cap", type=int, default=128)
@@ -788,11 +794,11 @@ def main():
     nb6.check(ctx, nb6.nb6_load_particles(ctx, 0, n, m_d, x_d, v_d, a_d, j_d, t_d,
                                           mem_kind=nb6.NB6_MEM_DEVICE, stream=stream))
 
-    def step():
+    def step(md=mode):
         nb6.check(ctx, nb6.nb6_load_particles(ctx, 0, ni, um_d, ux_d, uv_d, ua_d, uj_d, ut_d,
                                               idx_d, nb6.NB6_MEM_DEVICE, stream))
-        nb6.check(ctx, nb6.nb6_predict_j(ctx, 0, cl.tb, mode, stream))
-        nb6.check(ctx, nb6.nb6_regular_force(ctx, 0, ni, idx_d, h2_d, dtr_d, mode, acc, jerk,
+        nb6.check(ctx, nb6.nb6_predict_j(ctx, 0, cl.tb, md, stream))
+        nb6.check(ctx, nb6.nb6_regular_force(ctx, 0, ni, idx_d, h2_d, dtr_d, md, acc, jerk,
                                              nnb, lst, args.cap, nb6.NB6_MEM_DEVICE, stream))
 
     for w in range(args.warmup):
@@ -871,15 +877,49 @@ def main():
         out["irregular"] = irregular_leg(args, nb6, torch, ctx, cl, idx_np, idx_d, nnb, lst)
     if not args.no_corrector:
         out["corrector"] = corrector_leg(args, nb6, torch, cl, nnb)
+    # the other coordinate modes on the same workload (after the legs that
+    # read the headline call's lists): rate, and (with the CPU baseline)
+    # accuracy on the same oracle rows as the headline mode
+    mode_outs = {}
+    if not args.no_modes:
+        out["modes"] = {}
+        for name in sorted(MODES):
+            if name == args.mode:
+                continue
+            step(MODES[name])
+            torch.cuda.synchronize()
+            nb6.nb6_kernel_times(ctx)
+            ks = max(1, min(args.steps, 10))
+            t0 = time.perf_counter()
+            for k in range(ks):
+                step(MODES[name])
+            torch.cuda.synchronize()
+            m_ms = (time.perf_counter() - t0) * 1e3 / ks
+            mk, ck = nb6.nb6_kernel_times(ctx)
+            nb6.check(ctx, nb6.nb6_sync_status(ctx, stream))
+            f_ms = mk[1] / max(ck[1], 1)
+            out["modes"][name] = {
+                "value": round(pairs / (m_ms * 1e-3) / 1e9, 3), "ms_per_step": round(m_ms, 4),
+                "kernel_ginteractions_s": round(pairs / (f_ms * 1e-3) / 1e9, 3),
+                "pct_fp32_peak": round(100.0 * FLOP_PER_INTERACTION * pairs / (f_ms * 1e-3)
+                                       / 1e12 / FP32_PEAK_TFLOPS, 2)}
+            mode_outs[name] = (acc.cpu().numpy(), jerk.cpu().numpy(), nnb.cpu().numpy(),
+                               lst[:, :args.cap].cpu().numpy())
+            log(f"bench: mode {name}: {out['modes'][name]}")
     nb6.nb6_destroy(ctx)
     del acc, jerk, nnb, lst
     if not args.no_serving:
         out["serving"] = serving_leg(args, nb6, torch)
     if not args.no_cpu_baseline:
         log("bench: timing the FP64 oracle on a sample of the block ...")
-        base, accuracy = cpu_baseline(cl, idx_np, gpu_out, args.cap, args.cpu_seconds)
+        base, accuracy = cpu_baseline(cl, idx_np, {args.mode: gpu_out, **mode_outs}, args.cap,
+                                      args.cpu_seconds)
         out["cpu_baseline"] = base
-        out["accuracy"] = accuracy
+        out["accuracy"] = accuracy.pop(args.mode)
+        keys = ("n_i", "list_mismatch", "exempt_pairs", "acc_rel_max", "acc_scaled_max",
+                "jerk_rel_max", "jerk_scaled_max")
+        for name, summ in accuracy.items():
+            out["modes"][name]["accuracy"] = {k: summ[k] for k in keys if k in summ}
     print(json.dumps(out), flush=True)
 
 
