@@ -117,6 +117,9 @@ def counter_summary(fetch_csv, write_csv, valu_csv, copy_mib, config_line, pairs
         flops = 64.0 * (valu["SQ_INSTS_VALU_ADD_F32"] + valu["SQ_INSTS_VALU_MUL_F32"] +
                         2.0 * valu["SQ_INSTS_VALU_FMA_F32"] + valu["SQ_INSTS_VALU_TRANS_F32"])
         machine["fp32_flop"] = flops
+    def out_dir(csv_path):  # the rocprofv3 output directory that held a CSV
+        return os.path.relpath(os.path.dirname(os.path.abspath(csv_path)), ROOT)
+
     cmd = ("python3 bench.py --steps 2 --warmup 1 --no-serving --no-cpu-baseline --no-irregular "
            "--no-potential "
            f"--copy-mib {copy_mib}")
@@ -128,17 +131,16 @@ def counter_summary(fetch_csv, write_csv, valu_csv, copy_mib, config_line, pairs
         "the traffic counters (bytes = counter KiB x 1024 x factor).  Figures are the "
         "median over the run's force launches.",
         "",
-        "Commands (repo root, GPU box; then this summary from the CSV files):",
+        "Commands (repo root, on the MI355X; then this summary from the CSV files):",
         "",
-        f"    timeout -s KILL 120 rocprofv3 --pmc FETCH_SIZE -f csv -d gpurun_out/pmc_fetch "
+        f"    timeout -s KILL 120 rocprofv3 --pmc FETCH_SIZE -f csv -d {out_dir(fetch_csv)} "
         f"-o fetch -- {cmd}",
-        f"    timeout -s KILL 120 rocprofv3 --pmc WRITE_SIZE -f csv -d gpurun_out/pmc_write "
+        f"    timeout -s KILL 120 rocprofv3 --pmc WRITE_SIZE -f csv -d {out_dir(write_csv)} "
         f"-o write -- {cmd}",
         f"    timeout -s KILL 120 rocprofv3 --pmc {' '.join(VALU_COUNTERS)} -f csv "
-        f"-d gpurun_out/pmc_valu -o valu -- {cmd}",
-        "    python3 bench.py --counter-summary gpurun_out/pmc_fetch/fetch_counter_collection.csv "
-        "gpurun_out/pmc_write/write_counter_collection.csv "
-        f"gpurun_out/pmc_valu/valu_counter_collection.csv --copy-mib {copy_mib}",
+        f"-d {out_dir(valu_csv)} -o valu -- {cmd}",
+        f"    python3 bench.py --counter-summary {fetch_csv} {write_csv} {valu_csv} "
+        f"--copy-mib {copy_mib}",
         "",
         f"Kernel: `{kernel}`; config: {config_line}; {pairs:.4g} pair interactions per launch.",
         "",

@@ -26,7 +26,8 @@ from workloads import config, make_cluster  # noqa: E402
 MODES = {"ff": 1, "fp64": 2, "fp32": 4}
 TOL_SCALED = {"ff": 1e-6, "fp64": 1e-6, "fp32": 1e-4}
 TOL_REL = {"ff": 1e-6, "fp64": 1e-6, "fp32": None}
-OUT = os.path.join(os.path.dirname(os.path.dirname(__file__)), "gpurun_out")
+# File that collects one JSON line per parity case (unset: printed only).
+OUT = os.environ.get("NB6_PARITY_LOG")
 
 
 def _nb6():
@@ -43,9 +44,10 @@ def ctx():
 
 
 def _record(name, summary):
-    os.makedirs(OUT, exist_ok=True)
-    with open(os.path.join(OUT, "parity_summaries.jsonl"), "a") as f:
-        f.write(json.dumps({"case": name, **summary}) + "\n")
+    if OUT:
+        os.makedirs(os.path.dirname(os.path.abspath(OUT)), exist_ok=True)
+        with open(OUT, "a") as f:
+            f.write(json.dumps({"case": name, **summary}) + "\n")
     print(name, json.dumps(summary), flush=True)
 
 
