@@ -143,8 +143,11 @@ int nb6_predict_j(nb6_ctx *ctx, int cluster, double t_block, int modes,
  *   m_j (V / r^3 - 3 (R.V) R / r^5) to jerk_i.
  * Inputs:  idx_i[n_i] (cluster indices, 0 <= idx_i < N), h2_i[n_i]
  *          (squared neighbour radii, > 0 and >= 2^-126 as floats),
- *          dtr_i[n_i] (regular time-steps), dx_mode (one NB6_DX_* value,
- *          whose stream the last nb6_predict_j wrote),
+ *          dtr_i[n_i] (regular time-steps), dx_mode (one NB6_DX_* value
+ *          whose stream holds the cluster's latest prediction: the block
+ *          time of the last nb6_predict_j or served request on the cluster,
+ *          whichever came last; a stream still at an earlier block time is
+ *          refused with NB6_ERR_STATE),
  *          0 <= cap <= NB6_MAX_CAP.
  * Outputs: acc[n_i][3], jerk[n_i][3] (double), nnb[n_i] (true neighbour
  *          count, self excluded), list[n_i][cap] (the first min(nnb, cap)

@@ -478,7 +478,8 @@ int nb6_predict_j(nb6_ctx* c, int cluster, double t_block, int modes, void* stre
     TimedLaunch tl(c, 0, (hipStream_t)stream);
     HIP_TRY(c, launch_predict(pa, (hipStream_t)stream));
     tl.done();
-    cl->pred_valid = modes;
+    // records of other modes predicted to this same block time stay current
+    cl->pred_valid = (cl->t_pred == t_block ? cl->pred_valid : 0) | modes;
     cl->t_pred = t_block;
     return NB6_OK;
 }

@@ -273,9 +273,14 @@ def test_errors(ctx):
     assert nb6.nb6_regular_force(ctx, 0, 3, idx, h2, dtr, 3, *out, 8) == nb6.NB6_ERR_ARG
     assert nb6.nb6_regular_force(ctx, 0, 3, idx, h2, dtr, 1, *out, -1) == nb6.NB6_ERR_ARG
     assert nb6.nb6_regular_force(ctx, 7, 3, idx, h2, dtr, 1, *out, 8) == nb6.NB6_ERR_STATE
-    # only the FF stream predicted -> FP64 call refused
-    nb6.check(ctx, nb6.nb6_predict_j(ctx, 0, cl.tb, nb6.NB6_DX_FF))
+    # FF predicted to a later block time -> the FP64 stream (still at the
+    # earlier one) is refused; predicted to that time too, it is usable
+    nb6.check(ctx, nb6.nb6_predict_j(ctx, 0, cl.tb + 2.0 ** -10, nb6.NB6_DX_FF))
     assert nb6.nb6_regular_force(ctx, 0, 3, idx, h2, dtr, 2, *out, 8) == nb6.NB6_ERR_STATE
+    nb6.check(ctx, nb6.nb6_predict_j(ctx, 0, cl.tb + 2.0 ** -10, nb6.NB6_DX_FP64))
+    usable = (nb6.NB6_OK, nb6.NB6_WARN_NB_OVERFLOW)
+    assert nb6.nb6_regular_force(ctx, 0, 3, idx, h2, dtr, 2, *out, 8) in usable
+    assert nb6.nb6_regular_force(ctx, 0, 3, idx, h2, dtr, 1, *out, 8) in usable
     # a load invalidates the prediction
     load(ctx, cl)
     nb6.check(ctx, nb6.nb6_load_particles(ctx, 0, 2, cl.m[:2], cl.x[:2], cl.v[:2], cl.a[:2],

@@ -166,6 +166,42 @@ def test_served_equals_plain_call(clusters, hint, c, step, ni_max):
         nb6.nb6_destroy(ctx)
 
 
+def test_plain_calls_after_serving(clusters):
+    """A served request predicts its cluster to its own block time.  A plain
+    call afterwards uses those float-float records (the same bits as the
+    served result), and a mode whose records still hold the earlier block
+    time is refused instead of being mixed with the newer one."""
+    nb6 = _nb6()
+    ctx = nb6.nb6_create(0)
+    try:
+        _load_all(nb6, ctx, clusters)
+        c = 2
+        cl = clusters[c]
+        idx = np.arange(0, cl.n, 7, dtype=np.int32)
+        nb6.check(ctx, nb6.nb6_predict_j(ctx, c, cl.tb, 0))     # every mode at tb
+        tb2 = cl.tb + 2.0 ** -10
+        t, h = _submit(nb6, ctx, cl, c, tb2, idx, 64)            # FF at tb2
+        assert nb6.nb6_poll(ctx, t, wait=1)[0] in (nb6.NB6_OK, nb6.NB6_WARN_NB_OVERFLOW)
+        acc, jerk, nnb, lst, _ = nb6.regular_force_host(ctx, c, idx, cl.h2[idx],
+                                                        cl.dtr[idx], nb6.NB6_DX_FF, 64)
+        np.testing.assert_array_equal(acc, h.acc)
+        np.testing.assert_array_equal(jerk, h.jerk)
+        np.testing.assert_array_equal(nnb, h.nnb)
+        with pytest.raises(nb6.NB6Error) as e:
+            nb6.regular_force_host(ctx, c, idx, cl.h2[idx], cl.dtr[idx], nb6.NB6_DX_FP64, 64)
+        assert e.value.code == nb6.NB6_ERR_STATE
+        # predicting another mode to tb2 makes it usable, and keeps FF current
+        nb6.check(ctx, nb6.nb6_predict_j(ctx, c, tb2, nb6.NB6_DX_FP64))
+        a64 = nb6.regular_force_host(ctx, c, idx, cl.h2[idx], cl.dtr[idx], nb6.NB6_DX_FP64,
+                                     64)[0]
+        assert np.max(np.abs(a64 - acc) / np.linalg.norm(acc, axis=1)[:, None]) < 1e-5
+        aff = nb6.regular_force_host(ctx, c, idx, cl.h2[idx], cl.dtr[idx], nb6.NB6_DX_FF,
+                                     64)[0]
+        np.testing.assert_array_equal(aff, h.acc)
+    finally:
+        nb6.nb6_destroy(ctx)
+
+
 def test_admission_by_budget(clusters):
     nb6 = _nb6()
     budget = 4 << 20
