@@ -202,6 +202,52 @@ def test_plain_calls_after_serving(clusters):
         nb6.nb6_destroy(ctx)
 
 
+def test_plain_calls_beside_the_queue(clusters):
+    """Plain calls on some clusters while the queue serves others, on one
+    context: every result equals the same computation done alone (the queue
+    and the plain path keep separate scratch and status)."""
+    nb6 = _nb6()
+    ctx = nb6.nb6_create(0)
+    try:
+        _load_all(nb6, ctx, clusters)
+        rng = np.random.Generator(np.random.PCG64(21))
+        served = []
+        for r in range(6):
+            for c in (0, 1):
+                cl = clusters[c]
+                idx = np.sort(rng.choice(cl.n, int(rng.choice([16, 300, 1500])),
+                                         replace=False)).astype(np.int32)
+                served.append((c, cl.tb + r * 2.0 ** -12, idx))
+        plain = [(c, np.arange(c, clusters[c].n, 5, dtype=np.int32)) for c in (2, 3)]
+
+        def plain_call(c, idx):
+            cl = clusters[c]
+            nb6.check(ctx, nb6.nb6_predict_j(ctx, c, cl.tb, nb6.NB6_DX_FF))
+            return nb6.regular_force_host(ctx, c, idx, cl.h2[idx], cl.dtr[idx],
+                                          nb6.NB6_DX_FF, 64)[:3]
+
+        alone_plain = [plain_call(c, idx) for c, idx in plain]
+        alone_served = []
+        for c, tb, idx in served:
+            t, h = _submit(nb6, ctx, clusters[c], c, tb, idx, 64)
+            assert nb6.nb6_poll(ctx, t, wait=1)[0] in (nb6.NB6_OK, nb6.NB6_WARN_NB_OVERFLOW)
+            alone_served.append(h)
+        # now all at once: the whole queue, then plain calls while it drains
+        subs = [_submit(nb6, ctx, clusters[c], c, tb, idx, 64) for c, tb, idx in served]
+        mixed_plain = [plain_call(c, idx) for c, idx in plain for _ in range(2)]
+        for (t, h), ref in zip(subs, alone_served):
+            assert nb6.nb6_poll(ctx, t, wait=1)[0] in (nb6.NB6_OK, nb6.NB6_WARN_NB_OVERFLOW)
+            np.testing.assert_array_equal(h.acc, ref.acc)
+            np.testing.assert_array_equal(h.jerk, ref.jerk)
+            np.testing.assert_array_equal(h.nnb, ref.nnb)
+        for k, got in enumerate(mixed_plain):
+            ref = alone_plain[k // 2]
+            for a, b in zip(got, ref):
+                np.testing.assert_array_equal(a, b)
+    finally:
+        nb6.nb6_destroy(ctx)
+
+
 def test_admission_by_budget(clusters):
     nb6 = _nb6()
     budget = 4 << 20
