@@ -221,18 +221,6 @@ static std::vector<int64_t> row_offsets(const int32_t* count, int n, int cap) {
     return off;
 }
 
-// body(q0, q1) over the rows [0, n) on up to 8 host threads (one per 2^18
-// entries moved).
-template <typename F>
-static void for_rows(int n, int64_t entries, F body) {
-    const int nt = (int)std::min<int64_t>(8, std::max<int64_t>(1, entries >> 18));
-    std::vector<std::thread> helpers;
-    for (int t = 1; t < nt; ++t)
-        helpers.emplace_back(body, (int)((int64_t)n * t / nt), (int)((int64_t)n * (t + 1) / nt));
-    body(0, (int)((int64_t)n / nt));
-    for (auto& h : helpers) h.join();
-}
-
 // Row-major [n][cap] rows to a packed array (row q at off[q]), and back.
 static void pack_rows_host(const std::vector<int64_t>& off, int n, int cap,
                            const int32_t* rows, int32_t* packed) {

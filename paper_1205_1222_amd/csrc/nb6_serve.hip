@@ -15,10 +15,12 @@
 // kBatchWork pair interactions (a larger request runs alone), and each
 // persistent grid is sized to its work (a wave per item, at most what the chip
 // holds at the kernel's occupancy), so short batches start beside long ones
-// as their waves retire.  A host
-// completion thread watches each batch's end-of-work event (spinning on it
-// while batches are in flight), then stamps the batch's requests and frees
-// their memory and clusters.
+// as their waves retire.  Requests with host arrays cross PCIe through the
+// slot's pinned staging (one copy each way per request), so no copy waits
+// on the host.  A host completion thread watches each batch's end-of-work
+// event (spinning on it while batches are in flight), places the host
+// requests' outputs in the callers' arrays, then stamps the batch's requests
+// and frees their memory and clusters.
 //
 // A request's plan (make_plan: the rule of a plain call on the same context)
 // and its summation order depend only on the request, so its results are
@@ -128,6 +130,7 @@ struct ServeReq {
     ClusterState* cl = nullptr;
     int status = NB6_PENDING;
     int batch_size = 0;
+    size_t stage = 0;       // HOST requests: offset of its region in the slot's pinned staging
     double t_submit = 0, t_admit = 0, t_done = 0;
     // scratch carved from the arena
     double* part = nullptr;
@@ -175,11 +178,26 @@ size_t carve(ServeReq* r, char* base) {
     return off;
 }
 
+// Bytes from a HOST request's first device input to the end of its inputs,
+// and from its first output to the end of its outputs: carve() lays each
+// group out contiguously, so each crosses PCIe in one copy through the slot's
+// pinned staging, with the same layout there.
+size_t in_span(const ServeReq* r) {
+    return (size_t)((const char*)(r->d_dtr + r->rq.n_i) - (const char*)r->d_idx);
+}
+size_t out_span(const ServeReq* r) {
+    const size_t ni = (size_t)r->rq.n_i, cap = (size_t)r->rq.cap;
+    return (size_t)((const char*)(r->d_list + std::max<size_t>(1, ni * cap)) -
+                    (const char*)r->d_acc);
+}
+
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;           // recorded after the batch's last work
     char* host_blob = nullptr;           // pinned: BatchHeader, then kMaxBatch ReqDesc
     char* dev_blob = nullptr;            // its device copy
+    char* stage = nullptr;               // pinned staging of the HOST requests' arrays
+    size_t stage_cap = 0;
     bool busy = false;                   // holds a batch
     bool launched = false;               // its work is enqueued; `done` is pending
     std::vector<ServeReq*> reqs;
@@ -247,6 +265,7 @@ class Engine {
             if (s.stream) (void)hipStreamDestroy(s.stream);
             if (s.done) (void)hipEventDestroy(s.done);
             if (s.host_blob) (void)hipHostFree(s.host_blob);
+            if (s.stage) (void)hipHostFree(s.stage);
             if (s.dev_blob) (void)hipFree(s.dev_blob);
             s = Slot();
         }
@@ -467,11 +486,40 @@ class Engine {
                 std::this_thread::yield();
                 if (nc < kSlots) break;  // look for slots launched meanwhile
             }
+            // the HOST requests' outputs, from the pinned staging into the
+            // callers' arrays (the slot stays busy until complete(), so
+            // neither its staging nor its requests change meanwhile)
+            if (ready && err == hipSuccess) copy_out(*ready);
             lk.lock();
             if (ready) {
                 ready->launched = false;
                 complete(*ready, err);
             }
+        }
+    }
+
+    static void copy_out(const Slot& sl) {
+        for (const ServeReq* r : sl.reqs) {
+            if (r->rq.mem_kind != NB6_MEM_HOST) continue;
+            const size_t ni = (size_t)r->rq.n_i, cap = (size_t)r->rq.cap;
+            const char* base = sl.stage + r->stage + in_span(r);
+            auto at = [&](const void* dev) {
+                return base + ((const char*)dev - (const char*)r->d_acc);
+            };
+            std::memcpy(r->rq.acc, at(r->d_acc), 3 * ni * sizeof(double));
+            std::memcpy(r->rq.jerk, at(r->d_jerk), 3 * ni * sizeof(double));
+            std::memcpy(r->rq.nnb, at(r->d_nnb), ni * sizeof(int32_t));
+            if (cap == 0) continue;
+            // the first min(nnb, cap) entries of each row, as a plain call's
+            const int32_t* nnb = reinterpret_cast<const int32_t*>(at(r->d_nnb));
+            const int32_t* rows = reinterpret_cast<const int32_t*>(at(r->d_list));
+            for_rows((int)ni, (int64_t)(ni * cap), [&](int q0, int q1) {
+                for (int q = q0; q < q1; ++q) {
+                    const size_t k = (size_t)std::min<int64_t>(std::max(nnb[q], 0), (int64_t)cap);
+                    std::memcpy(r->rq.list + (size_t)q * cap, rows + (size_t)q * cap,
+                                k * sizeof(int32_t));
+                }
+            });
         }
     }
 
@@ -517,6 +565,21 @@ class Engine {
             return launch_class(a) < launch_class(b);
         });
         const int nreq = (int)reqs.size();
+        // pinned staging of the HOST requests: inputs then outputs of each
+        size_t stage_bytes = 0;
+        for (ServeReq* r : reqs) {
+            if (r->rq.mem_kind != NB6_MEM_HOST) continue;
+            r->stage = stage_bytes;
+            stage_bytes += align_up(in_span(r) + out_span(r));
+        }
+        if (stage_bytes > sl.stage_cap) {  // the slot is idle: its old staging is free
+            const size_t want = std::max(stage_bytes, 2 * sl.stage_cap);
+            if (sl.stage) HIP_TRY(nullptr, hipHostFree(sl.stage));
+            sl.stage = nullptr;
+            sl.stage_cap = 0;
+            HIP_TRY(nullptr, hipHostMalloc((void**)&sl.stage, want));
+            sl.stage_cap = want;
+        }
         long long blk0 = 0, item_in_mode = 0;
         int64_t chunk_need = 0;
         int prev_class = -1;
@@ -525,12 +588,12 @@ class Engine {
             ClusterState* cl = r->cl;
             const int ni = (int)r->rq.n_i;
             if (r->rq.mem_kind == NB6_MEM_HOST) {
-                HIP_TRY(nullptr, hipMemcpyAsync(r->d_idx, r->rq.idx_i, ni * sizeof(int32_t),
-                                           hipMemcpyHostToDevice, st));
-                HIP_TRY(nullptr, hipMemcpyAsync(r->d_h2, r->rq.h2_i, ni * sizeof(double),
-                                           hipMemcpyHostToDevice, st));
-                HIP_TRY(nullptr, hipMemcpyAsync(r->d_dtr, r->rq.dtr_i, ni * sizeof(double),
-                                           hipMemcpyHostToDevice, st));
+                char* in = sl.stage + r->stage;
+                auto at = [&](const void* dev) { return in + ((const char*)dev - (const char*)r->d_idx); };
+                std::memcpy(at(r->d_idx), r->rq.idx_i, ni * sizeof(int32_t));
+                std::memcpy(at(r->d_h2), r->rq.h2_i, ni * sizeof(double));
+                std::memcpy(at(r->d_dtr), r->rq.dtr_i, ni * sizeof(double));
+                HIP_TRY(nullptr, hipMemcpyAsync(r->d_idx, in, in_span(r), hipMemcpyHostToDevice, st));
             }
             if (launch_class(r) != prev_class) {
                 item_in_mode = 0;
@@ -615,18 +678,10 @@ class Engine {
             b = e;
         }
         HIP_TRY(nullptr, launch_serve_finalize(all, st));
-        for (ServeReq* r : reqs) {
+        for (ServeReq* r : reqs) {  // outputs into the staging; copy_out() places them
             if (r->rq.mem_kind != NB6_MEM_HOST) continue;
-            const size_t ni = (size_t)r->rq.n_i;
-            HIP_TRY(nullptr, hipMemcpyAsync(r->rq.acc, r->d_acc, 3 * ni * sizeof(double),
-                                       hipMemcpyDeviceToHost, st));
-            HIP_TRY(nullptr, hipMemcpyAsync(r->rq.jerk, r->d_jerk, 3 * ni * sizeof(double),
-                                       hipMemcpyDeviceToHost, st));
-            HIP_TRY(nullptr, hipMemcpyAsync(r->rq.nnb, r->d_nnb, ni * sizeof(int32_t),
-                                       hipMemcpyDeviceToHost, st));
-            if (r->rq.cap > 0)
-                HIP_TRY(nullptr, hipMemcpyAsync(r->rq.list, r->d_list, ni * r->rq.cap * sizeof(int32_t),
-                                           hipMemcpyDeviceToHost, st));
+            HIP_TRY(nullptr, hipMemcpyAsync(sl.stage + r->stage + in_span(r), r->d_acc,
+                                       out_span(r), hipMemcpyDeviceToHost, st));
         }
         HIP_TRY(nullptr, hipMemcpyAsync(sl.host_hdr()->status, sl.dev_hdr()->status,
                                    nreq * sizeof(unsigned), hipMemcpyDeviceToHost, st));
