@@ -342,10 +342,14 @@ def test_repeat_calls_are_bitwise_identical(ctx):
         np.testing.assert_array_equal(x, y)
 
 
-@pytest.mark.parametrize("block", ["all", "pow2_0", "pow2_4", "pow2_10", "pow2_14"])
-def test_config3_full_size_sampled(ctx, block):
+@pytest.mark.parametrize("block,mode", [("all", "ff"), ("pow2_0", "ff"), ("pow2_4", "ff"),
+                                        ("pow2_10", "ff"), ("pow2_14", "ff"),
+                                        ("all", "fp64"), ("pow2_10", "fp64"),
+                                        ("all", "fp32"), ("pow2_10", "fp32")])
+def test_config3_full_size_sampled(ctx, block, mode):
     """N = 131072 with binaries, in the launch configuration the benchmark
-    times; the oracle checks a sample of the active i."""
+    times; the oracle checks a sample of the active i, with each coordinate
+    mode's bars."""
     nb6 = _nb6()
     cfg = config(3)
     cl = cfg["cluster"]
@@ -353,7 +357,7 @@ def test_config3_full_size_sampled(ctx, block):
     load(ctx, cl)
     cap = 256
     acc, jerk, nnb, lst, rc = nb6.regular_force_host(ctx, 0, idx, cl.h2[idx], cl.dtr[idx],
-                                                     1, cap)
+                                                     MODES[mode], cap)
     rng = np.random.Generator(np.random.PCG64(5))
     samp = np.sort(rng.choice(len(idx), min(256, len(idx)), replace=False))
     xp, vp = oracle.predict(cl.x, cl.v, cl.a, cl.jerk, cl.t, cl.tb)
@@ -363,10 +367,17 @@ def test_config3_full_size_sampled(ctx, block):
                 cl.h2[si], cl.dtr[si])
     s = c.summary()
     s["slices"] = nb6.nb6_last_slices(ctx)
-    _record(f"C3_{block}_ff", s)
-    assert c.incomplete == 0 and c.list_mismatch == 0 and c.nnb_mismatch == 0
-    assert s["acc_scaled_max"] <= 1e-6 and s["jerk_scaled_max"] <= 1e-6, s
-    assert s.get("acc_rel_max", 0.0) <= 1e-6 and s.get("jerk_rel_max", 0.0) <= 1e-6, s
+    _record(f"C3_{block}_{mode}", s)
+    assert c.incomplete == 0
+    if mode == "fp32":
+        assert c.list_mismatch <= max(1, len(samp) // 100), c.mismatches[:10]
+    else:
+        assert c.list_mismatch == 0 and c.nnb_mismatch == 0
+    tol = TOL_SCALED[mode]
+    assert s["acc_scaled_max"] <= tol and s["jerk_scaled_max"] <= tol, s
+    if TOL_REL[mode] is not None:
+        assert s.get("acc_rel_max", 0.0) <= TOL_REL[mode], s
+        assert s.get("jerk_rel_max", 0.0) <= TOL_REL[mode], s
 
 
 @pytest.mark.parametrize("mode", ["ff", "fp64", "fp32"])
