@@ -311,6 +311,24 @@ def test_errors(ctx):
     assert list(nnb.cpu().numpy()[1:]) == [-1, -1]
 
 
+def test_empty_blocks(ctx):
+    """n_i == 0 is a no-op for every block call, with NULL arrays, in both
+    memory kinds; the context computes normally afterwards."""
+    nb6 = _nb6()
+    cl = make_cluster(512, 41, masses="equal", k_nb=16)
+    load(ctx, cl)
+    params = (0.02, 2.0 ** -20, 1.0, 0.5, 2.0)
+    nulls = {name: None for name, _ in nb6.nb6_corr_block._fields_[2:]}
+    for mk in (nb6.NB6_MEM_HOST, nb6.NB6_MEM_DEVICE):
+        assert nb6.nb6_regular_force(ctx, 0, 0, None, None, None, MODES["ff"], None, None,
+                                     None, None, 0, mk) == nb6.NB6_OK
+        assert nb6.nb6_set_lists(ctx, 0, 0, None, None, None, 8, mk) == nb6.NB6_OK
+        assert nb6.nb6_irregular_force(ctx, 0, cl.tb, 0, None, None, None, mk) == nb6.NB6_OK
+        assert nb6.nb6_regular_correct(ctx, 0, 1.0, nulls, params, mk) == nb6.NB6_OK
+    idx = np.arange(0, cl.n, 4, dtype=np.int32)
+    check_mode(ctx, cl, idx, "ff", "after_empty_blocks")
+
+
 def test_subset_update_then_predict(ctx):
     nb6 = _nb6()
     cfg = config(2, n=4096)
