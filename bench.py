@@ -25,8 +25,9 @@ same call with the potential output), ``irregular`` (the irregular force
 over the lists the call returned, per block size), ``corrector`` (the
 regular corrector per block size), ``modes`` (the other two coordinate
 modes on the same block: rate, and accuracy on the same oracle rows),
-``serving`` (a trace of many clusters' blocks served through nb6_submit /
-nb6_poll against one block per launch).
+``load`` (nb6_load_particles from host arrays: the whole cluster and a
+block's subset update), ``serving`` (a trace of many clusters' blocks served
+through nb6_submit / nb6_poll against one block per launch).
 """
 from __future__ import annotations
 
@@ -499,6 +500,40 @@ def irregular_leg(args, nb6, torch, ctx, cl, idx_np, idx_d, nnb, lst):
 CORR_BYTES_PER_I = 8 + 8 * 24 + 8 + 4 + 8 + 4 * 24 + 16
 
 
+# Host bytes of one particle's stored state (m, t, x, v, a, jerk), the unit
+# of a host-array nb6_load_particles; a subset update adds its 4-byte index.
+LOAD_BYTES_PER_PARTICLE = 8 + 8 + 4 * 24
+
+
+def load_leg(nb6, cl, reps=5):
+    """nb6_load_particles from host arrays (copies and synchronisation
+    included): the whole cluster, and a 4096-particle subset update (the
+    corrector output of a block)."""
+    ctx = nb6.nb6_create(0)
+    n = cl.n
+    arrays = [np.ascontiguousarray(a) for a in (cl.m, cl.x, cl.v, cl.a, cl.jerk, cl.t)]
+    nb6.check(ctx, nb6.nb6_load_particles(ctx, 0, n, *arrays))  # allocation
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        nb6.check(ctx, nb6.nb6_load_particles(ctx, 0, n, *arrays))
+    full = (time.perf_counter() - t0) / reps
+    rng = np.random.Generator(np.random.PCG64(12051230))
+    idx = np.sort(rng.choice(n, min(4096, n), replace=False)).astype(np.int32)
+    sub = [np.ascontiguousarray(a[idx]) for a in arrays]
+    nb6.check(ctx, nb6.nb6_load_particles(ctx, 0, len(idx), *sub, idx))
+    t0 = time.perf_counter()
+    for _ in range(reps * 20):
+        nb6.check(ctx, nb6.nb6_load_particles(ctx, 0, len(idx), *sub, idx))
+    part = (time.perf_counter() - t0) / (reps * 20)
+    nb6.nb6_destroy(ctx)
+    out = {"full_n": n, "full_ms": round(full * 1e3, 4),
+           "full_gb_s": round(n * LOAD_BYTES_PER_PARTICLE / full / 1e9, 2),
+           "subset_n": len(idx), "subset_us": round(part * 1e6, 2),
+           "subset_gb_s": round(len(idx) * (LOAD_BYTES_PER_PARTICLE + 4) / part / 1e9, 2)}
+    log(f"bench: load from host arrays: {out}")
+    return out
+
+
 def corrector_leg(args, nb6, torch, cl, nnb):
     """Regular corrector (section 3.3 step 7) of blocks of the configuration:
     device arrays, synthetic force values of the right magnitudes, the step
@@ -696,6 +731,8 @@ def main():
     ap.add_argument("--no-irregular", action="store_true")
     ap.add_argument("--no-potential", action="store_true")
     ap.add_argument("--no-corrector", action="store_true")
+    ap.add_argument("--no-load", action="store_true",
+                    help="skip the host-array load timing")
     ap.add_argument("--no-modes", action="store_true",
                     help="skip the other coordinate modes' rate and accuracy")
     ap.add_argument("--serve-requests", type=int, default=20000)
@@ -879,6 +916,8 @@ def main():
         out["irregular"] = irregular_leg(args, nb6, torch, ctx, cl, idx_np, idx_d, nnb, lst)
     if not args.no_corrector:
         out["corrector"] = corrector_leg(args, nb6, torch, cl, nnb)
+    if not args.no_load:
+        out["load"] = load_leg(nb6, cl)
     # the other coordinate modes on the same workload (after the legs that
     # read the headline call's lists): rate, and (with the CPU baseline)
     # accuracy on the same oracle rows as the headline mode

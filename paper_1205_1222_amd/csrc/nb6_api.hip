@@ -412,18 +412,37 @@ int nb6_load_particles(nb6_ctx* c, int cluster, int64_t n, const double* m, cons
                               3 * n * sizeof(double), 3 * n * sizeof(double),
                               3 * n * sizeof(double), 3 * n * sizeof(double)};
         const void* src[7] = {idx, m, t, x, v, a, jerk};
-        for (int k = idx ? 0 : 1; k < 7; ++k) {
-            int rc = ensure(c, c->ld[k], sz[k]);
-            if (rc) return rc;
-            HIP_TRY(c, hipMemcpyAsync(c->ld[k].p, src[k], sz[k], hipMemcpyHostToDevice, st));
+        const void* dst[7] = {};
+        Stage lay;
+        size_t off[7] = {};
+        for (int k = idx ? 0 : 1; k < 7; ++k) off[k] = lay.add(sz[k]);
+        if (lay.end <= kStageLoadMax) {
+            // a block's subset update: the arrays go up in one copy through
+            // the pinned buffer (one call, one DMA, instead of seven)
+            int rc;
+            if ((rc = ensure(c, c->io, lay.end)) || (rc = ensure_pinned(c, c->pin, lay.end)))
+                return rc;
+            for (int k = idx ? 0 : 1; k < 7; ++k) {
+                std::memcpy(c->pin.p + off[k], src[k], sz[k]);
+                dst[k] = (const char*)c->io.p + off[k];
+            }
+            HIP_TRY(c, hipMemcpyAsync(c->io.p, c->pin.p, lay.end, hipMemcpyHostToDevice, st));
+        } else {
+            // a large load: the runtime pipelines pageable copies by itself
+            for (int k = idx ? 0 : 1; k < 7; ++k) {
+                int rc = ensure(c, c->ld[k], sz[k]);
+                if (rc) return rc;
+                HIP_TRY(c, hipMemcpyAsync(c->ld[k].p, src[k], sz[k], hipMemcpyHostToDevice, st));
+                dst[k] = c->ld[k].p;
+            }
         }
-        sa.idx = idx ? (const int32_t*)c->ld[0].p : nullptr;
-        sa.m = (const double*)c->ld[1].p;
-        sa.t = (const double*)c->ld[2].p;
-        sa.x = (const double*)c->ld[3].p;
-        sa.v = (const double*)c->ld[4].p;
-        sa.a = (const double*)c->ld[5].p;
-        sa.jk = (const double*)c->ld[6].p;
+        sa.idx = idx ? (const int32_t*)dst[0] : nullptr;
+        sa.m = (const double*)dst[1];
+        sa.t = (const double*)dst[2];
+        sa.x = (const double*)dst[3];
+        sa.v = (const double*)dst[4];
+        sa.a = (const double*)dst[5];
+        sa.jk = (const double*)dst[6];
     } else {
         sa.idx = idx; sa.m = m; sa.t = t; sa.x = x; sa.v = v; sa.a = a; sa.jk = jerk;
     }

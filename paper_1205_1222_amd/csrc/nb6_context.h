@@ -44,6 +44,8 @@ struct Stage {
 // directly rather than through the pinned buffer (which would add a second
 // host-side pass over them).
 constexpr size_t kStageListMax = size_t(1) << 20;
+// Host-array loads up to this size go up through the pinned buffer in one copy.
+constexpr size_t kStageLoadMax = size_t(8) << 20;
 
 struct ClusterState {
     int64_t n = 0;
