@@ -167,6 +167,26 @@ def test_config3_full_size_device_chain(ctx):
     assert np.median(ref.sa) > 0
 
 
+def test_config5_random_block(ctx):
+    """N = 2^20, a block of 4096 random active particles (~100 neighbours
+    each): lists from the regular force, stored, then the irregular force;
+    a sample is checked against the oracle."""
+    nb6 = _nb6()
+    cfg = config(5)
+    cl = cfg["cluster"]
+    idx = cfg["blocks"]["random4096"]
+    load(ctx, cl)
+    _, _, nnb, lst = regular_lists(ctx, cl, idx, cap=512)
+    nb6.set_lists_host(ctx, 0, idx, nnb, lst)
+    acc, jerk = nb6.irregular_force_host(ctx, 0, cl.tb, idx)
+    rng = np.random.Generator(np.random.PCG64(9))
+    samp = np.sort(rng.choice(len(idx), 256, replace=False))
+    xp, vp = oracle.predict(cl.x, cl.v, cl.a, cl.jerk, cl.t, cl.tb)
+    ref = oracle.irregular_force(cl.m, xp, vp, idx[samp], [lst[q, :nnb[q]] for q in samp])
+    check_irr(acc[samp], jerk[samp], ref, "C5_random4096")
+    assert np.median(nnb) > 50
+
+
 def test_list_semantics(ctx):
     nb6 = _nb6()
     cl = make_cluster(500, 43, masses="imf", k_nb=10)

@@ -398,6 +398,36 @@ def test_config3_full_size_sampled(ctx, block, mode):
         assert s.get("jerk_rel_max", 0.0) <= TOL_REL[mode], s
 
 
+def test_config3_two_i_per_lane_sampled():
+    """The two-i-per-lane kernel on all 131072 particles of C3 (its plan at
+    full size), sampled against the oracle with the FF bars."""
+    nb6 = _nb6()
+    c2 = nb6.nb6_create(0, ipl_hint=2)
+    try:
+        cfg = config(3)
+        cl = cfg["cluster"]
+        idx = cfg["blocks"]["all"]
+        load(c2, cl)
+        cap = 256
+        acc, jerk, nnb, lst, rc = nb6.regular_force_host(c2, 0, idx, cl.h2[idx], cl.dtr[idx],
+                                                         MODES["ff"], cap)
+        assert nb6.nb6_last_plan(c2)[0] == 2
+        rng = np.random.Generator(np.random.PCG64(6))
+        samp = np.sort(rng.choice(len(idx), 256, replace=False))
+        xp, vp = oracle.predict(cl.x, cl.v, cl.a, cl.jerk, cl.t, cl.tb)
+        si = idx[samp]
+        ref = oracle.regular_force(cl.m, xp, vp, si, cl.h2[si], cl.dtr[si], lcap=4096)
+        c = compare(acc[samp], jerk[samp], nnb[samp], lst[samp], cap, ref, cl.m, xp, vp, si,
+                    cl.h2[si], cl.dtr[si])
+        s = c.summary()
+        _record("C3_all_ff_ipl2", s)
+        assert c.incomplete == 0 and c.list_mismatch == 0 and c.nnb_mismatch == 0
+        assert s["acc_scaled_max"] <= 1e-6 and s["jerk_scaled_max"] <= 1e-6, s
+        assert s.get("acc_rel_max", 0.0) <= 1e-6 and s.get("jerk_rel_max", 0.0) <= 1e-6, s
+    finally:
+        nb6.nb6_destroy(c2)
+
+
 @pytest.mark.parametrize("mode", ["ff", "fp64", "fp32"])
 @pytest.mark.parametrize("block", ["random4096", "all"])
 def test_config5_full_size_sampled(ctx, block, mode):
