@@ -248,6 +248,45 @@ def test_plain_calls_beside_the_queue(clusters):
         nb6.nb6_destroy(ctx)
 
 
+def test_mixed_coordinate_modes(clusters):
+    """Requests in all three coordinate modes fused into the same batches
+    (one persistent launch per mode and work-partition class): each equals,
+    bit for bit, the plain call in its mode at its block time."""
+    nb6 = _nb6()
+    ctx = nb6.nb6_create(0)
+    try:
+        _load_all(nb6, ctx, clusters)
+        modes = (nb6.NB6_DX_FF, nb6.NB6_DX_FP64, nb6.NB6_DX_FP32)
+        rng = np.random.Generator(np.random.PCG64(31))
+        reqs = []
+        for r in range(3):
+            for c, cl in enumerate(clusters):
+                ni = int(rng.choice([40, 700]))
+                idx = np.sort(rng.choice(cl.n, ni, replace=False)).astype(np.int32)
+                reqs.append((c, cl.tb + r * 2.0 ** -12, idx, modes[(r + c) % 3]))
+        subs = [_submit(nb6, ctx, clusters[c], c, tb, idx, 64, mode)
+                for c, tb, idx, mode in reqs]
+        fused = 0
+        for (t, h), (c, tb, idx, mode) in zip(subs, reqs):
+            rc, info = nb6.nb6_poll(ctx, t, wait=1)
+            assert rc in (nb6.NB6_OK, nb6.NB6_WARN_NB_OVERFLOW)
+            fused = max(fused, info["batch_size"])
+        for (t, h), (c, tb, idx, mode) in zip(subs, reqs):
+            cl = clusters[c]
+            nb6.check(ctx, nb6.nb6_predict_j(ctx, c, tb, mode))
+            acc, jerk, nnb, lst, _ = nb6.regular_force_host(ctx, c, idx, cl.h2[idx],
+                                                            cl.dtr[idx], mode, 64)
+            np.testing.assert_array_equal(acc, h.acc)
+            np.testing.assert_array_equal(jerk, h.jerk)
+            np.testing.assert_array_equal(nnb, h.nnb)
+            for q in range(len(idx)):
+                k = min(64, nnb[q])
+                np.testing.assert_array_equal(lst[q, :k], h.lst[q, :k])
+        assert fused > 1
+    finally:
+        nb6.nb6_destroy(ctx)
+
+
 def test_admission_by_budget(clusters):
     nb6 = _nb6()
     budget = 4 << 20
