@@ -25,6 +25,7 @@
 // A request's plan (make_plan: the rule of a plain call on the same context)
 // and its summation order depend only on the request, so its results are
 // bit-identical alone, in any mix, and to the plain call.
+#include "nb6_arena.h"
 #include "nb6_context.h"
 
 #include <algorithm>
@@ -63,62 +64,35 @@ struct BatchHeader {
 };
 constexpr size_t kHeaderBytes = align_up(sizeof(BatchHeader));
 
-// First-fit allocator over one device arena, coalescing on free.
+// The serving arena: one device allocation of the HBM budget, carved by
+// OffsetArena (first fit, coalescing on free).
 class Arena {
   public:
     int init(nb6_ctx* c, size_t bytes) {
-        size_ = bytes / kAlign * kAlign;
-        if (size_ == 0) return fail(c, NB6_ERR_ARG, "serving budget is zero");
-        if (hipMalloc(&base_, size_) != hipSuccess) {
+        const size_t size = bytes / kAlign * kAlign;
+        if (size == 0) return fail(c, NB6_ERR_ARG, "serving budget is zero");
+        if (hipMalloc(&base_, size) != hipSuccess) {
             (void)hipGetLastError();
             base_ = nullptr;
-            return fail(c, NB6_ERR_NOMEM, "serving arena of %zu bytes", size_);
+            return fail(c, NB6_ERR_NOMEM, "serving arena of %zu bytes", size);
         }
-        free_[0] = size_;
+        off_.reset(size);
         return NB6_OK;
     }
     void release() {
         if (base_) (void)hipFree(base_);
         base_ = nullptr;
-        free_.clear();
+        off_.reset(0);
     }
-    size_t size() const { return size_; }
-    size_t used() const { return used_; }
-    bool alloc(size_t bytes, size_t* off) {
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second < bytes) continue;
-            *off = it->first;
-            const size_t rest = it->second - bytes;
-            const size_t at = it->first + bytes;
-            free_.erase(it);
-            if (rest) free_[at] = rest;
-            used_ += bytes;
-            return true;
-        }
-        return false;
-    }
-    void free(size_t off, size_t bytes) {
-        used_ -= bytes;
-        auto it = free_.emplace(off, bytes).first;
-        auto nx = std::next(it);
-        if (nx != free_.end() && it->first + it->second == nx->first) {
-            it->second += nx->second;
-            free_.erase(nx);
-        }
-        if (it != free_.begin()) {
-            auto pv = std::prev(it);
-            if (pv->first + pv->second == it->first) {
-                pv->second += it->second;
-                free_.erase(it);
-            }
-        }
-    }
+    size_t size() const { return off_.size(); }
+    size_t used() const { return off_.used(); }
+    bool alloc(size_t bytes, size_t* off) { return off_.alloc(bytes, off); }
+    void free(size_t off, size_t bytes) { off_.free(off, bytes); }
     char* base() const { return static_cast<char*>(base_); }
 
   private:
     void* base_ = nullptr;
-    size_t size_ = 0, used_ = 0;
-    std::map<size_t, size_t> free_;  // offset -> bytes
+    OffsetArena off_;
 };
 
 struct ServeReq {
