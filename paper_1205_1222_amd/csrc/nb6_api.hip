@@ -72,64 +72,10 @@ int ensure_pinned(nb6_ctx* c, PinBuf& b, size_t bytes) {
     return NB6_OK;
 }
 
+static_assert(kPlanTile == VTILE, "slice lengths must be whole candidate-bound tiles");
+
 Plan make_plan(const nb6_ctx* c, int64_t n, int64_t ni, int ipl) {
-    Plan p;
-    // One i per lane unless asked for two: the one-i kernel holds 74 VGPRs
-    // against 106, hence more waves per SIMD, and measured faster at every
-    // block size from 512 to 2^20 active particles (at N = 2^17 and 2^20).
-    p.ipl = ipl > 0 ? ipl : c->ipl_hint > 0 ? c->ipl_hint : 1;
-    // Slices are at least 256 j-particles long, and give each lane at least
-    // 32 of them.
-    auto max_slices = [&](int sh) {
-        const int64_t len = std::max<int64_t>(256, (int64_t)32 << sh);
-        return std::max<int64_t>(1, (n + len - 1) / len);
-    };
-    auto groups_of = [&](int sh) {
-        const int g = regf_group_size(p.ipl, sh);
-        return (ni + g - 1) / g;
-    };
-    // Lanes per i.  A block of at most 256 is latency-bound, not
-    // throughput-bound: its i share the lanes of a wavefront (64 lanes per i
-    // up to 64 i, then 32 and 16), with slices sized to balance the force
-    // kernel's dependent j-loads (slice_len / lanes / 4 per lane) against
-    // the finalize kernel's dependent partial loads (slices / 32).
-    int sh = 0;
-    bool lanes_plan = false;
-    if (p.ipl == 1) {
-        if (c->jl_hint > 0) {
-            while ((1 << sh) < c->jl_hint) ++sh;
-        } else if (ni <= 256) {
-            sh = ni <= 64 ? 6 : ni <= 128 ? 5 : 4;
-            lanes_plan = true;
-        }
-    }
-    p.jl_shift = sh;
-    const int64_t groups = groups_of(sh);
-    p.wpb = (int)std::min<int64_t>(4, groups);
-    // About 64 waves per SIMD over the launch, and slices of at most 16384
-    // j: many rounds at the kernel's occupancy, so the last round's
-    // imbalance is a small part (measured optimum at N_i = 2^12 .. 2^20).
-    const int64_t target = (int64_t)c->num_cu * 4 * 64;
-    int64_t s = c->slice_hint > 0 ? c->slice_hint
-                                  : std::max((target + groups - 1) / groups, (n + 16383) / 16384);
-    if (lanes_plan && c->slice_hint <= 0) {
-        // measured optimum about sqrt(1.5 n / lanes), taken to a power of 2
-        const double best = std::sqrt(1.5 * (double)n / (double)(1 << sh));
-        s = (int64_t)1 << (int)std::lround(std::log2(std::max(1.0, best)));
-    }
-    s = std::max<int64_t>(1, std::min<int64_t>(s, c->slice_hint > 0 ? (n + 255) / 256
-                                                                   : max_slices(sh)));
-    s = std::min<int64_t>(s, 65535);
-    // a multiple of 8 lets the force kernel keep each slice on one XCD; the
-    // count is kept even when rounding the length up to whole tiles leaves
-    // the last slices empty (their partials are zero)
-    const bool xcd_split = c->slice_hint <= 0 && s >= 8;
-    if (xcd_split) s = s / 8 * 8;
-    int64_t len = (n + s - 1) / s;
-    len = (len + VTILE - 1) / VTILE * VTILE;
-    p.slice_len = (int)len;
-    p.nslices = xcd_split ? (int)s : (int)((n + len - 1) / len);
-    return p;
+    return plan_rule(PlanInputs{c->num_cu, c->ipl_hint, c->jl_hint, c->slice_hint}, n, ni, ipl);
 }
 
 }  // namespace nb6

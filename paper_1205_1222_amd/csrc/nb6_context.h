@@ -5,6 +5,7 @@
 
 #include "../../include/nb6.h"
 #include "nb6_internal.h"
+#include "nb6_plan.h"
 
 #include <algorithm>
 #include <atomic>
@@ -84,9 +85,6 @@ inline size_t rec_size(int mi) {
 }
 
 // Wave-level work partition of one force call.
-struct Plan {
-    int ipl, jl_shift, wpb, nslices, slice_len;
-};
 
 class Engine;  // serving queue (nb6_serve.hip)
 
