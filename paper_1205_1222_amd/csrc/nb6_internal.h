@@ -270,7 +270,6 @@ hipError_t launch_serve_prepare(const BatchArgs& b, int chunks, hipStream_t s);
 hipError_t launch_regf(int mode, int ipl, int waves_per_block, bool pot, const RegfArgs& a,
                        hipStream_t s);
 // i-particles of one work item (one wavefront) of the force kernel.
-// i-particles of one work item (the same rule as plan_group_size).
 __host__ __device__ inline int regf_group_size(int ipl, int jl_shift) { return (64 * ipl) >> jl_shift; }
 hipError_t launch_finalize(const FinalArgs& a, hipStream_t s);
 hipError_t launch_predict(const PredictArgs& a, hipStream_t s);
