@@ -159,32 +159,6 @@ int get_cluster(nb6_ctx* c, int cluster, ClusterState** out) {
     return NB6_OK;
 }
 
-// Row offsets of lists holding min(count, cap) entries per row.
-static std::vector<int64_t> row_offsets(const int32_t* count, int n, int cap) {
-    std::vector<int64_t> off((size_t)n + 1);
-    off[0] = 0;
-    for (int q = 0; q < n; ++q) off[q + 1] = off[q] + std::min(std::max(count[q], 0), cap);
-    return off;
-}
-
-// Row-major [n][cap] rows to a packed array (row q at off[q]), and back.
-static void pack_rows_host(const std::vector<int64_t>& off, int n, int cap,
-                           const int32_t* rows, int32_t* packed) {
-    for_rows(n, off[n], [&](int q0, int q1) {
-        for (int q = q0; q < q1; ++q) {
-            const int32_t* r = rows + (size_t)q * cap;
-            std::copy(r, r + (off[q + 1] - off[q]), packed + off[q]);
-        }
-    });
-}
-static void unpack_rows_host(const std::vector<int64_t>& off, int n, int cap,
-                             const int32_t* packed, int32_t* rows) {
-    for_rows(n, off[n], [&](int q0, int q1) {
-        for (int q = q0; q < q1; ++q)
-            std::copy(packed + off[q], packed + off[q + 1], rows + (size_t)q * cap);
-    });
-}
-
 }  // namespace
 
 extern "C" {

@@ -6,13 +6,13 @@
 #include "../../include/nb6.h"
 #include "nb6_internal.h"
 #include "nb6_plan.h"
+#include "nb6_rows.h"
 
 #include <algorithm>
 #include <atomic>
 #include <cstdint>
 #include <mutex>
 #include <string>
-#include <thread>
 #include <vector>
 
 namespace nb6 {
@@ -129,17 +129,6 @@ void engine_shutdown(nb6_ctx* c);
 // Tell the serving queue that a cluster was released by a plain call.
 void engine_kick(nb6_ctx* c);
 
-// body(q0, q1) over the rows [0, n) on up to 8 host threads (one per 2^18
-// entries moved): the host side of list copies.
-template <typename F>
-void for_rows(int n, int64_t entries, F body) {
-    const int nt = (int)std::min<int64_t>(8, std::max<int64_t>(1, entries >> 18));
-    std::vector<std::thread> helpers;
-    for (int t = 1; t < nt; ++t)
-        helpers.emplace_back(body, (int)((int64_t)n * t / nt), (int)((int64_t)n * (t + 1) / nt));
-    body(0, (int)((int64_t)n / nt));
-    for (auto& h : helpers) h.join();
-}
 
 #define HIP_TRY(ctx, call)                                                          \
     do {                                                                            \
