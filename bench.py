@@ -781,8 +781,9 @@ def main():
         sys.exit(subprocess.run([probe]).returncode)
 
     if args.gpus != 1:
-        print(f"bench.py: --gpus {args.gpus} is not supported: this build measures one "
-              "GPU only (the multi-GPU j-split is a design note, not code).", file=sys.stderr)
+        print(f"bench.py: --gpus {args.gpus} is not supported: the library runs on one GPU "
+              "(the multi-GPU j-split is described in the design notes, not implemented).",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
