@@ -698,16 +698,6 @@ def block_sweep(args, cfg, nb6, torch, T, lanes=0, slices=None, max_ni=None, max
         nb6.nb6_destroy(ctx)
 
 
-def plan_sweep(args, cfg, nb6, torch, T):
-    """Blocks of at most 4096 under forced (lanes per i, slices) plans, beside the
-    automatic plan, to tune the plan rule."""
-    block_sweep(args, cfg, nb6, torch, T, max_ni=4096, max_reps=60)
-    for lanes in (1, 4, 16, 64):
-        for slices in (32, 64, 128, 256, 512, 1024):
-            block_sweep(args, cfg, nb6, torch, T, lanes=lanes, slices=slices, max_ni=4096,
-                        max_reps=60)
-
-
 def traffic_config(args):
     """The configuration a traffic record belongs to."""
     return (f"config {args.config} block {args.block} mode {args.mode} cap {args.cap} "
@@ -743,11 +733,7 @@ def main():
                          "(~140 MB), below what the fused batches would hold unchecked")
     ap.add_argument("--block-sweep", action="store_true",
                     help="time every block of the configuration (per-size curve) and exit")
-    ap.add_argument("--plan-sweep", action="store_true",
-                    help="time blocks of <= 4096 under forced lane / slice plans and exit")
     ap.add_argument("--lanes", type=int, default=0, help="lanes per i-particle (0: auto)")
-    ap.add_argument("--isa-rates", action="store_true",
-                    help="only run the vector-instruction issue-rate probe and exit")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="run one device copy of this size first: the known-size kernel that "
                          "calibrates the FETCH_SIZE/WRITE_SIZE counters")
@@ -772,13 +758,6 @@ def main():
             f.write(text)
         print(text)
         return
-
-    if args.isa_rates:
-        import subprocess
-        probe = os.path.join(ROOT, "paper_1205_1222_amd", "isa_rates")
-        if not os.path.exists(probe):
-            sys.exit(f"{probe} is missing: run python -m paper_1205_1222_amd.build")
-        sys.exit(subprocess.run([probe]).returncode)
 
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} is not supported: the library runs on one GPU "
@@ -812,9 +791,6 @@ def main():
     T = lambda a, dt=torch.float64: torch.from_numpy(np.ascontiguousarray(a)).to(dev, dt)  # noqa: E731
     if args.block_sweep:
         block_sweep(args, cfg, nb6, torch, T, lanes=args.lanes)
-        return
-    if args.plan_sweep:
-        plan_sweep(args, cfg, nb6, torch, T)
         return
     m_d, x_d, v_d, a_d, j_d, t_d = (T(q) for q in (cl.m, cl.x, cl.v, cl.a, cl.jerk, cl.t))
     idx_d = T(idx_np, torch.int32)

@@ -143,7 +143,11 @@ int nb6_predict_j(nb6_ctx *ctx, int cluster, double t_block, int modes,
  *   m_j (V / r^3 - 3 (R.V) R / r^5) to jerk_i.
  * Inputs:  idx_i[n_i] (cluster indices, 0 <= idx_i < N), h2_i[n_i]
  *          (squared neighbour radii, > 0 and >= 2^-126 as floats),
- *          dtr_i[n_i] (regular time-steps), dx_mode (one NB6_DX_* value
+ *          dtr_i[n_i] (regular time-steps, finite and >= 0: the offset of
+ *          the criterion's second end point is forward in time; HOST mode
+ *          refuses others with NB6_ERR_ARG, DEVICE mode gives that i a NaN
+ *          row and nnb = -1 and nb6_sync_status reports
+ *          NB6_ERR_DEVICE_INPUT), dx_mode (one NB6_DX_* value
  *          whose stream holds the cluster's latest prediction: the block
  *          time of the last nb6_predict_j or served request on the cluster,
  *          whichever came last; a stream still at an earlier block time is
@@ -177,7 +181,8 @@ int nb6_regular_force(nb6_ctx *ctx, int cluster, int64_t n_i,
  * Wait for `stream` and return (and clear) the GPU-side validation state of
  * the context: NB6_OK, or NB6_ERR_DEVICE_INPUT when a DEVICE-mode call met
  * an out-of-range index, an h2 that is not a positive normal float, a
- * non-finite predicted coordinate, or an invalid neighbour list
+ * dtr that is negative or not finite, a non-finite predicted coordinate,
+ * or an invalid neighbour list
  * (nb6_set_lists).  Results of such a call are NaN for the offending i.
  */
 int nb6_sync_status(nb6_ctx *ctx, void *stream);

@@ -22,23 +22,6 @@ HIPCC_FLAGS = [
 ]
 
 
-RATES = os.path.join(HERE, "isa_rates")
-
-
-def build_rates(verbose: bool = False) -> str:
-    """The instruction-rate probe used for the force kernel's roofline."""
-    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    flags = [f for f in HIPCC_FLAGS if f not in ("-shared", "-fPIC")]
-    cmd = [hipcc, *flags, "-o", RATES, os.path.join(CSRC, "isa_rates.hip")]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed building isa_rates")
-    return RATES
-
-
 def build(verbose: bool = False) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     tmp = LIB + ".tmp"
@@ -55,4 +38,3 @@ def build(verbose: bool = False) -> str:
 
 if __name__ == "__main__":
     print(build(verbose=True))
-    print(build_rates(verbose=True))

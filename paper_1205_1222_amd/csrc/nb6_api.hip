@@ -295,6 +295,9 @@ int nb6_load_particles(nb6_ctx* c, int cluster, int64_t n, const double* m, cons
             return fail(c, NB6_ERR_ARG, "non-finite value in the particle state");
     }
     if (!idx) {  // full load
+        if (cl->n != n && cl->queued.load() > 0)
+            return fail(c, NB6_ERR_STATE,
+                        "cluster %d has serving requests queued; it cannot be resized", cluster);
         if (cl->n != n) {
             HIP_TRY(c, hipDeviceSynchronize());
             if (cl->state) HIP_TRY(c, hipFree(cl->state));
@@ -491,8 +494,9 @@ int nb6_regular_force(nb6_ctx* c, int cluster, int64_t n_i, const int32_t* idx_i
             if (!(h2f >= FLT_MIN) || !(h2f <= FLT_MAX))
                 return fail(c, NB6_ERR_ARG, "h2_i[%d] = %g is not a positive normal float", q,
                             h2_i[q]);
-            if (!std::isfinite(dtr_i[q]))
-                return fail(c, NB6_ERR_ARG, "dtr_i[%d] is not finite", q);
+            if (!valid_dtr(dtr_i[q]))
+                return fail(c, NB6_ERR_ARG, "dtr_i[%d] = %g is not a finite value >= 0", q,
+                            dtr_i[q]);
         }
         // inputs go up in one copy from the pinned buffer; the outputs (and
         // lists up to kStageListMax bytes) come back in one copy into it
@@ -616,7 +620,7 @@ int nb6_regular_force(nb6_ctx* c, int cluster, int64_t n_i, const int32_t* idx_i
     if (cap > 0 && !hs.list_staged) {
         if (int rc = copy_lists_out(c, d_list, nnb, ni, cap, list, st)) return rc;
     }
-    if (status[0] & (ST_BAD_INDEX | ST_BAD_H2 | ST_NONFINITE))
+    if (status[0] & (ST_BAD_INDEX | ST_BAD_H2 | ST_NONFINITE | ST_BAD_DTR))
         return fail(c, NB6_ERR_DEVICE_INPUT, "GPU validation flagged 0x%x", status[0]);
     for (int q = 0; q < ni; ++q)
         if (nnb[q] > cap) return NB6_WARN_NB_OVERFLOW;
@@ -956,7 +960,7 @@ int nb6_sync_status(nb6_ctx* c, void* stream) {
     HIP_TRY(c, hipStreamSynchronize(st));
     HIP_TRY(c, launch_zero_u32(c->status, 4, st));
     HIP_TRY(c, hipStreamSynchronize(st));
-    if (status[0] & (ST_BAD_INDEX | ST_BAD_H2 | ST_NONFINITE | ST_BAD_LIST | ST_BAD_STEP))
+    if (status[0] & ST_INPUT_ERRORS)
         return fail(c, NB6_ERR_DEVICE_INPUT, "GPU validation flagged 0x%x", status[0]);
     return NB6_OK;
 }

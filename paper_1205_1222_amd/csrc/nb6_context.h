@@ -61,6 +61,10 @@ struct ClusterState {
     // Owner of the cluster: 0 free, 1 a serving request in flight, -1 a plain
     // call in progress.  Claimed with compare-and-swap from 0.
     std::atomic<int> owner{0};
+    // Serving requests submitted on this cluster and not yet finished.  A
+    // full load that would resize the cluster (and so free the buffers those
+    // requests were sized and will be launched with) is refused meanwhile.
+    std::atomic<int> queued{0};
     // Last stream work of each side on this cluster; the other side's stream
     // waits for it before touching the cluster (created on first use).
     hipEvent_t last_plain = nullptr;

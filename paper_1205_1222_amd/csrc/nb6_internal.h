@@ -42,8 +42,17 @@ __host__ __device__ inline long long vtiles(long long n) { return (n + VTILE - 1
 // Bits of the device status word.
 enum StatusBits {
     ST_BAD_INDEX = 1, ST_BAD_H2 = 2, ST_NONFINITE = 4, ST_OVERFLOW = 8, ST_BAD_LIST = 16,
-    ST_BAD_STEP = 32
+    ST_BAD_STEP = 32, ST_BAD_DTR = 64
 };
+// Bits that mark an input a call could not use (the caller's error).
+constexpr unsigned ST_INPUT_ERRORS =
+    ST_BAD_INDEX | ST_BAD_H2 | ST_NONFINITE | ST_BAD_LIST | ST_BAD_STEP | ST_BAD_DTR;
+
+// The regular time-step of an active particle offsets the second end point
+// of the velocity criterion forward in time (section 3.2), so it must be
+// finite and >= 0: the candidate radius of the force kernels, which keeps the
+// criterion off the common path, is a valid bound only then.
+__host__ __device__ inline bool valid_dtr(double dtr) { return dtr >= 0.0 && dtr <= 1.79e308; }
 
 // Cubic Taylor prediction of one coordinate in FP64 Horner form with explicit
 // fused multiply-adds (section 3.3 step 3): h = dt/2, t3 = dt/3,

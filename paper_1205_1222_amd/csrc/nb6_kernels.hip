@@ -224,15 +224,18 @@ __device__ __forceinline__ int load_i(const RegfArgs& a, const int q, const int 
     bool live = q < a.ni;
     int pi = live ? a.idx[q] : 0;
     float h2f = live ? checked_h2(a.h2[q]) : -1.0f;
-    const float dtf = live ? (float)a.dtr[q] : 0.0f;
+    const double dtr = live ? a.dtr[q] : 0.0;
+    float dtf = (float)dtr;
     if (live) {
         unsigned bad = 0;
         if (pi < 0 || pi >= a.n) bad |= ST_BAD_INDEX;
         if (h2f < 0.0f) bad |= ST_BAD_H2;
+        if (!valid_dtr(dtr)) bad |= ST_BAD_DTR;
         if (bad) {
             if (s == 0) atomicOr(a.status, bad);
             pi = 0;
             h2f = -1.0f;
+            dtf = 0.0f;
             live = false;
         }
     }
@@ -462,7 +465,7 @@ __device__ __forceinline__ void wave_sync() {
 
 __device__ __forceinline__ bool invalid_i(const FinalArgs& a, int q) {
     const int32_t self = a.idx[q];
-    return self < 0 || self >= a.n || checked_h2(a.h2[q]) < 0.0f;
+    return self < 0 || self >= a.n || checked_h2(a.h2[q]) < 0.0f || !valid_dtr(a.dtr[q]);
 }
 
 // LDS of the finalize kernels: the four waves' slice sums of one component,
@@ -629,7 +632,7 @@ __device__ __forceinline__ void finalize_block(const FinalArgs& a, const int blk
         const float h2f = live[k] ? checked_h2(a.h2[q]) : -1.0f;
         count[k] = live[k] ? a.cnt[q] : 0;
         first[k] = live[k] && lane < a.caps ? a.lst[(size_t)q * a.caps + lane] : 0;
-        ok[k] = live[k] && self[k] >= 0 && self[k] < a.n && h2f >= 0.0f;
+        ok[k] = live[k] && self[k] >= 0 && self[k] < a.n && h2f >= 0.0f && valid_dtr(a.dtr[q]);
     }
     // the count is read: reset it for the next call, and store the number of
     // neighbours (the i itself is among the found; -1 marks an invalid i)

@@ -102,6 +102,7 @@ struct ServeReq {
     Plan plan{};
     size_t bytes = 0, off = 0;
     ClusterState* cl = nullptr;
+    int64_t n_submit = 0;   // cluster size the request was checked and sized against
     int status = NB6_PENDING;
     int batch_size = 0;
     size_t stage = 0;       // HOST requests: offset of its region in the slot's pinned staging
@@ -215,6 +216,7 @@ class Engine {
             for (ServeReq* r : pending_) {
                 r->status = NB6_ERR_STATE;
                 r->t_done = now();
+                r->cl->queued.fetch_sub(1);
             }
             pending_.clear();
             cv_sched_.notify_all();
@@ -277,8 +279,9 @@ class Engine {
                     if (!(h2f >= 1.17549435e-38f) || !(h2f <= 3.40282347e38f))
                         return fail(c_, NB6_ERR_ARG, "h2_i[%lld] is not a positive normal float",
                                     (long long)q);
-                    if (!std::isfinite(rq->dtr_i[q]))
-                        return fail(c_, NB6_ERR_ARG, "dtr_i[%lld] is not finite", (long long)q);
+                    if (!valid_dtr(rq->dtr_i[q]))
+                        return fail(c_, NB6_ERR_ARG, "dtr_i[%lld] is not a finite value >= 0",
+                                    (long long)q);
                 }
             }
             // the record stream of this mode is allocated once, here; requests
@@ -292,13 +295,19 @@ class Engine {
                     return rc;
             }
             r->plan = make_plan(c_, r->cl->n, ni);
+            r->n_submit = r->cl->n;
+            // held until the request finishes: the cluster keeps its size and
+            // buffers meanwhile
+            r->cl->queued.fetch_add(1);
         }
         r->bytes = carve(r.get(), nullptr);
         std::unique_lock<std::mutex> lk(mu_);
-        if (r->bytes > arena_.size())
+        if (r->bytes > arena_.size()) {
+            r->cl->queued.fetch_sub(1);
             return fail(c_, NB6_ERR_ADMISSION,
                         "request needs %zu bytes of scratch; the serving budget is %zu",
                         r->bytes, arena_.size());
+        }
         r->ticket = next_ticket_++;
         r->t_submit = now();
         *ticket = r->ticket;
@@ -364,6 +373,15 @@ class Engine {
         r->t_done = t;
         arena_.free(r->off, r->bytes);
         r->cl->owner.store(0);
+        r->cl->queued.fetch_sub(1);
+    }
+
+    // The buffers a request was sized against are still those of its
+    // cluster (a resize is refused while it is queued; this is the check
+    // that no descriptor is built from anything else).
+    static bool cluster_intact(const ServeReq* r) {
+        const ClusterState* cl = r->cl;
+        return cl->n == r->n_submit && cl->state && cl->rec[r->mi].p && cl->tmax.p;
     }
 
     void sched_loop() {
@@ -390,6 +408,15 @@ class Engine {
                 int free_owner = 0;  // one request per cluster, no plain call on it
                 if (!r->cl->owner.compare_exchange_strong(free_owner, 1)) {
                     ++it;
+                    continue;
+                }
+                if (!cluster_intact(r)) {  // never launched: fails on its own
+                    it = pending_.erase(it);
+                    r->status = NB6_ERR_STATE;
+                    r->t_done = now();
+                    r->cl->owner.store(0);
+                    r->cl->queued.fetch_sub(1);
+                    cv_polled_.notify_all();
                     continue;
                 }
                 size_t off;
@@ -511,7 +538,7 @@ class Engine {
             int st = NB6_OK;
             if (err != hipSuccess)
                 st = NB6_ERR_HIP;
-            else if (status[b] & (ST_BAD_INDEX | ST_BAD_H2 | ST_NONFINITE))
+            else if (status[b] & (ST_BAD_INDEX | ST_BAD_H2 | ST_NONFINITE | ST_BAD_DTR))
                 st = NB6_ERR_DEVICE_INPUT;
             else if (status[b] & ST_OVERFLOW)
                 st = NB6_WARN_NB_OVERFLOW;

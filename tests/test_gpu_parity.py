@@ -270,6 +270,11 @@ def test_errors(ctx):
     h2b = h2.copy()
     h2b[2] = 0.0
     assert nb6.nb6_regular_force(ctx, 0, 3, idx, h2b, dtr, 1, *out, 8) == nb6.NB6_ERR_ARG
+    # the criterion's time offset is forward: a negative or non-finite dtr is refused
+    for bad_dtr in (-2.0 ** -8, np.nan, np.inf):
+        dtrb = dtr.copy()
+        dtrb[1] = bad_dtr
+        assert nb6.nb6_regular_force(ctx, 0, 3, idx, h2, dtrb, 1, *out, 8) == nb6.NB6_ERR_ARG
     assert nb6.nb6_regular_force(ctx, 0, 3, idx, h2, dtr, 3, *out, 8) == nb6.NB6_ERR_ARG
     assert nb6.nb6_regular_force(ctx, 0, 3, idx, h2, dtr, 1, *out, -1) == nb6.NB6_ERR_ARG
     assert nb6.nb6_regular_force(ctx, 7, 3, idx, h2, dtr, 1, *out, 8) == nb6.NB6_ERR_STATE
@@ -306,6 +311,16 @@ def test_errors(ctx):
                                          lst, 8, nb6.NB6_MEM_DEVICE, s))
     assert nb6.nb6_sync_status(ctx, s) == nb6.NB6_ERR_DEVICE_INPUT
     assert nb6.nb6_sync_status(ctx, s) == nb6.NB6_OK  # cleared
+    a = acc.cpu().numpy()
+    assert np.all(np.isfinite(a[0])) and np.all(np.isnan(a[1])) and np.all(np.isnan(a[2]))
+    assert list(nnb.cpu().numpy()[1:]) == [-1, -1]
+    # a negative or NaN dtr found on the device: NaN rows, nnb = -1, status
+    t_idx = torch.tensor(idx, dtype=torch.int32, device=dev)
+    t_h2 = torch.tensor(h2, dtype=torch.float64, device=dev)
+    t_dtr = torch.tensor([dtr[0], -dtr[1], np.nan], dtype=torch.float64, device=dev)
+    nb6.check(ctx, nb6.nb6_regular_force(ctx, 0, 3, t_idx, t_h2, t_dtr, 1, acc, jerk, nnb,
+                                         lst, 8, nb6.NB6_MEM_DEVICE, s))
+    assert nb6.nb6_sync_status(ctx, s) == nb6.NB6_ERR_DEVICE_INPUT
     a = acc.cpu().numpy()
     assert np.all(np.isfinite(a[0])) and np.all(np.isnan(a[1])) and np.all(np.isnan(a[2]))
     assert list(nnb.cpu().numpy()[1:]) == [-1, -1]

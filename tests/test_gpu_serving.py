@@ -370,3 +370,56 @@ def test_device_mode_serving(clusters):
         np.testing.assert_array_equal(nnb.cpu().numpy(), h.nnb)
     finally:
         nb6.nb6_destroy(ctx)
+
+
+def test_resize_refused_while_requests_are_queued(clusters):
+    """A full load that would resize a cluster is refused while requests on
+    it are queued or running, so no request is launched with buffers sized
+    for another N.  Whichever way the race between the reload and the queue
+    goes, every request ends with the results of the state it was submitted
+    against, and the reload succeeds once the queue has drained."""
+    nb6 = _nb6()
+    ctx = nb6.nb6_create(0)
+    try:
+        _load_all(nb6, ctx, clusters)
+        cl = clusters[3]
+        idx = np.arange(cl.n, dtype=np.int32)
+        subs = [_submit(nb6, ctx, cl, 3, cl.tb, idx, 64) for _ in range(4)]
+        small = make_cluster(1500, 77, masses="equal", k_nb=16)
+        rc = nb6.nb6_load_particles(ctx, 3, small.n, small.m, small.x, small.v, small.a,
+                                    small.jerk, small.t)
+        refused = rc == nb6.NB6_ERR_STATE
+        assert rc in (nb6.NB6_OK, nb6.NB6_ERR_STATE), rc
+        done = {}
+        if not refused:  # accepted only after every request had finished
+            for t, _ in subs:
+                done[t] = nb6.nb6_poll(ctx, t, wait=0)[0]  # a final status releases t
+                assert done[t] != nb6.NB6_PENDING
+        first = None
+        for t, h in subs:
+            rc = done[t] if t in done else nb6.nb6_poll(ctx, t, wait=1)[0]
+            assert rc in (nb6.NB6_OK, nb6.NB6_WARN_NB_OVERFLOW), rc
+            if first is None:
+                first = h
+            np.testing.assert_array_equal(h.acc, first.acc)
+            np.testing.assert_array_equal(h.nnb, first.nnb)
+        xp, vp = oracle.predict(cl.x, cl.v, cl.a, cl.jerk, cl.t, cl.tb)
+        si = idx[::97]
+        ref = oracle.regular_force(cl.m, xp, vp, si, cl.h2[si], cl.dtr[si], lcap=4096)
+        c = compare(first.acc[si], first.jerk[si], first.nnb[si], first.lst[si], 64, ref,
+                    cl.m, xp, vp, si, cl.h2[si], cl.dtr[si])
+        assert c.list_mismatch == 0 and c.summary()["acc_scaled_max"] <= 1e-6, c.summary()
+        print("reload refused while queued:", refused, flush=True)
+        # the queue has drained: the resize is accepted and the cluster works
+        nb6.check(ctx, nb6.nb6_load_particles(ctx, 3, small.n, small.m, small.x, small.v,
+                                              small.a, small.jerk, small.t))
+        si = np.arange(0, small.n, 3, dtype=np.int32)
+        t, h = _submit(nb6, ctx, small, 3, small.tb, si, 64)
+        assert nb6.nb6_poll(ctx, t, wait=1)[0] in (nb6.NB6_OK, nb6.NB6_WARN_NB_OVERFLOW)
+        xp, vp = oracle.predict(small.x, small.v, small.a, small.jerk, small.t, small.tb)
+        ref = oracle.regular_force(small.m, xp, vp, si, small.h2[si], small.dtr[si], lcap=4096)
+        c = compare(h.acc, h.jerk, h.nnb, h.lst, 64, ref, small.m, xp, vp, si, small.h2[si],
+                    small.dtr[si])
+        assert c.list_mismatch == 0 and c.summary()["acc_scaled_max"] <= 1e-6, c.summary()
+    finally:
+        nb6.nb6_destroy(ctx)
