@@ -56,6 +56,8 @@ def pin_golden_forces(lib=None):
         if c["jerk"] != "skip":
             assert _close(r.jerk, c["jerk"], 1e-14), (c["name"], r.jerk, c["jerk"])
         assert _close(r.pot, c["pot"], 1e-14), (c["name"], r.pot, c["pot"])
+        assert _close(r.sa, c["sa"], 1e-14), (c["name"], r.sa, c["sa"])
+        assert _close(r.sj, c["sj"], 1e-14), (c["name"], r.sj, c["sj"])
         got = [list(map(int, l)) for l in r.lists]
         assert got == c["lists"], (c["name"], got, c["lists"])
         assert list(map(int, r.nnb)) == [len(l) for l in c["lists"]], c["name"]

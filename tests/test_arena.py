@@ -10,6 +10,11 @@ import pytest
 
 from paper_1205_1222_amd import build
 
+# The host logic runs under AddressSanitizer and UBSan: any invalid access,
+# leak or undefined operation ends the driver with a report.
+SANITIZE = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+            "-fno-omit-frame-pointer", "-g"]
+
 DRIVER = r"""
 #include "nb6_arena.h"
 #include <cstdio>
@@ -81,7 +86,7 @@ def test_arena_first_fit_and_coalescing(tmp_path):
     src = tmp_path / "arena_driver.cpp"
     src.write_text(DRIVER)
     exe = tmp_path / "arena_driver"
-    r = subprocess.run([gxx, "-O1", "-std=c++17", "-I", build.CSRC, str(src), "-o", str(exe)],
+    r = subprocess.run([gxx, *SANITIZE, "-O1", "-std=c++17", "-I", build.CSRC, str(src), "-o", str(exe)],
                        capture_output=True, text=True)
     assert r.returncode == 0, r.stderr[-2000:]
     r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)

@@ -41,6 +41,18 @@ MUTANTS = {
     "pair_terms_jerk_sign": ("djrk[3 * p + c] = m[j] * (V[c] / r3 - 3.0 * rv * R[c] / r5);",
                              "djrk[3 * p + c] = m[j] * (V[c] / r3 + 3.0 * rv * R[c] / r5);"),
     "pair_terms_rmin_max": ("rmin[p] = sqrt((p2 < r2) ? p2 : r2);", "rmin[p] = sqrt((p2 < r2) ? r2 : p2);"),
+    # the scale sums every error bar divides by
+    "scale_sa_power": ("nsum_add(&SA, m[j] / r2);", "nsum_add(&SA, m[j] / r3);"),
+    "scale_sa_mass_of_i": ("nsum_add(&SA, m[j] / r2);", "nsum_add(&SA, m[i] / r2);"),
+    "scale_sj_factor": ("nsum_add(&SJ, m[j] * (vabs / r3 + 3.0 * fabs(rv) / (r2 * r2)));",
+                        "nsum_add(&SJ, m[j] * (vabs / r3 + fabs(rv) / (r2 * r2)));"),
+    "scale_sj_power": ("nsum_add(&SJ, m[j] * (vabs / r3 + 3.0 * fabs(rv) / (r2 * r2)));",
+                       "nsum_add(&SJ, m[j] * (vabs / r2 + 3.0 * fabs(rv) / (r2 * r2)));"),
+    "scale_sj_signed_rv": ("nsum_add(&SJ, m[j] * (vabs / r3 + 3.0 * fabs(rv) / (r2 * r2)));",
+                           "nsum_add(&SJ, m[j] * (vabs / r3 + 3.0 * rv / (r2 * r2)));"),
+    "irr_scale_sa_power": ("nsum_add(&SA, mj / d2);", "nsum_add(&SA, mj / d3);"),
+    "irr_scale_sj_factor": ("nsum_add(&SJ, mj * (vabs / d3 + 3.0 * fabs(rdotv) / (d2 * d2)));",
+                            "nsum_add(&SJ, mj * (vabs / d3 + fabs(rdotv) / (d2 * d2)));"),
     # regular corrector
     "corr_no_list_correction": ("const double dF = (f_new[k] - f_old[k]) + (g_new[k] - g_old[k]);",
                                 "const double dF = (f_new[k] - f_old[k]);"),

@@ -9,6 +9,11 @@ import pytest
 
 from paper_1205_1222_amd import build
 
+# The host logic runs under AddressSanitizer and UBSan: any invalid access,
+# leak or undefined operation ends the driver with a report.
+SANITIZE = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+            "-fno-omit-frame-pointer", "-g"]
+
 DRIVER = r"""
 #include "nb6_rows.h"
 #include <cstdio>
@@ -60,7 +65,7 @@ def test_row_offsets_and_round_trip(tmp_path):
     src = tmp_path / "rows_driver.cpp"
     src.write_text(DRIVER)
     exe = tmp_path / "rows_driver"
-    r = subprocess.run([gxx, "-O1", "-std=c++17", "-pthread", "-I", build.CSRC, str(src),
+    r = subprocess.run([gxx, *SANITIZE, "-O1", "-std=c++17", "-pthread", "-I", build.CSRC, str(src),
                         "-o", str(exe)], capture_output=True, text=True)
     assert r.returncode == 0, r.stderr[-2000:]
     r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
