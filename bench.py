@@ -47,7 +47,7 @@ sys.path.insert(0, ROOT)
 
 FLOP_PER_INTERACTION = 53
 FP32_PEAK_TFLOPS = 157.3          # 256 CU x 2.4 GHz x 256 FLOP/clk
-MODES = {"ff": 1, "fp64": 2, "fp32": 4}
+MODES = {"ff": 1, "fp64": 2, "fp32": 4, "local": 8}
 
 
 # Counter figures of the force kernel (HBM traffic, FP32 VALU instruction
@@ -709,7 +709,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--mode", default="ff", choices=sorted(MODES))
+    ap.add_argument("--mode", default="local", choices=sorted(MODES))
     ap.add_argument("--config", type=int, default=3, choices=[1, 2, 3, 5])
     ap.add_argument("--block", default="all")
     ap.add_argument("--cap", type=int, default=256)

@@ -60,10 +60,25 @@ extern "C" {
  * 'two-float' form as an option (section 3.4 and its footnote); GPUIRR always
  * uses two-float coordinates (section 3.5).
  */
-#define NB6_DX_FF    1   /* float-float (hi + lo) coordinates, default   */
+#define NB6_DX_FF    1   /* float-float (hi + lo) coordinates             */
 #define NB6_DX_FP64  2   /* double coordinates, difference in FP64       */
 #define NB6_DX_FP32  4   /* plain float coordinates (the paper's default) */
-#define NB6_DX_ALL   7
+#define NB6_DX_LOCAL 8   /* tile-local coordinates (below), the fastest form
+                            that keeps the float-float accuracy            */
+#define NB6_DX_ALL   15
+/*
+ * NB6_DX_LOCAL: the j-records follow a spatial (Morton) order of the
+ * cluster, and each tile of 32 consecutive records carries the FP64 centre
+ * of its predicted positions; a record holds its particle's offset from that
+ * centre rounded to FP32.  R_j - R_i is formed as that offset plus the FP32
+ * rounding of (centre - R_i), computed in FP64 once per tile and i.  The
+ * error of a pair is about 2^-24 (|R_ij| + tile extent): the large
+ * coordinates cancel in FP64, and only quantities of the pair's own scale
+ * are rounded.  The order is rebuilt from the stored state by
+ * nb6_load_particles after a full load and after a cluster's worth of subset
+ * updates (it only sets how compact the tiles are, never which pairs are
+ * summed).
+ */
 
 /* Largest neighbour-list capacity of nb6_regular_force. */
 #define NB6_MAX_CAP  1023
@@ -114,7 +129,10 @@ const char *nb6_last_error(const nb6_ctx *ctx);
  *   idx != NULL: update n existing particles; entry k of every array
  *                belongs to particle idx[k].  0 <= idx[k] < cluster size.
  * The cluster must be predicted again (nb6_predict_j) before the next force
- * call.  Errors: NB6_ERR_ARG (n <= 0, bad idx, non-finite host data),
+ * call.  A full load, and the update that brings the particles updated since
+ * the last ordering to the cluster size, also rebuild the cluster's spatial
+ * order (NB6_DX_LOCAL) from the stored positions, on the same stream.
+ * Errors: NB6_ERR_ARG (n <= 0, bad idx, non-finite host data),
  * NB6_ERR_NOMEM, NB6_ERR_HIP.
  */
 int nb6_load_particles(nb6_ctx *ctx, int cluster, int64_t n,
@@ -128,8 +146,10 @@ int nb6_load_particles(nb6_ctx *ctx, int cluster, int64_t n,
  *   dt = t_block - t_j;  x_p = x + v dt + a dt^2/2 + jerk dt^3/6;
  *   v_p = v + a dt + jerk dt^2/2     (FP64),
  * and write the j-streams the force kernel reads for every coordinate mode
- * in the bit mask `modes` (NB6_DX_*; 0 means all).  Errors: NB6_ERR_STATE
- * (cluster not loaded), NB6_ERR_ARG, NB6_ERR_HIP.
+ * in the bit mask `modes` (NB6_DX_*; 0 means all).  NB6_DX_LOCAL also
+ * writes the FP64 prediction of every particle (the i-side of that mode),
+ * but marks only its own stream current.  Errors: NB6_ERR_STATE (cluster
+ * not loaded), NB6_ERR_ARG, NB6_ERR_HIP.
  */
 int nb6_predict_j(nb6_ctx *ctx, int cluster, double t_block, int modes,
                   void *stream);
@@ -190,7 +210,8 @@ int nb6_sync_status(nb6_ctx *ctx, void *stream);
 /*
  * Read back the predicted positions and velocities of every particle of the
  * cluster as the j-stream of `dx_mode` holds them (NB6_DX_FF: hi + lo,
- * NB6_DX_FP64: the FP64 prediction, NB6_DX_FP32: the float), widened to
+ * NB6_DX_FP64 and NB6_DX_LOCAL: the FP64 prediction, NB6_DX_FP32: the
+ * float), widened to
  * double: x[N][3], v[N][3].  For checks of the predictor (section 3.3 step 3)
  * and for callers that want the predicted state.  Errors: NB6_ERR_STATE when
  * that stream is not current, NB6_ERR_ARG, NB6_ERR_NOMEM, NB6_ERR_HIP.
@@ -320,7 +341,7 @@ int nb6_regular_correct(nb6_ctx *ctx, const nb6_corr_block *blk,
 typedef struct nb6_request {
     int            cluster;
     double         t_block;
-    int            dx_mode;     /* NB6_DX_FF, NB6_DX_FP64 or NB6_DX_FP32 */
+    int            dx_mode;     /* one NB6_DX_* value                    */
     int64_t        n_i;
     const int32_t *idx_i;
     const double  *h2_i;

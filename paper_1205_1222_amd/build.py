@@ -12,7 +12,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libnb6.so")
-SOURCES = ["nb6_api.hip", "nb6_kernels.hip", "nb6_irr.hip", "nb6_corr.hip", "nb6_serve.hip"]
+SOURCES = ["nb6_api.hip", "nb6_kernels.hip", "nb6_order.hip", "nb6_irr.hip", "nb6_corr.hip",
+           "nb6_serve.hip"]
 ARCH = os.environ.get("NB6_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

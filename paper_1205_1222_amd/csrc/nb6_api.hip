@@ -220,12 +220,13 @@ int nb6_destroy(nb6_ctx* c) {
         if (!cl) continue;
         if (cl->state) (void)hipFree(cl->state);
         for (auto& r : cl->rec) release(r);
-        for (DevBuf* b : {&cl->tmax, &cl->nbl, &cl->nbc}) release(*b);
+        for (DevBuf* b : {&cl->tmax, &cl->org, &cl->perm, &cl->inv, &cl->nbl, &cl->nbc})
+            release(*b);
         if (cl->last_plain) (void)hipEventDestroy(cl->last_plain);
         if (cl->last_served) (void)hipEventDestroy(cl->last_served);
         delete cl;
     }
-    for (DevBuf* b : {&c->part, &c->cnt, &c->lst, &c->io, &c->out_list})
+    for (DevBuf* b : {&c->part, &c->cnt, &c->lst, &c->io, &c->out_list, &c->order_tmp})
         release(*b);
     if (c->pin.p) (void)hipHostFree(c->pin.p);
     for (auto& b : c->ld) release(b);
@@ -270,6 +271,22 @@ int nb6_last_plan(const nb6_ctx* c, int out[4]) {
     return NB6_OK;
 }
 
+// Spatial order of the cluster's particles (the local-coordinate stream's
+// record order) from its stored positions, on stream st.
+static int build_order(nb6_ctx* c, ClusterState* cl, hipStream_t st) {
+    const size_t n = (size_t)cl->n;
+    int rc;
+    if ((rc = ensure(c, cl->perm, n * sizeof(int32_t))) ||
+        (rc = ensure(c, cl->inv, n * sizeof(int32_t))) ||
+        (rc = ensure(c, c->order_tmp, order_scratch_bytes(cl->n))))
+        return rc;
+    HIP_TRY(c, launch_order(cl->state, cl->n, c->order_tmp.p, c->order_tmp.cap,
+                            (int32_t*)cl->perm.p, (int32_t*)cl->inv.p, st));
+    cl->order_valid = true;
+    cl->updated_since_order = 0;
+    return NB6_OK;
+}
+
 int nb6_load_particles(nb6_ctx* c, int cluster, int64_t n, const double* m, const double* x,
                        const double* v, const double* a, const double* jerk, const double* t,
                        const int32_t* idx, int mem_kind, void* stream) {
@@ -306,8 +323,10 @@ int nb6_load_particles(nb6_ctx* c, int cluster, int64_t n, const double* m, cons
             // the predicted records and stored lists are sized by n:
             // reallocated on next use
             for (DevBuf& b : cl->rec) release(b);
-            for (DevBuf* b : {&cl->tmax, &cl->nbl, &cl->nbc}) release(*b);
+            for (DevBuf* b : {&cl->tmax, &cl->org, &cl->perm, &cl->inv, &cl->nbl, &cl->nbc})
+                release(*b);
             cl->lcap = 0;
+            cl->order_valid = false;
             if (hipMalloc(&cl->state, (size_t)n * sizeof(StateRec)) != hipSuccess) {
                 (void)hipGetLastError();
                 cl->state = nullptr;
@@ -372,6 +391,14 @@ int nb6_load_particles(nb6_ctx* c, int cluster, int64_t n, const double* m, cons
     HIP_TRY(c, launch_scatter(sa, st));
     // a full load starts every stored neighbour list empty
     if (!idx && cl->nbc.p) HIP_TRY(c, launch_zero_u32((unsigned*)cl->nbc.p, (int)n, st));
+    // the spatial order of the local-coordinate stream: rebuilt from the
+    // stored state after a full load and once the subset updates since the
+    // last build have touched as many particles as the cluster holds
+    cl->updated_since_order = idx ? cl->updated_since_order + n : cl->n;
+    if (!idx) cl->order_valid = false;
+    if (!cl->order_valid || cl->updated_since_order >= cl->n) {
+        if (int rc = build_order(c, cl, st)) return rc;
+    }
     if (mem_kind == NB6_MEM_HOST) HIP_TRY(c, hipStreamSynchronize(st));
     cl->pred_valid = 0;
     return NB6_OK;
@@ -394,19 +421,36 @@ int nb6_predict_j(nb6_ctx* c, int cluster, double t_block, int modes, void* stre
     pa.st = cl->state;
     pa.tb = t_block;
     pa.status = c->status;
-    const int bits[3] = {NB6_DX_FF, NB6_DX_FP64, NB6_DX_FP32};
-    for (int mi = 0; mi < 3; ++mi) {
-        if (!(modes & bits[mi])) continue;
+    const int bits[NMODES] = {NB6_DX_FF, NB6_DX_FP64, NB6_DX_FP32, NB6_DX_LOCAL};
+    const bool loc = (modes & NB6_DX_LOCAL) != 0;
+    for (int mi = 0; mi < NMODES; ++mi) {
+        if (!(modes & bits[mi]) && !(loc && mi == MODE_F64)) continue;
         int rc = ensure(c, cl->rec[mi], (size_t)cl->n * rec_size(mi));
         if (rc) return rc;
     }
     if (int rc = ensure(c, cl->tmax, (size_t)vtiles(cl->n) * sizeof(float))) return rc;
+    if (loc) {
+        if (!cl->order_valid)
+            return fail(c, NB6_ERR_STATE, "cluster %d has no spatial order", cluster);
+        if (int rc = ensure(c, cl->org, (size_t)vtiles(cl->n) * sizeof(TileOrg))) return rc;
+    }
     pa.tmax = (float*)cl->tmax.p;
     pa.ff = (modes & NB6_DX_FF) ? (RecFF*)cl->rec[MODE_FF].p : nullptr;
     pa.f64 = (modes & NB6_DX_FP64) ? (RecF64*)cl->rec[MODE_F64].p : nullptr;
     pa.f32 = (modes & NB6_DX_FP32) ? (RecF32*)cl->rec[MODE_F32].p : nullptr;
     TimedLaunch tl(c, 0, (hipStream_t)stream);
-    HIP_TRY(c, launch_predict(pa, (hipStream_t)stream));
+    if (pa.ff || pa.f64 || pa.f32) HIP_TRY(c, launch_predict(pa, (hipStream_t)stream));
+    if (loc) {
+        // the local stream, and the FP64 prediction by index as its i-side
+        PredictArgs pl = pa;
+        pl.ff = nullptr;
+        pl.f32 = nullptr;
+        pl.f64 = (RecF64*)cl->rec[MODE_F64].p;
+        pl.loc = (RecLoc*)cl->rec[MODE_LOC].p;
+        pl.org = (TileOrg*)cl->org.p;
+        pl.perm = (const int32_t*)cl->perm.p;
+        HIP_TRY(c, launch_predict_loc(pl, (hipStream_t)stream));
+    }
     tl.done();
     // records of other modes predicted to this same block time stay current
     cl->pred_valid = (cl->t_pred == t_block ? cl->pred_valid : 0) | modes;
@@ -560,6 +604,10 @@ int nb6_regular_force(nb6_ctx* c, int cluster, int64_t n_i, const int32_t* idx_i
     ra.nslices = p.nslices;
     ra.jl_shift = p.jl_shift;
     ra.tmax = (const float*)cl->tmax.p;
+    if (mi == MODE_LOC) {
+        ra.org = (const TileOrg*)cl->org.p;
+        ra.ivw = cl->rec[MODE_F64].p;
+    }
     ra.part = (double*)c->part.p;
     ra.cnt = d_cnt;
     ra.lst = (int32_t*)c->lst.p;
@@ -593,6 +641,9 @@ int nb6_regular_force(nb6_ctx* c, int cluster, int64_t n_i, const int32_t* idx_i
     fa.rec = ra.rec;
     fa.dtr = d_dtr;
     fa.mode = mi;
+    fa.org = ra.org;
+    fa.inv = mi == MODE_LOC ? (const int32_t*)cl->inv.p : nullptr;
+    fa.ivw = ra.ivw;
     {
         TimedLaunch tl(c, 2, st);
         HIP_TRY(c, launch_finalize(fa, st));
@@ -655,7 +706,10 @@ int nb6_get_predicted(nb6_ctx* c, int cluster, int dx_mode, double* x, double* v
         dx = (double*)c->io.p;
         dv = (double*)((char*)c->io.p + o_v);
     }
-    HIP_TRY(c, launch_unpack(mi, cl->rec[mi].p, n, dx, dv, st));
+    // the local stream's positions are those of the FP64 prediction it
+    // was formed from (the records hold tile offsets)
+    const int um = mi == MODE_LOC ? MODE_F64 : mi;
+    HIP_TRY(c, launch_unpack(um, cl->rec[um].p, n, dx, dv, st));
     if (mem_kind == NB6_MEM_HOST) {
         HIP_TRY(c, hipMemcpyAsync(x, dx, 3 * n * sizeof(double), hipMemcpyDeviceToHost, st));
         HIP_TRY(c, hipMemcpyAsync(v, dv, 3 * n * sizeof(double), hipMemcpyDeviceToHost, st));

@@ -51,8 +51,12 @@ constexpr size_t kStageLoadMax = size_t(8) << 20;
 struct ClusterState {
     int64_t n = 0;
     StateRec* state = nullptr; // [n] stored state, one record per particle
-    DevBuf rec[3];             // j-records by mode index
-    DevBuf tmax;               // max vabs per tile of VTILE records (any mode)
+    DevBuf rec[NMODES];        // j-records by mode index (MODE_LOC: spatial order)
+    DevBuf tmax;               // max vabs per tile of VTILE records (index order)
+    DevBuf org;                // MODE_LOC tile centres [vtiles(n)]
+    DevBuf perm, inv;          // spatial order: slot -> particle, particle -> slot
+    bool order_valid = false;  // perm / inv hold the order of the current state
+    int64_t updated_since_order = 0;  // particles of subset updates since then
     DevBuf nbl;                // stored neighbour lists [n][lcap] (irregular force)
     DevBuf nbc;                // entries of each stored list [n]
     int lcap = 0;
@@ -76,16 +80,19 @@ inline int mode_index(int dx_mode) {
         case NB6_DX_FF: return MODE_FF;
         case NB6_DX_FP64: return MODE_F64;
         case NB6_DX_FP32: return MODE_F32;
+        case NB6_DX_LOCAL: return MODE_LOC;
         default: return -1;
     }
 }
 
 inline int mode_bit(int mi) {
-    return mi == MODE_FF ? NB6_DX_FF : mi == MODE_F64 ? NB6_DX_FP64 : NB6_DX_FP32;
+    return mi == MODE_FF ? NB6_DX_FF : mi == MODE_F64 ? NB6_DX_FP64
+         : mi == MODE_F32 ? NB6_DX_FP32 : NB6_DX_LOCAL;
 }
 
 inline size_t rec_size(int mi) {
-    return mi == MODE_FF ? sizeof(RecFF) : mi == MODE_F64 ? sizeof(RecF64) : sizeof(RecF32);
+    return mi == MODE_FF ? sizeof(RecFF) : mi == MODE_F64 ? sizeof(RecF64)
+         : mi == MODE_F32 ? sizeof(RecF32) : sizeof(RecLoc);
 }
 
 // Wave-level work partition of one force call.
@@ -108,6 +115,7 @@ struct nb6_ctx {
     nb6::DevBuf out_list;                             // HOST-mode lists too big to stage
     nb6::PinBuf pin;                                  // pinned mirror of `io`
     nb6::DevBuf ld[7];                                // HOST-mode load staging
+    nb6::DevBuf order_tmp;                            // spatial-order sort scratch
     unsigned* status = nullptr;                       // device status word
     std::string err;
     nb6::Plan last_plan{0, 0, 0, 0, 0};

@@ -30,8 +30,25 @@ struct __attribute__((aligned(16))) RecF32 {  // plain float coordinates, 32 B
     float x, y, z, m;
     float vx, vy, vz, vabs;
 };
+// Tile-local coordinates, 32 B.  These records follow the cluster's spatial
+// order (slot k holds particle perm[k]); e is the FP32 rounding of the FP64
+// difference between the predicted position and the centre of the record's
+// tile of VTILE slots, p the particle's index in the cluster.
+struct __attribute__((aligned(16))) RecLoc {
+    float ex, ey, ez, m;
+    float vx, vy, vz;
+    int32_t p;
+};
+// Centre of one tile of VTILE local records: the FP64 midpoint of the
+// bounding box of their predicted positions, and the largest vabs among them
+// (the candidate bound of the force kernel).
+struct __attribute__((aligned(16))) TileOrg {
+    double x, y, z;
+    float vmax, pad;
+};
 
-enum Mode { MODE_FF = 0, MODE_F64 = 1, MODE_F32 = 2 };
+enum Mode { MODE_FF = 0, MODE_F64 = 1, MODE_F32 = 2, MODE_LOC = 3 };
+constexpr int NMODES = 4;
 
 // j-particles per tile of the force kernel: its FP32 partial sums are folded
 // into FP64 once per tile, and the predictor records max |v| of every tile of
@@ -97,6 +114,8 @@ struct RegfArgs {
     int            nslices;
     int            jl_shift;  // log2 of the lanes that share one i (0: one lane per i)
     const float*   tmax;      // [vtiles(n)] max of vabs over each tile of VTILE j
+    const TileOrg* org;       // MODE_LOC: [vtiles(n)] tile centres (else null)
+    const void*    ivw;       // MODE_LOC: FP64 records by particle (the i-side)
     double*        part;      // [ceil(ni/64)][nslices][NPART or NPART_POT][64]
     int32_t*       cnt;       // [ni] neighbours found, the i itself included (zero on
                               // entry; the finalize leaves it zero again)
@@ -123,10 +142,14 @@ struct FinalArgs {
     int            cap;
     unsigned*      status;
     // the ordered rescan of an overflowed list: the force call's records,
-    // their coordinate mode (MODE_*) and the i's dtr
+    // their coordinate mode (MODE_*) and the i's dtr; for MODE_LOC also the
+    // tile centres, the slot of each particle and the FP64 records
     const void*    rec;
     const double*  dtr;
     int            mode;
+    const TileOrg* org;
+    const int32_t* inv;
+    const void*    ivw;
 };
 
 // ---------------------------------------------------------------------------
@@ -152,6 +175,11 @@ struct PredictArgs {
     RecF32*       f32; // may be null
     float*        tmax; // [vtiles(n)] max vabs per tile (always written)
     unsigned*     status;
+    // the local-coordinate stream (launch_predict_loc): slot k of `loc`
+    // holds particle perm[k]; `f64` receives every particle's FP64 record
+    RecLoc*        loc;
+    TileOrg*       org;  // [vtiles(n)]
+    const int32_t* perm;
 };
 
 struct ScatterArgs {
@@ -282,6 +310,14 @@ hipError_t launch_regf(int mode, int ipl, int waves_per_block, bool pot, const R
 __host__ __device__ inline int regf_group_size(int ipl, int jl_shift) { return (64 * ipl) >> jl_shift; }
 hipError_t launch_finalize(const FinalArgs& a, hipStream_t s);
 hipError_t launch_predict(const PredictArgs& a, hipStream_t s);
+// The local-coordinate stream: a.loc, a.org and a.f64 from a.perm.
+hipError_t launch_predict_loc(const PredictArgs& a, hipStream_t s);
+// Spatial order of a cluster from its stored positions: perm[slot] =
+// particle (Morton order, ties by index) and inv[particle] = slot.  scratch
+// holds order_scratch_bytes(n) bytes.
+size_t order_scratch_bytes(int64_t n);
+hipError_t launch_order(const StateRec* st, int64_t n, void* scratch, size_t scratch_bytes,
+                        int32_t* perm, int32_t* inv, hipStream_t s);
 hipError_t launch_scatter(const ScatterArgs& a, hipStream_t s);
 // Widen the j-records of one mode to double position and velocity arrays.
 hipError_t launch_unpack(int mode, const void* rec, int64_t n, double* x, double* v,

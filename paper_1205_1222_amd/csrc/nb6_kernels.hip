@@ -3,6 +3,9 @@
 //   predict_kernel    cubic Taylor prediction of every j-particle to the block
 //                     time in FP64, writing the j-records the force kernel
 //                     reads (section 3.3 step 3).
+//   predict_loc_kernel the same for the local-coordinate stream: records in
+//                     the cluster's spatial order, each tile of VTILE records
+//                     with the FP64 centre of its predicted positions.
 //   regf_kernel       regular force, jerk and neighbour appends for one
 //                     (i-group, j-slice) pair (section 3.3 step 6 with the
 //                     velocity criterion of section 3.2).
@@ -21,7 +24,10 @@
 //     fetched with scalar loads into SGPRs and used directly as operands of
 //     the vector instructions: no LDS traffic and no VGPRs spent on j.
 //   * The neighbour test and the force use FP32; the coordinate difference
-//     is formed from float-float, FP64 or FP32 coordinates.
+//     is formed from float-float, FP64 or FP32 coordinates, or (local mode)
+//     as a record's FP32 offset from its tile's centre plus the FP32 rounding
+//     of (centre - R_i), computed in FP64 once per tile: one FP32 add per
+//     component, with the large coordinates cancelled in FP64.
 //   * Force terms are summed in FP32 over tiles of TILE j-particles and each
 //     tile sum is added into an FP64 accumulator (FP64 adds run at the full
 //     vector rate on CDNA), so the rounding error is that of a TILE-term
@@ -54,49 +60,90 @@ template <int MODE> struct RecOf;
 template <> struct RecOf<MODE_FF>  { using T = RecFF; };
 template <> struct RecOf<MODE_F64> { using T = RecF64; };
 template <> struct RecOf<MODE_F32> { using T = RecF32; };
+template <> struct RecOf<MODE_LOC> { using T = RecLoc; };
 
+// The record an i-particle's own state is read from: its j-record, except in
+// the local mode, whose i-side is the FP64 prediction by particle index.
+template <int MODE> struct IRecOf { using T = typename RecOf<MODE>::T; };
+template <> struct IRecOf<MODE_LOC> { using T = RecF64; };
+
+// i-side coordinates.  In the local mode, c is (tile centre - R_i) rounded to
+// FP32, formed in FP64 on entry to each tile of j (tile_enter).
 template <int MODE> struct IPos;
 template <> struct IPos<MODE_FF>  { float xh, yh, zh, xl, yl, zl; };
 template <> struct IPos<MODE_F64> { double x, y, z; };
 template <> struct IPos<MODE_F32> { float x, y, z; };
+template <> struct IPos<MODE_LOC> { double x, y, z; float cx, cy, cz; };
 
 // h2: squared neighbour radius; c: (h + dtr |v_i|) (1 + 2^-16), the i-part
 // of the candidate radius.
 struct IAux { float vx, vy, vz, vabs, h2, dtr, c; };
 
+template <typename P>
+__device__ __forceinline__ void take_vel(const P& r, IAux& v) {
+    v.vx = r.vx; v.vy = r.vy; v.vz = r.vz; v.vabs = r.vabs;
+}
 __device__ __forceinline__ void get_ipos(const RecFF& r, IPos<MODE_FF>& p, IAux& v) {
     p.xh = r.xh; p.yh = r.yh; p.zh = r.zh;
     p.xl = r.xl; p.yl = r.yl; p.zl = r.zl;
-    v.vx = r.vx; v.vy = r.vy; v.vz = r.vz; v.vabs = r.vabs;
+    take_vel(r, v);
 }
 __device__ __forceinline__ void get_ipos(const RecF64& r, IPos<MODE_F64>& p, IAux& v) {
     p.x = r.x; p.y = r.y; p.z = r.z;
-    v.vx = r.vx; v.vy = r.vy; v.vz = r.vz; v.vabs = r.vabs;
+    take_vel(r, v);
 }
 __device__ __forceinline__ void get_ipos(const RecF32& r, IPos<MODE_F32>& p, IAux& v) {
     p.x = r.x; p.y = r.y; p.z = r.z;
-    v.vx = r.vx; v.vy = r.vy; v.vz = r.vz; v.vabs = r.vabs;
+    take_vel(r, v);
+}
+__device__ __forceinline__ void get_ipos(const RecF64& r, IPos<MODE_LOC>& p, IAux& v) {
+    p.x = r.x; p.y = r.y; p.z = r.z;
+    p.cx = p.cy = p.cz = 0.0f;
+    take_vel(r, v);
+}
+
+// Entering a tile of j: the local mode forms (centre - R_i) in FP64 and
+// rounds it once; the other modes need nothing per tile.
+template <int MODE>
+__device__ __forceinline__ void tile_enter(IPos<MODE>&, double, double, double) {}
+template <>
+__device__ __forceinline__ void tile_enter<MODE_LOC>(IPos<MODE_LOC>& p, double ox, double oy,
+                                                     double oz) {
+    p.cx = (float)(ox - p.x);
+    p.cy = (float)(oy - p.y);
+    p.cz = (float)(oz - p.z);
 }
 
 // R_j - R_i in FP32 from each coordinate representation.
-__device__ __forceinline__ void coord_diff(const RecFF& j, const IPos<MODE_FF>& i,
-                                           float& dx, float& dy, float& dz) {
-    dx = (j.xh - i.xh) + (j.xl - i.xl);
-    dy = (j.yh - i.yh) + (j.yl - i.yl);
-    dz = (j.zh - i.zh) + (j.zl - i.zl);
+__device__ __forceinline__ void coord_diff(const RecFF& j, const IPos<MODE_FF>& i, float d[3]) {
+    d[0] = (j.xh - i.xh) + (j.xl - i.xl);
+    d[1] = (j.yh - i.yh) + (j.yl - i.yl);
+    d[2] = (j.zh - i.zh) + (j.zl - i.zl);
 }
-__device__ __forceinline__ void coord_diff(const RecF64& j, const IPos<MODE_F64>& i,
-                                           float& dx, float& dy, float& dz) {
-    dx = (float)(j.x - i.x);
-    dy = (float)(j.y - i.y);
-    dz = (float)(j.z - i.z);
+__device__ __forceinline__ void coord_diff(const RecF64& j, const IPos<MODE_F64>& i, float d[3]) {
+    d[0] = (float)(j.x - i.x);
+    d[1] = (float)(j.y - i.y);
+    d[2] = (float)(j.z - i.z);
 }
-__device__ __forceinline__ void coord_diff(const RecF32& j, const IPos<MODE_F32>& i,
-                                           float& dx, float& dy, float& dz) {
-    dx = j.x - i.x;
-    dy = j.y - i.y;
-    dz = j.z - i.z;
+__device__ __forceinline__ void coord_diff(const RecF32& j, const IPos<MODE_F32>& i, float d[3]) {
+    d[0] = j.x - i.x;
+    d[1] = j.y - i.y;
+    d[2] = j.z - i.z;
 }
+// (R_j - centre) + (centre - R_i): two FP32 quantities of the pair's own
+// scale (the tile is compact), so one FP32 add per component.
+__device__ __forceinline__ void coord_diff(const RecLoc& j, const IPos<MODE_LOC>& i, float d[3]) {
+    d[0] = j.ex + i.cx;
+    d[1] = j.ey + i.cy;
+    d[2] = j.ez + i.cz;
+}
+
+// The cluster index of the j-particle a record holds: the record's position
+// in the stream, except in the local mode (spatial order), whose record
+// carries it.
+template <typename R>
+__device__ __forceinline__ int j_index(const R&, int slot) { return slot; }
+__device__ __forceinline__ int j_index(const RecLoc& r, int) { return r.p; }
 
 // |R|^2 in FP32.
 __device__ __forceinline__ float dist2(float dx, float dy, float dz) {
@@ -123,53 +170,52 @@ __device__ __forceinline__ float sq_bound(const IAux& ia, float w) {
     return b * b;
 }
 
-// One i-j interaction.  run[0..2] += m r^-3 R, run[3..5] += m r^-3 (V + alpha R)
-// with alpha = -3 (R.V)/r^2 and, when NP == 7, run[6] += m / r (the potential
-// sum), unless j is a neighbour of i, in which case j is appended to i's list
-// instead.
+// The term of one (i, j) pair (section 3.3 step 6).  With u = 1/|R|,
+// g = m_j u^3 and s = 3 (R.V) u^2:
+//   sum[0..2] += g R                  (acceleration),
+//   sum[3..5] += g (V - s R)          (its time derivative, the jerk),
+//   sum[6]    += m_j u                (when NP == 7: the potential sum),
+// unless j is a neighbour of i (section 3.2), which is then appended to i's
+// list and contributes u = 0 instead.
 //
-// The velocity criterion is evaluated only for candidate pairs, r^2 < bnd2
-// with bnd2 = (c_i + dtr_i w)^2 for some w >= |v_j| (the caller's choice:
-// |v_j| itself, or the largest |v| of j's tile): since
-// |R + dtr V| >= |R| - dtr (|v_i| + |v_j|), a pair outside that radius is not
-// a neighbour, and the 2^-16 relative margin folded into c_i covers the FP32
-// rounding of every quantity involved, so the decision equals that of the
-// full test.  Candidates are rare, so the branch is seldom taken by any lane
-// of a wavefront.
+// The criterion runs only for candidate pairs, |R|^2 < bnd2, where
+// bnd2 = (c_i + dtr_i w)^2 for some w >= |v_j| (the caller's choice: v_j's
+// own bound, or that of j's tile).  Since |R + dtr V| >= |R| - dtr (|v_i| +
+// |v_j|), a pair outside that radius is no neighbour; the 2^-16 relative
+// margin inside c_i covers the FP32 rounding of every quantity involved, so
+// the decision is that of the criterion alone.  A wavefront takes the branch
+// only when one of its lanes is near j.
 template <int MODE, int NP>
-__device__ __forceinline__ void interact(const typename RecOf<MODE>::T& r, int j,
-                                         const IPos<MODE>& ip, const IAux& ia, float bnd2,
-                                         float run[NP], int qq, const RegfArgs& a) {
-    float dx, dy, dz;
-    coord_diff(r, ip, dx, dy, dz);
-    const float dvx = r.vx - ia.vx;
-    const float dvy = r.vy - ia.vy;
-    const float dvz = r.vz - ia.vz;
-    const float r2 = dist2(dx, dy, dz);
-    const float rv = fmaf(dz, dvz, fmaf(dy, dvy, dx * dvx));
-    float rinv = __builtin_amdgcn_rsqf(r2);
+__device__ __forceinline__ void pair_term(const typename RecOf<MODE>::T& r, int slot,
+                                          const IPos<MODE>& ip, const IAux& ia, float bnd2,
+                                          float sum[NP], int row, const RegfArgs& a) {
+    float R[3];
+    coord_diff(r, ip, R);
+    const float V[3] = {r.vx - ia.vx, r.vy - ia.vy, r.vz - ia.vz};
+    const float r2 = dist2(R[0], R[1], R[2]);
+    float u = __builtin_amdgcn_rsqf(r2);
+    const float rv = fmaf(R[2], V[2], fmaf(R[1], V[1], R[0] * V[0]));
     if (r2 < bnd2) {
         // Keeps the criterion behind the branch: without it the compiler may
         // compute it for every pair and merge the two tests (8 more vector
         // instructions per interaction).  Emits no instruction.
         __asm__ volatile("");
-        if (velocity_criterion(r2, dx, dy, dz, dvx, dvy, dvz, ia.dtr, ia.h2)) {
-            const int slot = atomicAdd(a.cnt + qq, 1);
-            if (slot < a.caps) a.lst[(size_t)qq * a.caps + slot] = j;
-            rinv = 0.0f;
+        if (velocity_criterion(r2, R[0], R[1], R[2], V[0], V[1], V[2], ia.dtr, ia.h2)) {
+            const int k = atomicAdd(a.cnt + row, 1);
+            if (k < a.caps) a.lst[(size_t)row * a.caps + k] = j_index(r, slot);
+            u = 0.0f;
         }
     }
-    const float rinv2 = rinv * rinv;
-    const float mr = r.m * rinv;
-    const float mr3 = mr * rinv2;
-    const float alpha = (-3.0f * rv) * rinv2;
-    if constexpr (NP == 7) run[6] += mr;
-    run[0] = fmaf(mr3, dx, run[0]);
-    run[1] = fmaf(mr3, dy, run[1]);
-    run[2] = fmaf(mr3, dz, run[2]);
-    run[3] = fmaf(mr3, fmaf(alpha, dx, dvx), run[3]);
-    run[4] = fmaf(mr3, fmaf(alpha, dy, dvy), run[4]);
-    run[5] = fmaf(mr3, fmaf(alpha, dz, dvz), run[5]);
+    const float u2 = u * u;
+    const float mu = r.m * u;
+    const float g = mu * u2;
+    const float s = (3.0f * rv) * u2;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        sum[c] = fmaf(g, R[c], sum[c]);
+        sum[3 + c] = fmaf(g, fmaf(-s, R[c], V[c]), sum[3 + c]);
+    }
+    if constexpr (NP == 7) sum[6] += mu;
 }
 
 // The j-records are not written while the force kernel runs, so they are
@@ -198,6 +244,28 @@ __device__ __forceinline__ RecF32 load_rec(const_ptr<RecF32> p) {
     r.vx = p->vx; r.vy = p->vy; r.vz = p->vz; r.vabs = p->vabs;
     return r;
 }
+__device__ __forceinline__ RecLoc load_rec(const_ptr<RecLoc> p) {
+    RecLoc r;
+    r.ex = p->ex; r.ey = p->ey; r.ez = p->ez; r.m = p->m;
+    r.vx = p->vx; r.vy = p->vy; r.vz = p->vz; r.p = p->p;
+    return r;
+}
+
+// The candidate bound w of a tile of j (the largest vabs of its records),
+// and, in the local mode, the tile's centre entered into the i-positions.
+template <int MODE, int IPL>
+__device__ __forceinline__ float enter_tile(const RegfArgs& a, int jt, IPos<MODE> ip[IPL]) {
+    if constexpr (MODE == MODE_LOC) {
+        const_ptr<TileOrg> o = (const_ptr<TileOrg>)(a.org) + jt / TILE;
+        const double ox = o->x, oy = o->y, oz = o->z;
+        const float w = o->vmax;
+#pragma unroll
+        for (int k = 0; k < IPL; ++k) tile_enter<MODE>(ip[k], ox, oy, oz);
+        return w;
+    } else {
+        return ((const_ptr<float>)(a.tmax))[jt / TILE];
+    }
+}
 
 // h2 as the float the kernels compare against, or -1 when it is not a
 // positive normal float (then the i is invalid).
@@ -220,7 +288,7 @@ __device__ __forceinline__ size_t part_index(int q, int s, int c, int nslices, i
 template <int MODE>
 __device__ __forceinline__ int load_i(const RegfArgs& a, const int q, const int s,
                                       IPos<MODE>& ip, IAux& ia) {
-    using Rec = typename RecOf<MODE>::T;
+    using IRec = typename IRecOf<MODE>::T;
     bool live = q < a.ni;
     int pi = live ? a.idx[q] : 0;
     float h2f = live ? checked_h2(a.h2[q]) : -1.0f;
@@ -239,7 +307,7 @@ __device__ __forceinline__ int load_i(const RegfArgs& a, const int q, const int 
             live = false;
         }
     }
-    const Rec* rv = static_cast<const Rec*>(a.rec);  // per-lane address
+    const IRec* rv = static_cast<const IRec*>(MODE == MODE_LOC ? a.ivw : a.rec);  // per lane
     get_ipos(rv[pi], ip, ia);
     ia.h2 = h2f;
     ia.dtr = dtf;
@@ -273,7 +341,6 @@ __device__ __forceinline__ void regf_item(const RegfArgs& a, const int group, co
 #pragma unroll
         for (int c = 0; c < NP; ++c) sum[k][c] = 0.0;
 
-    const_ptr<float> tmax = (const_ptr<float>)(a.tmax);
     for (int jt = j0; jt < j1; jt += TILE) {  // j0 is a multiple of TILE
         const int je = min(jt + TILE, j1);
         float run[IPL][NP];
@@ -282,7 +349,7 @@ __device__ __forceinline__ void regf_item(const RegfArgs& a, const int group, co
 #pragma unroll
             for (int c = 0; c < NP; ++c) run[k][c] = 0.0f;
         // candidate bound of the tile: its largest |v_j| for every j
-        const float vm = tmax[jt / TILE];
+        const float vm = enter_tile<MODE, IPL>(a, jt, ip);
         float bnd2[IPL];
 #pragma unroll
         for (int k = 0; k < IPL; ++k) bnd2[k] = sq_bound(ia[k], vm);
@@ -301,15 +368,15 @@ __device__ __forceinline__ void regf_item(const RegfArgs& a, const int group, co
             for (int g = 0; g < G; ++g)
 #pragma unroll
                 for (int k = 0; k < IPL; ++k)
-                    interact<MODE, NP>(r[g], j + g, ip[k], ia[k], bnd2[k], run[k],
-                                   ibase + k * 64 + (int)__lane_id(), a);
+                    pair_term<MODE, NP>(r[g], j + g, ip[k], ia[k], bnd2[k], run[k],
+                                        ibase + k * 64 + (int)__lane_id(), a);
         }
         for (; j < je; ++j) {
             const Rec r = load_rec(rec + j);
 #pragma unroll
             for (int k = 0; k < IPL; ++k)
-                interact<MODE, NP>(r, j, ip[k], ia[k], bnd2[k], run[k],
-                               ibase + k * 64 + (int)__lane_id(), a);
+                pair_term<MODE, NP>(r, j, ip[k], ia[k], bnd2[k], run[k],
+                                    ibase + k * 64 + (int)__lane_id(), a);
         }
 #pragma unroll
         for (int k = 0; k < IPL; ++k)
@@ -327,6 +394,30 @@ __device__ __forceinline__ void regf_item(const RegfArgs& a, const int group, co
 #pragma unroll
             for (int c = 0; c < NP; ++c) p[c * 64] = sum[k][c];
         }
+    }
+}
+
+// Terms of G records j, j + jl, ... for a lane that reads its own records
+// (the lanes-per-i kernel).  The candidate bound is each record's vabs; in
+// the local mode it is that of the record's tile, whose centre the lane
+// enters first (the tiles are loaded together, ahead of the terms).
+template <int MODE, int NP, int G>
+__device__ __forceinline__ void lane_terms(const RegfArgs& a, const typename RecOf<MODE>::T* r,
+                                           int j, int jl, IPos<MODE>& ip, const IAux& ia,
+                                           float run[NP], int row) {
+    if constexpr (MODE == MODE_LOC) {
+        TileOrg o[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) o[g] = a.org[(j + g * jl) / TILE];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            tile_enter<MODE>(ip, o[g].x, o[g].y, o[g].z);
+            pair_term<MODE, NP>(r[g], j + g * jl, ip, ia, sq_bound(ia, o[g].vmax), run, row, a);
+        }
+    } else {
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+            pair_term<MODE, NP>(r[g], j + g * jl, ip, ia, sq_bound(ia, r[g].vabs), run, row, a);
     }
 }
 
@@ -370,13 +461,11 @@ __device__ __forceinline__ void regf_item_lanes(const RegfArgs& a, const int gro
             Rec r[JG];
 #pragma unroll
             for (int g = 0; g < JG; ++g) r[g] = rec[j + g * jl];
-#pragma unroll
-            for (int g = 0; g < JG; ++g)
-                interact<MODE, NP>(r[g], j + g * jl, ip, ia, sq_bound(ia, r[g].vabs), run, qq, a);
+            lane_terms<MODE, NP, JG>(a, r, j, jl, ip, ia, run, qq);
         }
         for (; j < je; j += jl) {
-            const Rec r = rec[j];
-            interact<MODE, NP>(r, j, ip, ia, sq_bound(ia, r.vabs), run, qq, a);
+            const Rec r[1] = {rec[j]};
+            lane_terms<MODE, NP, 1>(a, r, j, jl, ip, ia, run, qq);
         }
 #pragma unroll
         for (int c = 0; c < NP; ++c) sum[c] += (double)run[c];
@@ -533,11 +622,12 @@ __device__ __forceinline__ void finalize_sums(const FinalArgs& a, const int blk,
 template <int MODE>
 __device__ __forceinline__ void rescan_list(const FinalArgs& a, const int q, const int32_t self) {
     using Rec = typename RecOf<MODE>::T;
+    using IRec = typename IRecOf<MODE>::T;
     const Rec* rec = static_cast<const Rec*>(a.rec);
     const int lane = threadIdx.x & 63;
     IPos<MODE> ip;
     IAux ia;
-    get_ipos(rec[self], ip, ia);
+    get_ipos(static_cast<const IRec*>(MODE == MODE_LOC ? a.ivw : a.rec)[self], ip, ia);
     const float h2f = checked_h2(a.h2[q]);
     const float dtf = (float)a.dtr[q];
     int32_t* out = a.list + (size_t)q * a.cap;
@@ -546,18 +636,31 @@ __device__ __forceinline__ void rescan_list(const FinalArgs& a, const int q, con
     for (int j0 = 0; j0 < a.n && found < a.cap; j0 += 4 * 64) {
         // the four records first (clamped indices: in bounds for every lane),
         // then the tests without short-circuit evaluation, so that the loads
-        // are not moved into branches and issued one after another
+        // are not moved into branches and issued one after another.  In the
+        // local mode particle j sits in slot inv[j], and the test enters its
+        // tile's centre as the force kernel does, so the bits are the same.
         Rec r[4];
+        int slot[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) r[u] = rec[min(j0 + 64 * u + lane, a.n - 1)];
+        for (int u = 0; u < 4; ++u) {
+            const int j = min(j0 + 64 * u + lane, a.n - 1);
+            slot[u] = MODE == MODE_LOC ? a.inv[j] : j;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) r[u] = rec[slot[u]];
         bool nb[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int j = j0 + 64 * u + lane;
-            float dx, dy, dz;
-            coord_diff(r[u], ip, dx, dy, dz);
-            const bool hit = velocity_criterion(dist2(dx, dy, dz), dx, dy, dz, r[u].vx - ia.vx,
-                                                r[u].vy - ia.vy, r[u].vz - ia.vz, dtf, h2f);
+            if constexpr (MODE == MODE_LOC) {
+                const TileOrg& o = a.org[slot[u] / TILE];
+                tile_enter<MODE>(ip, o.x, o.y, o.z);
+            }
+            float d[3];
+            coord_diff(r[u], ip, d);
+            const bool hit = velocity_criterion(dist2(d[0], d[1], d[2]), d[0], d[1], d[2],
+                                                r[u].vx - ia.vx, r[u].vy - ia.vy,
+                                                r[u].vz - ia.vz, dtf, h2f);
             nb[u] = (j < a.n) & (j != self) & hit;
         }
 #pragma unroll
@@ -582,6 +685,7 @@ __device__ __forceinline__ void finalize_list(const FinalArgs& a, const int q,
         switch (a.mode) {  // uniform
             case MODE_FF: rescan_list<MODE_FF>(a, q, self); break;
             case MODE_F64: rescan_list<MODE_F64>(a, q, self); break;
+            case MODE_LOC: rescan_list<MODE_LOC>(a, q, self); break;
             default: rescan_list<MODE_F32>(a, q, self); break;
         }
         return;
@@ -660,14 +764,14 @@ __global__ void __launch_bounds__(256) finalize_kernel(FinalArgs a) {
 // The copies below name every field (a struct copy out of the constant
 // address space does not compile); the sizes pin the field lists, so a field
 // added to an argument struct cannot be left out here unnoticed.
-static_assert(sizeof(RegfArgs) == 104, "load_regf_args must copy every RegfArgs field");
-static_assert(sizeof(FinalArgs) == 136, "load_final_args must copy every FinalArgs field");
+static_assert(sizeof(RegfArgs) == 120, "load_regf_args must copy every RegfArgs field");
+static_assert(sizeof(FinalArgs) == 160, "load_final_args must copy every FinalArgs field");
 
 __device__ __forceinline__ RegfArgs load_regf_args(const_ptr<ReqDesc> d) {
     RegfArgs a;
     a.rec = d->rg.rec; a.n = d->rg.n; a.idx = d->rg.idx; a.h2 = d->rg.h2; a.dtr = d->rg.dtr;
     a.ni = d->rg.ni; a.slice_len = d->rg.slice_len; a.nslices = d->rg.nslices;
-    a.jl_shift = d->rg.jl_shift; a.tmax = d->rg.tmax;
+    a.jl_shift = d->rg.jl_shift; a.tmax = d->rg.tmax; a.org = d->rg.org; a.ivw = d->rg.ivw;
     a.part = d->rg.part; a.cnt = d->rg.cnt; a.lst = d->rg.lst; a.caps = d->rg.caps;
     a.status = d->rg.status;
     return a;
@@ -680,6 +784,7 @@ __device__ __forceinline__ FinalArgs load_final_args(const_ptr<ReqDesc> d) {
     f.list = d->fin.list;
     f.cap = d->fin.cap; f.status = d->fin.status;
     f.rec = d->fin.rec; f.dtr = d->fin.dtr; f.mode = d->fin.mode;
+    f.org = d->fin.org; f.inv = d->fin.inv; f.ivw = d->fin.ivw;
     return f;
 }
 
@@ -747,6 +852,7 @@ __global__ void __launch_bounds__(256) serve_finalize_kernel(BatchArgs b) {
 // clear the same chunk of its n_i neighbour counts.
 __device__ __forceinline__ float predict_one(const PredictArgs& a, int64_t k);
 __device__ __forceinline__ void store_tile_max(const PredictArgs& a, int64_t k, float v);
+__device__ __forceinline__ void predict_loc_slot(const PredictArgs& a, int64_t k);
 
 __global__ void __launch_bounds__(256) serve_prepare_kernel(BatchArgs b) {
     const ReqDesc* d = b.reqs + blockIdx.x;
@@ -755,8 +861,12 @@ __global__ void __launch_bounds__(256) serve_prepare_kernel(BatchArgs b) {
     for (int64_t e = base + threadIdx.x; e < base + PREPARE_CHUNK; e += blockDim.x) {
         if (e < ni) d->rg.cnt[e] = 0;
         if (d->do_predict) {  // uniform across the workgroup
-            const float v = e < d->pred.n ? predict_one(d->pred, e) : 0.0f;
-            store_tile_max(d->pred, e, v);
+            if (d->pred.loc) {
+                predict_loc_slot(d->pred, e);
+            } else {
+                const float v = e < d->pred.n ? predict_one(d->pred, e) : 0.0f;
+                store_tile_max(d->pred, e, v);
+            }
         }
     }
 }
@@ -765,47 +875,62 @@ __global__ void __launch_bounds__(256) serve_prepare_kernel(BatchArgs b) {
 // Prediction of every j-particle to the block time (FP64 Horner form of the
 // cubic Taylor series), and the j-records of each requested mode.
 // ---------------------------------------------------------------------------
-// Predicts particle k and returns the vabs of its records.
-__device__ __forceinline__ float predict_one(const PredictArgs& a, const int64_t k) {
+// Prediction of particle k to a.tb (FP64; non-finite results are flagged in
+// the status word): position xp, velocity vp, the FP32 velocity vf and mass
+// m of its records, and vabs, an upper bound of |vf| (rounded up by 2^-20).
+struct Predicted {
+    double xp[3], vp[3];
+    float vf[3], m, vabs;
+};
+__device__ __forceinline__ Predicted predict_particle(const PredictArgs& a, const int64_t k) {
     const StateRec& s = a.st[k];
     const double dt = a.tb - s.t;
     const double h = 0.5 * dt, t3 = dt * (1.0 / 3.0);
-    double xp[3], vp[3];
+    Predicted P;
     bool finite = isfinite(dt);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        predict_coord(dt, h, t3, s.x[c], s.v[c], s.a[c], s.jk[c], xp[c], vp[c]);
-        finite = finite && isfinite(xp[c]) && isfinite(vp[c]);
+        predict_coord(dt, h, t3, s.x[c], s.v[c], s.a[c], s.jk[c], P.xp[c], P.vp[c]);
+        finite = finite && isfinite(P.xp[c]) && isfinite(P.vp[c]);
     }
-    const float m = (float)s.m;
     if (!finite) atomicOr(a.status, (unsigned)ST_NONFINITE);
-    // upper bound of the float velocity's magnitude (rounded up by 2^-20)
-    const float vf[3] = {(float)vp[0], (float)vp[1], (float)vp[2]};
-    const float vabs = (float)(sqrt((double)vf[0] * vf[0] + (double)vf[1] * vf[1] +
-                                    (double)vf[2] * vf[2]) * (1.0 + 0x1p-20));
+    P.m = (float)s.m;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) P.vf[c] = (float)P.vp[c];
+    P.vabs = (float)(sqrt((double)P.vf[0] * P.vf[0] + (double)P.vf[1] * P.vf[1] +
+                          (double)P.vf[2] * P.vf[2]) * (1.0 + 0x1p-20));
+    return P;
+}
+
+__device__ __forceinline__ RecF64 f64_record(const Predicted& P) {
+    RecF64 r;
+    r.x = P.xp[0]; r.y = P.xp[1]; r.z = P.xp[2];
+    r.vx = P.vf[0]; r.vy = P.vf[1]; r.vz = P.vf[2]; r.m = P.m;
+    r.vabs = P.vabs; r.pad = 0.0f;
+    return r;
+}
+
+// Predicts particle k, writes its record of each requested mode in index
+// order, and returns its vabs.
+__device__ __forceinline__ float predict_one(const PredictArgs& a, const int64_t k) {
+    const Predicted P = predict_particle(a, k);
     if (a.ff) {
         RecFF r;
-        r.xh = (float)xp[0]; r.xl = (float)(xp[0] - (double)r.xh);
-        r.yh = (float)xp[1]; r.yl = (float)(xp[1] - (double)r.yh);
-        r.zh = (float)xp[2]; r.zl = (float)(xp[2] - (double)r.zh);
-        r.m = m; r.vabs = vabs;
-        r.vx = vf[0]; r.vy = vf[1]; r.vz = vf[2]; r.pad = 0.0f;
+        r.xh = (float)P.xp[0]; r.xl = (float)(P.xp[0] - (double)r.xh);
+        r.yh = (float)P.xp[1]; r.yl = (float)(P.xp[1] - (double)r.yh);
+        r.zh = (float)P.xp[2]; r.zl = (float)(P.xp[2] - (double)r.zh);
+        r.m = P.m; r.vabs = P.vabs;
+        r.vx = P.vf[0]; r.vy = P.vf[1]; r.vz = P.vf[2]; r.pad = 0.0f;
         a.ff[k] = r;
     }
-    if (a.f64) {
-        RecF64 r;
-        r.x = xp[0]; r.y = xp[1]; r.z = xp[2];
-        r.vx = vf[0]; r.vy = vf[1]; r.vz = vf[2]; r.m = m;
-        r.vabs = vabs; r.pad = 0.0f;
-        a.f64[k] = r;
-    }
+    if (a.f64) a.f64[k] = f64_record(P);
     if (a.f32) {
         RecF32 r;
-        r.x = (float)xp[0]; r.y = (float)xp[1]; r.z = (float)xp[2]; r.m = m;
-        r.vx = vf[0]; r.vy = vf[1]; r.vz = vf[2]; r.vabs = vabs;
+        r.x = (float)P.xp[0]; r.y = (float)P.xp[1]; r.z = (float)P.xp[2]; r.m = P.m;
+        r.vx = P.vf[0]; r.vy = P.vf[1]; r.vz = P.vf[2]; r.vabs = P.vabs;
         a.f32[k] = r;
     }
-    return vabs;
+    return P.vabs;
 }
 
 // Largest vabs of the VTILE consecutive particles k0 .. k0 + VTILE - 1 held by
@@ -821,6 +946,62 @@ __global__ void __launch_bounds__(256) predict_kernel(PredictArgs a) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const float v = k < a.n ? predict_one(a, k) : 0.0f;
     store_tile_max(a, k, v);
+}
+
+// Slot k of the local-coordinate stream, by every lane of a VTILE-aligned
+// group of lanes holding slots k0 .. k0 + VTILE - 1 (lanes past the end take
+// part with empty values): predicts particle perm[k] and writes its FP64
+// record (by particle index); then the tile's centre -- the midpoint of the
+// bounding box of its predicted positions, in FP64 -- and largest vabs go to
+// org[k0 / VTILE], and the slot's record holds the FP32 rounding of the
+// offset from that centre.
+__device__ __forceinline__ void predict_loc_slot(const PredictArgs& a, const int64_t k) {
+    const bool live = k < a.n;
+    Predicted P{};
+    int p = 0;
+    if (live) {
+        p = a.perm[k];
+        P = predict_particle(a, p);
+        a.f64[p] = f64_record(P);
+    }
+    double lo[3], hi[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        lo[c] = live ? P.xp[c] : __builtin_inf();
+        hi[c] = live ? P.xp[c] : -__builtin_inf();
+    }
+    float vmax = live ? P.vabs : 0.0f;
+#pragma unroll
+    for (int d = VTILE / 2; d > 0; d >>= 1) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            lo[c] = fmin(lo[c], __shfl_xor(lo[c], d, VTILE));
+            hi[c] = fmax(hi[c], __shfl_xor(hi[c], d, VTILE));
+        }
+        vmax = fmaxf(vmax, __shfl_xor(vmax, d, VTILE));
+    }
+    double o[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) o[c] = 0.5 * (lo[c] + hi[c]);
+    if (!live) return;
+    RecLoc r;
+    r.ex = (float)(P.xp[0] - o[0]);
+    r.ey = (float)(P.xp[1] - o[1]);
+    r.ez = (float)(P.xp[2] - o[2]);
+    r.m = P.m;
+    r.vx = P.vf[0]; r.vy = P.vf[1]; r.vz = P.vf[2];
+    r.p = p;
+    a.loc[k] = r;
+    if ((k % VTILE) == 0) {
+        TileOrg t;
+        t.x = o[0]; t.y = o[1]; t.z = o[2];
+        t.vmax = vmax; t.pad = 0.0f;
+        a.org[k / VTILE] = t;
+    }
+}
+
+__global__ void __launch_bounds__(256) predict_loc_kernel(PredictArgs a) {
+    predict_loc_slot(a, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // Load or subset update of the stored state: entry e (structure-of-arrays
@@ -911,6 +1092,8 @@ hipError_t launch_regf(int mode, int ipl, int wpb, bool pot, const RegfArgs& a,
         NB6_REGF_CASE(MODE_F64, 2)
         NB6_REGF_CASE(MODE_F32, 1)
         NB6_REGF_CASE(MODE_F32, 2)
+        NB6_REGF_CASE(MODE_LOC, 1)
+        NB6_REGF_CASE(MODE_LOC, 2)
 #undef NB6_REGF_CASE
         default: return hipErrorInvalidValue;
     }
@@ -932,6 +1115,14 @@ hipError_t launch_predict(const PredictArgs& a, hipStream_t s) {
     if (a.n <= 0) return hipSuccess;
     dim3 grid((unsigned)((a.n + 255) / 256));
     hipLaunchKernelGGL(predict_kernel, grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_predict_loc(const PredictArgs& a, hipStream_t s) {
+    if (a.n <= 0) return hipSuccess;
+    if (!a.loc || !a.org || !a.perm || !a.f64) return hipErrorInvalidValue;
+    dim3 grid((unsigned)((a.n + 255) / 256));
+    hipLaunchKernelGGL(predict_loc_kernel, grid, dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
@@ -977,6 +1168,7 @@ static const void* serve_regf_fn(int mode, int cls) {
         case MODE_FF: return serve_regf_fn_mode<MODE_FF>(cls);
         case MODE_F64: return serve_regf_fn_mode<MODE_F64>(cls);
         case MODE_F32: return serve_regf_fn_mode<MODE_F32>(cls);
+        case MODE_LOC: return serve_regf_fn_mode<MODE_LOC>(cls);
         default: return nullptr;
     }
 }

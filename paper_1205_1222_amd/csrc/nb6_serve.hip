@@ -59,7 +59,7 @@ int serve_class(const Plan& p) {
 // i-per-lane class) and the requests' status words.  Header and descriptors
 // go up in one copy.
 struct BatchHeader {
-    unsigned long long counters[3 * SERVE_CLASSES];
+    unsigned long long counters[NMODES * SERVE_CLASSES];
     unsigned status[kMaxBatch];
 };
 constexpr size_t kHeaderBytes = align_up(sizeof(BatchHeader));
@@ -192,7 +192,7 @@ class Engine {
 
     int start() {
         HIP_TRY(c_, hipSetDevice(c_->device));
-        for (int m = 0; m < 3; ++m)
+        for (int m = 0; m < NMODES; ++m)
             for (int k = 0; k < SERVE_CLASSES; ++k) {
                 HIP_TRY(c_, serve_regf_blocks_per_cu(m, k, &blocks_per_cu_[m][k]));
                 blocks_per_cu_[m][k] = std::max(1, blocks_per_cu_[m][k]);
@@ -294,6 +294,16 @@ class Engine {
                 if (int rc = ensure(c_, r->cl->tmax, (size_t)vtiles(r->cl->n) * sizeof(float)))
                     return rc;
             }
+            if (r->mi == MODE_LOC) {  // the FP64 i-side and the tile centres
+                if (!r->cl->order_valid)
+                    return fail(c_, NB6_ERR_STATE, "cluster %d has no spatial order", rq->cluster);
+                int rc = NB6_OK;
+                if ((!r->cl->rec[MODE_F64].p &&
+                     (rc = ensure(c_, r->cl->rec[MODE_F64], (size_t)r->cl->n * sizeof(RecF64)))) ||
+                    (!r->cl->org.p &&
+                     (rc = ensure(c_, r->cl->org, (size_t)vtiles(r->cl->n) * sizeof(TileOrg)))))
+                    return rc;
+            }
             r->plan = make_plan(c_, r->cl->n, ni);
             r->n_submit = r->cl->n;
             // held until the request finishes: the cluster keeps its size and
@@ -381,7 +391,9 @@ class Engine {
     // that no descriptor is built from anything else).
     static bool cluster_intact(const ServeReq* r) {
         const ClusterState* cl = r->cl;
-        return cl->n == r->n_submit && cl->state && cl->rec[r->mi].p && cl->tmax.p;
+        return cl->n == r->n_submit && cl->state && cl->rec[r->mi].p && cl->tmax.p &&
+               (r->mi != MODE_LOC || (cl->org.p && cl->perm.p && cl->inv.p &&
+                                      cl->rec[MODE_F64].p && cl->order_valid));
     }
 
     void sched_loop() {
@@ -617,6 +629,12 @@ class Engine {
             d.pred.ff = r->mi == MODE_FF ? (RecFF*)cl->rec[MODE_FF].p : nullptr;
             d.pred.f64 = r->mi == MODE_F64 ? (RecF64*)cl->rec[MODE_F64].p : nullptr;
             d.pred.f32 = r->mi == MODE_F32 ? (RecF32*)cl->rec[MODE_F32].p : nullptr;
+            if (r->mi == MODE_LOC) {  // the local stream and its FP64 i-side
+                d.pred.f64 = (RecF64*)cl->rec[MODE_F64].p;
+                d.pred.loc = (RecLoc*)cl->rec[MODE_LOC].p;
+                d.pred.org = (TileOrg*)cl->org.p;
+                d.pred.perm = (const int32_t*)cl->perm.p;
+            }
             d.pred.tmax = (float*)cl->tmax.p;
             d.pred.status = status;
             const Plan& p = r->plan;
@@ -628,6 +646,10 @@ class Engine {
             d.rg.nslices = p.nslices;
             d.rg.jl_shift = p.jl_shift;
             d.rg.tmax = (const float*)cl->tmax.p;
+            if (r->mi == MODE_LOC) {
+                d.rg.org = (const TileOrg*)cl->org.p;
+                d.rg.ivw = cl->rec[MODE_F64].p;
+            }
             d.rg.part = r->part; d.rg.cnt = r->cnt; d.rg.lst = r->lst;
             d.rg.caps = r->rq.cap + 1;
             d.rg.status = status;
@@ -637,6 +659,8 @@ class Engine {
             d.fin.acc = r->d_acc; d.fin.jerk = r->d_jerk; d.fin.nnb = r->d_nnb;
             d.fin.list = r->d_list; d.fin.cap = r->rq.cap; d.fin.status = status;
             d.fin.rec = d.rg.rec; d.fin.dtr = r->d_dtr; d.fin.mode = r->mi;
+            d.fin.org = d.rg.org; d.fin.ivw = d.rg.ivw;
+            d.fin.inv = r->mi == MODE_LOC ? (const int32_t*)cl->inv.p : nullptr;
             d.mode = r->mi;
             const int gsize = regf_group_size(p.ipl, p.jl_shift);
             d.groups = (ni + gsize - 1) / gsize;
@@ -702,7 +726,7 @@ class Engine {
     std::deque<ServeReq*> pending_;
     std::unordered_map<uint64_t, ServeReq*> tickets_;
     Slot slots_[kSlots];
-    int blocks_per_cu_[3][SERVE_CLASSES] = {};  // resident workgroups per CU, per launch
+    int blocks_per_cu_[NMODES][SERVE_CLASSES] = {};  // resident workgroups per CU, per launch
     Arena arena_;
     uint64_t next_ticket_ = 1;
     bool stop_ = false;

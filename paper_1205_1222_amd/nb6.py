@@ -41,7 +41,8 @@ NB6_MEM_DEVICE = 1
 NB6_DX_FF = 1
 NB6_DX_FP64 = 2
 NB6_DX_FP32 = 4
-NB6_DX_ALL = 7
+NB6_DX_LOCAL = 8
+NB6_DX_ALL = 15
 NB6_MAX_CAP = 1023
 NB6_MAX_LIST_CAP = 8192
 

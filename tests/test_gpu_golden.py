@@ -16,9 +16,9 @@ pytestmark = pytest.mark.gpu
 from workloads.clusters import Cluster  # noqa: E402
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "closed_forms.json")
-MODES = {"ff": 1, "fp64": 2, "fp32": 4}
+MODES = {"ff": 1, "fp64": 2, "fp32": 4, "local": 8}
 # scaled by the sum of the terms' magnitudes: FP32 arithmetic per term
-TOL = {"ff": 1e-6, "fp64": 1e-6, "fp32": 1e-5}
+TOL = {"ff": 1e-6, "fp64": 1e-6, "fp32": 1e-5, "local": 1e-6}
 
 
 def _nb6():

@@ -3,7 +3,7 @@
 Bars (see the design notes for their derivation):
 * neighbour lists: exact, except pairs within 1e-6 (relative) of the
   neighbour radius, which may fall on either side;
-* FF and FP64 coordinate modes: per-particle force and jerk errors scaled by
+* FF, FP64 and local coordinate modes: per-particle force and jerk errors scaled by
   the sum of term magnitudes <= 1e-6; relative to the net value <= 1e-6
   wherever the net acceleration is at least 1e-3 of its scale and the net
   jerk at least 0.1 of its scale (below that, FP32 rounding of the individual
@@ -23,9 +23,9 @@ import oracle  # noqa: E402
 from oracle.compare import compare  # noqa: E402
 from workloads import config, make_cluster  # noqa: E402
 
-MODES = {"ff": 1, "fp64": 2, "fp32": 4}
-TOL_SCALED = {"ff": 1e-6, "fp64": 1e-6, "fp32": 1e-4}
-TOL_REL = {"ff": 1e-6, "fp64": 1e-6, "fp32": None}
+MODES = {"ff": 1, "fp64": 2, "fp32": 4, "local": 8}
+TOL_SCALED = {"ff": 1e-6, "fp64": 1e-6, "fp32": 1e-4, "local": 1e-6}
+TOL_REL = {"ff": 1e-6, "fp64": 1e-6, "fp32": None, "local": 1e-6}
 # File that collects one JSON line per parity case (unset: printed only).
 OUT = os.environ.get("NB6_PARITY_LOG")
 
@@ -96,7 +96,8 @@ def test_predict_matches_oracle(ctx):
     cl = config(2, n=4096)["cluster"]
     load(ctx, cl)
     xo, vo = oracle.predict(cl.x, cl.v, cl.a, cl.jerk, cl.t, cl.tb)
-    for mode, tol_x in (("fp64", 1e-15), ("ff", 1e-14), ("fp32", 2.0 ** -23)):
+    for mode, tol_x in (("fp64", 1e-15), ("ff", 1e-14), ("fp32", 2.0 ** -23),
+                        ("local", 1e-15)):
         x = np.empty((cl.n, 3))
         v = np.empty((cl.n, 3))
         nb6.check(ctx, nb6.nb6_get_predicted(ctx, 0, MODES[mode], x, v))
@@ -108,7 +109,7 @@ def test_predict_matches_oracle(ctx):
         assert ev <= 2.0 ** -24, (mode, ev)
 
 
-@pytest.mark.parametrize("mode", ["ff", "fp64", "fp32"])
+@pytest.mark.parametrize("mode", ["ff", "fp64", "fp32", "local"])
 def test_config1_all_active(ctx, mode):
     cfg = config(1)
     cl = cfg["cluster"]
@@ -117,7 +118,7 @@ def test_config1_all_active(ctx, mode):
     check_mode(ctx, cl, idx, mode, f"C1_all_{mode}")
 
 
-@pytest.mark.parametrize("mode", ["ff", "fp64"])
+@pytest.mark.parametrize("mode", ["ff", "fp64", "local"])
 def test_config2_random_block(ctx, mode):
     cfg = config(2)
     cl = cfg["cluster"]
@@ -128,12 +129,14 @@ def test_config2_random_block(ctx, mode):
 
 @pytest.mark.parametrize("mode,offset", [("ff", (3.0, -2.0, 1.5)),
                                          ("ff", (1000.0, -500.0, 250.0)),
-                                         ("fp64", (1000.0, -500.0, 250.0))])
+                                         ("fp64", (1000.0, -500.0, 250.0)),
+                                         ("local", (3.0, -2.0, 1.5)),
+                                         ("local", (1000.0, -500.0, 250.0))])
 def test_offset_cluster(ctx, mode, offset):
-    """A cluster far from the coordinate origin keeps the FF and FP64 bars:
-    both form every coordinate difference from the full-precision positions.
-    Differences of FP32 positions (the high parts alone) would be off by
-    ~3e-5 of the force at the larger offset."""
+    """A cluster far from the coordinate origin keeps the FF, FP64 and local
+    bars: each cancels the large coordinates in full precision (the local
+    mode against FP64 tile centres).  Differences of FP32 positions (the high
+    parts alone) would be off by ~3e-5 of the force at the larger offset."""
     import dataclasses
     base = make_cluster(4096, 91, masses="imf", k_nb=32)
     cl = dataclasses.replace(base, x=base.x + np.array(offset))
@@ -152,6 +155,7 @@ def test_ragged_sizes_and_slicings(ctx):
         idx = np.sort(rng.choice(cl.n, ni, replace=False)).astype(np.int32)
         ref = oracle_ref(cl, idx)
         check_mode(ctx, cl, idx, "ff", f"ragged_n{ni}", ref=ref)
+        check_mode(ctx, cl, idx, "local", f"ragged_n{ni}_local", ref=ref)
         results[ni] = (idx, ref)
     # force many slices (wavefront finalize) and a single slice
     for hint in (1, 3, 40):
@@ -160,6 +164,7 @@ def test_ragged_sizes_and_slicings(ctx):
             load(c2, cl)
             idx, ref = results[130]
             check_mode(c2, cl, idx, "ff", f"ragged_hint{hint}", ref=ref)
+            check_mode(c2, cl, idx, "local", f"ragged_hint{hint}_local", ref=ref)
             assert nb6.nb6_last_slices(c2) == min(hint, (cl.n + 255) // 256)
         finally:
             nb6.nb6_destroy(c2)
@@ -176,7 +181,9 @@ def test_lanes_per_i(ctx):
     rng = np.random.Generator(np.random.PCG64(11))
     for ni in (1, 2, 3, 5, 31, 64, 100, 200, 300):
         idx = np.sort(rng.choice(cl.n, ni, replace=False)).astype(np.int32)
-        check_mode(ctx, cl, idx, "ff", f"lanes_auto_n{ni}")
+        ref = oracle_ref(cl, idx)
+        check_mode(ctx, cl, idx, "ff", f"lanes_auto_n{ni}", ref=ref)
+        check_mode(ctx, cl, idx, "local", f"lanes_auto_n{ni}_local", ref=ref)
         ipl, lanes, slices, slen = nb6.nb6_last_plan(ctx)
         print("plan", ni, ipl, lanes, slices, slen, flush=True)
         assert ipl == 1
@@ -192,6 +199,7 @@ def test_lanes_per_i(ctx):
         try:
             load(c2, cl)
             check_mode(c2, cl, idx, "ff", f"lanes_forced{jl}_s{hint}", ref=ref)
+            check_mode(c2, cl, idx, "local", f"lanes_forced{jl}_s{hint}_local", ref=ref)
             assert nb6.nb6_last_plan(c2)[1] == jl
         finally:
             nb6.nb6_destroy(c2)
@@ -378,7 +386,10 @@ def test_repeat_calls_are_bitwise_identical(ctx):
 @pytest.mark.parametrize("block,mode", [("all", "ff"), ("pow2_0", "ff"), ("pow2_4", "ff"),
                                         ("pow2_10", "ff"), ("pow2_14", "ff"),
                                         ("all", "fp64"), ("pow2_10", "fp64"),
-                                        ("all", "fp32"), ("pow2_10", "fp32")])
+                                        ("all", "fp32"), ("pow2_10", "fp32"),
+                                        ("all", "local"), ("pow2_0", "local"),
+                                        ("pow2_4", "local"), ("pow2_10", "local"),
+                                        ("pow2_14", "local")])
 def test_config3_full_size_sampled(ctx, block, mode):
     """N = 131072 with binaries, in the launch configuration the benchmark
     times; the oracle checks a sample of the active i, with each coordinate
@@ -405,7 +416,7 @@ def test_config3_full_size_sampled(ctx, block, mode):
     if mode == "fp32":
         assert c.list_mismatch <= max(1, len(samp) // 100), c.mismatches[:10]
     else:
-        assert c.list_mismatch == 0 and c.nnb_mismatch == 0
+        assert c.list_mismatch == 0 and c.nnb_mismatch == 0, c.mismatches[:10]
     tol = TOL_SCALED[mode]
     assert s["acc_scaled_max"] <= tol and s["jerk_scaled_max"] <= tol, s
     if TOL_REL[mode] is not None:
@@ -443,10 +454,10 @@ def test_config3_two_i_per_lane_sampled():
         nb6.nb6_destroy(c2)
 
 
-@pytest.mark.parametrize("mode", ["ff", "fp64", "fp32"])
+@pytest.mark.parametrize("mode", ["ff", "fp64", "fp32", "local"])
 @pytest.mark.parametrize("block", ["random4096", "all"])
 def test_config5_full_size_sampled(ctx, block, mode):
-    """N = 2^20, ~100 neighbours, in the three coordinate modes, in the launch
+    """N = 2^20, ~100 neighbours, in every coordinate mode, in the launch
     configuration the benchmark times; the oracle checks 256 sampled i."""
     nb6 = _nb6()
     cfg = config(5)
@@ -478,16 +489,16 @@ def test_config5_full_size_sampled(ctx, block, mode):
         assert s.get("jerk_rel_max", 0.0) <= TOL_REL[mode], s
 
 
-@pytest.mark.parametrize("mode", ["ff", "fp64", "fp32"])
+@pytest.mark.parametrize("mode", ["ff", "fp64", "fp32", "local"])
 def test_potential(ctx, mode):
     """The optional regular potential (-sum m/r over the non-neighbours) against
     the oracle, on a one-lane-per-i block, a small lanes-per-i block and C3's
     binaries; asking for it leaves acc, jerk and the lists bit-identical."""
     nb6 = _nb6()
-    tol = {"ff": 1e-6, "fp64": 1e-6, "fp32": 1e-5}[mode]
+    tol = {"ff": 1e-6, "fp64": 1e-6, "fp32": 1e-5, "local": 1e-6}[mode]
     cases = [(config(2)["cluster"], config(2)["blocks"]["random1024"]),
              (config(2)["cluster"], config(2)["blocks"]["random1024"][:37])]
-    if mode == "ff":
+    if mode in ("ff", "local"):
         c3 = config(3)
         cases.append((c3["cluster"], c3["blocks"]["pow2_12"]))
     for cl, idx in cases:
@@ -511,17 +522,20 @@ def test_potential(ctx, mode):
         assert ok.mean() > 0.98 and rel[ok].max() <= tol, rel[ok].max()
 
 
+@pytest.mark.parametrize("mode", ["ff", "local"])
 @pytest.mark.parametrize("n", [1024, 1500])
-def test_everything_neighbour_long_lists(ctx, n):
+def test_everything_neighbour_long_lists(ctx, n, mode):
     """h -> infinity: every j is a neighbour.  N = 1024 fills the largest list
     exactly (1023 entries, sorted on the GPU); N = 1500 overflows it and the
-    ordered overflow scan must return the first 1023 indices."""
+    ordered overflow scan must return the first 1023 indices (in the local
+    mode it visits the particles through their slots in the spatial order)."""
     nb6 = _nb6()
     cl = make_cluster(n, 31, masses="equal", k_nb=8)
     load(ctx, cl)
     idx = np.array([0, 7, n // 2, n - 1], np.int32)
     cap = nb6.NB6_MAX_CAP
-    acc, jerk, nnb, lst, rc = nb6.regular_force_host(ctx, 0, idx, 1e30, cl.dtr[idx], 1, cap)
+    acc, jerk, nnb, lst, rc = nb6.regular_force_host(ctx, 0, idx, 1e30, cl.dtr[idx],
+                                                     MODES[mode], cap)
     assert np.all(acc == 0.0) and np.all(jerk == 0.0)
     assert np.all(nnb == n - 1)
     assert rc == (nb6.NB6_OK if n - 1 <= cap else nb6.NB6_WARN_NB_OVERFLOW)
@@ -529,10 +543,10 @@ def test_everything_neighbour_long_lists(ctx, n):
         want = [j for j in range(n) if j != i][:cap]
         np.testing.assert_array_equal(lst[q, :min(cap, n - 1)], want)
     with pytest.raises(Exception):
-        nb6.regular_force_host(ctx, 0, idx, 1e30, cl.dtr[idx], 1, cap + 1)
+        nb6.regular_force_host(ctx, 0, idx, 1e30, cl.dtr[idx], MODES[mode], cap + 1)
 
 
-@pytest.mark.parametrize("mode", ["ff", "fp64", "fp32"])
+@pytest.mark.parametrize("mode", ["ff", "fp64", "fp32", "local"])
 def test_overflow_rescan_every_mode(ctx, mode):
     """A list capacity below the neighbour count: the finalize rebuilds such a
     list by an ordered rescan in the call's own coordinate mode, which must
@@ -640,7 +654,7 @@ def test_tiny_clusters_and_repeated_indices(ctx):
         np.testing.assert_array_equal(lst[a_, :nnb[a_]], lst[b_, :nnb[b_]])
 
 
-@pytest.mark.parametrize("mode", ["ff", "fp64", "fp32"])
+@pytest.mark.parametrize("mode", ["ff", "fp64", "fp32", "local"])
 def test_two_i_per_lane(mode):
     """The two-i-per-lane force kernel (a context option; the default plan
     takes one): oracle parity on a ragged random block and a whole cluster,
@@ -693,3 +707,41 @@ def test_nonfinite_device_state_is_reported(ctx):
     load(ctx, cl)
     idx = cfg["blocks"]["all"][:64]
     check_mode(ctx, cl, idx, "ff", "reload_after_nonfinite")
+
+
+def test_local_order_follows_the_state(ctx):
+    """The local stream's spatial order is built from the stored state at a
+    full load and rebuilt once subset updates have touched as many particles
+    as the cluster holds.  Corrector-sized moves of a quarter of the cluster
+    per step keep the bars while the order ages; the fourth update triggers
+    the rebuild, after which the results are bit-identical to a fresh context
+    that full-loads the same state."""
+    import dataclasses
+    nb6 = _nb6()
+    base = config(2, n=4096)["cluster"]
+    cl = dataclasses.replace(base, x=base.x.copy(), v=base.v.copy(), t=base.t.copy())
+    load(ctx, cl)
+    rng = np.random.Generator(np.random.PCG64(21))
+    idx = np.sort(rng.choice(cl.n, 512, replace=False)).astype(np.int32)
+    check_mode(ctx, cl, idx, "local", "order_fresh")
+    perm = rng.permutation(cl.n)
+    for step in range(4):
+        upd = np.sort(perm[step * 1024:(step + 1) * 1024]).astype(np.int32)
+        # the stored state of a block after its step: drifted by v dt
+        cl.x[upd] += cl.v[upd] * 2.0 ** -7
+        cl.t[upd] = cl.tb
+        nb6.check(ctx, nb6.nb6_load_particles(
+            ctx, 0, len(upd), np.ascontiguousarray(cl.m[upd]), np.ascontiguousarray(cl.x[upd]),
+            np.ascontiguousarray(cl.v[upd]), np.ascontiguousarray(cl.a[upd]),
+            np.ascontiguousarray(cl.jerk[upd]), np.ascontiguousarray(cl.t[upd]), upd))
+        nb6.check(ctx, nb6.nb6_predict_j(ctx, 0, cl.tb, nb6.NB6_DX_LOCAL))
+        got = check_mode(ctx, cl, idx, "local", f"order_step{step}")
+    fresh = nb6.nb6_create(0)
+    try:
+        load(fresh, cl)
+        want = nb6.regular_force_host(fresh, 0, idx, cl.h2[idx], cl.dtr[idx], MODES["local"],
+                                      512)
+    finally:
+        nb6.nb6_destroy(fresh)
+    for a, b in zip(got[:3], want[:3]):
+        np.testing.assert_array_equal(a, b)

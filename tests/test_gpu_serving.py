@@ -3,6 +3,8 @@
 * every served result matches the FP64 oracle (same bars as the plain path);
 * a request gives bit-identical results alone and fused with others;
 * served results equal the plain call's when both use one i per lane;
+* requests of C4's size (32768- and 65536-body clusters, blocks of up to all
+  their particles) fused with small ones match the oracle on sampled rows;
 * admission: a request larger than the HBM budget is refused; requests that
   only fit one at a time all complete;
 * overflowed lists, unknown tickets, double polls.
@@ -69,7 +71,8 @@ def _submit(nb6, ctx, cl, c, tb, idx, cap, mode=1):
     return t, h
 
 
-def test_served_results_match_oracle(clusters):
+@pytest.mark.parametrize("mode", [1, 8])
+def test_served_results_match_oracle(clusters, mode):
     nb6 = _nb6()
     ctx = nb6.nb6_create(0)
     try:
@@ -77,7 +80,7 @@ def test_served_results_match_oracle(clusters):
         cap = 256
         subs = []
         for c, tb, idx in _requests(clusters):
-            subs.append((c, tb, idx) + _submit(nb6, ctx, clusters[c], c, tb, idx, cap))
+            subs.append((c, tb, idx) + _submit(nb6, ctx, clusters[c], c, tb, idx, cap, mode))
         sizes = []
         for c, tb, idx, t, h in subs:
             rc, info = nb6.nb6_poll(ctx, t, wait=1)
@@ -99,7 +102,8 @@ def test_served_results_match_oracle(clusters):
         nb6.nb6_destroy(ctx)
 
 
-def test_alone_and_mixed_are_bit_identical(clusters):
+@pytest.mark.parametrize("mode", [1, 8])
+def test_alone_and_mixed_are_bit_identical(clusters, mode):
     nb6 = _nb6()
     ctx = nb6.nb6_create(0)
     try:
@@ -108,7 +112,7 @@ def test_alone_and_mixed_are_bit_identical(clusters):
         reqs = _requests(clusters, seed=7, per_cluster=2)
         alone = []
         for c, tb, idx in reqs:  # one at a time
-            t, h = _submit(nb6, ctx, clusters[c], c, tb, idx, cap)
+            t, h = _submit(nb6, ctx, clusters[c], c, tb, idx, cap, mode)
             rc, info = nb6.nb6_poll(ctx, t, wait=1)
             assert info["batch_size"] == 1
             alone.append(h)
@@ -117,7 +121,7 @@ def test_alone_and_mixed_are_bit_identical(clusters):
         tickets = []
         for k in reversed(range(len(reqs))):
             c, tb, idx = reqs[k]
-            t, h = _submit(nb6, ctx, clusters[c], c, tb, idx, cap)
+            t, h = _submit(nb6, ctx, clusters[c], c, tb, idx, cap, mode)
             tickets.append((k, t, h))
         fused = 0
         for k, t, h in tickets:
@@ -136,10 +140,11 @@ def test_alone_and_mixed_are_bit_identical(clusters):
         nb6.nb6_destroy(ctx)
 
 
-@pytest.mark.parametrize("hint,c,step,ni_max", [(1, 2, 7, None), (0, 3, 1, 4500),
-                                                (2, 3, 1, 4500), (0, 1, 1, 2000),
-                                                (0, 0, 1, 20)])
-def test_served_equals_plain_call(clusters, hint, c, step, ni_max):
+@pytest.mark.parametrize("hint,c,step,ni_max,mode", [(1, 2, 7, None, 1), (0, 3, 1, 4500, 1),
+                                                     (2, 3, 1, 4500, 1), (0, 1, 1, 2000, 1),
+                                                     (0, 0, 1, 20, 1), (0, 3, 1, 4500, 8),
+                                                     (2, 3, 1, 4500, 8), (0, 0, 1, 20, 8)])
+def test_served_equals_plain_call(clusters, hint, c, step, ni_max, mode):
     """A served request takes the plan a plain call on the same context takes
     (one i per lane, or two when the context asks for it; lanes per i for
     small blocks), hence the same bits."""
@@ -149,12 +154,12 @@ def test_served_equals_plain_call(clusters, hint, c, step, ni_max):
         _load_all(nb6, ctx, clusters)
         cl = clusters[c]
         idx = np.arange(0, cl.n, step, dtype=np.int32)[:ni_max]
-        t, h = _submit(nb6, ctx, cl, c, cl.tb, idx, 64)
+        t, h = _submit(nb6, ctx, cl, c, cl.tb, idx, 64, mode)
         rc, _ = nb6.nb6_poll(ctx, t, wait=1)
         assert rc in (nb6.NB6_OK, nb6.NB6_WARN_NB_OVERFLOW)
-        nb6.check(ctx, nb6.nb6_predict_j(ctx, c, cl.tb, nb6.NB6_DX_FF))
+        nb6.check(ctx, nb6.nb6_predict_j(ctx, c, cl.tb, mode))
         acc, jerk, nnb, lst, _ = nb6.regular_force_host(ctx, c, idx, cl.h2[idx], cl.dtr[idx],
-                                                        1, 64)
+                                                        mode, 64)
         print("plan", len(idx), nb6.nb6_last_plan(ctx), flush=True)
         np.testing.assert_array_equal(acc, h.acc)
         np.testing.assert_array_equal(jerk, h.jerk)
@@ -249,21 +254,21 @@ def test_plain_calls_beside_the_queue(clusters):
 
 
 def test_mixed_coordinate_modes(clusters):
-    """Requests in all three coordinate modes fused into the same batches
+    """Requests in all four coordinate modes fused into the same batches
     (one persistent launch per mode and work-partition class): each equals,
     bit for bit, the plain call in its mode at its block time."""
     nb6 = _nb6()
     ctx = nb6.nb6_create(0)
     try:
         _load_all(nb6, ctx, clusters)
-        modes = (nb6.NB6_DX_FF, nb6.NB6_DX_FP64, nb6.NB6_DX_FP32)
+        modes = (nb6.NB6_DX_FF, nb6.NB6_DX_FP64, nb6.NB6_DX_FP32, nb6.NB6_DX_LOCAL)
         rng = np.random.Generator(np.random.PCG64(31))
         reqs = []
         for r in range(3):
             for c, cl in enumerate(clusters):
                 ni = int(rng.choice([40, 700]))
                 idx = np.sort(rng.choice(cl.n, ni, replace=False)).astype(np.int32)
-                reqs.append((c, cl.tb + r * 2.0 ** -12, idx, modes[(r + c) % 3]))
+                reqs.append((c, cl.tb + r * 2.0 ** -12, idx, modes[(r + c) % 4]))
         subs = [_submit(nb6, ctx, clusters[c], c, tb, idx, 64, mode)
                 for c, tb, idx, mode in reqs]
         fused = 0
@@ -421,5 +426,53 @@ def test_resize_refused_while_requests_are_queued(clusters):
         c = compare(h.acc, h.jerk, h.nnb, h.lst, 64, ref, small.m, xp, vp, si, small.h2[si],
                     small.dtr[si])
         assert c.list_mismatch == 0 and c.summary()["acc_scaled_max"] <= 1e-6, c.summary()
+    finally:
+        nb6.nb6_destroy(ctx)
+
+
+def test_large_clusters_fused_with_small_match_oracle():
+    """Blocks of the serving trace's largest clusters (32768 and 65536 bodies,
+    equal masses, ~50 neighbours; blocks of 4096 up to every particle) fused
+    with small blocks of small clusters, in the float-float and local modes:
+    every request completes, is fused with others, and 128 sampled rows of
+    each (all rows of the small ones) meet the oracle bars."""
+    nb6 = _nb6()
+    sizes = [32768, 65536, 4096, 6000]
+    cls = [make_cluster(n, 900 + k, masses="equal", k_nb=50) for k, n in enumerate(sizes)]
+    ctx = nb6.nb6_create(0)
+    try:
+        _load_all(nb6, ctx, cls)
+        rng = np.random.Generator(np.random.PCG64(77))
+        reqs = []
+        for mode in (nb6.NB6_DX_FF, nb6.NB6_DX_LOCAL):
+            for c, ni in ((0, 32768), (1, 65536), (1, 4096), (0, 8192), (2, 16), (3, 300),
+                          (2, 1024), (3, 64)):
+                idx = (np.arange(cls[c].n, dtype=np.int32) if ni == cls[c].n else
+                       np.sort(rng.choice(cls[c].n, ni, replace=False)).astype(np.int32))
+                tb = cls[c].tb + len(reqs) * 2.0 ** -14
+                reqs.append((c, tb, idx, mode))
+        cap = 128
+        subs = [_submit(nb6, ctx, cls[c], c, tb, idx, cap, mode) for c, tb, idx, mode in reqs]
+        fused = 0
+        for (t, h), (c, tb, idx, mode) in zip(subs, reqs):
+            rc, info = nb6.nb6_poll(ctx, t, wait=1)
+            assert rc in (nb6.NB6_OK, nb6.NB6_WARN_NB_OVERFLOW), rc
+            fused = max(fused, info["batch_size"])
+        assert fused > 1
+        for (t, h), (c, tb, idx, mode) in zip(subs, reqs):
+            cl = cls[c]
+            samp = np.sort(rng.choice(len(idx), min(128, len(idx)), replace=False))
+            si = idx[samp]
+            xp, vp = oracle.predict(cl.x, cl.v, cl.a, cl.jerk, cl.t, tb)
+            ref = oracle.regular_force(cl.m, xp, vp, si, cl.h2[si], cl.dtr[si], lcap=4096)
+            cmp_ = compare(h.acc[samp], h.jerk[samp], h.nnb[samp], h.lst[samp], cap, ref, cl.m,
+                           xp, vp, si, cl.h2[si], cl.dtr[si])
+            s = cmp_.summary()
+            print("C4-scale", cl.n, len(idx), mode, s["acc_rel_max"], s["jerk_rel_max"],
+                  flush=True)
+            assert cmp_.incomplete == 0
+            assert cmp_.list_mismatch == 0 and cmp_.nnb_mismatch == 0, s
+            assert s["acc_scaled_max"] <= 1e-6 and s["jerk_scaled_max"] <= 1e-6, s
+            assert s.get("acc_rel_max", 0) <= 1e-6 and s.get("jerk_rel_max", 0) <= 1e-6, s
     finally:
         nb6.nb6_destroy(ctx)

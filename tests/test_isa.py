@@ -58,9 +58,9 @@ def _meta(asm, name, key):
 
 def test_every_force_kernel_is_present(asm):
     names = _kernels(asm)
-    # 3 coordinate modes x {one-i, two-i, lanes} x {with, without potential}
-    # plus the serving kernels: 3 coordinate modes x {one-i, lanes, two-i}
-    assert len(names) == 27, names
+    # 4 coordinate modes x {one-i, two-i, lanes} x {with, without potential}
+    # plus the serving kernels: 4 coordinate modes x {one-i, lanes, two-i}
+    assert len(names) == 36, names
 
 
 def test_criterion_stays_behind_its_branch(asm):
