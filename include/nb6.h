@@ -198,6 +198,42 @@ int nb6_regular_force(nb6_ctx *ctx, int cluster, int64_t n_i,
                       int32_t cap, int mem_kind, void *stream);
 
 /*
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.
+ *
+ * nb6_regular_force with device arrays only (every array argument is device
+ * memory; the call is ordered on `stream` and returns without waiting), whose
+ * force-call scratch -- the slice partial sums, the per-i neighbour counters
+ * and the unsorted list rows -- lives in one fixed device array of
+ * NB6_NOALLOC_SCRATCH_BYTES per GPU, instead of buffers the context grows.
+ * The call allocates nothing: the cluster must be loaded and predicted in
+ * dx_mode (those calls allocate its records), and NB6_OPT_TIMING does not
+ * record this call's launches.  The counters are cleared by the call itself,
+ * with a kernel.
+ *
+ * The scratch of a call is 8 np S ceil(n_i / 64) 64 + 4 n_i + 4 n_i (cap + 1)
+ * bytes (each part rounded up to 256 B; np = 6, or 7 with pot; S j-slices).
+ * When nb6_regular_force's plan on the same context fits the array, the call
+ * takes it and both give the same bits; otherwise it takes the most slices
+ * that fit (then the sums differ from nb6_regular_force's by rounding only),
+ * e.g. about 1100 instead of 4096 for a block of 1024 at N = 2^20 with the
+ * potential and cap 1023.  A block too large for one slice (n_i above about
+ * 16000 at cap 1023, 62000 at cap 256) is refused with NB6_ERR_ARG, the
+ * message giving the bytes it needs.
+ *
+ * The array is shared by every context on one GPU and keeps the last call's
+ * contents: calls that overlap on one GPU (different streams, contexts or
+ * threads without ordering between them) race and give undefined results.
+ * Other errors are those of nb6_regular_force.
+ */
+#define NB6_NOALLOC_SCRATCH_BYTES (64u << 20)
+int nb6_regular_force_noalloc(nb6_ctx *ctx, int cluster, int64_t n_i,
+                              const int32_t *idx_i, const double *h2_i,
+                              const double *dtr_i, int dx_mode, double *acc,
+                              double *jerk, double *pot, int32_t *nnb,
+                              int32_t *list, int32_t cap, void *stream);
+
+/*
  * Wait for `stream` and return (and clear) the GPU-side validation state of
  * the context: NB6_OK, or NB6_ERR_DEVICE_INPUT when a DEVICE-mode call met
  * an out-of-range index, an h2 that is not a positive normal float, a

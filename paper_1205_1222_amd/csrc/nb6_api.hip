@@ -82,6 +82,32 @@ Plan make_plan(const nb6_ctx* c, int64_t n, int64_t ni, int ipl) {
 
 namespace {
 
+// Scratch of nb6_regular_force_noalloc: one fixed array per GPU in the code
+// object, held from the library's first use on that GPU until the process
+// ends.  Host code never passes its name as an address (in host code the
+// name is a host-side stand-in): the array's device address on each GPU is
+// taken once, with that GPU current, by hipGetSymbolAddress.
+static __device__ __align__(256) unsigned char scratch[NB6_NOALLOC_SCRATCH_BYTES];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices] = {};
+
+// Device address of `scratch` on `device`, which must be the current device.
+int scratch_address(int device, void** out) {
+    if (device < 0 || device >= kMaxDevices) return NB6_ERR_ARG;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch[device]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return NB6_ERR_HIP;
+        }
+        g_scratch[device] = p;
+    }
+    *out = g_scratch[device];
+    return NB6_OK;
+}
+
 bool finite_all(const double* p, int64_t n) {
     for (int64_t k = 0; k < n; ++k)
         if (!std::isfinite(p[k])) return false;
@@ -95,8 +121,9 @@ struct TimedLaunch {
     int kind;
     hipStream_t st;
     hipEvent_t a = nullptr, b = nullptr;
+    // kind < 0: not timed
     TimedLaunch(nb6_ctx* c_, int k, hipStream_t s) : c(c_), kind(k), st(s) {
-        if (!c->timing) return;
+        if (!c->timing || kind < 0) return;
         if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
             a = b = nullptr;
             return;
@@ -196,8 +223,9 @@ int nb6_create(nb6_ctx** out, const nb6_options* opt) {
         delete c;
         return NB6_ERR_NOMEM;
     }
+    void* scr = nullptr;  // the no-allocation scratch's address on this GPU
     if (launch_zero_u32(c->status, 4, nullptr) != hipSuccess ||
-        hipDeviceSynchronize() != hipSuccess) {
+        hipDeviceSynchronize() != hipSuccess || scratch_address(c->device, &scr) != NB6_OK) {
         (void)hipFree(c->status);
         delete c;
         return NB6_ERR_HIP;
@@ -487,6 +515,97 @@ static int copy_lists_out(nb6_ctx* c, const int32_t* d_list, const int32_t* nnb,
     return NB6_OK;
 }
 
+// Device arrays of one force call: its inputs and outputs, and its scratch
+// (slice partial sums, per-i counters that must be zero on entry, list rows).
+struct ForceIO {
+    const int32_t* idx;
+    const double* h2;
+    const double* dtr;
+    double* acc;
+    double* jerk;
+    double* pot;  // null: no potential
+    int32_t* nnb;
+    int32_t* list;
+};
+struct ForceScratch {
+    double* part;
+    int32_t* cnt;
+    int32_t* lst;
+};
+
+// Bytes of a force call's scratch for plan p: the partials of every
+// 64-particle block and slice, then the counters, then the list rows, each
+// starting on a 256-byte boundary (the layout of the no-allocation array).
+static size_t force_scratch_layout(const Plan& p, int ni, int npart, int caps, size_t off[3]) {
+    const size_t ni64 = ((size_t)ni + 63) / 64 * 64;
+    Stage lay;
+    off[0] = lay.add((size_t)p.nslices * npart * ni64 * sizeof(double));
+    off[1] = lay.add((size_t)ni * sizeof(int32_t));
+    off[2] = lay.add((size_t)ni * caps * sizeof(int32_t));
+    return lay.end;
+}
+
+// The two launches of a force call, force kernel then finalize, on st (event
+// timing when `timed` and the context has it on).
+static int launch_force_call(nb6_ctx* c, const ClusterState* cl, int mi, int ni, int cap,
+                             const Plan& p, const ForceIO& io, const ForceScratch& fs,
+                             hipStream_t st, bool timed) {
+    RegfArgs ra{};
+    ra.rec = cl->rec[mi].p;
+    ra.n = (int)cl->n;
+    ra.idx = io.idx;
+    ra.h2 = io.h2;
+    ra.dtr = io.dtr;
+    ra.ni = ni;
+    ra.slice_len = p.slice_len;
+    ra.nslices = p.nslices;
+    ra.jl_shift = p.jl_shift;
+    ra.tmax = (const float*)cl->tmax.p;
+    if (mi == MODE_LOC) {
+        ra.org = (const TileOrg*)cl->org.p;
+        ra.ivw = cl->rec[MODE_F64].p;
+    }
+    ra.part = fs.part;
+    ra.cnt = fs.cnt;
+    ra.lst = fs.lst;
+    ra.caps = cap + 1;  // room for the i-particle itself
+    ra.status = c->status;
+    {
+        TimedLaunch tl(c, timed ? 1 : -1, st);
+        HIP_TRY(c, launch_regf(mi, p.ipl, p.wpb, io.pot != nullptr, ra, st));
+        tl.done();
+    }
+    FinalArgs fa{};
+    fa.part = ra.part;
+    fa.cnt = ra.cnt;
+    fa.lst = ra.lst;
+    fa.nslices = p.nslices;
+    fa.ni = ni;
+    fa.caps = ra.caps;
+    fa.n = (int)cl->n;
+    fa.idx = io.idx;
+    fa.h2 = io.h2;
+    fa.acc = io.acc;
+    fa.jerk = io.jerk;
+    fa.pot = io.pot;
+    fa.nnb = io.nnb;
+    fa.list = io.list;
+    fa.cap = cap;
+    fa.status = c->status;
+    fa.rec = ra.rec;
+    fa.dtr = io.dtr;
+    fa.mode = mi;
+    fa.org = ra.org;
+    fa.inv = mi == MODE_LOC ? (const int32_t*)cl->inv.p : nullptr;
+    fa.ivw = ra.ivw;
+    {
+        TimedLaunch tl(c, timed ? 2 : -1, st);
+        HIP_TRY(c, launch_finalize(fa, st));
+        tl.done();
+    }
+    return NB6_OK;
+}
+
 int nb6_regular_force(nb6_ctx* c, int cluster, int64_t n_i, const int32_t* idx_i,
                       const double* h2_i, const double* dtr_i, int dx_mode, double* acc,
                       double* jerk, double* pot, int32_t* nnb, int32_t* list, int32_t cap,
@@ -593,62 +712,11 @@ int nb6_regular_force(nb6_ctx* c, int cluster, int64_t n_i, const int32_t* idx_i
         c->cnt_dirty = false;
     }
 
-    RegfArgs ra{};
-    ra.rec = cl->rec[mi].p;
-    ra.n = (int)n;
-    ra.idx = d_idx;
-    ra.h2 = d_h2;
-    ra.dtr = d_dtr;
-    ra.ni = ni;
-    ra.slice_len = p.slice_len;
-    ra.nslices = p.nslices;
-    ra.jl_shift = p.jl_shift;
-    ra.tmax = (const float*)cl->tmax.p;
-    if (mi == MODE_LOC) {
-        ra.org = (const TileOrg*)cl->org.p;
-        ra.ivw = cl->rec[MODE_F64].p;
-    }
-    ra.part = (double*)c->part.p;
-    ra.cnt = d_cnt;
-    ra.lst = (int32_t*)c->lst.p;
-    ra.caps = caps;
-    ra.status = c->status;
     // the finalize resets the counts; until it is launched they are dirty
     c->cnt_dirty = true;
-    {
-        TimedLaunch tl(c, 1, st);
-        HIP_TRY(c, launch_regf(mi, p.ipl, p.wpb, pot != nullptr, ra, st));
-        tl.done();
-    }
-
-    FinalArgs fa{};
-    fa.part = ra.part;
-    fa.cnt = ra.cnt;
-    fa.lst = ra.lst;
-    fa.nslices = p.nslices;
-    fa.ni = ni;
-    fa.caps = caps;
-    fa.n = (int)n;
-    fa.idx = d_idx;
-    fa.h2 = d_h2;
-    fa.acc = d_acc;
-    fa.jerk = d_jerk;
-    fa.pot = pot ? d_pot : nullptr;
-    fa.nnb = d_nnb;
-    fa.list = d_list;
-    fa.cap = cap;
-    fa.status = c->status;
-    fa.rec = ra.rec;
-    fa.dtr = d_dtr;
-    fa.mode = mi;
-    fa.org = ra.org;
-    fa.inv = mi == MODE_LOC ? (const int32_t*)cl->inv.p : nullptr;
-    fa.ivw = ra.ivw;
-    {
-        TimedLaunch tl(c, 2, st);
-        HIP_TRY(c, launch_finalize(fa, st));
-        tl.done();
-    }
+    const ForceIO io{d_idx, d_h2, d_dtr, d_acc, d_jerk, pot ? d_pot : nullptr, d_nnb, d_list};
+    const ForceScratch fs{(double*)c->part.p, d_cnt, (int32_t*)c->lst.p};
+    if (int rc2 = launch_force_call(c, cl, mi, ni, cap, p, io, fs, st, true)) return rc2;
     c->cnt_dirty = false;
     c->last_plan = p;
 
@@ -675,6 +743,68 @@ int nb6_regular_force(nb6_ctx* c, int cluster, int64_t n_i, const int32_t* idx_i
         return fail(c, NB6_ERR_DEVICE_INPUT, "GPU validation flagged 0x%x", status[0]);
     for (int q = 0; q < ni; ++q)
         if (nnb[q] > cap) return NB6_WARN_NB_OVERFLOW;
+    return NB6_OK;
+}
+
+int nb6_regular_force_noalloc(nb6_ctx* c, int cluster, int64_t n_i, const int32_t* idx_i,
+                              const double* h2_i, const double* dtr_i, int dx_mode,
+                              double* acc, double* jerk, double* pot, int32_t* nnb,
+                              int32_t* list, int32_t cap, void* stream) {
+    if (!c) return NB6_ERR_ARG;
+    c->err.clear();
+    std::lock_guard<std::mutex> lk(c->cluster_mu);
+    ClusterState* cl = nullptr;
+    if (int rc = get_cluster(c, cluster, &cl)) return rc;
+    PlainClaim claim;
+    if (int rc = claim.claim(c, cl, (hipStream_t)stream)) return rc;
+    const int mi = mode_index(dx_mode);
+    if (mi < 0) return fail(c, NB6_ERR_ARG, "bad dx_mode %d", dx_mode);
+    if (!(cl->pred_valid & dx_mode))
+        return fail(c, NB6_ERR_STATE, "cluster %d has no current prediction for dx_mode %d",
+                    cluster, dx_mode);
+    if (n_i < 0 || n_i > INT32_MAX / 2) return fail(c, NB6_ERR_ARG, "n_i = %lld", (long long)n_i);
+    if (cap < 0 || cap > MAX_CAPS - 1)
+        return fail(c, NB6_ERR_ARG, "cap = %d outside [0, %d]", cap, MAX_CAPS - 1);
+    if (n_i == 0) return NB6_OK;
+    if (!idx_i || !h2_i || !dtr_i || !acc || !jerk || !nnb || (cap > 0 && !list))
+        return fail(c, NB6_ERR_ARG, "null argument");
+    HIP_TRY(c, hipSetDevice(c->device));
+    void* base = nullptr;
+    if (scratch_address(c->device, &base) != NB6_OK)
+        return fail(c, NB6_ERR_HIP, "no address for the scratch array on device %d", c->device);
+    hipStream_t st = (hipStream_t)stream;
+    const int ni = (int)n_i;
+    const int npart = pot ? NPART_POT : NPART;
+    const size_t limit = NB6_NOALLOC_SCRATCH_BYTES;
+    // the plain call's plan when its scratch fits; otherwise the most
+    // j-slices whose partials fit beside the counters and the list rows
+    Plan p = make_plan(c, cl->n, ni);
+    size_t off[3];
+    size_t need = force_scratch_layout(p, ni, npart, cap + 1, off);
+    if (need > limit) {
+        Plan none = p;
+        none.nslices = 0;
+        const size_t fixed = force_scratch_layout(none, ni, npart, cap + 1, off);
+        const size_t per_slice = (((size_t)ni + 63) / 64 * 64) * npart * sizeof(double);
+        int64_t s = fixed + 256 < limit ? (int64_t)((limit - fixed - 256) / per_slice) : 0;
+        if (s >= 8) s = s / 8 * 8;
+        if (s >= 1) {
+            p = plan_rule(PlanInputs{c->num_cu, c->ipl_hint, c->jl_hint, (int)s}, cl->n, ni, 0);
+            need = force_scratch_layout(p, ni, npart, cap + 1, off);
+        }
+        if (s < 1 || need > limit)
+            return fail(c, NB6_ERR_ARG,
+                        "the call needs %zu bytes of scratch (%zu with one j-slice); the "
+                        "no-allocation array holds %zu", need, fixed + per_slice, limit);
+    }
+    char* b = static_cast<char*>(base);
+    const ForceScratch fs{(double*)(b + off[0]), (int32_t*)(b + off[1]), (int32_t*)(b + off[2])};
+    // the counters start at zero: cleared by a kernel (no memset node, so a
+    // captured graph may hold the call)
+    HIP_TRY(c, launch_zero_u32((unsigned*)fs.cnt, ni, st));
+    const ForceIO io{idx_i, h2_i, dtr_i, acc, jerk, pot, nnb, list};
+    if (int rc = launch_force_call(c, cl, mi, ni, cap, p, io, fs, st, false)) return rc;
+    c->last_plan = p;
     return NB6_OK;
 }
 

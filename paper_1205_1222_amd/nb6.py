@@ -45,6 +45,7 @@ NB6_DX_LOCAL = 8
 NB6_DX_ALL = 15
 NB6_MAX_CAP = 1023
 NB6_MAX_LIST_CAP = 8192
+NB6_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 EXPORTED = [
     "nb6_create", "nb6_destroy", "nb6_last_error", "nb6_load_particles",
@@ -52,6 +53,7 @@ EXPORTED = [
     "nb6_last_plan",
     "nb6_get_predicted", "nb6_kernel_times", "nb6_submit", "nb6_poll",
     "nb6_set_lists", "nb6_irregular_force", "nb6_regular_correct",
+    "nb6_regular_force_noalloc",
 ]
 
 NB6_OPT_TIMING = 1
@@ -123,6 +125,8 @@ def lib():
         L.nb6_predict_j.argtypes = [vp, ctypes.c_int, ctypes.c_double, ctypes.c_int, vp]
         L.nb6_regular_force.argtypes = [vp, ctypes.c_int, i64, vp, vp, vp, ctypes.c_int,
                                         vp, vp, vp, vp, vp, ctypes.c_int32, ctypes.c_int, vp]
+        L.nb6_regular_force_noalloc.argtypes = [vp, ctypes.c_int, i64, vp, vp, vp, ctypes.c_int,
+                                                vp, vp, vp, vp, vp, ctypes.c_int32, vp]
         L.nb6_sync_status.argtypes = [vp, vp]
         L.nb6_kernel_times.argtypes = [vp, vp, vp]
         L.nb6_submit.argtypes = [vp, ctypes.POINTER(nb6_request), ctypes.POINTER(ctypes.c_uint64)]
@@ -233,6 +237,16 @@ def nb6_regular_force(ctx, cluster, n_i, idx_i, h2_i, dtr_i, dx_mode, acc, jerk,
         ctx, cluster, n_i, _ptr(idx_i, np.int32), _ptr(h2_i, f), _ptr(dtr_i, f),
         dx_mode, _ptr(acc, f), _ptr(jerk, f), _ptr(pot, f), _ptr(nnb, np.int32),
         _ptr(nblist, np.int32), cap, mem_kind, _stream(stream))
+
+
+def nb6_regular_force_noalloc(ctx, cluster, n_i, idx_i, h2_i, dtr_i, dx_mode, acc, jerk,
+                              nnb, nblist, cap, stream=None, pot=None):
+    """The C entry point (device arrays only); ``pot`` as in nb6_regular_force."""
+    f = np.float64
+    return lib().nb6_regular_force_noalloc(
+        ctx, cluster, n_i, _ptr(idx_i, np.int32), _ptr(h2_i, f), _ptr(dtr_i, f),
+        dx_mode, _ptr(acc, f), _ptr(jerk, f), _ptr(pot, f), _ptr(nnb, np.int32),
+        _ptr(nblist, np.int32), cap, _stream(stream))
 
 
 def nb6_set_lists(ctx, cluster, n_i, idx_i, nnb_i, nblist, cap, mem_kind=NB6_MEM_HOST,
