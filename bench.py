@@ -56,7 +56,7 @@ MODES = {"ff": 1, "fp64": 2, "fp32": 4, "local": 8}
 # kernel sources are the ones the counters were taken from.
 KERNEL_SOURCES = ("paper_1205_1222_amd/csrc/nb6_kernels.hip",
                   "paper_1205_1222_amd/csrc/nb6_internal.h")
-COUNTER_FILE = os.path.join("profiles", "regf_ff_plummer131072_all_counters.md")
+COUNTER_FILE = os.path.join("profiles", "regf_{mode}_plummer131072_all_counters.md")
 VALU_COUNTERS = ("SQ_INSTS_VALU", "SQ_INSTS_VALU_ADD_F32", "SQ_INSTS_VALU_MUL_F32",
                  "SQ_INSTS_VALU_FMA_F32", "SQ_INSTS_VALU_TRANS_F32", "SQ_INSTS_SALU",
                  "SQ_INSTS_SMEM", "SQ_WAVES")
@@ -85,7 +85,7 @@ def _median(v):
     return v[len(v) // 2]
 
 
-def counter_summary(fetch_csv, write_csv, valu_csv, copy_mib, config_line, pairs):
+def counter_summary(fetch_csv, write_csv, valu_csv, copy_mib, config_line, pairs, mode="local"):
     """Markdown summary of the counter runs of the force kernel: per-launch HBM
     bytes (each counter scaled by what it reads for the device copy of copy_mib
     MiB made at the start of the same run) and FP32 VALU instruction counts."""
@@ -122,10 +122,10 @@ def counter_summary(fetch_csv, write_csv, valu_csv, copy_mib, config_line, pairs
         return os.path.relpath(os.path.dirname(os.path.abspath(csv_path)), ROOT)
 
     cmd = ("python3 bench.py --steps 2 --warmup 1 --no-serving --no-cpu-baseline --no-irregular "
-           "--no-potential "
-           f"--copy-mib {copy_mib}")
+           "--no-potential --no-corrector --no-load --no-modes --no-blocks --no-c5 "
+           f"--mode {mode} --copy-mib {copy_mib}")
     lines = [
-        "# Counters of the force kernel, Plummer N = 131072, all 131072 active (FF)",
+        f"# Counters of the force kernel, Plummer N = 131072, all 131072 active ({mode} coordinates)",
         "",
         "rocprofv3 counter runs of the benchmark (one counter group per run).  Each run "
         f"begins with a {copy_mib} MiB device-to-device copy whose known size calibrates "
@@ -167,9 +167,11 @@ def counter_summary(fetch_csv, write_csv, valu_csv, copy_mib, config_line, pairs
 
 
 def counters_from_profile(config_line):
-    """The counter record of COUNTER_FILE when it was taken from the current
-    kernel sources and the same configuration, else None."""
-    path = os.path.join(ROOT, COUNTER_FILE)
+    """The counter record of the configuration's coordinate mode (COUNTER_FILE)
+    when it was taken from the current kernel sources and the same
+    configuration, else None."""
+    mode = re.search(r"\bmode (\w+)", config_line)
+    path = os.path.join(ROOT, COUNTER_FILE.format(mode=mode.group(1) if mode else "local"))
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -230,6 +232,44 @@ def cpu_baseline(cl, idx, gpu_outs, cap, target_s):
     return base, summaries
 
 
+def served_accuracy(cls, reqs, tbs, kept, cap, rows=128):
+    """Served results of the kept requests against the oracle: each request's
+    cluster predicted to its block time by the oracle, and up to ``rows``
+    sampled rows of the request compared with the usual bars."""
+    import oracle
+    from oracle.compare import compare
+
+    rng = np.random.Generator(np.random.PCG64(12051232))
+    worst = {"acc_rel_max": 0.0, "acc_scaled_max": 0.0, "jerk_rel_max": 0.0,
+             "jerk_scaled_max": 0.0}
+    tot = {"requests": 0, "rows": 0, "list_mismatch": 0, "nnb_mismatch": 0,
+           "exempt_pairs": 0, "incomplete": 0}
+    sizes = []
+    for k in sorted(kept):
+        c, idx = reqs[k]
+        cl = cls[c]
+        a_, j_, n_, l_ = (t.cpu().numpy() for t in kept[k])
+        samp = np.sort(rng.choice(len(idx), min(rows, len(idx)), replace=False))
+        si = idx[samp]
+        xp, vp = oracle.predict(cl.x, cl.v, cl.a, cl.jerk, cl.t, tbs[k])
+        ref = oracle.regular_force(cl.m, xp, vp, si, cl.h2[si], cl.dtr[si], lcap=4096)
+        summ = compare(a_[samp], j_[samp], n_[samp], l_[samp, :cap], cap, ref, cl.m, xp, vp, si,
+                       cl.h2[si], cl.dtr[si]).summary()
+        tot["requests"] += 1
+        tot["rows"] += len(samp)
+        for key in ("list_mismatch", "nnb_mismatch", "exempt_pairs", "incomplete"):
+            tot[key] += summ[key]
+        for key in worst:
+            worst[key] = max(worst[key], summ.get(key, 0.0))
+        sizes.append((cl.n, len(idx)))
+    out = {**tot, **worst,
+           "largest": sorted(sizes, key=lambda t: t[0] * t[1])[-3:],
+           "cluster_sizes": [min(t[0] for t in sizes), max(t[0] for t in sizes)],
+           "block_sizes": [min(t[1] for t in sizes), max(t[1] for t in sizes)]}
+    log(f"bench: served results against the oracle: {out}")
+    return out
+
+
 def serving_leg(args, nb6, torch):
     """Serving trace: 64 Plummer clusters (N log-uniform 4096..65536), blocks of
     2^k random active particles, open-loop Poisson arrivals at rho times the
@@ -258,6 +298,19 @@ def serving_leg(args, nb6, torch):
     h2_all = np.concatenate([cls[c].h2[idx] for c, idx in reqs])
     dtr_all = np.concatenate([cls[c].dtr[idx] for c, idx in reqs])
     off = np.concatenate([[0], np.cumsum([len(idx) for _, idx in reqs])])
+    # requests whose results are kept and checked against the oracle (first
+    # offered load): 16 blocks of >= 4096 particles of the >= 32768-body
+    # clusters, 16 more blocks of >= 4096, and 32 of any size
+    rng_s = np.random.Generator(np.random.PCG64(12051231))
+    big_cl = [k for k, (c, idx) in enumerate(reqs) if cls[c].n >= 32768 and len(idx) >= 4096]
+    big = [k for k, (c, idx) in enumerate(reqs) if len(idx) >= 4096]
+    pick = set(rng_s.choice(big_cl, min(16, len(big_cl)), replace=False).tolist())
+    rest = [k for k in big if k not in pick]
+    pick |= set(rng_s.choice(rest, min(16, len(rest)), replace=False).tolist())
+    rest = [k for k in range(len(reqs)) if k not in pick]
+    pick |= set(rng_s.choice(rest, min(32, len(rest)), replace=False).tolist())
+    check_reqs = sorted(pick)
+    kept = {}
     d_idx = torch.from_numpy(idx_all).to(dev)
     d_h2 = torch.from_numpy(h2_all).to(dev)
     d_dtr = torch.from_numpy(dtr_all).to(dev)
@@ -366,6 +419,8 @@ def serving_leg(args, nb6, torch):
             ni = len(idx)
             o = outputs(ni)
             live[k] = o
+            if rho == rhos[0] and k in pick:
+                kept[k] = o
             wait_until(t_start, arrivals[k])
             sub_wall[k] = time.perf_counter() - t_start
             rc, t = nb6.nb6_submit(sctx, c, tbs[k], mode, ni, d_idx[off[k]:off[k + 1]],
@@ -403,6 +458,7 @@ def serving_leg(args, nb6, torch):
         runs.append(run)
     nb6.nb6_destroy(sctx)
     nb6.nb6_destroy(pctx)
+    accuracy = served_accuracy(cls, reqs, tbs, kept, cap) if args.serve_check else None
     head = runs[0]
     return {
         "workload": "64 Plummer clusters, N log-uniform 4096..65536; blocks of 2^k random "
@@ -410,7 +466,7 @@ def serving_leg(args, nb6, torch):
         "requests": len(reqs), "list_cap": cap, "hbm_budget_mb": args.serve_budget_mb,
         "plain_service_ms": round(s_bar * 1e3, 4),
         "p50_ms": head["served"]["p50_ms"], "p99_ms": head["served"]["p99_ms"],
-        "rho": head["rho"], "runs": runs,
+        "rho": head["rho"], "runs": runs, "accuracy": accuracy,
     }
 
 
@@ -487,10 +543,14 @@ def irregular_leg(args, nb6, torch, ctx, cl, idx_np, idx_d, nnb, lst):
     nb6.check(wctx, nb6.nb6_sync_status(wctx, stream))
     nb6.nb6_destroy(wctx)
     whole = res["blocks"][-1]
+    # a gather rate: algorithmic bytes over kernel time; most of the state
+    # records are served from the MALL, so this is not an HBM counter figure
     res["roofline"] = {"bound": "hbm", "achieved": whole["algorithmic_gb_s"],
                        "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": round(whole["algorithmic_gb_s"] / HBM_PEAK_GBS, 4),
-                       "traffic": None}
+                       "traffic": None,
+                       "basis": "algorithmic gather bytes (list entries and 112-B state "
+                                "records) per kernel time; the records mostly hit the MALL"}
     return res
 
 
@@ -587,7 +647,10 @@ def corrector_leg(args, nb6, torch, cl, nnb):
     res["roofline"] = {"bound": "hbm", "achieved": whole["algorithmic_gb_s"],
                        "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": round(whole["algorithmic_gb_s"] / HBM_PEAK_GBS, 4),
-                       "traffic": None}
+                       "traffic": None,
+                       "basis": "algorithmic bytes per whole call on the stream (events "
+                                "around back-to-back calls: includes the per-call launch "
+                                "gap, about 11 us)"}
     return res
 
 
@@ -623,11 +686,14 @@ def potential_leg(args, nb6, torch, ctx, idx_d, h2_d, dtr_d, ni, mode, regf_ms, 
             "finalize_ms": round(ms[2] / max(cnt[2], 1), 5)}
 
 
-def block_sweep(args, cfg, nb6, torch, T, lanes=0, slices=None, max_ni=None, max_reps=200):
-    """Force-call time for every block of the configuration (one JSON line each):
-    wall time per call on a context without event timing (back-to-back calls on
-    one stream, so host launch cost shows only where it exceeds the GPU time),
-    and per-kernel GPU times on a second context with event timing."""
+def block_sweep(args, cfg, nb6, torch, T, lanes=0, slices=None, max_ni=None, max_reps=200,
+                host=True, emit=True):
+    """Force-call time for every block of the configuration: wall time per call
+    on a context without event timing (back-to-back calls on one stream, so
+    host launch cost shows only where it exceeds the GPU time), per-kernel GPU
+    times on a second context with event timing, and (with ``host``) the same
+    call with host arrays.  Returns one record per block (and prints each as a
+    JSON line with ``emit``)."""
     cl = cfg["cluster"]
     n = cl.n
     stream = torch.cuda.current_stream()
@@ -641,6 +707,7 @@ def block_sweep(args, cfg, nb6, torch, T, lanes=0, slices=None, max_ni=None, max
                                               cl.t))
         nb6.check(ctx, nb6.nb6_predict_j(ctx, 0, cl.tb, mode, stream))
         ctxs.append(ctx)
+    records = []
     for name, idx in sorted(cfg["blocks"].items(), key=lambda kv: len(kv[1])):
         ni = len(idx)
         if max_ni is not None and ni > max_ni:
@@ -668,34 +735,127 @@ def block_sweep(args, cfg, nb6, torch, T, lanes=0, slices=None, max_ni=None, max
             torch.cuda.synchronize()
             out.append((time.perf_counter() - t0) / reps)
         wall = out[0]
-        # the same call with host arrays in and out (copies and synchronisation
-        # included), as a host program without device buffers would make it
-        h_idx, h_h2, h_dtr = idx.astype(np.int32), cl.h2[idx].copy(), cl.dtr[idx].copy()
-        h_out = (np.empty((ni, 3)), np.empty((ni, 3)), np.empty(ni, np.int32),
-                 np.empty((ni, args.cap), np.int32))
-        host_reps = max(3, reps // 4)
-        for k in range(host_reps + 1):
-            if k == 1:
-                t0 = time.perf_counter()
-            nb6.check(ctxs[0], nb6.nb6_regular_force(
-                ctxs[0], 0, ni, h_idx, h_h2, h_dtr, mode, *h_out, args.cap, nb6.NB6_MEM_HOST),
-                (nb6.NB6_OK, nb6.NB6_WARN_NB_OVERFLOW))
-        host_wall = (time.perf_counter() - t0) / host_reps
         ms, cnt = nb6.nb6_kernel_times(ctxs[1])
         pairs = ni * (n - 1)
         ipl, jl, ns, slen = nb6.nb6_last_plan(ctxs[1])
-        print(json.dumps({"block": name, "N": n, "N_i": ni, "mode": args.mode,
-                          "ipl": ipl, "lanes": jl, "slices": ns, "slice_len": slen,
-                          "forced": [lanes, slices], "reps": reps,
-                          "call_us": round(wall * 1e6, 2),
-                          "host_call_us": round(host_wall * 1e6, 2),
-                          "force_us": round(ms[1] / cnt[1] * 1e3, 2),
-                          "finalize_us": round(ms[2] / cnt[2] * 1e3, 2),
-                          "call_gint_s": round(pairs / wall / 1e9, 3),
-                          "force_gint_s": round(pairs / (ms[1] / cnt[1] * 1e-3) / 1e9, 3)}),
-              flush=True)
+        force_ms = ms[1] / cnt[1]
+        rec = {"block": name, "N": n, "N_i": ni, "mode": args.mode,
+               "ipl": ipl, "lanes": jl, "slices": ns, "slice_len": slen,
+               "forced": [lanes, slices], "reps": reps,
+               "call_us": round(wall * 1e6, 2),
+               "force_us": round(force_ms * 1e3, 2),
+               "finalize_us": round(ms[2] / max(cnt[2], 1) * 1e3, 2),
+               "call_gint_s": round(pairs / wall / 1e9, 3),
+               "force_gint_s": round(pairs / (force_ms * 1e-3) / 1e9, 3),
+               "force_frac": round(FLOP_PER_INTERACTION * pairs / (force_ms * 1e-3) / 1e12
+                                   / FP32_PEAK_TFLOPS, 4)}
+        if host:
+            # the same call with host arrays in and out (copies and
+            # synchronisation included), as a host program without device
+            # buffers would make it
+            h_idx, h_h2, h_dtr = idx.astype(np.int32), cl.h2[idx].copy(), cl.dtr[idx].copy()
+            h_out = (np.empty((ni, 3)), np.empty((ni, 3)), np.empty(ni, np.int32),
+                     np.empty((ni, args.cap), np.int32))
+            host_reps = max(3, reps // 4)
+            for k in range(host_reps + 1):
+                if k == 1:
+                    t0 = time.perf_counter()
+                nb6.check(ctxs[0], nb6.nb6_regular_force(
+                    ctxs[0], 0, ni, h_idx, h_h2, h_dtr, mode, *h_out, args.cap,
+                    nb6.NB6_MEM_HOST), (nb6.NB6_OK, nb6.NB6_WARN_NB_OVERFLOW))
+            rec["host_call_us"] = round((time.perf_counter() - t0) / host_reps * 1e6, 2)
+        records.append(rec)
+        if emit:
+            print(json.dumps(rec), flush=True)
     for ctx in ctxs:
         nb6.nb6_destroy(ctx)
+    return records
+
+
+def c5_leg(args, nb6, torch, with_oracle, cpu_seconds):
+    """C5: the 2^20-body Plummer sphere (equal masses, ~100 neighbours).  Every
+    coordinate mode's force on all 2^20 active particles (force-kernel time
+    from events, whole call from the wall clock), and each mode's accuracy on
+    the configuration's 10^4 sampled active particles against the oracle (one
+    oracle run, timed: the CPU rate at this size)."""
+    import oracle
+    from oracle.compare import compare
+    from workloads import config
+
+    t_gen = time.perf_counter()
+    cfg = config(5)
+    cl = cfg["cluster"]
+    n = cl.n
+    log(f"bench: C5 inputs in {time.perf_counter() - t_gen:.1f} s")
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    T = lambda a, dt=torch.float64: torch.from_numpy(np.ascontiguousarray(a)).to(dev, dt)  # noqa: E731
+    ctx = nb6.nb6_create(0, flags=nb6.NB6_OPT_TIMING)
+    cap = args.cap
+    res = {"workload": cfg["description"], "N": n, "list_cap": cap, "modes": {}}
+    try:
+        nb6.check(ctx, nb6.nb6_load_particles(ctx, 0, n, cl.m, cl.x, cl.v, cl.a, cl.jerk,
+                                              cl.t))
+        nb6.check(ctx, nb6.nb6_predict_j(ctx, 0, cl.tb, 0, stream))
+        idx = cfg["blocks"]["all"]
+        idx_d, h2_d, dtr_d = T(idx, torch.int32), T(cl.h2[idx]), T(cl.dtr[idx])
+        acc = torch.empty((n, 3), dtype=torch.float64, device=dev)
+        jerk = torch.empty_like(acc)
+        nnb = torch.empty(n, dtype=torch.int32, device=dev)
+        lst = torch.empty((n, cap), dtype=torch.int32, device=dev)
+        pairs = n * (n - 1)
+        order = [args.mode] + [m for m in sorted(MODES) if m != args.mode]
+        for name in order:
+            def call():
+                nb6.check(ctx, nb6.nb6_regular_force(ctx, 0, n, idx_d, h2_d, dtr_d, MODES[name],
+                                                     acc, jerk, nnb, lst, cap,
+                                                     nb6.NB6_MEM_DEVICE, stream))
+            call()
+            torch.cuda.synchronize()
+            nb6.nb6_kernel_times(ctx)
+            t0 = time.perf_counter()
+            for _ in range(2):
+                call()
+            torch.cuda.synchronize()
+            wall = (time.perf_counter() - t0) / 2
+            ms, cnt = nb6.nb6_kernel_times(ctx)
+            f_ms = ms[1] / cnt[1]
+            res["modes"][name] = {
+                "call_ms": round(wall * 1e3, 3), "kernel_ms": round(f_ms, 3),
+                "ginteractions_s": round(pairs / wall / 1e9, 3),
+                "kernel_ginteractions_s": round(pairs / (f_ms * 1e-3) / 1e9, 3),
+                "pct_fp32_peak": round(100.0 * FLOP_PER_INTERACTION * pairs / (f_ms * 1e-3)
+                                       / 1e12 / FP32_PEAK_TFLOPS, 2),
+                "slices": nb6.nb6_last_slices(ctx)}
+            log(f"bench: C5 all active, {name}: {res['modes'][name]}")
+        nb6.check(ctx, nb6.nb6_sync_status(ctx, stream))
+        del acc, jerk, nnb, lst
+        if with_oracle:
+            samp = cfg["blocks"]["sample10000"]
+            outs = {}
+            for name in order:
+                a_, j_, n_, l_, _ = nb6.regular_force_host(ctx, 0, samp, cl.h2[samp],
+                                                           cl.dtr[samp], MODES[name], cap)
+                outs[name] = (a_, j_, n_, l_)
+            xp, vp = oracle.predict(cl.x, cl.v, cl.a, cl.jerk, cl.t, cl.tb)
+            t0 = time.perf_counter()
+            ref = oracle.regular_force(cl.m, xp, vp, samp, cl.h2[samp], cl.dtr[samp], lcap=4096)
+            dt = time.perf_counter() - t0
+            res["oracle"] = {"sample": f"{len(samp)} sampled active i against all {n} j",
+                             "seconds": round(dt, 2),
+                             "ginteractions_s": round(len(samp) * (n - 1) / dt / 1e9, 4),
+                             "cores": oracle.max_threads()}
+            keys = ("n_i", "list_mismatch", "exempt_pairs", "nnb_mismatch", "acc_rel_p99",
+                    "acc_rel_max", "acc_scaled_max", "jerk_rel_p99", "jerk_rel_max",
+                    "jerk_scaled_max", "jerk_rel_floor1e-3_max")
+            for name, (a_, j_, n_, l_) in outs.items():
+                summ = compare(a_, j_, n_, l_, cap, ref, cl.m, xp, vp, samp, cl.h2[samp],
+                               cl.dtr[samp]).summary()
+                res["modes"][name]["accuracy"] = {k: summ[k] for k in keys if k in summ}
+                log(f"bench: C5 accuracy {name}: {res['modes'][name]['accuracy']}")
+    finally:
+        nb6.nb6_destroy(ctx)
+    return res
 
 
 def traffic_config(args):
@@ -725,6 +885,12 @@ def main():
                     help="skip the host-array load timing")
     ap.add_argument("--no-modes", action="store_true",
                     help="skip the other coordinate modes' rate and accuracy")
+    ap.add_argument("--no-c5", action="store_true",
+                    help="skip the 2^20-body configuration's rates and accuracy")
+    ap.add_argument("--no-blocks", action="store_true",
+                    help="skip the per-size curve (every power-of-two block of C3)")
+    ap.add_argument("--no-serve-check", dest="serve_check", action="store_false",
+                    help="skip the oracle check of sampled served requests")
     ap.add_argument("--serve-requests", type=int, default=20000)
     ap.add_argument("--serve-calibrate", type=int, default=300)
     ap.add_argument("--serve-cap", type=int, default=128)
@@ -753,8 +919,8 @@ def main():
         pairs = len(cfg["blocks"][args.block]) * (cfg["cluster"].n - 1)
         f_csv, w_csv, v_csv = args.counter_summary
         text = counter_summary(f_csv, w_csv, None if v_csv == "-" else v_csv, args.copy_mib,
-                               traffic_config(args), pairs)
-        with open(os.path.join(ROOT, COUNTER_FILE), "w") as f:
+                               traffic_config(args), pairs, args.mode)
+        with open(os.path.join(ROOT, COUNTER_FILE.format(mode=args.mode)), "w") as f:
             f.write(text)
         print(text)
         return
@@ -869,7 +1035,11 @@ def main():
                       "finalize": ms_k[2] / max(cnt_k[2], 1)},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3),
                      "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": None},
+                     "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": None,
+                     "flop_convention": f"{FLOP_PER_INTERACTION} FP32 operations per "
+                                        "interaction (the operation count of the paper's "
+                                        "inner loop, rsqrt counted once)",
+                     "kernel_ms": round(regf_ms, 5), "pairs": pairs},
     }
     rec = counters_from_profile(traffic_config(args))
     if rec is not None:
@@ -879,8 +1049,10 @@ def main():
         out["roofline"]["traffic_unit"] = "bytes per force launch"
         if "fp32_flop" in rec:
             # the second reading of the peak fraction: counted FP32 VALU work
+            # (FMA = 2) of the counter runs over this run's kernel time
             out["pct_fp32_peak_counted"] = round(
                 100.0 * rec["fp32_flop"] / (regf_ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, 2)
+            out["roofline"]["frac_counted"] = round(out["pct_fp32_peak_counted"] / 100.0, 4)
     gpu_out = (acc.cpu().numpy(), jerk.cpu().numpy(), nnb.cpu().numpy(),
                lst[:, :args.cap].cpu().numpy())
     out["lists"] = {"cap": args.cap, "mean": round(float(gpu_out[2].mean()), 2),
@@ -926,8 +1098,15 @@ def main():
             log(f"bench: mode {name}: {out['modes'][name]}")
     nb6.nb6_destroy(ctx)
     del acc, jerk, nnb, lst
+    if not args.no_blocks and args.config == 3:
+        out["blocks"] = block_sweep(args, cfg, nb6, torch, T, host=False, emit=False,
+                                    max_reps=100)
+        log("bench: per-size curve: " + ", ".join(
+            f"{r['N_i']}: {r['call_us']} us" for r in out["blocks"]))
     if not args.no_serving:
         out["serving"] = serving_leg(args, nb6, torch)
+    if not args.no_c5:
+        out["c5"] = c5_leg(args, nb6, torch, not args.no_cpu_baseline, args.cpu_seconds)
     if not args.no_cpu_baseline:
         log("bench: timing the FP64 oracle on a sample of the block ...")
         base, accuracy = cpu_baseline(cl, idx_np, {args.mode: gpu_out, **mode_outs}, args.cap,

@@ -77,7 +77,11 @@ extern "C" {
  * are rounded.  The order is rebuilt from the stored state by
  * nb6_load_particles after a full load and after a cluster's worth of subset
  * updates (it only sets how compact the tiles are, never which pairs are
- * summed).
+ * summed).  A block small enough to share a wavefront's lanes among its
+ * i-particles (at most 256 of them unless the context forces the lanes) is
+ * bound by memory latency, not arithmetic: in this mode it takes the
+ * float-float differences, from the float-float prediction the mode also
+ * writes (as its i-side).
  */
 
 /* Largest neighbour-list capacity of nb6_regular_force. */
@@ -147,8 +151,8 @@ int nb6_load_particles(nb6_ctx *ctx, int cluster, int64_t n,
  *   v_p = v + a dt + jerk dt^2/2     (FP64),
  * and write the j-streams the force kernel reads for every coordinate mode
  * in the bit mask `modes` (NB6_DX_*; 0 means all).  NB6_DX_LOCAL also
- * writes the FP64 prediction of every particle (the i-side of that mode),
- * but marks only its own stream current.  Errors: NB6_ERR_STATE (cluster
+ * writes the float-float prediction of every particle (the i-side of that
+ * mode), but marks only its own stream current.  Errors: NB6_ERR_STATE (cluster
  * not loaded), NB6_ERR_ARG, NB6_ERR_HIP.
  */
 int nb6_predict_j(nb6_ctx *ctx, int cluster, double t_block, int modes,
@@ -245,8 +249,8 @@ int nb6_sync_status(nb6_ctx *ctx, void *stream);
 
 /*
  * Read back the predicted positions and velocities of every particle of the
- * cluster as the j-stream of `dx_mode` holds them (NB6_DX_FF: hi + lo,
- * NB6_DX_FP64 and NB6_DX_LOCAL: the FP64 prediction, NB6_DX_FP32: the
+ * cluster as the j-stream of `dx_mode` holds them (NB6_DX_FF and
+ * NB6_DX_LOCAL: hi + lo, NB6_DX_FP64: the FP64 prediction, NB6_DX_FP32: the
  * float), widened to
  * double: x[N][3], v[N][3].  For checks of the predictor (section 3.3 step 3)
  * and for callers that want the predicted state.  Errors: NB6_ERR_STATE when

@@ -452,7 +452,7 @@ int nb6_predict_j(nb6_ctx* c, int cluster, double t_block, int modes, void* stre
     const int bits[NMODES] = {NB6_DX_FF, NB6_DX_FP64, NB6_DX_FP32, NB6_DX_LOCAL};
     const bool loc = (modes & NB6_DX_LOCAL) != 0;
     for (int mi = 0; mi < NMODES; ++mi) {
-        if (!(modes & bits[mi]) && !(loc && mi == MODE_F64)) continue;
+        if (!(modes & bits[mi]) && !(loc && mi == MODE_FF)) continue;
         int rc = ensure(c, cl->rec[mi], (size_t)cl->n * rec_size(mi));
         if (rc) return rc;
     }
@@ -469,11 +469,12 @@ int nb6_predict_j(nb6_ctx* c, int cluster, double t_block, int modes, void* stre
     TimedLaunch tl(c, 0, (hipStream_t)stream);
     if (pa.ff || pa.f64 || pa.f32) HIP_TRY(c, launch_predict(pa, (hipStream_t)stream));
     if (loc) {
-        // the local stream, and the FP64 prediction by index as its i-side
+        // the local stream, and the float-float prediction by index as its
+        // i-side (and small blocks' stream)
         PredictArgs pl = pa;
-        pl.ff = nullptr;
+        pl.f64 = nullptr;
         pl.f32 = nullptr;
-        pl.f64 = (RecF64*)cl->rec[MODE_F64].p;
+        pl.ff = (RecFF*)cl->rec[MODE_FF].p;
         pl.loc = (RecLoc*)cl->rec[MODE_LOC].p;
         pl.org = (TileOrg*)cl->org.p;
         pl.perm = (const int32_t*)cl->perm.p;
@@ -550,6 +551,11 @@ static size_t force_scratch_layout(const Plan& p, int ni, int npart, int caps, s
 static int launch_force_call(nb6_ctx* c, const ClusterState* cl, int mi, int ni, int cap,
                              const Plan& p, const ForceIO& io, const ForceScratch& fs,
                              hipStream_t st, bool timed) {
+    // A small block (lanes per i) is latency-bound, not issue-bound: in the
+    // local mode it runs on the float-float records by particle index that
+    // the local stream's prediction also writes (its i-side), where each
+    // lane's records need no tile centre.
+    if (mi == MODE_LOC && p.jl_shift > 0) mi = MODE_FF;
     RegfArgs ra{};
     ra.rec = cl->rec[mi].p;
     ra.n = (int)cl->n;
@@ -563,7 +569,7 @@ static int launch_force_call(nb6_ctx* c, const ClusterState* cl, int mi, int ni,
     ra.tmax = (const float*)cl->tmax.p;
     if (mi == MODE_LOC) {
         ra.org = (const TileOrg*)cl->org.p;
-        ra.ivw = cl->rec[MODE_F64].p;
+        ra.ivw = cl->rec[MODE_FF].p;
     }
     ra.part = fs.part;
     ra.cnt = fs.cnt;
@@ -836,9 +842,9 @@ int nb6_get_predicted(nb6_ctx* c, int cluster, int dx_mode, double* x, double* v
         dx = (double*)c->io.p;
         dv = (double*)((char*)c->io.p + o_v);
     }
-    // the local stream's positions are those of the FP64 prediction it
-    // was formed from (the records hold tile offsets)
-    const int um = mi == MODE_LOC ? MODE_F64 : mi;
+    // the local stream's positions are those of the float-float prediction
+    // written with it (the records hold tile offsets)
+    const int um = mi == MODE_LOC ? MODE_FF : mi;
     HIP_TRY(c, launch_unpack(um, cl->rec[um].p, n, dx, dv, st));
     if (mem_kind == NB6_MEM_HOST) {
         HIP_TRY(c, hipMemcpyAsync(x, dx, 3 * n * sizeof(double), hipMemcpyDeviceToHost, st));

@@ -115,7 +115,7 @@ struct RegfArgs {
     int            jl_shift;  // log2 of the lanes that share one i (0: one lane per i)
     const float*   tmax;      // [vtiles(n)] max of vabs over each tile of VTILE j
     const TileOrg* org;       // MODE_LOC: [vtiles(n)] tile centres (else null)
-    const void*    ivw;       // MODE_LOC: FP64 records by particle (the i-side)
+    const void*    ivw;       // MODE_LOC: float-float records by particle (the i-side)
     double*        part;      // [ceil(ni/64)][nslices][NPART or NPART_POT][64]
     int32_t*       cnt;       // [ni] neighbours found, the i itself included (zero on
                               // entry; the finalize leaves it zero again)
@@ -143,7 +143,7 @@ struct FinalArgs {
     unsigned*      status;
     // the ordered rescan of an overflowed list: the force call's records,
     // their coordinate mode (MODE_*) and the i's dtr; for MODE_LOC also the
-    // tile centres, the slot of each particle and the FP64 records
+    // tile centres, the slot of each particle and the float-float records
     const void*    rec;
     const double*  dtr;
     int            mode;
@@ -176,7 +176,8 @@ struct PredictArgs {
     float*        tmax; // [vtiles(n)] max vabs per tile (always written)
     unsigned*     status;
     // the local-coordinate stream (launch_predict_loc): slot k of `loc`
-    // holds particle perm[k]; `f64` receives every particle's FP64 record
+    // holds particle perm[k]; `ff` receives every particle's float-float
+    // record
     RecLoc*        loc;
     TileOrg*       org;  // [vtiles(n)]
     const int32_t* perm;
@@ -310,7 +311,7 @@ hipError_t launch_regf(int mode, int ipl, int waves_per_block, bool pot, const R
 __host__ __device__ inline int regf_group_size(int ipl, int jl_shift) { return (64 * ipl) >> jl_shift; }
 hipError_t launch_finalize(const FinalArgs& a, hipStream_t s);
 hipError_t launch_predict(const PredictArgs& a, hipStream_t s);
-// The local-coordinate stream: a.loc, a.org and a.f64 from a.perm.
+// The local-coordinate stream: a.loc, a.org and a.ff from a.perm.
 hipError_t launch_predict_loc(const PredictArgs& a, hipStream_t s);
 // Spatial order of a cluster from its stored positions: perm[slot] =
 // particle (Morton order, ties by index) and inv[particle] = slot.  scratch

@@ -63,9 +63,10 @@ template <> struct RecOf<MODE_F32> { using T = RecF32; };
 template <> struct RecOf<MODE_LOC> { using T = RecLoc; };
 
 // The record an i-particle's own state is read from: its j-record, except in
-// the local mode, whose i-side is the FP64 prediction by particle index.
+// the local mode, whose i-side is the float-float prediction by particle
+// index (hi + lo, exact in FP64).
 template <int MODE> struct IRecOf { using T = typename RecOf<MODE>::T; };
-template <> struct IRecOf<MODE_LOC> { using T = RecF64; };
+template <> struct IRecOf<MODE_LOC> { using T = RecFF; };
 
 // i-side coordinates.  In the local mode, c is (tile centre - R_i) rounded to
 // FP32, formed in FP64 on entry to each tile of j (tile_enter).
@@ -96,8 +97,10 @@ __device__ __forceinline__ void get_ipos(const RecF32& r, IPos<MODE_F32>& p, IAu
     p.x = r.x; p.y = r.y; p.z = r.z;
     take_vel(r, v);
 }
-__device__ __forceinline__ void get_ipos(const RecF64& r, IPos<MODE_LOC>& p, IAux& v) {
-    p.x = r.x; p.y = r.y; p.z = r.z;
+__device__ __forceinline__ void get_ipos(const RecFF& r, IPos<MODE_LOC>& p, IAux& v) {
+    p.x = (double)r.xh + (double)r.xl;
+    p.y = (double)r.yh + (double)r.yl;
+    p.z = (double)r.zh + (double)r.zl;
     p.cx = p.cy = p.cz = 0.0f;
     take_vel(r, v);
 }
@@ -910,19 +913,21 @@ __device__ __forceinline__ RecF64 f64_record(const Predicted& P) {
     return r;
 }
 
+__device__ __forceinline__ RecFF ff_record(const Predicted& P) {
+    RecFF r;
+    r.xh = (float)P.xp[0]; r.xl = (float)(P.xp[0] - (double)r.xh);
+    r.yh = (float)P.xp[1]; r.yl = (float)(P.xp[1] - (double)r.yh);
+    r.zh = (float)P.xp[2]; r.zl = (float)(P.xp[2] - (double)r.zh);
+    r.m = P.m; r.vabs = P.vabs;
+    r.vx = P.vf[0]; r.vy = P.vf[1]; r.vz = P.vf[2]; r.pad = 0.0f;
+    return r;
+}
+
 // Predicts particle k, writes its record of each requested mode in index
 // order, and returns its vabs.
 __device__ __forceinline__ float predict_one(const PredictArgs& a, const int64_t k) {
     const Predicted P = predict_particle(a, k);
-    if (a.ff) {
-        RecFF r;
-        r.xh = (float)P.xp[0]; r.xl = (float)(P.xp[0] - (double)r.xh);
-        r.yh = (float)P.xp[1]; r.yl = (float)(P.xp[1] - (double)r.yh);
-        r.zh = (float)P.xp[2]; r.zl = (float)(P.xp[2] - (double)r.zh);
-        r.m = P.m; r.vabs = P.vabs;
-        r.vx = P.vf[0]; r.vy = P.vf[1]; r.vz = P.vf[2]; r.pad = 0.0f;
-        a.ff[k] = r;
-    }
+    if (a.ff) a.ff[k] = ff_record(P);
     if (a.f64) a.f64[k] = f64_record(P);
     if (a.f32) {
         RecF32 r;
@@ -950,8 +955,9 @@ __global__ void __launch_bounds__(256) predict_kernel(PredictArgs a) {
 
 // Slot k of the local-coordinate stream, by every lane of a VTILE-aligned
 // group of lanes holding slots k0 .. k0 + VTILE - 1 (lanes past the end take
-// part with empty values): predicts particle perm[k] and writes its FP64
-// record (by particle index); then the tile's centre -- the midpoint of the
+// part with empty values): predicts particle perm[k] and writes its
+// float-float record (by particle index); then the tile's centre -- the
+// midpoint of the
 // bounding box of its predicted positions, in FP64 -- and largest vabs go to
 // org[k0 / VTILE], and the slot's record holds the FP32 rounding of the
 // offset from that centre.
@@ -962,7 +968,7 @@ __device__ __forceinline__ void predict_loc_slot(const PredictArgs& a, const int
     if (live) {
         p = a.perm[k];
         P = predict_particle(a, p);
-        a.f64[p] = f64_record(P);
+        a.ff[p] = ff_record(P);
     }
     double lo[3], hi[3];
 #pragma unroll
@@ -1120,7 +1126,7 @@ hipError_t launch_predict(const PredictArgs& a, hipStream_t s) {
 
 hipError_t launch_predict_loc(const PredictArgs& a, hipStream_t s) {
     if (a.n <= 0) return hipSuccess;
-    if (!a.loc || !a.org || !a.perm || !a.f64) return hipErrorInvalidValue;
+    if (!a.loc || !a.org || !a.perm || !a.ff) return hipErrorInvalidValue;
     dim3 grid((unsigned)((a.n + 255) / 256));
     hipLaunchKernelGGL(predict_loc_kernel, grid, dim3(256), 0, s, a);
     return hipGetLastError();

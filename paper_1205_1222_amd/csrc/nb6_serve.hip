@@ -99,6 +99,8 @@ struct ServeReq {
     uint64_t ticket = 0;
     nb6_request rq{};
     int mi = 0;
+    int km = 0;             // the force kernel's mode: mi, except float-float
+                            // for a local-mode request of the lanes-per-i class
     Plan plan{};
     size_t bytes = 0, off = 0;
     ClusterState* cl = nullptr;
@@ -294,17 +296,19 @@ class Engine {
                 if (int rc = ensure(c_, r->cl->tmax, (size_t)vtiles(r->cl->n) * sizeof(float)))
                     return rc;
             }
-            if (r->mi == MODE_LOC) {  // the FP64 i-side and the tile centres
+            if (r->mi == MODE_LOC) {  // the float-float i-side and the tile centres
                 if (!r->cl->order_valid)
                     return fail(c_, NB6_ERR_STATE, "cluster %d has no spatial order", rq->cluster);
                 int rc = NB6_OK;
-                if ((!r->cl->rec[MODE_F64].p &&
-                     (rc = ensure(c_, r->cl->rec[MODE_F64], (size_t)r->cl->n * sizeof(RecF64)))) ||
+                if ((!r->cl->rec[MODE_FF].p &&
+                     (rc = ensure(c_, r->cl->rec[MODE_FF], (size_t)r->cl->n * sizeof(RecFF)))) ||
                     (!r->cl->org.p &&
                      (rc = ensure(c_, r->cl->org, (size_t)vtiles(r->cl->n) * sizeof(TileOrg)))))
                     return rc;
             }
             r->plan = make_plan(c_, r->cl->n, ni);
+            // a small block runs on the float-float records (the plain call's rule)
+            r->km = (r->mi == MODE_LOC && serve_class(r->plan) == SERVE_LANES) ? MODE_FF : r->mi;
             r->n_submit = r->cl->n;
             // held until the request finishes: the cluster keeps its size and
             // buffers meanwhile
@@ -393,7 +397,7 @@ class Engine {
         const ClusterState* cl = r->cl;
         return cl->n == r->n_submit && cl->state && cl->rec[r->mi].p && cl->tmax.p &&
                (r->mi != MODE_LOC || (cl->org.p && cl->perm.p && cl->inv.p &&
-                                      cl->rec[MODE_F64].p && cl->order_valid));
+                                      cl->rec[MODE_FF].p && cl->order_valid));
     }
 
     void sched_loop() {
@@ -572,7 +576,7 @@ class Engine {
         std::vector<ServeReq*>& reqs = sl.reqs;
         // one persistent launch per (mode, work-partition class) present
         auto launch_class = [](const ServeReq* r) {
-            return r->mi * SERVE_CLASSES + serve_class(r->plan);
+            return r->km * SERVE_CLASSES + serve_class(r->plan);
         };
         std::stable_sort(reqs.begin(), reqs.end(), [&](const ServeReq* a, const ServeReq* b) {
             return launch_class(a) < launch_class(b);
@@ -629,8 +633,8 @@ class Engine {
             d.pred.ff = r->mi == MODE_FF ? (RecFF*)cl->rec[MODE_FF].p : nullptr;
             d.pred.f64 = r->mi == MODE_F64 ? (RecF64*)cl->rec[MODE_F64].p : nullptr;
             d.pred.f32 = r->mi == MODE_F32 ? (RecF32*)cl->rec[MODE_F32].p : nullptr;
-            if (r->mi == MODE_LOC) {  // the local stream and its FP64 i-side
-                d.pred.f64 = (RecF64*)cl->rec[MODE_F64].p;
+            if (r->mi == MODE_LOC) {  // the local stream and its float-float i-side
+                d.pred.ff = (RecFF*)cl->rec[MODE_FF].p;
                 d.pred.loc = (RecLoc*)cl->rec[MODE_LOC].p;
                 d.pred.org = (TileOrg*)cl->org.p;
                 d.pred.perm = (const int32_t*)cl->perm.p;
@@ -638,7 +642,7 @@ class Engine {
             d.pred.tmax = (float*)cl->tmax.p;
             d.pred.status = status;
             const Plan& p = r->plan;
-            d.rg.rec = cl->rec[r->mi].p;
+            d.rg.rec = cl->rec[r->km].p;
             d.rg.n = (int)cl->n;
             d.rg.idx = r->d_idx; d.rg.h2 = r->d_h2; d.rg.dtr = r->d_dtr;
             d.rg.ni = ni;
@@ -646,9 +650,9 @@ class Engine {
             d.rg.nslices = p.nslices;
             d.rg.jl_shift = p.jl_shift;
             d.rg.tmax = (const float*)cl->tmax.p;
-            if (r->mi == MODE_LOC) {
+            if (r->km == MODE_LOC) {
                 d.rg.org = (const TileOrg*)cl->org.p;
-                d.rg.ivw = cl->rec[MODE_F64].p;
+                d.rg.ivw = cl->rec[MODE_FF].p;
             }
             d.rg.part = r->part; d.rg.cnt = r->cnt; d.rg.lst = r->lst;
             d.rg.caps = r->rq.cap + 1;
@@ -658,10 +662,10 @@ class Engine {
             d.fin.n = (int)cl->n; d.fin.idx = r->d_idx; d.fin.h2 = r->d_h2;
             d.fin.acc = r->d_acc; d.fin.jerk = r->d_jerk; d.fin.nnb = r->d_nnb;
             d.fin.list = r->d_list; d.fin.cap = r->rq.cap; d.fin.status = status;
-            d.fin.rec = d.rg.rec; d.fin.dtr = r->d_dtr; d.fin.mode = r->mi;
+            d.fin.rec = d.rg.rec; d.fin.dtr = r->d_dtr; d.fin.mode = r->km;
             d.fin.org = d.rg.org; d.fin.ivw = d.rg.ivw;
-            d.fin.inv = r->mi == MODE_LOC ? (const int32_t*)cl->inv.p : nullptr;
-            d.mode = r->mi;
+            d.fin.inv = r->km == MODE_LOC ? (const int32_t*)cl->inv.p : nullptr;
+            d.mode = r->km;
             const int gsize = regf_group_size(p.ipl, p.jl_shift);
             d.groups = (ni + gsize - 1) / gsize;
             d.item0 = item_in_mode;
@@ -691,7 +695,7 @@ class Engine {
                 items += (long long)sl.host_desc()[e].groups * reqs[e]->plan.nslices;
                 ++e;
             }
-            const int mi = reqs[b]->mi, k = serve_class(reqs[b]->plan);
+            const int mi = reqs[b]->km, k = serve_class(reqs[b]->plan);
             const long long fit = (long long)c_->num_cu * blocks_per_cu_[mi][k];
             const int blocks = (int)std::min<long long>(fit, (items + 3) / 4);
             BatchArgs g{};

@@ -101,7 +101,7 @@ def test_committed_record_matches_the_sources():
     the benchmark's default configuration, so the benchmark reports its
     traffic (skipped, with the reason, while the kernels have changed since
     the counters were taken: the benchmark then reports null)."""
-    args = bench.argparse.Namespace(config=3, block="all", mode="ff", cap=256, ipl=0,
+    args = bench.argparse.Namespace(config=3, block="all", mode="local", cap=256, ipl=0,
                                     slices=0, lanes=0)
     rec = bench.counters_from_profile(bench.traffic_config(args))
     if rec is None:

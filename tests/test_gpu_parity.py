@@ -97,7 +97,7 @@ def test_predict_matches_oracle(ctx):
     load(ctx, cl)
     xo, vo = oracle.predict(cl.x, cl.v, cl.a, cl.jerk, cl.t, cl.tb)
     for mode, tol_x in (("fp64", 1e-15), ("ff", 1e-14), ("fp32", 2.0 ** -23),
-                        ("local", 1e-15)):
+                        ("local", 1e-14)):
         x = np.empty((cl.n, 3))
         v = np.empty((cl.n, 3))
         nb6.check(ctx, nb6.nb6_get_predicted(ctx, 0, MODES[mode], x, v))
