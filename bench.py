@@ -446,7 +446,9 @@ def serving_leg(args, nb6, torch):
                           "max_batch": int(batch.max()),
                           # submit -> admission, and admission -> completion
                           "queue_p50_ms": q(admit - sub, 0.5),
-                          "exec_p50_ms": q(done - admit, 0.5)},
+                          "queue_p99_ms": q(admit - sub, 0.99),
+                          "exec_p50_ms": q(done - admit, 0.5),
+                          "exec_p99_ms": q(done - admit, 0.99)},
                "plain": {"p50_ms": q(lat_plain, 0.5), "p99_ms": q(lat_plain, 0.99),
                          "ginteractions_s": round(total / span_plain / 1e9, 3)}}
         log(f"bench: rho={rho}: served p50/p99 = {run['served']['p50_ms']}/"
