@@ -122,7 +122,7 @@ def counter_summary(fetch_csv, write_csv, valu_csv, copy_mib, config_line, pairs
         return os.path.relpath(os.path.dirname(os.path.abspath(csv_path)), ROOT)
 
     cmd = ("python3 bench.py --steps 2 --warmup 1 --no-serving --no-cpu-baseline --no-irregular "
-           "--no-potential --no-corrector --no-load --no-modes --no-blocks --no-c5 "
+           "--no-potential --no-corrector --no-load --no-modes --no-blocks --no-c5 --no-small "
            f"--mode {mode} --copy-mib {copy_mib}")
     lines = [
         f"# Counters of the force kernel, Plummer N = 131072, all 131072 active ({mode} coordinates)",
@@ -774,6 +774,75 @@ def block_sweep(args, cfg, nb6, torch, T, lanes=0, slices=None, max_ni=None, max
     return records
 
 
+def small_config_leg(ci, block, args, nb6, torch, with_oracle):
+    """A parity configuration as a measured line: C1 (1024 bodies, all
+    active) or C2 (16384 bodies, a random block of 1024 on stored state
+    predicted to the block time).  Every coordinate mode: wall time per call
+    back to back (device arrays), force and finalize kernel times, rate; and
+    its accuracy on the whole block against the oracle."""
+    import oracle
+    from oracle.compare import compare
+    from workloads import config
+
+    cfg = config(ci)
+    cl = cfg["cluster"]
+    idx = cfg["blocks"][block]
+    n, ni = cl.n, len(idx)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    T = lambda a, dt=torch.float64: torch.from_numpy(np.ascontiguousarray(a)).to(dev, dt)  # noqa: E731
+    cap = args.cap
+    res = {"workload": cfg["description"] + f"; block {block}", "N": n, "N_i": ni,
+           "list_cap": cap, "modes": {}}
+    ctx = nb6.nb6_create(0, flags=nb6.NB6_OPT_TIMING)
+    try:
+        nb6.check(ctx, nb6.nb6_load_particles(ctx, 0, n, cl.m, cl.x, cl.v, cl.a, cl.jerk, cl.t))
+        nb6.check(ctx, nb6.nb6_predict_j(ctx, 0, cl.tb, 0, stream))
+        idx_d, h2_d, dtr_d = T(idx, torch.int32), T(cl.h2[idx]), T(cl.dtr[idx])
+        acc = torch.empty((ni, 3), dtype=torch.float64, device=dev)
+        jerk = torch.empty_like(acc)
+        nnb = torch.empty(ni, dtype=torch.int32, device=dev)
+        lst = torch.empty((ni, cap), dtype=torch.int32, device=dev)
+        pairs = ni * (n - 1)
+        if with_oracle:
+            xp, vp = oracle.predict(cl.x, cl.v, cl.a, cl.jerk, cl.t, cl.tb)
+            ref = oracle.regular_force(cl.m, xp, vp, idx, cl.h2[idx], cl.dtr[idx], lcap=4096)
+        for name in [args.mode] + [m for m in sorted(MODES) if m != args.mode]:
+            def call():
+                nb6.check(ctx, nb6.nb6_regular_force(ctx, 0, ni, idx_d, h2_d, dtr_d, MODES[name],
+                                                     acc, jerk, nnb, lst, cap,
+                                                     nb6.NB6_MEM_DEVICE, stream))
+            call()
+            torch.cuda.synchronize()
+            nb6.nb6_kernel_times(ctx)
+            reps = 50
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                call()
+            torch.cuda.synchronize()
+            wall = (time.perf_counter() - t0) / reps
+            ms, cnt = nb6.nb6_kernel_times(ctx)
+            rec = {"call_us": round(wall * 1e6, 2),
+                   "force_us": round(ms[1] / max(cnt[1], 1) * 1e3, 2),
+                   "finalize_us": round(ms[2] / max(cnt[2], 1) * 1e3, 2),
+                   "ginteractions_s": round(pairs / wall / 1e9, 3),
+                   "plan": nb6.nb6_last_plan(ctx)}
+            if with_oracle:
+                summ = compare(acc.cpu().numpy(), jerk.cpu().numpy(), nnb.cpu().numpy(),
+                               lst.cpu().numpy(), cap, ref, cl.m, xp, vp, idx, cl.h2[idx],
+                               cl.dtr[idx]).summary()
+                keys = ("n_i", "list_mismatch", "exempt_pairs", "nnb_mismatch", "acc_rel_max",
+                        "acc_scaled_max", "jerk_rel_max", "jerk_scaled_max")
+                rec["accuracy"] = {k: summ[k] for k in keys if k in summ}
+            res["modes"][name] = rec
+        nb6.check(ctx, nb6.nb6_sync_status(ctx, stream))
+    finally:
+        nb6.nb6_destroy(ctx)
+    log(f"bench: C{ci} {block}: " + ", ".join(
+        f"{k} {v['call_us']} us" for k, v in res["modes"].items()))
+    return res
+
+
 def c5_leg(args, nb6, torch, with_oracle, cpu_seconds):
     """C5: the 2^20-body Plummer sphere (equal masses, ~100 neighbours).  Every
     coordinate mode's force on all 2^20 active particles (force-kernel time
@@ -889,6 +958,8 @@ def main():
                     help="skip the other coordinate modes' rate and accuracy")
     ap.add_argument("--no-c5", action="store_true",
                     help="skip the 2^20-body configuration's rates and accuracy")
+    ap.add_argument("--no-small", action="store_true",
+                    help="skip the C1 and C2 configurations' rates and accuracy")
     ap.add_argument("--no-blocks", action="store_true",
                     help="skip the per-size curve (every power-of-two block of C3)")
     ap.add_argument("--no-serve-check", dest="serve_check", action="store_false",
@@ -1107,6 +1178,9 @@ def main():
             f"{r['N_i']}: {r['call_us']} us" for r in out["blocks"]))
     if not args.no_serving:
         out["serving"] = serving_leg(args, nb6, torch)
+    if not args.no_small:
+        out["c1"] = small_config_leg(1, "all", args, nb6, torch, not args.no_cpu_baseline)
+        out["c2"] = small_config_leg(2, "random1024", args, nb6, torch, not args.no_cpu_baseline)
     if not args.no_c5:
         out["c5"] = c5_leg(args, nb6, torch, not args.no_cpu_baseline, args.cpu_seconds)
     if not args.no_cpu_baseline:
