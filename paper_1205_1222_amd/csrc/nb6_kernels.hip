@@ -35,10 +35,13 @@
 //   * The velocity criterion is evaluated only for candidate pairs inside a
 //     conservative radius, behind a branch that a wavefront almost never
 //     takes.
-//   * A neighbour is appended to its i's list with one atomic slot
-//     reservation; the finalize kernel sorts each list.  A list that
-//     overflows its capacity is rebuilt by an ordered scan, so the result is
-//     always the first `cap` neighbours in ascending j.
+//   * A lane keeps the neighbours it finds for an i in a short run in its
+//     own LDS column and moves a full run, and what is left at the end of
+//     the work item, to the i's list with one atomic slot reservation (a
+//     returning atomic per neighbour would stall the wavefront on every
+//     one); the finalize kernel sorts each list.  A list that overflows its
+//     capacity is rebuilt by an ordered scan, so the result is always the
+//     first `cap` neighbours in ascending j.
 //   * A call is two launches, force and finalize: the finalize leaves the
 //     per-i counters at zero for the next call, and rescans overflowed lists
 //     itself.
@@ -55,6 +58,91 @@ namespace nb6 {
 
 constexpr int TILE = VTILE; // j per FP32 tile before the FP64 fold
 constexpr int JG = 4;       // j-records loaded together
+constexpr int RUN = 16;     // staged neighbours per lane (split among its i)
+constexpr int WAVES = 4;    // most wavefronts in a force workgroup (256 threads)
+// LDS of a force workgroup of wpb wavefronts: RUN entries per lane.
+constexpr size_t run_lds_bytes(int wpb) { return (size_t)wpb * RUN * 64 * sizeof(int); }
+
+// A lane's run of neighbours found for one list row, in LDS: entry e of
+// lane l at run[64 e + l] (the wavefront's lanes interleaved, so the 64
+// lanes' stores of one entry hit distinct banks).  The lane's row is
+// row0 + (l >> shift); run, row0 and shift are wave-uniform, so n is the
+// lane's only register.  flush() reserves n slots of the row with one atomic
+// add on its counter and copies the run there; a neighbour found while the
+// run is full takes a slot of its own.  Slots at or past the row capacity
+// are dropped (the counter still counts them, and the finalize rebuilds such
+// a list by its ordered rescan).  The row thus ends with the same entries as
+// with one reservation per neighbour, in another order, which the
+// finalize's sort removes.  Flushes happen between tiles of j (flush_half)
+// and at the end of the work item.
+template <int N>
+struct Staged {
+    int* run;
+    int row0, shift;
+    int n;
+
+    // The lane id, opaque to the optimiser: what is derived from it stays on
+    // the rare path that needs it instead of being kept live across the j
+    // loop in registers.
+    __device__ __forceinline__ static int lane() {
+        int l = (int)__lane_id();
+        __asm__ volatile("" : "+v"(l));
+        return l;
+    }
+    __device__ __forceinline__ void flush(const RegfArgs& a) {
+        if (n > 0) {
+            const int l = lane();
+            const int row = row0 + (l >> shift);
+            const int base = atomicAdd(a.cnt + row, n);
+            int* out = a.lst + (size_t)row * a.caps;
+#pragma unroll 1
+            for (int e = 0; e < n; ++e)
+                if (base + e < a.caps) out[base + e] = run[64 * e + l];
+            n = 0;
+        }
+    }
+    __device__ __forceinline__ void flush_half(const RegfArgs& a) {
+        if (n >= N / 2) flush(a);
+    }
+    // The flush of a wavefront whose 2^shift consecutive lanes share a row,
+    // called by the whole wavefront: the lanes of a row add up their run
+    // lengths (a scan over the row's lanes), its first lane reserves the
+    // total with one atomic add, and each lane copies its run to the slots
+    // after those of the row's lower lanes.  A row's lanes would otherwise
+    // send their reservations to one counter, where they are served one by
+    // one.
+    __device__ __forceinline__ void flush_shared(const RegfArgs& a) {
+        const int l = lane();
+        const int w = 1 << shift;
+        const int r = l & (w - 1);  // the lane's place among its row's lanes
+        int incl = n;
+        for (int d = 1; d < w; d <<= 1) {
+            const int t = __shfl_up(incl, d, w);
+            if (r >= d) incl += t;
+        }
+        const int total = __shfl(incl, w - 1, w);
+        const int row = row0 + (l >> shift);
+        int base = 0;
+        if (r == 0 && total > 0) base = atomicAdd(a.cnt + row, total);
+        base = __shfl(base, 0, w) + (incl - n);
+        int* out = a.lst + (size_t)row * a.caps;
+#pragma unroll 1
+        for (int e = 0; e < n; ++e)
+            if (base + e < a.caps) out[base + e] = run[64 * e + l];
+        n = 0;
+    }
+    __device__ __forceinline__ void push(int j, const RegfArgs& a) {
+        const int l = lane();
+        if (n < N) {
+            run[64 * n + l] = j;
+            ++n;
+        } else {
+            const int row = row0 + (l >> shift);
+            const int k = atomicAdd(a.cnt + row, 1);
+            if (k < a.caps) a.lst[(size_t)row * a.caps + k] = j;
+        }
+    }
+};
 
 template <int MODE> struct RecOf;
 template <> struct RecOf<MODE_FF>  { using T = RecFF; };
@@ -178,8 +266,8 @@ __device__ __forceinline__ float sq_bound(const IAux& ia, float w) {
 //   sum[0..2] += g R                  (acceleration),
 //   sum[3..5] += g (V - s R)          (its time derivative, the jerk),
 //   sum[6]    += m_j u                (when NP == 7: the potential sum),
-// unless j is a neighbour of i (section 3.2), which is then appended to i's
-// list and contributes u = 0 instead.
+// unless j is a neighbour of i (section 3.2), which is then added to the
+// lane's run for i's list row and contributes u = 0 instead.
 //
 // The criterion runs only for candidate pairs, |R|^2 < bnd2, where
 // bnd2 = (c_i + dtr_i w)^2 for some w >= |v_j| (the caller's choice: v_j's
@@ -188,10 +276,11 @@ __device__ __forceinline__ float sq_bound(const IAux& ia, float w) {
 // margin inside c_i covers the FP32 rounding of every quantity involved, so
 // the decision is that of the criterion alone.  A wavefront takes the branch
 // only when one of its lanes is near j.
-template <int MODE, int NP>
+template <int MODE, int NP, int N>
 __device__ __forceinline__ void pair_term(const typename RecOf<MODE>::T& r, int slot,
                                           const IPos<MODE>& ip, const IAux& ia, float bnd2,
-                                          float sum[NP], int row, const RegfArgs& a) {
+                                          float sum[NP], Staged<N>& stg,
+                                          const RegfArgs& a) {
     float R[3];
     coord_diff(r, ip, R);
     const float V[3] = {r.vx - ia.vx, r.vy - ia.vy, r.vz - ia.vz};
@@ -204,8 +293,7 @@ __device__ __forceinline__ void pair_term(const typename RecOf<MODE>::T& r, int 
         // instructions per interaction).  Emits no instruction.
         __asm__ volatile("");
         if (velocity_criterion(r2, R[0], R[1], R[2], V[0], V[1], V[2], ia.dtr, ia.h2)) {
-            const int k = atomicAdd(a.cnt + row, 1);
-            if (k < a.caps) a.lst[(size_t)row * a.caps + k] = j_index(r, slot);
+            stg.push(j_index(r, slot), a);
             u = 0.0f;
         }
     }
@@ -318,11 +406,18 @@ __device__ __forceinline__ int load_i(const RegfArgs& a, const int q, const int 
     return live ? q : 0;
 }
 
+// The wavefront's part of its workgroup's run storage (RUN entries per lane,
+// wavefront after wavefront).
+__device__ __forceinline__ int* run_wave(int* runs) {
+    return runs + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * (RUN * 64);
+}
+
 // Force, jerk and neighbour appends of one (i-group, j-slice) work item:
 // 64 * IPL active particles starting at group * 64 * IPL, against the
-// j-particles of slice s.
+// j-particles of slice s.  runs: the wavefront's run storage (run_wave).
 template <int MODE, int IPL, int NP>
-__device__ __forceinline__ void regf_item(const RegfArgs& a, const int group, const int s) {
+__device__ __forceinline__ void regf_item(const RegfArgs& a, const int group, const int s,
+                                          int* runs) {
     using Rec = typename RecOf<MODE>::T;
     const_ptr<Rec> rec = (const_ptr<Rec>)(a.rec);
     const int lane = threadIdx.x & 63;
@@ -334,6 +429,15 @@ __device__ __forceinline__ void regf_item(const RegfArgs& a, const int group, co
     for (int k = 0; k < IPL; ++k) (void)load_i<MODE>(a, ibase + k * 64 + lane, s, ip[k], ia[k]);
     // A lane's list row is its q = ibase + k * 64 + lane, recomputed from the
     // lane id where it is needed (lanes without a valid i never append).
+    constexpr int N = RUN / IPL;
+    Staged<N> stg[IPL];
+#pragma unroll
+    for (int k = 0; k < IPL; ++k) {
+        stg[k].run = runs + k * N * 64;
+        stg[k].row0 = ibase + k * 64;
+        stg[k].shift = 0;
+        stg[k].n = 0;
+    }
 
     const int j0 = s * a.slice_len;
     const int j1 = min(j0 + a.slice_len, a.n);
@@ -371,21 +475,24 @@ __device__ __forceinline__ void regf_item(const RegfArgs& a, const int group, co
             for (int g = 0; g < G; ++g)
 #pragma unroll
                 for (int k = 0; k < IPL; ++k)
-                    pair_term<MODE, NP>(r[g], j + g, ip[k], ia[k], bnd2[k], run[k],
-                                        ibase + k * 64 + (int)__lane_id(), a);
+                    pair_term<MODE, NP, N>(r[g], j + g, ip[k], ia[k], bnd2[k], run[k],
+                                           stg[k], a);
         }
         for (; j < je; ++j) {
             const Rec r = load_rec(rec + j);
 #pragma unroll
             for (int k = 0; k < IPL; ++k)
-                pair_term<MODE, NP>(r, j, ip[k], ia[k], bnd2[k], run[k],
-                                    ibase + k * 64 + (int)__lane_id(), a);
+                pair_term<MODE, NP, N>(r, j, ip[k], ia[k], bnd2[k], run[k], stg[k], a);
         }
 #pragma unroll
         for (int k = 0; k < IPL; ++k)
 #pragma unroll
             for (int c = 0; c < NP; ++c) sum[k][c] += (double)run[k][c];
+#pragma unroll
+        for (int k = 0; k < IPL; ++k) stg[k].flush_half(a);
     }
+#pragma unroll
+    for (int k = 0; k < IPL; ++k) stg[k].flush(a);
 
     // partial sums by 64-particle block: part[q / 64][s][c][q % 64], so each
     // component of a wave's 64 particles is one contiguous 512-byte store
@@ -407,7 +514,7 @@ __device__ __forceinline__ void regf_item(const RegfArgs& a, const int group, co
 template <int MODE, int NP, int G>
 __device__ __forceinline__ void lane_terms(const RegfArgs& a, const typename RecOf<MODE>::T* r,
                                            int j, int jl, IPos<MODE>& ip, const IAux& ia,
-                                           float run[NP], int row) {
+                                           float run[NP], Staged<RUN>& stg) {
     if constexpr (MODE == MODE_LOC) {
         TileOrg o[G];
 #pragma unroll
@@ -415,12 +522,14 @@ __device__ __forceinline__ void lane_terms(const RegfArgs& a, const typename Rec
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             tile_enter<MODE>(ip, o[g].x, o[g].y, o[g].z);
-            pair_term<MODE, NP>(r[g], j + g * jl, ip, ia, sq_bound(ia, o[g].vmax), run, row, a);
+            pair_term<MODE, NP, RUN>(r[g], j + g * jl, ip, ia, sq_bound(ia, o[g].vmax), run, stg,
+                                     a);
         }
     } else {
 #pragma unroll
         for (int g = 0; g < G; ++g)
-            pair_term<MODE, NP>(r[g], j + g * jl, ip, ia, sq_bound(ia, r[g].vabs), run, row, a);
+            pair_term<MODE, NP, RUN>(r[g], j + g * jl, ip, ia, sq_bound(ia, r[g].vabs), run, stg,
+                                     a);
     }
 }
 
@@ -433,8 +542,8 @@ __device__ __forceinline__ void lane_terms(const RegfArgs& a, const typename Rec
 // first of them stores the partial.  Used when the active block is too small
 // to give every lane its own i and still fill the chip.
 template <int MODE, int NP>
-__device__ __forceinline__ void regf_item_lanes(const RegfArgs& a, const int group,
-                                                const int s) {
+__device__ __forceinline__ void regf_item_lanes(const RegfArgs& a, const int group, const int s,
+                                                int* runs) {
     using Rec = typename RecOf<MODE>::T;
     const Rec* rec = static_cast<const Rec*>(a.rec);
     const int lane = threadIdx.x & 63;
@@ -445,7 +554,12 @@ __device__ __forceinline__ void regf_item_lanes(const RegfArgs& a, const int gro
 
     IPos<MODE> ip;
     IAux ia;
-    const int qq = load_i<MODE>(a, q, s, ip, ia);
+    (void)load_i<MODE>(a, q, s, ip, ia);
+    Staged<RUN> stg;
+    stg.run = runs;
+    stg.row0 = group * (64 >> sh);
+    stg.shift = sh;
+    stg.n = 0;
 
     const int j0 = s * a.slice_len;
     const int j1 = min(j0 + a.slice_len, a.n);
@@ -464,15 +578,17 @@ __device__ __forceinline__ void regf_item_lanes(const RegfArgs& a, const int gro
             Rec r[JG];
 #pragma unroll
             for (int g = 0; g < JG; ++g) r[g] = rec[j + g * jl];
-            lane_terms<MODE, NP, JG>(a, r, j, jl, ip, ia, run, qq);
+            lane_terms<MODE, NP, JG>(a, r, j, jl, ip, ia, run, stg);
         }
         for (; j < je; j += jl) {
             const Rec r[1] = {rec[j]};
-            lane_terms<MODE, NP, 1>(a, r, j, jl, ip, ia, run, qq);
+            lane_terms<MODE, NP, 1>(a, r, j, jl, ip, ia, run, stg);
         }
 #pragma unroll
         for (int c = 0; c < NP; ++c) sum[c] += (double)run[c];
+        if (__any(stg.n >= RUN / 2)) stg.flush_shared(a);  // uniform
     }
+    stg.flush_shared(a);
 
     for (int d = 1; d < jl; d <<= 1)
 #pragma unroll
@@ -493,7 +609,7 @@ __device__ __forceinline__ void regf_item_lanes(const RegfArgs& a, const int gro
 // VGPRs): below that the scalar-load latency of the j-records is no longer
 // hidden.
 template <int MODE, int IPL, int NP>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(IPL == 1 ? 6 : 4)))
 regf_kernel(RegfArgs a, int gblocks) {
     const int b = blockIdx.x;
     int s, gb;
@@ -507,8 +623,9 @@ regf_kernel(RegfArgs a, int gblocks) {
     }
     const int wpb = blockDim.x >> 6;
     const int group = gb * wpb + (threadIdx.x >> 6);
+    extern __shared__ int runs[];  // run_lds_bytes(wpb)
     if (group * 64 * IPL >= a.ni) return;  // uniform across the wave
-    regf_item<MODE, IPL, NP>(a, group, s);
+    regf_item<MODE, IPL, NP>(a, group, s, run_wave(runs));
 }
 
 // The force kernel for lanes that share an i (a.jl_shift > 0), with the grid
@@ -528,8 +645,9 @@ regf_lanes_kernel(RegfArgs a, int gblocks) {
     }
     const int wpb = blockDim.x >> 6;
     const int group = gb * wpb + (threadIdx.x >> 6);
+    extern __shared__ int runs[];  // run_lds_bytes(wpb)
     if (group * (64 >> a.jl_shift) >= a.ni) return;  // uniform across the wave
-    regf_item_lanes<MODE, NP>(a, group, s);
+    regf_item_lanes<MODE, NP>(a, group, s, run_wave(runs));
 }
 
 // ---------------------------------------------------------------------------
@@ -806,8 +924,10 @@ __device__ __forceinline__ long long uniform_ll(long long v) {
 // (SERVE_ONE_I, SERVE_LANES, SERVE_TWO_I) gets a launch of its own, so the
 // one-i kernel keeps the registers, hence the occupancy, of the plain one.
 template <int MODE, int CLASS>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CLASS == SERVE_ONE_I ? 6 : 4)))
 serve_regf_kernel(BatchArgs b) {
+    __shared__ int runs[WAVES * RUN * 64];
+    int* const wruns = run_wave(runs);
     const_ptr<ReqDesc> reqs = (const_ptr<ReqDesc>)(b.reqs);
     const int wpb = blockDim.x >> 6;
     const long long waves = (long long)gridDim.x * wpb;
@@ -824,11 +944,11 @@ serve_regf_kernel(BatchArgs b) {
         const int groups = reqs[lo].groups;
         const int g = (int)(local % groups), s = (int)(local / groups);
         if (CLASS == SERVE_TWO_I)
-            regf_item<MODE, 2, NPART>(a, g, s);
+            regf_item<MODE, 2, NPART>(a, g, s, wruns);
         else if (CLASS == SERVE_LANES)
-            regf_item_lanes<MODE, NPART>(a, g, s);
+            regf_item_lanes<MODE, NPART>(a, g, s, wruns);
         else
-            regf_item<MODE, 1, NPART>(a, g, s);
+            regf_item<MODE, 1, NPART>(a, g, s, wruns);
         if (waves >= b.nitems) break;  // uniform: no item beyond the first
         unsigned long long got = 0;
         if ((threadIdx.x & 63) == 0) got = atomicAdd(b.counter, 1ull);
@@ -1078,10 +1198,10 @@ static hipError_t launch_regf_t(int wpb, const RegfArgs& a, hipStream_t st) {
     if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
     if (a.jl_shift > 0)
         hipLaunchKernelGGL((regf_lanes_kernel<MODE, NP>), dim3((unsigned)blocks), dim3(64 * wpb),
-                           0, st, a, gblocks);
+                           run_lds_bytes(wpb), st, a, gblocks);
     else
         hipLaunchKernelGGL((regf_kernel<MODE, IPL, NP>), dim3((unsigned)blocks), dim3(64 * wpb),
-                           0, st, a, gblocks);
+                           run_lds_bytes(wpb), st, a, gblocks);
     return hipGetLastError();
 }
 

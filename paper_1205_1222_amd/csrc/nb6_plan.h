@@ -33,12 +33,12 @@ inline int plan_group_size(int ipl, int jl_shift) { return (64 * ipl) >> jl_shif
 
 inline Plan plan_rule(const PlanInputs& in, int64_t n, int64_t ni, int ipl) {
     Plan p;
-    // One i per lane unless asked for two: the one-i kernel holds 74 VGPRs
-    // against 106, hence more waves per SIMD, and measured faster at every
+    // One i per lane unless asked for two: the one-i kernel holds at most 80
+    // VGPRs against about 110, hence more waves per SIMD, and measured faster at every
     // block size from 512 to 2^20 active particles (at N = 2^17 and 2^20).
     p.ipl = ipl > 0 ? ipl : in.ipl_hint > 0 ? in.ipl_hint : 1;
-    // Slices are at least 256 j-particles long, and give each lane at least
-    // 32 of them.
+    // Slices are at least 256 j-particles long (but see the short slices
+    // below), and give each lane at least 32 of them.
     auto max_slices = [&](int sh) {
         const int64_t len = std::max<int64_t>(256, (int64_t)32 << sh);
         return std::max<int64_t>(1, (n + len - 1) / len);
@@ -76,8 +76,20 @@ inline Plan plan_rule(const PlanInputs& in, int64_t n, int64_t ni, int ipl) {
         const double best = std::sqrt(1.5 * (double)n / (double)(1 << sh));
         s = (int64_t)1 << (int)std::lround(std::log2(std::max(1.0, best)));
     }
-    s = std::max<int64_t>(1, std::min<int64_t>(s, in.slice_hint > 0 ? (n + 255) / 256
-                                                                   : max_slices(sh)));
+    // A one-lane-per-i block in a small cluster gives too few work items at
+    // 256 j per slice: each wavefront's chain of dependent j-loads is then
+    // the launch's duration (N = N_i = 1024: 4 slices).  Such plans may take
+    // up to sqrt(1.5 N) slices (to a power of 2 below it, as for the lanes),
+    // down to one tile of j each: measured 85 -> 37 us per call at N = N_i =
+    // 1024, 68 -> 56 us at N = 16384, N_i = 1024, and no change at N =
+    // 131072, whose 256-j slices already number more.
+    int64_t cap = max_slices(sh);
+    if (sh == 0) {
+        const double root = std::sqrt(1.5 * (double)n);
+        const int64_t lim = (int64_t)1 << (int)std::floor(std::log2(std::max(1.0, root)));
+        cap = std::max(cap, std::min<int64_t>(lim, (n + kPlanTile - 1) / kPlanTile));
+    }
+    s = std::max<int64_t>(1, std::min<int64_t>(s, in.slice_hint > 0 ? (n + 255) / 256 : cap));
     s = std::min<int64_t>(s, 65535);
     // a multiple of 8 lets the force kernel keep each slice on one XCD; the
     // count is kept even when rounding the length up to whole tiles leaves

@@ -294,7 +294,7 @@ def test_mixed_coordinate_modes(clusters):
 
 def test_admission_by_budget(clusters):
     nb6 = _nb6()
-    budget = 4 << 20
+    budget = 6 << 20
     ctx = nb6.nb6_create(0, hbm_budget=budget)
     try:
         _load_all(nb6, ctx, clusters)
@@ -305,7 +305,8 @@ def test_admission_by_budget(clusters):
         rc, _ = nb6.nb6_submit(ctx, 3, cl.tb, 1, len(big), big, cl.h2[big].copy(),
                                cl.dtr[big].copy(), h.acc, h.jerk, h.nnb, h.lst, 1023)
         assert rc == nb6.NB6_ERR_ADMISSION
-        # each fits alone (~1.5 MB) but not two at once
+        # each fits alone (3.4 to 4.4 MB: lists, staging and 32 or 64 slices of
+        # partials) but not two at once
         subs = []
         for c in range(4):
             cl = clusters[c]

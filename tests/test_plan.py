@@ -15,6 +15,7 @@ SANITIZE = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all",
 
 DRIVER = r"""
 #include "nb6_plan.h"
+#include <cmath>
 #include <cstdio>
 #include <vector>
 
@@ -67,6 +68,12 @@ int main() {
                             p.slice_len);
             // the XCD split keeps a multiple of 8 whenever it applies
             if (h[2] <= 0 && p.nslices >= 8) CHECK(p.nslices % 8 == 0, "S %d", p.nslices);
+            // more slices than one per 256 j: plans of one lane per i only,
+            // and at most sqrt(1.5 n) of them
+            if (h[2] <= 0 && (int64_t)p.nslices * 256 > n + 255)
+                CHECK(p.jl_shift == 0 && (double)p.nslices <= std::sqrt(1.5 * (double)n),
+                      "short slices: n %lld ni %lld S %d", (long long)n, (long long)ni,
+                      p.nslices);
             // a forced slice count is kept within one slice per 256 j
             if (h[2] > 0) CHECK(p.nslices <= std::max<int64_t>(1, (n + 255) / 256) &&
                                 p.nslices <= h[2], "forced S %d", p.nslices);
