@@ -588,7 +588,7 @@ __device__ __forceinline__ void regf_item_lanes(const RegfArgs& a, const int gro
         for (int c = 0; c < NP; ++c) sum[c] += (double)run[c];
         if (__any(stg.n >= RUN / 2)) stg.flush_shared(a);  // uniform
     }
-    stg.flush_shared(a);
+    if (__any(stg.n > 0)) stg.flush_shared(a);  // uniform
 
     for (int d = 1; d < jl; d <<= 1)
 #pragma unroll
