@@ -528,7 +528,8 @@ def test_everything_neighbour_long_lists(ctx, n, mode):
     """h -> infinity: every j is a neighbour.  N = 1024 fills the largest list
     exactly (1023 entries, sorted on the GPU); N = 1500 overflows it and the
     ordered overflow scan must return the first 1023 indices (in the local
-    mode it visits the particles through their slots in the spatial order)."""
+    mode it visits the particles through their slots in the spatial order).
+    Four i (lanes per i) and 300 i (one lane per i)."""
     nb6 = _nb6()
     cl = make_cluster(n, 31, masses="equal", k_nb=8)
     load(ctx, cl)
@@ -541,6 +542,19 @@ def test_everything_neighbour_long_lists(ctx, n, mode):
     assert rc == (nb6.NB6_OK if n - 1 <= cap else nb6.NB6_WARN_NB_OVERFLOW)
     for q, i in enumerate(idx):
         want = [j for j in range(n) if j != i][:cap]
+        np.testing.assert_array_equal(lst[q, :min(cap, n - 1)], want)
+    # one lane per i: every work item finds more neighbours per lane than the
+    # lane's staged run holds, so full runs, the per-neighbour reservations
+    # past them and the flushes between tiles all take part
+    idx = np.sort(np.random.Generator(np.random.PCG64(5)).choice(n, 300, replace=False))
+    idx = idx.astype(np.int32)
+    acc, jerk, nnb, lst, rc = nb6.regular_force_host(ctx, 0, idx, 1e30, cl.dtr[idx],
+                                                     MODES[mode], cap)
+    assert nb6.nb6_last_plan(ctx)[1] == 1
+    assert np.all(acc == 0.0) and np.all(jerk == 0.0)
+    assert np.all(nnb == n - 1)
+    for q, i in enumerate(idx):
+        want = np.delete(np.arange(n), i)[:cap]
         np.testing.assert_array_equal(lst[q, :min(cap, n - 1)], want)
     with pytest.raises(Exception):
         nb6.regular_force_host(ctx, 0, idx, 1e30, cl.dtr[idx], MODES[mode], cap + 1)
