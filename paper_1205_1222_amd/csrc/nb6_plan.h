@@ -76,15 +76,19 @@ inline Plan plan_rule(const PlanInputs& in, int64_t n, int64_t ni, int ipl) {
         const double best = std::sqrt(1.5 * (double)n / (double)(1 << sh));
         s = (int64_t)1 << (int)std::lround(std::log2(std::max(1.0, best)));
     }
-    // A one-lane-per-i block in a small cluster gives too few work items at
-    // 256 j per slice: each wavefront's chain of dependent j-loads is then
-    // the launch's duration (N = N_i = 1024: 4 slices).  Such plans may take
-    // up to sqrt(1.5 N) slices (to a power of 2 below it, as for the lanes),
-    // down to one tile of j each: measured 85 -> 37 us per call at N = N_i =
-    // 1024, 68 -> 56 us at N = 16384, N_i = 1024, and no change at N =
-    // 131072, whose 256-j slices already number more.
+    // A one-lane-per-i call whose 256-j slices give fewer than 8 waves per
+    // CU leaves the chip idle, and each wavefront's chain of dependent
+    // j-loads is then the launch's duration (N = N_i = 1024: 4 slices, 64
+    // waves).  Such calls may take up to sqrt(1.5 N) slices (the power of 2
+    // below it, as for the lanes), down to one tile of j each: measured 85 ->
+    // 37 us per call at N = N_i = 1024 and 68 -> 55 us at N = 16384, N_i =
+    // 1024.  Calls that already fill the chip keep 256-j slices: shorter
+    // ones only add work items, which costs the serving queue's fused
+    // batches throughput (measured on the C4 trace: 872 Gint/s at
+    // saturation with short slices wherever the root allowed them, 991 with
+    // this bound).
     int64_t cap = max_slices(sh);
-    if (sh == 0) {
+    if (sh == 0 && groups * cap < (int64_t)in.num_cu * 8) {
         const double root = std::sqrt(1.5 * (double)n);
         const int64_t lim = (int64_t)1 << (int)std::floor(std::log2(std::max(1.0, root)));
         cap = std::max(cap, std::min<int64_t>(lim, (n + kPlanTile - 1) / kPlanTile));

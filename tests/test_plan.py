@@ -69,9 +69,11 @@ int main() {
             // the XCD split keeps a multiple of 8 whenever it applies
             if (h[2] <= 0 && p.nslices >= 8) CHECK(p.nslices % 8 == 0, "S %d", p.nslices);
             // more slices than one per 256 j: plans of one lane per i only,
-            // and at most sqrt(1.5 n) of them
+            // whose 256-j slices would give fewer than 8 waves per CU, and at
+            // most sqrt(1.5 n) of them
             if (h[2] <= 0 && (int64_t)p.nslices * 256 > n + 255)
-                CHECK(p.jl_shift == 0 && (double)p.nslices <= std::sqrt(1.5 * (double)n),
+                CHECK(p.jl_shift == 0 && (double)p.nslices <= std::sqrt(1.5 * (double)n) &&
+                      groups * std::max<int64_t>(1, (n + 255) / 256) < 8 * (int64_t)cu,
                       "short slices: n %lld ni %lld S %d", (long long)n, (long long)ni,
                       p.nslices);
             // a forced slice count is kept within one slice per 256 j
