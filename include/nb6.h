@@ -108,6 +108,13 @@ typedef struct nb6_options {
  * irregular-force launch so that nb6_kernel_times() can report their GPU
  * durations. */
 #define NB6_OPT_TIMING 1
+/* Run every force call on its active particles in the caller's order.  By
+ * default a plain call whose block holds at least 8192 particles and three
+ * quarters of its cluster first sorts them by the cluster's spatial order (a
+ * counting sort over the cluster's particles), so that the particles sharing
+ * a wavefront lie close together and test fewer candidate pairs; every
+ * output is the same bits either way. */
+#define NB6_OPT_CALLER_ORDER 2
 
 /*
  * Create a context on options->device (NULL options: device 0, defaults).

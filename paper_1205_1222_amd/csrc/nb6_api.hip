@@ -199,6 +199,7 @@ int nb6_create(nb6_ctx** out, const nb6_options* opt) {
         c->slice_hint = opt->slice_hint;
         c->hbm_budget = opt->hbm_budget;
         c->timing = (opt->flags & NB6_OPT_TIMING) != 0;
+        c->iorder = (opt->flags & NB6_OPT_CALLER_ORDER) == 0;
         c->ipl_hint = opt->ipl_hint;
         c->jl_hint = opt->jl_hint;
         if (c->ipl_hint < 0 || c->ipl_hint > 2 || c->jl_hint < 0 || c->jl_hint > 64 ||
@@ -254,7 +255,8 @@ int nb6_destroy(nb6_ctx* c) {
         if (cl->last_served) (void)hipEventDestroy(cl->last_served);
         delete cl;
     }
-    for (DevBuf* b : {&c->part, &c->cnt, &c->lst, &c->io, &c->out_list, &c->order_tmp})
+    for (DevBuf* b : {&c->part, &c->cnt, &c->lst, &c->io, &c->out_list, &c->order_tmp, &c->iord,
+                       &c->iord_tmp})
         release(*b);
     if (c->pin.p) (void)hipHostFree(c->pin.p);
     for (auto& b : c->ld) release(b);
@@ -516,6 +518,10 @@ static int copy_lists_out(nb6_ctx* c, const int32_t* d_list, const int32_t* nnb,
     return NB6_OK;
 }
 
+// Smallest one-lane-per-i block that a plain call runs in the i-order (it
+// must also hold three quarters of its cluster).
+constexpr int kIOrderMin = 8192;
+
 // Device arrays of one force call: its inputs and outputs, and its scratch
 // (slice partial sums, per-i counters that must be zero on entry, list rows).
 struct ForceIO {
@@ -532,6 +538,7 @@ struct ForceScratch {
     double* part;
     int32_t* cnt;
     int32_t* lst;
+    const int32_t* iord;  // the i-order, or null
 };
 
 // Bytes of a force call's scratch for plan p: the partials of every
@@ -576,6 +583,7 @@ static int launch_force_call(nb6_ctx* c, const ClusterState* cl, int mi, int ni,
     ra.lst = fs.lst;
     ra.caps = cap + 1;  // room for the i-particle itself
     ra.status = c->status;
+    ra.iord = fs.iord;
     {
         TimedLaunch tl(c, timed ? 1 : -1, st);
         HIP_TRY(c, launch_regf(mi, p.ipl, p.wpb, io.pot != nullptr, ra, st));
@@ -604,6 +612,7 @@ static int launch_force_call(nb6_ctx* c, const ClusterState* cl, int mi, int ni,
     fa.org = ra.org;
     fa.inv = mi == MODE_LOC ? (const int32_t*)cl->inv.p : nullptr;
     fa.ivw = ra.ivw;
+    fa.iord = fs.iord;
     {
         TimedLaunch tl(c, timed ? 2 : -1, st);
         HIP_TRY(c, launch_finalize(fa, st));
@@ -718,10 +727,31 @@ int nb6_regular_force(nb6_ctx* c, int cluster, int64_t n_i, const int32_t* idx_i
         c->cnt_dirty = false;
     }
 
+    // A block of one lane per i that holds most of its cluster runs in the
+    // cluster's spatial order of its particles (the i-order): a wavefront's
+    // i then lie close together, so its lanes take the candidate branch for
+    // nearly the same j, and the branch is taken far less often.  Measured
+    // in one process against the caller's order: C3 all active, force
+    // kernel 2.2 % faster, call 1.3 % (the finalize's scattered stores and
+    // the counting sort take the rest); half of C3 active, no change; 8192
+    // and 16384 of it, 4-6 % slower (their i are too sparse to share
+    // candidates, and the candidate work bunches in few work items).  The
+    // bits of every result are the same either way.
+    const int32_t* iord = nullptr;
+    if (c->iorder && p.jl_shift == 0 && ni >= kIOrderMin && 4 * (int64_t)ni >= 3 * n &&
+        cl->order_valid && cl->inv.p) {
+        if ((rc = ensure(c, c->iord, (size_t)ni * sizeof(int32_t))) ||
+            (rc = ensure(c, c->iord_tmp, iorder_scratch_bytes(ni, n))))
+            return rc;
+        HIP_TRY(c, launch_iorder(d_idx, ni, (const int32_t*)cl->inv.p, n, c->iord_tmp.p,
+                                 c->iord_tmp.cap, (int32_t*)c->iord.p, st));
+        iord = (const int32_t*)c->iord.p;
+    }
+
     // the finalize resets the counts; until it is launched they are dirty
     c->cnt_dirty = true;
     const ForceIO io{d_idx, d_h2, d_dtr, d_acc, d_jerk, pot ? d_pot : nullptr, d_nnb, d_list};
-    const ForceScratch fs{(double*)c->part.p, d_cnt, (int32_t*)c->lst.p};
+    const ForceScratch fs{(double*)c->part.p, d_cnt, (int32_t*)c->lst.p, iord};
     if (int rc2 = launch_force_call(c, cl, mi, ni, cap, p, io, fs, st, true)) return rc2;
     c->cnt_dirty = false;
     c->last_plan = p;
@@ -804,7 +834,10 @@ int nb6_regular_force_noalloc(nb6_ctx* c, int cluster, int64_t n_i, const int32_
                         "no-allocation array holds %zu", need, fixed + per_slice, limit);
     }
     char* b = static_cast<char*>(base);
-    const ForceScratch fs{(double*)(b + off[0]), (int32_t*)(b + off[1]), (int32_t*)(b + off[2])};
+    // no i-order here: its sort would need scratch of its own (the results
+    // are the same bits without it)
+    const ForceScratch fs{(double*)(b + off[0]), (int32_t*)(b + off[1]), (int32_t*)(b + off[2]),
+                          nullptr};
     // the counters start at zero: cleared by a kernel (no memset node, so a
     // captured graph may hold the call)
     HIP_TRY(c, launch_zero_u32((unsigned*)fs.cnt, ni, st));

@@ -116,10 +116,12 @@ struct nb6_ctx {
     nb6::PinBuf pin;                                  // pinned mirror of `io`
     nb6::DevBuf ld[7];                                // HOST-mode load staging
     nb6::DevBuf order_tmp;                            // spatial-order sort scratch
+    nb6::DevBuf iord, iord_tmp;                       // a force call's i-order, its sort scratch
     unsigned* status = nullptr;                       // device status word
     std::string err;
     nb6::Plan last_plan{0, 0, 0, 0, 0};
     bool timing = false;
+    bool iorder = true;  // large plain calls run in the spatial i-order
     struct Timed { int kind; hipEvent_t a, b; };  // kind: 0 predict, 1 force, 2 finalize, 3 irregular
     std::vector<Timed> timed;                         // pending event pairs
     // Cluster states are shared with the serving queue's thread.

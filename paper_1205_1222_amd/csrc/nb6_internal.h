@@ -122,6 +122,8 @@ struct RegfArgs {
     int32_t*       lst;       // [ni][caps] neighbours in the order found
     int            caps;      // per-i list capacity (cap + 1)
     unsigned*      status;    // device status word
+    const int32_t* iord;      // [ni] or null: work position -> active position; the
+                              // partials, counts and rows are by work position
 };
 
 struct FinalArgs {
@@ -150,6 +152,7 @@ struct FinalArgs {
     const TileOrg* org;
     const int32_t* inv;
     const void*    ivw;
+    const int32_t* iord;      // the force call's i-order (null: identity)
 };
 
 // ---------------------------------------------------------------------------
@@ -319,6 +322,13 @@ hipError_t launch_predict_loc(const PredictArgs& a, hipStream_t s);
 size_t order_scratch_bytes(int64_t n);
 hipError_t launch_order(const StateRec* st, int64_t n, void* scratch, size_t scratch_bytes,
                         int32_t* perm, int32_t* inv, hipStream_t s);
+// i-order of an active block of ni positions: iord[k] = the active position
+// of the k-th particle in the spatial order inv (positions of one slot, a
+// repeated index, in either order; an index outside [0, n) sorts last).
+// scratch holds iorder_scratch_bytes(ni, n) bytes.
+size_t iorder_scratch_bytes(int64_t ni, int64_t n);
+hipError_t launch_iorder(const int32_t* idx, int ni, const int32_t* inv, int64_t n,
+                         void* scratch, size_t scratch_bytes, int32_t* iord, hipStream_t s);
 hipError_t launch_scatter(const ScatterArgs& a, hipStream_t s);
 // Widen the j-records of one mode to double position and velocity arrays.
 hipError_t launch_unpack(int mode, const void* rec, int64_t n, double* x, double* v,

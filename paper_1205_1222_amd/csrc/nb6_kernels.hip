@@ -371,19 +371,21 @@ __device__ __forceinline__ size_t part_index(int q, int s, int c, int nslices, i
     return (((size_t)(q >> 6) * nslices + s) * np + c) * 64 + (q & 63);
 }
 
-// State of active particle q for the force kernel: position, velocity,
-// neighbour radius and the i-part of the candidate radius.  Returns the list
-// row the lane appends to (row 0 for lanes without a valid i: those never
-// append, since their h2 is -1 and their candidate radius NaN).  A bad index
-// or radius is flagged once, by the work items of slice 0.
+// State of the i-particle at work position q for the force kernel (active
+// position iord[q], or q without an i-order): position, velocity, neighbour
+// radius and the i-part of the candidate radius.  Returns the list row the
+// lane appends to, q (row 0 for lanes without a valid i: those never append,
+// since their h2 is -1 and their candidate radius NaN).  A bad index or
+// radius is flagged once, by the work items of slice 0.
 template <int MODE>
 __device__ __forceinline__ int load_i(const RegfArgs& a, const int q, const int s,
                                       IPos<MODE>& ip, IAux& ia) {
     using IRec = typename IRecOf<MODE>::T;
     bool live = q < a.ni;
-    int pi = live ? a.idx[q] : 0;
-    float h2f = live ? checked_h2(a.h2[q]) : -1.0f;
-    const double dtr = live ? a.dtr[q] : 0.0;
+    const int qa = live && a.iord ? a.iord[q] : q;
+    int pi = live ? a.idx[qa] : 0;
+    float h2f = live ? checked_h2(a.h2[qa]) : -1.0f;
+    const double dtr = live ? a.dtr[qa] : 0.0;
     float dtf = (float)dtr;
     if (live) {
         unsigned bad = 0;
@@ -719,17 +721,18 @@ __device__ __forceinline__ void finalize_sums(const FinalArgs& a, const int blk,
     sh.sum[w][lane] = sum;
     __syncthreads();
     if (w == 0 && q < a.ni) {
-        if (invalid_i(a, q)) {
+        const int o = a.iord ? a.iord[q] : q;  // the active position
+        if (invalid_i(a, o)) {
             const double nan = __builtin_nan("");
-            if (c < 3) a.acc[3 * q + c] = nan;
-            else if (c < 6) a.jerk[3 * q + c - 3] = nan;
-            else a.pot[q] = nan;
+            if (c < 3) a.acc[3 * o + c] = nan;
+            else if (c < 6) a.jerk[3 * o + c - 3] = nan;
+            else a.pot[o] = nan;
         } else {
             const double t = ((sh.sum[0][lane] + sh.sum[1][lane]) + sh.sum[2][lane]) +
                              sh.sum[3][lane];
-            if (c < 3) a.acc[3 * q + c] = t;
-            else if (c < 6) a.jerk[3 * q + c - 3] = t;
-            else a.pot[q] = -t;  // the potential is minus the sum of m / r
+            if (c < 3) a.acc[3 * o + c] = t;
+            else if (c < 6) a.jerk[3 * o + c - 3] = t;
+            else a.pot[o] = -t;  // the potential is minus the sum of m / r
         }
     }
     __syncthreads();  // the LDS is reused for lists
@@ -794,10 +797,11 @@ __device__ __forceinline__ void rescan_list(const FinalArgs& a, const int q, con
     }
 }
 
-// Sorted list of particle q (wave-uniform) from its `count` found entries;
-// `first` holds entry `lane` when lane < min(count, caps).  sl: this wave's
-// LDS buffer, for lists longer than one wavefront.
-__device__ __forceinline__ void finalize_list(const FinalArgs& a, const int q,
+// Sorted list of the i at active position q (wave-uniform; its found entries
+// are in scratch row qs) from its `count` found entries; `first` holds entry
+// `lane` when lane < min(count, caps).  sl: this wave's LDS buffer, for lists
+// longer than one wavefront.
+__device__ __forceinline__ void finalize_list(const FinalArgs& a, const int q, const int qs,
                                               const int32_t self, const int count,
                                               const int32_t first, int32_t* sl) {
     const int lane = threadIdx.x & 63;
@@ -821,7 +825,7 @@ __device__ __forceinline__ void finalize_list(const FinalArgs& a, const int q,
         if (lane < count && v != self && pos < a.cap) out[pos] = v;
         return;
     }
-    const int32_t* l = a.lst + (size_t)q * a.caps;
+    const int32_t* l = a.lst + (size_t)qs * a.caps;
     for (int e = lane; e < count; e += 64) sl[e] = l[e];
     wave_sync();
     for (int e = lane; e < count; e += 64) {
@@ -847,17 +851,21 @@ __device__ __forceinline__ void finalize_block(const FinalArgs& a, const int blk
     constexpr int PPW = FINAL_PPB / 4;
     const int q0 = blk * FINAL_PPB + w * PPW;
     // every load of the wave's particles is issued before the first sort
-    int32_t self[PPW], count[PPW], first[PPW];
+    // (q0 + k: the work position, whose count and row the force kernel
+    // filled; o: the active position, which the outputs are indexed by)
+    int32_t self[PPW], count[PPW], first[PPW], o[PPW];
     bool live[PPW], ok[PPW];
 #pragma unroll
     for (int k = 0; k < PPW; ++k) {
         const int q = q0 + k;
         live[k] = q < a.ni;
-        self[k] = live[k] ? a.idx[q] : -1;
-        const float h2f = live[k] ? checked_h2(a.h2[q]) : -1.0f;
+        o[k] = live[k] && a.iord ? a.iord[q] : q;
+        self[k] = live[k] ? a.idx[o[k]] : -1;
+        const float h2f = live[k] ? checked_h2(a.h2[o[k]]) : -1.0f;
         count[k] = live[k] ? a.cnt[q] : 0;
         first[k] = live[k] && lane < a.caps ? a.lst[(size_t)q * a.caps + lane] : 0;
-        ok[k] = live[k] && self[k] >= 0 && self[k] < a.n && h2f >= 0.0f && valid_dtr(a.dtr[q]);
+        ok[k] = live[k] && self[k] >= 0 && self[k] < a.n && h2f >= 0.0f &&
+                valid_dtr(a.dtr[o[k]]);
     }
     // the count is read: reset it for the next call, and store the number of
     // neighbours (the i itself is among the found; -1 marks an invalid i)
@@ -865,11 +873,11 @@ __device__ __forceinline__ void finalize_block(const FinalArgs& a, const int blk
     for (int k = 0; k < PPW; ++k)
         if (live[k] && lane == 0) {
             a.cnt[q0 + k] = 0;
-            a.nnb[q0 + k] = ok[k] ? count[k] - 1 : -1;
+            a.nnb[o[k]] = ok[k] ? count[k] - 1 : -1;
         }
 #pragma unroll
     for (int k = 0; k < PPW; ++k)
-        if (ok[k]) finalize_list(a, q0 + k, self[k], count[k], first[k], sh.list[w]);
+        if (ok[k]) finalize_list(a, o[k], q0 + k, self[k], count[k], first[k], sh.list[w]);
 }
 
 template <int NP>
@@ -885,8 +893,8 @@ __global__ void __launch_bounds__(256) finalize_kernel(FinalArgs a) {
 // The copies below name every field (a struct copy out of the constant
 // address space does not compile); the sizes pin the field lists, so a field
 // added to an argument struct cannot be left out here unnoticed.
-static_assert(sizeof(RegfArgs) == 120, "load_regf_args must copy every RegfArgs field");
-static_assert(sizeof(FinalArgs) == 160, "load_final_args must copy every FinalArgs field");
+static_assert(sizeof(RegfArgs) == 128, "load_regf_args must copy every RegfArgs field");
+static_assert(sizeof(FinalArgs) == 168, "load_final_args must copy every FinalArgs field");
 
 __device__ __forceinline__ RegfArgs load_regf_args(const_ptr<ReqDesc> d) {
     RegfArgs a;
@@ -894,7 +902,7 @@ __device__ __forceinline__ RegfArgs load_regf_args(const_ptr<ReqDesc> d) {
     a.ni = d->rg.ni; a.slice_len = d->rg.slice_len; a.nslices = d->rg.nslices;
     a.jl_shift = d->rg.jl_shift; a.tmax = d->rg.tmax; a.org = d->rg.org; a.ivw = d->rg.ivw;
     a.part = d->rg.part; a.cnt = d->rg.cnt; a.lst = d->rg.lst; a.caps = d->rg.caps;
-    a.status = d->rg.status;
+    a.status = d->rg.status; a.iord = d->rg.iord;
     return a;
 }
 __device__ __forceinline__ FinalArgs load_final_args(const_ptr<ReqDesc> d) {
@@ -905,7 +913,7 @@ __device__ __forceinline__ FinalArgs load_final_args(const_ptr<ReqDesc> d) {
     f.list = d->fin.list;
     f.cap = d->fin.cap; f.status = d->fin.status;
     f.rec = d->fin.rec; f.dtr = d->fin.dtr; f.mode = d->fin.mode;
-    f.org = d->fin.org; f.inv = d->fin.inv; f.ivw = d->fin.ivw;
+    f.org = d->fin.org; f.inv = d->fin.inv; f.ivw = d->fin.ivw; f.iord = d->fin.iord;
     return f;
 }
 

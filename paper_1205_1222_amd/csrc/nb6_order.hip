@@ -19,9 +19,17 @@
 // The order is a function of the stored state it is built from; which state
 // that is (the runtime rebuilds it after a full load and after a cluster's
 // worth of subset updates) is decided on the host.
+//
+// launch_iorder: the i-order of an active block, its positions sorted by
+// their particles' slots in that order (a counting sort over the n slots:
+// counts, an exclusive scan, placement), so that the i-particles of one
+// wavefront of the force kernel lie close together and take the candidate
+// branch for nearly the same j.  Every i-particle's result is independent of
+// where in the launch it is computed, so the i-order changes no bits.
 #include "nb6_internal.h"
 
 #include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_scan.hpp>
 #include <rocprim/iterator/counting_iterator.hpp>
 
 namespace nb6 {
@@ -159,7 +167,68 @@ __global__ void __launch_bounds__(256) invert_kernel(const int32_t* perm, int64_
     if (k < n) inv[perm[k]] = (int32_t)k;
 }
 
+// Slot of active position q's particle in the cluster's spatial order (n
+// for an index out of range, which the force kernel flags).
+__device__ __forceinline__ int slot_of(const int32_t* idx, int q, const int32_t* inv,
+                                       int64_t n) {
+    const int32_t p = idx[q];
+    return (p >= 0 && p < n) ? inv[p] : (int)n;
+}
+
+// Counting sort of the active positions by slot: count per slot, ...
+__global__ void __launch_bounds__(256) slot_count_kernel(const int32_t* idx, int ni,
+                                                         const int32_t* inv, int64_t n,
+                                                         int* count) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < ni) atomicAdd(count + slot_of(idx, q, inv, n), 1);
+}
+
+// ... then, after the exclusive scan of the counts, place each position at
+// its slot's next free place.  Positions that share a slot (a repeated
+// index) land in either order.
+__global__ void __launch_bounds__(256) slot_place_kernel(const int32_t* idx, int ni,
+                                                         const int32_t* inv, int64_t n,
+                                                         int* next, int32_t* iord) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < ni) iord[atomicAdd(next + slot_of(idx, q, inv, n), 1)] = q;
+}
+
 }  // namespace
+
+size_t iorder_scratch_bytes(int64_t ni, int64_t n) {
+    (void)ni;
+    size_t tmp = 0;
+    (void)rocprim::exclusive_scan(nullptr, tmp, (const int*)nullptr, (int*)nullptr, 0,
+                                  (size_t)n + 1, rocprim::plus<int>());
+    const size_t cbytes = ((size_t)(n + 1) * sizeof(int) + 255) / 256 * 256;
+    return 2 * cbytes + tmp;
+}
+
+hipError_t launch_iorder(const int32_t* idx, int ni, const int32_t* inv, int64_t n,
+                         void* scratch, size_t scratch_bytes, int32_t* iord, hipStream_t s) {
+    if (ni <= 0) return hipSuccess;
+    if (n <= 0 || n >= 0x7fffffffLL) return hipErrorInvalidValue;
+    char* p = static_cast<char*>(scratch);
+    const size_t cbytes = ((size_t)(n + 1) * sizeof(int) + 255) / 256 * 256;
+    int* count = reinterpret_cast<int*>(p);
+    int* next = reinterpret_cast<int*>(p + cbytes);
+    void* tmp = p + 2 * cbytes;
+    size_t tmp_bytes = 0;
+    hipError_t e = rocprim::exclusive_scan(nullptr, tmp_bytes, count, next, 0, (size_t)n + 1,
+                                           rocprim::plus<int>(), s);
+    if (e != hipSuccess) return e;
+    if (2 * cbytes + tmp_bytes > scratch_bytes) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)((ni + 255) / 256)), block(256);
+    if ((e = launch_zero_u32(reinterpret_cast<unsigned*>(count), (int)(n + 1), s)) != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(slot_count_kernel, grid, block, 0, s, idx, ni, inv, n, count);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    e = rocprim::exclusive_scan(tmp, tmp_bytes, count, next, 0, (size_t)n + 1,
+                                rocprim::plus<int>(), s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(slot_place_kernel, grid, block, 0, s, idx, ni, inv, n, next, iord);
+    return hipGetLastError();
+}
 
 size_t order_scratch_bytes(int64_t n) {
     size_t tmp = 0;

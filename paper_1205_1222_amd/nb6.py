@@ -57,6 +57,7 @@ EXPORTED = [
 ]
 
 NB6_OPT_TIMING = 1
+NB6_OPT_CALLER_ORDER = 2
 
 
 class nb6_options(ctypes.Structure):

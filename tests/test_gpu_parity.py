@@ -787,3 +787,88 @@ def test_momentum_conservation_c1(ctx, mode):
     pj = np.linalg.norm((m * jerk).sum(0)) / np.abs(m * np.linalg.norm(jerk, axis=1)[:, None]).sum()
     _record(f"momentum_C1_{mode}", {"acc": float(pa), "jerk": float(pj)})
     assert pa <= 1e-6 and pj <= 1e-6, (pa, pj)
+
+
+@pytest.mark.parametrize("mode", ["ff", "local"])
+def test_spatial_i_order_changes_no_bits(mode):
+    """A block of at least 8192 particles that holds three quarters of its
+    cluster runs in the cluster's spatial order of its particles; a context
+    with NB6_OPT_CALLER_ORDER runs the same call in the caller's order.  Every
+    output is the same bits (with repeated particles in the block, and with an
+    index out of range, which both flag and both give a NaN row), and the
+    results match the oracle on sampled rows."""
+    import torch
+    nb6 = _nb6()
+    cl = make_cluster(10000, 41, masses="imf", k_nb=30)
+    rng = np.random.Generator(np.random.PCG64(17))
+    idx = rng.permutation(cl.n)[:9000]
+    idx = np.concatenate([idx, idx[:300]])  # 300 particles twice
+    rng.shuffle(idx)
+    idx = idx.astype(np.int32)
+    assert len(idx) >= 8192 and 4 * len(idx) >= 3 * cl.n
+    cap = 128
+    outs = []
+    for flags in (0, nb6.NB6_OPT_CALLER_ORDER):
+        c = nb6.nb6_create(0, flags=flags)
+        try:
+            load(c, cl)
+            outs.append(nb6.regular_force_host(c, 0, idx, cl.h2[idx], cl.dtr[idx], MODES[mode],
+                                               cap))
+            assert nb6.nb6_last_plan(c)[1] == 1
+        finally:
+            nb6.nb6_destroy(c)
+    (a0, j0, n0, l0, r0), (a1, j1, n1, l1, r1) = outs
+    assert r0 == r1
+    np.testing.assert_array_equal(a0, a1)
+    np.testing.assert_array_equal(j0, j1)
+    np.testing.assert_array_equal(n0, n1)
+    k = np.minimum(n0, cap)
+    for q in range(len(idx)):
+        np.testing.assert_array_equal(l0[q, :k[q]], l1[q, :k[q]])
+    # repeated particles: identical rows
+    first = {}
+    for q, p in enumerate(idx):
+        if p in first:
+            np.testing.assert_array_equal(a0[q], a0[first[p]])
+            assert n0[q] == n0[first[p]]
+        else:
+            first[p] = q
+    samp = np.sort(rng.choice(len(idx), 256, replace=False))
+    si = idx[samp]
+    xp, vp = oracle.predict(cl.x, cl.v, cl.a, cl.jerk, cl.t, cl.tb)
+    ref = oracle.regular_force(cl.m, xp, vp, si, cl.h2[si], cl.dtr[si], lcap=4096)
+    cmp_ = compare(a0[samp], j0[samp], n0[samp], l0[samp], cap, ref, cl.m, xp, vp, si,
+                   cl.h2[si], cl.dtr[si])
+    s = cmp_.summary()
+    _record(f"iorder_{mode}", s)
+    assert cmp_.list_mismatch == 0 and cmp_.nnb_mismatch == 0, s
+    assert s["acc_scaled_max"] <= 1e-6 and s["jerk_scaled_max"] <= 1e-6, s
+    # an index out of range (device arrays: no host check) in the block
+    dev = torch.device("cuda:0")
+    T = lambda a, dt=torch.float64: torch.from_numpy(np.ascontiguousarray(a)).to(dev, dt)  # noqa: E731
+    bad = idx.copy()
+    bad[4321] = cl.n
+    st = torch.cuda.current_stream()
+    res = []
+    for flags in (0, nb6.NB6_OPT_CALLER_ORDER):
+        c = nb6.nb6_create(0, flags=flags)
+        try:
+            load(c, cl)
+            acc = torch.empty((len(bad), 3), dtype=torch.float64, device=dev)
+            jerk = torch.empty_like(acc)
+            nnb = torch.empty(len(bad), dtype=torch.int32, device=dev)
+            lst = torch.empty((len(bad), cap), dtype=torch.int32, device=dev)
+            h2 = cl.h2[np.minimum(bad, cl.n - 1)]
+            dtr = cl.dtr[np.minimum(bad, cl.n - 1)]
+            nb6.check(c, nb6.nb6_regular_force(c, 0, len(bad), T(bad, torch.int32), T(h2), T(dtr),
+                                               MODES[mode], acc, jerk, nnb, lst, cap,
+                                               nb6.NB6_MEM_DEVICE, st))
+            assert nb6.nb6_sync_status(c, st) == nb6.NB6_ERR_DEVICE_INPUT
+            res.append((acc.cpu().numpy(), nnb.cpu().numpy()))
+        finally:
+            nb6.nb6_destroy(c)
+    assert np.all(np.isnan(res[0][0][4321])) and res[0][1][4321] == -1
+    np.testing.assert_array_equal(res[0][0], res[1][0])
+    np.testing.assert_array_equal(res[0][1], res[1][1])
+    ok = np.arange(len(bad)) != 4321
+    np.testing.assert_array_equal(res[0][0][ok], a0[ok])
