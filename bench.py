@@ -138,9 +138,11 @@ def counter_summary(fetch_csv, write_csv, valu_csv, copy_mib, config_line, pairs
         f"-o fetch -- {cmd}",
         f"    timeout -s KILL 120 rocprofv3 --pmc WRITE_SIZE -f csv -d {out_dir(write_csv)} "
         f"-o write -- {cmd}",
+    ] + ([
         f"    timeout -s KILL 120 rocprofv3 --pmc {' '.join(VALU_COUNTERS)} -f csv "
         f"-d {out_dir(valu_csv)} -o valu -- {cmd}",
-        f"    python3 bench.py --counter-summary {fetch_csv} {write_csv} {valu_csv} "
+    ] if valu_csv else []) + [
+        f"    python3 bench.py --counter-summary {fetch_csv} {write_csv} {valu_csv or '-'} "
         f"--copy-mib {copy_mib} --mode {mode}",
         "",
         f"Kernel: `{kernel}`; config: {config_line}; {pairs:.4g} pair interactions per launch.",

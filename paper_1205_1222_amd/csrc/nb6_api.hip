@@ -534,11 +534,20 @@ struct ForceIO {
     int32_t* nnb;
     int32_t* list;
 };
+// An i-order of the call: iord[work position] = active position, and the
+// force kernel's i-side in work order (index, radius, dtr, i-record).
+struct IOrder {
+    const int32_t* iord;
+    const int32_t* idx;
+    const double* h2;
+    const double* dtr;
+    const void* irec;
+};
 struct ForceScratch {
     double* part;
     int32_t* cnt;
     int32_t* lst;
-    const int32_t* iord;  // the i-order, or null
+    IOrder io;  // all null: the caller's order
 };
 
 // Bytes of a force call's scratch for plan p: the partials of every
@@ -566,9 +575,11 @@ static int launch_force_call(nb6_ctx* c, const ClusterState* cl, int mi, int ni,
     RegfArgs ra{};
     ra.rec = cl->rec[mi].p;
     ra.n = (int)cl->n;
-    ra.idx = io.idx;
-    ra.h2 = io.h2;
-    ra.dtr = io.dtr;
+    const bool ord = fs.io.iord != nullptr;
+    ra.idx = ord ? fs.io.idx : io.idx;
+    ra.h2 = ord ? fs.io.h2 : io.h2;
+    ra.dtr = ord ? fs.io.dtr : io.dtr;
+    ra.irec = ord ? fs.io.irec : nullptr;
     ra.ni = ni;
     ra.slice_len = p.slice_len;
     ra.nslices = p.nslices;
@@ -583,7 +594,6 @@ static int launch_force_call(nb6_ctx* c, const ClusterState* cl, int mi, int ni,
     ra.lst = fs.lst;
     ra.caps = cap + 1;  // room for the i-particle itself
     ra.status = c->status;
-    ra.iord = fs.iord;
     {
         TimedLaunch tl(c, timed ? 1 : -1, st);
         HIP_TRY(c, launch_regf(mi, p.ipl, p.wpb, io.pot != nullptr, ra, st));
@@ -612,7 +622,7 @@ static int launch_force_call(nb6_ctx* c, const ClusterState* cl, int mi, int ni,
     fa.org = ra.org;
     fa.inv = mi == MODE_LOC ? (const int32_t*)cl->inv.p : nullptr;
     fa.ivw = ra.ivw;
-    fa.iord = fs.iord;
+    fa.iord = fs.io.iord;
     {
         TimedLaunch tl(c, timed ? 2 : -1, st);
         HIP_TRY(c, launch_finalize(fa, st));
@@ -737,21 +747,38 @@ int nb6_regular_force(nb6_ctx* c, int cluster, int64_t n_i, const int32_t* idx_i
     // and 16384 of it, 4-6 % slower (their i are too sparse to share
     // candidates, and the candidate work bunches in few work items).  The
     // bits of every result are the same either way.
-    const int32_t* iord = nullptr;
+    // The force kernel reads its i-side in work order, staged contiguously:
+    // read through the i-order directly, each work item's 64 lanes would
+    // touch 64 scattered lines per array, every slice over again.
+    IOrder ord{};
     if (c->iorder && p.jl_shift == 0 && ni >= kIOrderMin && 4 * (int64_t)ni >= 3 * n &&
         cl->order_valid && cl->inv.p) {
-        if ((rc = ensure(c, c->iord, (size_t)ni * sizeof(int32_t))) ||
+        const int irec_mode = mi == MODE_LOC ? MODE_FF : mi;  // the mode's i-records
+        const size_t rb = rec_size(irec_mode);
+        Stage lay;
+        const size_t o_iord = lay.add((size_t)ni * sizeof(int32_t));
+        const size_t o_idx = lay.add((size_t)ni * sizeof(int32_t));
+        const size_t o_h2 = lay.add((size_t)ni * sizeof(double));
+        const size_t o_dtr = lay.add((size_t)ni * sizeof(double));
+        const size_t o_rec = lay.add((size_t)ni * rb);
+        if ((rc = ensure(c, c->iord, lay.end)) ||
             (rc = ensure(c, c->iord_tmp, iorder_scratch_bytes(ni, n))))
             return rc;
+        char* b = (char*)c->iord.p;
+        int32_t* iord = (int32_t*)(b + o_iord);
         HIP_TRY(c, launch_iorder(d_idx, ni, (const int32_t*)cl->inv.p, n, c->iord_tmp.p,
-                                 c->iord_tmp.cap, (int32_t*)c->iord.p, st));
-        iord = (const int32_t*)c->iord.p;
+                                 c->iord_tmp.cap, iord, st));
+        HIP_TRY(c, launch_istage(iord, ni, d_idx, d_h2, d_dtr, n, cl->rec[irec_mode].p, (int)rb,
+                                 (int32_t*)(b + o_idx), (double*)(b + o_h2),
+                                 (double*)(b + o_dtr), b + o_rec, st));
+        ord = IOrder{iord, (const int32_t*)(b + o_idx), (const double*)(b + o_h2),
+                     (const double*)(b + o_dtr), b + o_rec};
     }
 
     // the finalize resets the counts; until it is launched they are dirty
     c->cnt_dirty = true;
     const ForceIO io{d_idx, d_h2, d_dtr, d_acc, d_jerk, pot ? d_pot : nullptr, d_nnb, d_list};
-    const ForceScratch fs{(double*)c->part.p, d_cnt, (int32_t*)c->lst.p, iord};
+    const ForceScratch fs{(double*)c->part.p, d_cnt, (int32_t*)c->lst.p, ord};
     if (int rc2 = launch_force_call(c, cl, mi, ni, cap, p, io, fs, st, true)) return rc2;
     c->cnt_dirty = false;
     c->last_plan = p;
@@ -837,7 +864,7 @@ int nb6_regular_force_noalloc(nb6_ctx* c, int cluster, int64_t n_i, const int32_
     // no i-order here: its sort would need scratch of its own (the results
     // are the same bits without it)
     const ForceScratch fs{(double*)(b + off[0]), (int32_t*)(b + off[1]), (int32_t*)(b + off[2]),
-                          nullptr};
+                          IOrder{}};
     // the counters start at zero: cleared by a kernel (no memset node, so a
     // captured graph may hold the call)
     HIP_TRY(c, launch_zero_u32((unsigned*)fs.cnt, ni, st));

@@ -116,7 +116,7 @@ struct nb6_ctx {
     nb6::PinBuf pin;                                  // pinned mirror of `io`
     nb6::DevBuf ld[7];                                // HOST-mode load staging
     nb6::DevBuf order_tmp;                            // spatial-order sort scratch
-    nb6::DevBuf iord, iord_tmp;                       // a force call's i-order, its sort scratch
+    nb6::DevBuf iord, iord_tmp;                       // a call's i-order and work-order i-side; sort scratch
     unsigned* status = nullptr;                       // device status word
     std::string err;
     nb6::Plan last_plan{0, 0, 0, 0, 0};

@@ -122,8 +122,9 @@ struct RegfArgs {
     int32_t*       lst;       // [ni][caps] neighbours in the order found
     int            caps;      // per-i list capacity (cap + 1)
     unsigned*      status;    // device status word
-    const int32_t* iord;      // [ni] or null: work position -> active position; the
-                              // partials, counts and rows are by work position
+    const void*    irec;      // [ni] or null: the i-records in work order (a call run in
+                              // an i-order, whose idx, h2 and dtr are then in work
+                              // order too); null: the records by particle index
 };
 
 struct FinalArgs {
@@ -329,6 +330,13 @@ hipError_t launch_order(const StateRec* st, int64_t n, void* scratch, size_t scr
 size_t iorder_scratch_bytes(int64_t ni, int64_t n);
 hipError_t launch_iorder(const int32_t* idx, int ni, const int32_t* inv, int64_t n,
                          void* scratch, size_t scratch_bytes, int32_t* iord, hipStream_t s);
+// The force kernel's i-side in work order k = 0 .. ni-1 of an i-order:
+// widx[k] = idx[iord[k]], wh2, wdtr likewise, and wrec[k] the rec_bytes-byte
+// i-record (a multiple of 16) of particle widx[k] from irec (of particle 0
+// for an index outside [0, n), which the force kernel flags).
+hipError_t launch_istage(const int32_t* iord, int ni, const int32_t* idx, const double* h2,
+                         const double* dtr, int64_t n, const void* irec, int rec_bytes,
+                         int32_t* widx, double* wh2, double* wdtr, void* wrec, hipStream_t s);
 hipError_t launch_scatter(const ScatterArgs& a, hipStream_t s);
 // Widen the j-records of one mode to double position and velocity arrays.
 hipError_t launch_unpack(int mode, const void* rec, int64_t n, double* x, double* v,

@@ -371,21 +371,21 @@ __device__ __forceinline__ size_t part_index(int q, int s, int c, int nslices, i
     return (((size_t)(q >> 6) * nslices + s) * np + c) * 64 + (q & 63);
 }
 
-// State of the i-particle at work position q for the force kernel (active
-// position iord[q], or q without an i-order): position, velocity, neighbour
-// radius and the i-part of the candidate radius.  Returns the list row the
-// lane appends to, q (row 0 for lanes without a valid i: those never append,
-// since their h2 is -1 and their candidate radius NaN).  A bad index or
-// radius is flagged once, by the work items of slice 0.
+// State of the i-particle at work position q for the force kernel: position,
+// velocity, neighbour radius and the i-part of the candidate radius (from
+// the i-records in work order when the call runs in an i-order, else from
+// the records by particle index).  Returns the list row the lane appends to,
+// q (row 0 for lanes without a valid i: those never append, since their h2
+// is -1 and their candidate radius NaN).  A bad index or radius is flagged
+// once, by the work items of slice 0.
 template <int MODE>
 __device__ __forceinline__ int load_i(const RegfArgs& a, const int q, const int s,
                                       IPos<MODE>& ip, IAux& ia) {
     using IRec = typename IRecOf<MODE>::T;
     bool live = q < a.ni;
-    const int qa = live && a.iord ? a.iord[q] : q;
-    int pi = live ? a.idx[qa] : 0;
-    float h2f = live ? checked_h2(a.h2[qa]) : -1.0f;
-    const double dtr = live ? a.dtr[qa] : 0.0;
+    int pi = live ? a.idx[q] : 0;
+    float h2f = live ? checked_h2(a.h2[q]) : -1.0f;
+    const double dtr = live ? a.dtr[q] : 0.0;
     float dtf = (float)dtr;
     if (live) {
         unsigned bad = 0;
@@ -401,7 +401,7 @@ __device__ __forceinline__ int load_i(const RegfArgs& a, const int q, const int 
         }
     }
     const IRec* rv = static_cast<const IRec*>(MODE == MODE_LOC ? a.ivw : a.rec);  // per lane
-    get_ipos(rv[pi], ip, ia);
+    get_ipos(live && a.irec ? static_cast<const IRec*>(a.irec)[q] : rv[pi], ip, ia);
     ia.h2 = h2f;
     ia.dtr = dtf;
     ia.c = (float)((sqrt((double)h2f) + (double)dtf * (double)ia.vabs) * (1.0 + 0x1p-16));
@@ -902,7 +902,7 @@ __device__ __forceinline__ RegfArgs load_regf_args(const_ptr<ReqDesc> d) {
     a.ni = d->rg.ni; a.slice_len = d->rg.slice_len; a.nslices = d->rg.nslices;
     a.jl_shift = d->rg.jl_shift; a.tmax = d->rg.tmax; a.org = d->rg.org; a.ivw = d->rg.ivw;
     a.part = d->rg.part; a.cnt = d->rg.cnt; a.lst = d->rg.lst; a.caps = d->rg.caps;
-    a.status = d->rg.status; a.iord = d->rg.iord;
+    a.status = d->rg.status; a.irec = d->rg.irec;
     return a;
 }
 __device__ __forceinline__ FinalArgs load_final_args(const_ptr<ReqDesc> d) {

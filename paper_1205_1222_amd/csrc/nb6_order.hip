@@ -193,7 +193,37 @@ __global__ void __launch_bounds__(256) slot_place_kernel(const int32_t* idx, int
     if (q < ni) iord[atomicAdd(next + slot_of(idx, q, inv, n), 1)] = q;
 }
 
+// One work position k of an i-order: its index, radius, dtr and i-record.
+__global__ void __launch_bounds__(256) istage_kernel(const int32_t* iord, int ni,
+                                                     const int32_t* idx, const double* h2,
+                                                     const double* dtr, int64_t n,
+                                                     const uint4* irec, int words,
+                                                     int32_t* widx, double* wh2, double* wdtr,
+                                                     uint4* wrec) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= ni) return;
+    const int q = iord[k];
+    const int32_t p = idx[q];
+    widx[k] = p;
+    wh2[k] = h2[q];
+    wdtr[k] = dtr[q];
+    const uint4* src = irec + (size_t)((p >= 0 && p < n) ? p : 0) * words;
+    uint4* dst = wrec + (size_t)k * words;
+    for (int w = 0; w < words; ++w) dst[w] = src[w];
+}
+
 }  // namespace
+
+hipError_t launch_istage(const int32_t* iord, int ni, const int32_t* idx, const double* h2,
+                         const double* dtr, int64_t n, const void* irec, int rec_bytes,
+                         int32_t* widx, double* wh2, double* wdtr, void* wrec, hipStream_t s) {
+    if (ni <= 0) return hipSuccess;
+    if (rec_bytes <= 0 || rec_bytes % 16 != 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(istage_kernel, dim3((unsigned)((ni + 255) / 256)), dim3(256), 0, s, iord,
+                       ni, idx, h2, dtr, n, static_cast<const uint4*>(irec), rec_bytes / 16,
+                       widx, wh2, wdtr, static_cast<uint4*>(wrec));
+    return hipGetLastError();
+}
 
 size_t iorder_scratch_bytes(int64_t ni, int64_t n) {
     (void)ni;
