@@ -224,6 +224,8 @@ int nb6_regular_force(nb6_ctx *ctx, int cluster, int64_t n_i,
  *
  * The scratch of a call is 8 np S ceil(n_i / 64) 64 + 4 n_i + 4 n_i (cap + 1)
  * bytes (each part rounded up to 256 B; np = 6, or 7 with pot; S j-slices).
+ * It runs in the caller's order (no spatial i-order, which would need scratch
+ * of its own; see NB6_OPT_CALLER_ORDER).
  * When nb6_regular_force's plan on the same context fits the array, the call
  * takes it and both give the same bits; otherwise it takes the most slices
  * that fit (then the sums differ from nb6_regular_force's by rounding only),
