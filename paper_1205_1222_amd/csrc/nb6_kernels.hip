@@ -19,7 +19,11 @@
 //
 // Design:
 //   * i-particles live in VGPRs, IPL of them per lane (or one per 2^k lanes
-//     for small blocks).
+//     for small blocks).  A call on a large block that holds most of its
+//     cluster passes its i-side in a spatial work order (the host side sorts
+//     it), so the i of one wavefront lie close together; the partials, counts
+//     and list rows are then by work position, and the finalize writes each
+//     output at its active position.
 //   * Every lane of a wavefront reads the same j-record, so records are
 //     fetched with scalar loads into SGPRs and used directly as operands of
 //     the vector instructions: no LDS traffic and no VGPRs spent on j.
