@@ -90,10 +90,11 @@ constexpr int NPART = 6;
 constexpr int NPART_POT = 7;
 // Largest per-i list capacity (cap + 1 slots: the i itself is found too).
 constexpr int MAX_CAPS = 1024;
-// Particles per finalize workgroup for the lists; the first np ceil(ni / 64)
-// workgroups also reduce one component of the slice partials of 64
-// particles each.
-constexpr int FINAL_PPB = 8;
+// Particles per finalize workgroup for the lists, one per wave (two per
+// wave measured 2-3 us slower for blocks of 8 to 4096, the same from 16384
+// on); the first np ceil(ni / 64) workgroups also reduce one component of the
+// slice partials of 64 particles each.
+constexpr int FINAL_PPB = 4;
 __host__ __device__ inline long long final_list_blocks(long long ni) {
     return (ni + FINAL_PPB - 1) / FINAL_PPB;
 }

@@ -664,7 +664,7 @@ regf_lanes_kernel(RegfArgs a, int gblocks) {
 //            in runs of 8 slices and the run sums are combined in a fixed
 //            order, so the result depends on the slicing only (lane t of a
 //            wave reads particle 64 m + t: contiguous loads).
-//   lists -- particles 8b .. 8b + 7, two per wave: the neighbour count, and
+//   lists -- particles 4b .. 4b + 3, one per wave: the neighbour count, and
 //            the counter reset to zero for the next call.  count <= caps:
 //            every neighbour was stored, and an entry's output position is
 //            its rank among the entries (they are distinct), less one past
