@@ -567,11 +567,7 @@ static size_t force_scratch_layout(const Plan& p, int ni, int npart, int caps, s
 static int launch_force_call(nb6_ctx* c, const ClusterState* cl, int mi, int ni, int cap,
                              const Plan& p, const ForceIO& io, const ForceScratch& fs,
                              hipStream_t st, bool timed) {
-    // A small block (lanes per i) is latency-bound, not issue-bound: in the
-    // local mode it runs on the float-float records by particle index that
-    // the local stream's prediction also writes (its i-side), where each
-    // lane's records need no tile centre.
-    if (mi == MODE_LOC && p.jl_shift > 0) mi = MODE_FF;
+    mi = kernel_mode(mi, p);  // a latency-bound local-mode call: float-float
     RegfArgs ra{};
     ra.rec = cl->rec[mi].p;
     ra.n = (int)cl->n;

@@ -90,6 +90,20 @@ inline int mode_bit(int mi) {
          : mi == MODE_F32 ? NB6_DX_FP32 : NB6_DX_LOCAL;
 }
 
+// The force kernel's coordinate mode for a call in mode mi with plan p.  A
+// local-mode call with lanes per i (a small block, bound by the latency of
+// its dependent loads) runs on the float-float records by particle index
+// that the local prediction also writes (its i-side): each lane reads its own
+// records there, where the local form would add a tile-centre load and FP64
+// differences to every pair.  (The one-lane-per-i float-float kernel cannot
+// stand in the same way for other latency-bound local calls: its candidate
+// bound is the per-tile maximum speed in index order, which the local
+// prediction does not write.)  Plain and served calls take the same mode, so
+// they give the same bits.
+inline int kernel_mode(int mi, const Plan& p) {
+    return (mi == MODE_LOC && p.jl_shift > 0) ? MODE_FF : mi;
+}
+
 inline size_t rec_size(int mi) {
     return mi == MODE_FF ? sizeof(RecFF) : mi == MODE_F64 ? sizeof(RecF64)
          : mi == MODE_F32 ? sizeof(RecF32) : sizeof(RecLoc);

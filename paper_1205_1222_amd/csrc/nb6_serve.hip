@@ -99,8 +99,7 @@ struct ServeReq {
     uint64_t ticket = 0;
     nb6_request rq{};
     int mi = 0;
-    int km = 0;             // the force kernel's mode: mi, except float-float
-                            // for a local-mode request of the lanes-per-i class
+    int km = 0;             // the force kernel's mode: kernel_mode(mi, plan)
     Plan plan{};
     size_t bytes = 0, off = 0;
     ClusterState* cl = nullptr;
@@ -308,7 +307,7 @@ class Engine {
             }
             r->plan = make_plan(c_, r->cl->n, ni);
             // a small block runs on the float-float records (the plain call's rule)
-            r->km = (r->mi == MODE_LOC && serve_class(r->plan) == SERVE_LANES) ? MODE_FF : r->mi;
+            r->km = kernel_mode(r->mi, r->plan);
             r->n_submit = r->cl->n;
             // held until the request finishes: the cluster keeps its size and
             // buffers meanwhile
