@@ -819,6 +819,20 @@ def test_spatial_i_order_changes_no_bits(mode):
             nb6.nb6_destroy(c)
     (a0, j0, n0, l0, r0), (a1, j1, n1, l1, r1) = outs
     assert r0 == r1
+    # with the potential: its sums through the i-order as well
+    pots = []
+    for flags in (0, nb6.NB6_OPT_CALLER_ORDER):
+        c = nb6.nb6_create(0, flags=flags)
+        try:
+            load(c, cl)
+            res_p = nb6.regular_force_host(c, 0, idx, cl.h2[idx], cl.dtr[idx], MODES[mode], cap,
+                                           with_pot=True)
+            np.testing.assert_array_equal(res_p[0], a0)
+            pots.append(res_p[5])
+        finally:
+            nb6.nb6_destroy(c)
+    np.testing.assert_array_equal(pots[0], pots[1])
+    assert np.all(np.isfinite(pots[0])) and np.all(pots[0] < 0.0)
     np.testing.assert_array_equal(a0, a1)
     np.testing.assert_array_equal(j0, j1)
     np.testing.assert_array_equal(n0, n1)
