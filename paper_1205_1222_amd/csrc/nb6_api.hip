@@ -465,18 +465,20 @@ int nb6_predict_j(nb6_ctx* c, int cluster, double t_block, int modes, void* stre
         if (int rc = ensure(c, cl->org, (size_t)vtiles(cl->n) * sizeof(TileOrg))) return rc;
     }
     pa.tmax = (float*)cl->tmax.p;
-    pa.ff = (modes & NB6_DX_FF) ? (RecFF*)cl->rec[MODE_FF].p : nullptr;
+    // the local mode's i-side is the float-float prediction by index, which
+    // the index pass writes with its tiles' candidate bounds (a latency-bound
+    // local-mode call runs the float-float kernel on them)
+    pa.ff = (modes & NB6_DX_FF) || loc ? (RecFF*)cl->rec[MODE_FF].p : nullptr;
     pa.f64 = (modes & NB6_DX_FP64) ? (RecF64*)cl->rec[MODE_F64].p : nullptr;
     pa.f32 = (modes & NB6_DX_FP32) ? (RecF32*)cl->rec[MODE_F32].p : nullptr;
     TimedLaunch tl(c, 0, (hipStream_t)stream);
     if (pa.ff || pa.f64 || pa.f32) HIP_TRY(c, launch_predict(pa, (hipStream_t)stream));
     if (loc) {
-        // the local stream, and the float-float prediction by index as its
-        // i-side (and small blocks' stream)
+        // the local stream by slot (the index pass above wrote its i-side)
         PredictArgs pl = pa;
         pl.f64 = nullptr;
         pl.f32 = nullptr;
-        pl.ff = (RecFF*)cl->rec[MODE_FF].p;
+        pl.ff = nullptr;
         pl.loc = (RecLoc*)cl->rec[MODE_LOC].p;
         pl.org = (TileOrg*)cl->org.p;
         pl.perm = (const int32_t*)cl->perm.p;

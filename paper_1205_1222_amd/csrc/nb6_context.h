@@ -91,17 +91,18 @@ inline int mode_bit(int mi) {
 }
 
 // The force kernel's coordinate mode for a call in mode mi with plan p.  A
-// local-mode call with lanes per i (a small block, bound by the latency of
-// its dependent loads) runs on the float-float records by particle index
-// that the local prediction also writes (its i-side): each lane reads its own
-// records there, where the local form would add a tile-centre load and FP64
-// differences to every pair.  (The one-lane-per-i float-float kernel cannot
-// stand in the same way for other latency-bound local calls: its candidate
-// bound is the per-tile maximum speed in index order, which the local
-// prediction does not write.)  Plain and served calls take the same mode, so
-// they give the same bits.
+// local-mode call whose plan is latency-bound -- lanes per i (a small
+// block), or j-slices shorter than 256 (a small call in a small cluster) --
+// runs on the float-float records by particle index that the local
+// prediction also writes (its i-side, with the per-tile candidate bounds in
+// index order): such a work item spends its time on the chain of dependent
+// loads, and the local form adds a tile-centre load and FP64 differences to
+// it (measured on one box, force kernel, local against float-float: N = N_i =
+// 1024, 16.3 against 12.6 us; N_i = 1024 of 16384, 40.8 against 29.2 us;
+// from 256-j slices on the local form is the faster).  Plain and served calls
+// take the same mode, so they give the same bits.
 inline int kernel_mode(int mi, const Plan& p) {
-    return (mi == MODE_LOC && p.jl_shift > 0) ? MODE_FF : mi;
+    return (mi == MODE_LOC && (p.jl_shift > 0 || p.slice_len < 256)) ? MODE_FF : mi;
 }
 
 inline size_t rec_size(int mi) {

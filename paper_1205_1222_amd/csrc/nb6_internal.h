@@ -316,7 +316,8 @@ hipError_t launch_regf(int mode, int ipl, int waves_per_block, bool pot, const R
 __host__ __device__ inline int regf_group_size(int ipl, int jl_shift) { return (64 * ipl) >> jl_shift; }
 hipError_t launch_finalize(const FinalArgs& a, hipStream_t s);
 hipError_t launch_predict(const PredictArgs& a, hipStream_t s);
-// The local-coordinate stream: a.loc, a.org and a.ff from a.perm.
+// The local-coordinate stream: a.loc and a.org (and a.ff when set) from
+// a.perm.
 hipError_t launch_predict_loc(const PredictArgs& a, hipStream_t s);
 // Spatial order of a cluster from its stored positions: perm[slot] =
 // particle (Morton order, ties by index) and inv[particle] = slot.  scratch

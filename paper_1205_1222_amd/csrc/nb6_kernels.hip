@@ -996,11 +996,14 @@ __global__ void __launch_bounds__(256) serve_prepare_kernel(BatchArgs b) {
     for (int64_t e = base + threadIdx.x; e < base + PREPARE_CHUNK; e += blockDim.x) {
         if (e < ni) d->rg.cnt[e] = 0;
         if (d->do_predict) {  // uniform across the workgroup
-            if (d->pred.loc) {
-                predict_loc_slot(d->pred, e);
-            } else {
-                const float v = e < d->pred.n ? predict_one(d->pred, e) : 0.0f;
-                store_tile_max(d->pred, e, v);
+            // the records by index (in the local mode: the float-float ones,
+            // its i-side) with their tiles' candidate bounds ...
+            const float v = e < d->pred.n ? predict_one(d->pred, e) : 0.0f;
+            store_tile_max(d->pred, e, v);
+            if (d->pred.loc) {  // ... and the local stream by slot
+                PredictArgs q = d->pred;
+                q.ff = nullptr;
+                predict_loc_slot(q, e);
             }
         }
     }
@@ -1087,12 +1090,12 @@ __global__ void __launch_bounds__(256) predict_kernel(PredictArgs a) {
 
 // Slot k of the local-coordinate stream, by every lane of a VTILE-aligned
 // group of lanes holding slots k0 .. k0 + VTILE - 1 (lanes past the end take
-// part with empty values): predicts particle perm[k] and writes its
-// float-float record (by particle index); then the tile's centre -- the
-// midpoint of the
-// bounding box of its predicted positions, in FP64 -- and largest vabs go to
-// org[k0 / VTILE], and the slot's record holds the FP32 rounding of the
-// offset from that centre.
+// part with empty values): predicts particle perm[k] (and writes its
+// float-float record by particle index when a.ff is set; the library writes
+// those in an index pass, with their tiles' candidate bounds); then the
+// tile's centre -- the midpoint of the bounding box of its predicted
+// positions, in FP64 -- and largest vabs go to org[k0 / VTILE], and the
+// slot's record holds the FP32 rounding of the offset from that centre.
 __device__ __forceinline__ void predict_loc_slot(const PredictArgs& a, const int64_t k) {
     const bool live = k < a.n;
     Predicted P{};
@@ -1100,7 +1103,7 @@ __device__ __forceinline__ void predict_loc_slot(const PredictArgs& a, const int
     if (live) {
         p = a.perm[k];
         P = predict_particle(a, p);
-        a.ff[p] = ff_record(P);
+        if (a.ff) a.ff[p] = ff_record(P);
     }
     double lo[3], hi[3];
 #pragma unroll
@@ -1258,7 +1261,7 @@ hipError_t launch_predict(const PredictArgs& a, hipStream_t s) {
 
 hipError_t launch_predict_loc(const PredictArgs& a, hipStream_t s) {
     if (a.n <= 0) return hipSuccess;
-    if (!a.loc || !a.org || !a.perm || !a.ff) return hipErrorInvalidValue;
+    if (!a.loc || !a.org || !a.perm) return hipErrorInvalidValue;
     dim3 grid((unsigned)((a.n + 255) / 256));
     hipLaunchKernelGGL(predict_loc_kernel, grid, dim3(256), 0, s, a);
     return hipGetLastError();
