@@ -78,10 +78,11 @@ extern "C" {
  * nb6_load_particles after a full load and after a cluster's worth of subset
  * updates (it only sets how compact the tiles are, never which pairs are
  * summed).  A block small enough to share a wavefront's lanes among its
- * i-particles (at most 256 of them unless the context forces the lanes) is
- * bound by memory latency, not arithmetic: in this mode it takes the
- * float-float differences, from the float-float prediction the mode also
- * writes (as its i-side).
+ * i-particles (at most 256 of them unless the context forces the lanes), or
+ * a call whose j-slices are shorter than 256 particles (a small block in a
+ * small cluster), is bound by memory latency, not arithmetic: in this mode it
+ * takes the float-float differences, from the float-float prediction the
+ * mode also writes (as its i-side).
  */
 
 /* Largest neighbour-list capacity of nb6_regular_force. */
