@@ -38,9 +38,10 @@ inline Plan plan_rule(const PlanInputs& in, int64_t n, int64_t ni, int ipl) {
     // block size from 512 to 2^20 active particles (at N = 2^17 and 2^20).
     p.ipl = ipl > 0 ? ipl : in.ipl_hint > 0 ? in.ipl_hint : 1;
     // Slices are at least 256 j-particles long (but see the short slices
-    // below), and give each lane at least 32 of them.
-    auto max_slices = [&](int sh) {
-        const int64_t len = std::max<int64_t>(256, (int64_t)32 << sh);
+    // below), and give each lane at least 32 of them (16 for the smallest
+    // lanes plans, below).
+    auto max_slices = [&](int sh, int per_lane = 32) {
+        const int64_t len = std::max<int64_t>(256, (int64_t)per_lane << sh);
         return std::max<int64_t>(1, (n + len - 1) / len);
     };
     auto groups_of = [&](int sh) {
@@ -72,9 +73,15 @@ inline Plan plan_rule(const PlanInputs& in, int64_t n, int64_t ni, int ipl) {
     int64_t s = in.slice_hint > 0 ? in.slice_hint
                                   : std::max((target + groups - 1) / groups, (n + 16383) / 16384);
     if (lanes_plan && in.slice_hint <= 0) {
-        // measured optimum about sqrt(1.5 n / lanes), taken to a power of 2
+        // measured optimum about sqrt(1.5 n / lanes), taken to a power of 2;
+        // twice that for at most 8 groups (a few hundred waves, each one's
+        // chain of j-loads the launch's duration), down to 16 j per lane: at
+        // N = 131072 and 64 lanes, N_i = 1, 2, 4, 8 took 14.8, 15.5, 17.2,
+        // 18.9 us per call at 128 slices against 16.1, 16.7, 18.0, 19.6 at
+        // 64; from 16 on the two were the same
         const double best = std::sqrt(1.5 * (double)n / (double)(1 << sh));
         s = (int64_t)1 << (int)std::lround(std::log2(std::max(1.0, best)));
+        if (groups <= 8) s *= 2;
     }
     // A one-lane-per-i call whose 256-j slices give fewer than 8 waves per
     // CU leaves the chip idle, and each wavefront's chain of dependent
@@ -87,7 +94,7 @@ inline Plan plan_rule(const PlanInputs& in, int64_t n, int64_t ni, int ipl) {
     // batches throughput (measured on the C4 trace: 872 Gint/s at
     // saturation with short slices wherever the root allowed them, 991 with
     // this bound).
-    int64_t cap = max_slices(sh);
+    int64_t cap = lanes_plan && groups <= 8 ? max_slices(sh, 16) : max_slices(sh);
     if (sh == 0 && groups * cap < (int64_t)in.num_cu * 8) {
         const double root = std::sqrt(1.5 * (double)n);
         const int64_t lim = (int64_t)1 << (int)std::floor(std::log2(std::max(1.0, root)));
