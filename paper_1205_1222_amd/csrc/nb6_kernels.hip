@@ -607,6 +607,106 @@ __device__ __forceinline__ void regf_item_lanes(const RegfArgs& a, const int gro
     }
 }
 
+// j-records per chunk that a lanes workgroup stages through LDS: a multiple
+// of every lanes tile (TILE x 16, 32 or 64 j), so chunks nest in tiles.
+constexpr int LCHUNK = 256;
+template <int MODE> constexpr size_t lanes_stage_bytes() { return LCHUNK * sizeof(typename RecOf<MODE>::T); }
+// Staged when the workgroup has several waves and each wave reads each
+// record in several lanes (at most 32 lanes per i): LDS serves such a read
+// once for all its lanes.  At 64 lanes per i every lane reads a record of
+// its own and the vector cache was the faster (C3, N = 131072: N_i = 8 .. 64
+// took 12.3, 17.2, 18.6, 25.3 us per force kernel through it, 14.1, 21.4,
+// 21.8, 28.0 through LDS; at 32 and 16 lanes N_i = 128 and 256 took 33.4
+// and 55.2 us through it, 30.4 and 45.2 through LDS).
+__host__ __device__ constexpr bool lanes_staged(int jl_shift, int wpb) {
+    return wpb > 1 && jl_shift > 0 && jl_shift <= 5;
+}
+
+// regf_item_lanes for a workgroup of several waves (different i-groups, the
+// same slice): the workgroup copies each chunk of the slice's j-records into
+// LDS once, and every wave reads them there, where the plain form has each
+// wave load the whole slice through the vector cache (48 B per pair, the
+// launch's bound from 64 active particles on).  Each lane visits the same j
+// in the same order, folds its FP32 sums at the same tile ends and adds its
+// i's lanes in the same butterfly, so the partials have the same bits.
+// Waves without particles (live false) still copy chunks and meet every
+// barrier; the chunk loop's bounds are uniform across the workgroup.
+template <int MODE, int NP>
+__device__ __forceinline__ void regf_item_lanes_lds(const RegfArgs& a, const int group, const int s,
+                                                    int* runs, typename RecOf<MODE>::T* stage,
+                                                    const bool live) {
+    using Rec = typename RecOf<MODE>::T;
+    constexpr int P = (int)(sizeof(Rec) / sizeof(uint4));  // 16-byte pieces per record
+    static_assert(sizeof(Rec) % sizeof(uint4) == 0, "records are whole 16-byte pieces");
+    const uint4* src = static_cast<const uint4*>(a.rec);
+    uint4* dst = reinterpret_cast<uint4*>(stage);
+    const int lane = threadIdx.x & 63;
+    const int sh = a.jl_shift;
+    const int jl = 1 << sh;
+    const int jsub = lane & (jl - 1);
+    const int q = group * (64 >> sh) + (lane >> sh);
+
+    IPos<MODE> ip;
+    IAux ia;
+    if (live) (void)load_i<MODE>(a, q, s, ip, ia);
+    Staged<RUN> stg;
+    stg.run = runs;
+    stg.row0 = group * (64 >> sh);
+    stg.shift = sh;
+    stg.n = 0;
+
+    const int j0 = s * a.slice_len;
+    const int j1 = min(j0 + a.slice_len, a.n);
+
+    double sum[NP];
+#pragma unroll
+    for (int c = 0; c < NP; ++c) sum[c] = 0.0;
+
+    for (int jt = j0; jt < j1; jt += TILE * jl) {
+        const int te = min(jt + TILE * jl, j1);
+        float run[NP];
+#pragma unroll
+        for (int c = 0; c < NP; ++c) run[c] = 0.0f;
+        for (int jc = jt; jc < te; jc += LCHUNK) {
+            const int ce = min(jc + LCHUNK, te);
+            __syncthreads();  // every wave is done with the previous chunk
+            for (int e = (int)threadIdx.x; e < (ce - jc) * P; e += (int)blockDim.x)
+                dst[e] = src[(size_t)jc * P + e];
+            __syncthreads();
+            if (live) {  // uniform across the wave
+                int j = jc + jsub;  // jc - jt is a multiple of jl
+                for (; j + (JG - 1) * jl < ce; j += JG * jl) {
+                    Rec r[JG];
+#pragma unroll
+                    for (int g = 0; g < JG; ++g) r[g] = stage[j + g * jl - jc];
+                    lane_terms<MODE, NP, JG>(a, r, j, jl, ip, ia, run, stg);
+                }
+                for (; j < ce; j += jl) {
+                    const Rec r[1] = {stage[j - jc]};
+                    lane_terms<MODE, NP, 1>(a, r, j, jl, ip, ia, run, stg);
+                }
+            }
+        }
+        if (live) {
+#pragma unroll
+            for (int c = 0; c < NP; ++c) sum[c] += (double)run[c];
+            if (__any(stg.n >= RUN / 2)) stg.flush_shared(a);  // uniform
+        }
+    }
+    if (!live) return;
+    if (__any(stg.n > 0)) stg.flush_shared(a);  // uniform
+
+    for (int d = 1; d < jl; d <<= 1)
+#pragma unroll
+        for (int c = 0; c < NP; ++c) sum[c] += __shfl_xor(sum[c], d);
+
+    if (jsub == 0 && q < a.ni) {
+        double* p = a.part + part_index(q, s, 0, a.nslices, NP);
+#pragma unroll
+        for (int c = 0; c < NP; ++c) p[c * 64] = sum[c];
+    }
+}
+
 // One launch of one request: a 1-D grid of nslices x gblocks workgroups,
 // gblocks = i-groups / waves per block.  Workgroups are handed to the 8 XCDs
 // in turn (workgroup id mod 8), so when nslices is a multiple of 8 the
@@ -651,8 +751,19 @@ regf_lanes_kernel(RegfArgs a, int gblocks) {
     }
     const int wpb = blockDim.x >> 6;
     const int group = gb * wpb + (threadIdx.x >> 6);
-    extern __shared__ int runs[];  // run_lds_bytes(wpb)
-    if (group * (64 >> a.jl_shift) >= a.ni) return;  // uniform across the wave
+    // run_lds_bytes(wpb), then (several waves, not the local mode) the
+    // stage of lanes_stage_bytes<MODE>()
+    extern __shared__ int runs[];
+    const bool live = group * (64 >> a.jl_shift) < a.ni;  // uniform across the wave
+    if constexpr (MODE != MODE_LOC) {
+        if (lanes_staged(a.jl_shift, wpb)) {  // uniform across the workgroup
+            using Rec = typename RecOf<MODE>::T;
+            Rec* stage = reinterpret_cast<Rec*>(runs + (size_t)wpb * RUN * 64);
+            regf_item_lanes_lds<MODE, NP>(a, group, s, run_wave(runs), stage, live);
+            return;
+        }
+    }
+    if (!live) return;
     regf_item_lanes<MODE, NP>(a, group, s, run_wave(runs));
 }
 
@@ -1211,9 +1322,12 @@ static hipError_t launch_regf_t(int wpb, const RegfArgs& a, hipStream_t st) {
     const int gblocks = (groups + wpb - 1) / wpb;
     const long long blocks = (long long)gblocks * a.nslices;
     if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-    if (a.jl_shift > 0)
+    if (a.jl_shift > 0) {
+        const size_t stage =
+            MODE != MODE_LOC && lanes_staged(a.jl_shift, wpb) ? lanes_stage_bytes<MODE>() : 0;
         hipLaunchKernelGGL((regf_lanes_kernel<MODE, NP>), dim3((unsigned)blocks), dim3(64 * wpb),
-                           run_lds_bytes(wpb), st, a, gblocks);
+                           run_lds_bytes(wpb) + stage, st, a, gblocks);
+    }
     else
         hipLaunchKernelGGL((regf_kernel<MODE, IPL, NP>), dim3((unsigned)blocks), dim3(64 * wpb),
                            run_lds_bytes(wpb), st, a, gblocks);
