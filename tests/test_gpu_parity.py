@@ -204,6 +204,9 @@ def test_lanes_per_i(ctx):
             check_mode(c2, cl, idx, "ff", f"lanes_forced{jl}_s{hint}", ref=ref)
             check_mode(c2, cl, idx, "local", f"lanes_forced{jl}_s{hint}_local", ref=ref)
             assert nb6.nb6_last_plan(c2)[1] == jl
+            if jl == 16:  # staged through LDS: 48-byte and 32-byte records too
+                for mode in ("fp64", "fp32"):
+                    check_mode(c2, cl, idx, mode, f"lanes_forced{jl}_s{hint}_{mode}", ref=ref)
         finally:
             nb6.nb6_destroy(c2)
     for bad in ({"jl_hint": 3}, {"jl_hint": 128}, {"jl_hint": 4, "ipl_hint": 2}):

@@ -256,7 +256,9 @@ def test_plain_calls_beside_the_queue(clusters):
 def test_mixed_coordinate_modes(clusters):
     """Requests in all four coordinate modes fused into the same batches
     (one persistent launch per mode and work-partition class): each equals,
-    bit for bit, the plain call in its mode at its block time."""
+    bit for bit, the plain call in its mode at its block time.  Blocks of 200
+    take 16 lanes per i: the plain call's workgroups read the j-records from
+    LDS, the served items from the vector cache."""
     nb6 = _nb6()
     ctx = nb6.nb6_create(0)
     try:
@@ -266,7 +268,7 @@ def test_mixed_coordinate_modes(clusters):
         reqs = []
         for r in range(3):
             for c, cl in enumerate(clusters):
-                ni = int(rng.choice([40, 700]))
+                ni = int(rng.choice([40, 200, 700]))
                 idx = np.sort(rng.choice(cl.n, ni, replace=False)).astype(np.int32)
                 reqs.append((c, cl.tb + r * 2.0 ** -12, idx, modes[(r + c) % 4]))
         subs = [_submit(nb6, ctx, clusters[c], c, tb, idx, 64, mode)
