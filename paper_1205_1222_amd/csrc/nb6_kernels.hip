@@ -10,7 +10,8 @@
 //                     (i-group, j-slice) pair (section 3.3 step 6 with the
 //                     velocity criterion of section 3.2).
 //   regf_lanes_kernel the same for small active blocks, with several lanes
-//                     per i splitting the slice's j.
+//                     per i splitting the slice's j (at 16 or 32 lanes per
+//                     i the workgroup's waves read the j-records from LDS).
 //   finalize_kernel   fixed-order reduction of the j-slice partial sums and
 //                     the sorted neighbour list of each i (the reduction and
 //                     list-gathering kernels of section 3.4); the exact list
