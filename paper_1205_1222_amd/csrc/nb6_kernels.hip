@@ -791,11 +791,6 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ __forceinline__ bool invalid_i(const FinalArgs& a, int q) {
-    const int32_t self = a.idx[q];
-    return self < 0 || self >= a.n || checked_h2(a.h2[q]) < 0.0f || !valid_dtr(a.dtr[q]);
-}
-
 // LDS of the finalize kernels: the four waves' slice sums of one component,
 // and later (the same bytes) one buffer of MAX_CAPS list entries per wave.
 union FinalShared {
@@ -815,6 +810,13 @@ __device__ __forceinline__ void finalize_sums(const FinalArgs& a, const int blk,
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int q = blk * 64 + lane;
+    // the i's own entries are loaded with the partials (one round of loads
+    // for a small block); the active position first when the call ran in
+    // the spatial order
+    const bool mine = w == 0 && q < a.ni;
+    const int o = mine && a.iord ? a.iord[q] : q;
+    const int32_t self = mine ? a.idx[o] : 0;
+    const double h2 = mine ? a.h2[o] : 0.0, dtr = mine ? a.dtr[o] : 0.0;
     double sum = 0.0;
     if (q < a.ni) {
         const double* p = a.part + part_index(q, 0, c, a.nslices, NP);
@@ -836,9 +838,8 @@ __device__ __forceinline__ void finalize_sums(const FinalArgs& a, const int blk,
     }
     sh.sum[w][lane] = sum;
     __syncthreads();
-    if (w == 0 && q < a.ni) {
-        const int o = a.iord ? a.iord[q] : q;  // the active position
-        if (invalid_i(a, o)) {
+    if (mine) {
+        if (self < 0 || self >= a.n || checked_h2(h2) < 0.0f || !valid_dtr(dtr)) {
             const double nan = __builtin_nan("");
             if (c < 3) a.acc[3 * o + c] = nan;
             else if (c < 6) a.jerk[3 * o + c - 3] = nan;
