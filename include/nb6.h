@@ -78,8 +78,9 @@ extern "C" {
  * nb6_load_particles after a full load and after a cluster's worth of subset
  * updates (it only sets how compact the tiles are, never which pairs are
  * summed).  A block small enough to share a wavefront's lanes among its
- * i-particles (at most 256 of them unless the context forces the lanes), or
- * a call whose j-slices are shorter than 256 particles (a small block in a
+ * i-particles (at most 256 of them, up to 1024 in a cluster too small for
+ * one lane per i to fill the GPU, or any when the context forces the lanes),
+ * or a call whose j-slices are shorter than 256 particles (a small block in a
  * small cluster), is bound by memory latency, not arithmetic: in this mode it
  * takes the float-float differences, from the float-float prediction the
  * mode also writes (as its i-side).

@@ -54,13 +54,21 @@ inline Plan plan_rule(const PlanInputs& in, int64_t n, int64_t ni, int ipl) {
     // kernel's dependent j-loads (slice_len / lanes / 4 per lane) against
     // the finalize kernel's dependent partial loads (slices / 32).
     int sh = 0;
-    bool lanes_plan = false;
+    bool lanes_plan = false, mid_lanes = false;
     if (p.ipl == 1) {
         if (in.jl_hint > 0) {
             while ((1 << sh) < in.jl_hint) ++sh;
         } else if (ni <= 256) {
             sh = ni <= 64 ? 6 : ni <= 128 ? 5 : 4;
             lanes_plan = true;
+        } else if (ni <= 1024 && groups_of(0) * max_slices(0) < (int64_t)in.num_cu * 8) {
+            // A block of up to 1024 in a cluster too small for one lane per
+            // i to fill the chip at 256-j slices (the short slices below)
+            // takes 16 lanes per i, on slices of at least 256 j and about
+            // 4096 waves (C1, N = N_i = 1024: 18.6 -> 16.1 us per call; C2,
+            // N_i = 1024 of N = 16384: 36.0 -> 33.3 us).
+            sh = 4;
+            mid_lanes = true;
         }
     }
     p.jl_shift = sh;
@@ -83,6 +91,7 @@ inline Plan plan_rule(const PlanInputs& in, int64_t n, int64_t ni, int ipl) {
         s = (int64_t)1 << (int)std::lround(std::log2(std::max(1.0, best)));
         if (groups <= 8) s *= 2;
     }
+    if (mid_lanes && in.slice_hint <= 0) s = std::max<int64_t>(1, 4096 / groups);
     // A one-lane-per-i call whose 256-j slices give fewer than 8 waves per
     // CU leaves the chip idle, and each wavefront's chain of dependent
     // j-loads is then the launch's duration (N = N_i = 1024: 4 slices, 64
@@ -94,7 +103,7 @@ inline Plan plan_rule(const PlanInputs& in, int64_t n, int64_t ni, int ipl) {
     // batches throughput (measured on the C4 trace: 872 Gint/s at
     // saturation with short slices wherever the root allowed them, 991 with
     // this bound).
-    int64_t cap = lanes_plan && groups <= 8 ? max_slices(sh, 16) : max_slices(sh);
+    int64_t cap = (lanes_plan && groups <= 8) || mid_lanes ? max_slices(sh, 16) : max_slices(sh);
     if (sh == 0 && groups * cap < (int64_t)in.num_cu * 8) {
         const double root = std::sqrt(1.5 * (double)n);
         const int64_t lim = (int64_t)1 << (int)std::floor(std::log2(std::max(1.0, root)));

@@ -297,7 +297,10 @@ def test_mixed_coordinate_modes(clusters):
 def test_admission_by_budget(clusters):
     nb6 = _nb6()
     budget = 6 << 20
-    ctx = nb6.nb6_create(0, hbm_budget=budget)
+    # one lane per i forced, so the 600-particle requests below keep their
+    # slice counts (this cluster size would otherwise give them 16 lanes per
+    # i and fewer slices)
+    ctx = nb6.nb6_create(0, hbm_budget=budget, jl_hint=1)
     try:
         _load_all(nb6, ctx, clusters)
         cl = clusters[3]

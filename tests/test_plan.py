@@ -47,8 +47,21 @@ int main() {
             CHECK(p.jl_shift >= 0 && p.jl_shift <= 6, "shift %d", p.jl_shift);
             CHECK(p.jl_shift == 0 || p.ipl == 1, "lanes with two i per lane");
             if (p.ipl == 1 && h[1] == 0) {
-                const int want = ni <= 64 ? 6 : ni <= 128 ? 5 : ni <= 256 ? 4 : 0;
+                // up to 1024 i take 16 lanes when one lane per i would give
+                // fewer than 8 waves per CU at 256-j slices
+                const bool thin = ((ni + 63) / 64) * std::max<int64_t>(1, (n + 255) / 256) <
+                                  8 * (int64_t)cu;
+                const int want = ni <= 64 ? 6 : ni <= 128 ? 5 : ni <= 256 ? 4
+                               : ni <= 1024 && thin ? 4 : 0;
                 CHECK(p.jl_shift == want, "ni %lld shift %d", (long long)ni, p.jl_shift);
+                // and then at most one slice per 256 j, about 4096 waves
+                if (ni > 256 && want == 4 && h[2] <= 0)
+                    CHECK((int64_t)p.nslices <= std::max<int64_t>(1, (n + 255) / 256) &&
+                          (int64_t)p.nslices * ((ni + 3) / 4) <= 4096 &&
+                          (p.nslices >= 8 || (int64_t)p.nslices == std::max<int64_t>(1, std::min<int64_t>(
+                              4096 / ((ni + 3) / 4), (n + 255) / 256))),
+                          "mid lanes: n %lld ni %lld S %d len %d", (long long)n, (long long)ni,
+                          p.nslices, p.slice_len);
             }
             if (p.ipl == 1 && h[1] > 0) CHECK((1 << p.jl_shift) >= h[1], "jl hint");
             const int64_t g = nb6::plan_group_size(p.ipl, p.jl_shift);
