@@ -1043,9 +1043,10 @@ __device__ __forceinline__ long long uniform_ll(long long v) {
 // Persistent: wavefront w of the launch takes work item (request, i-group,
 // j-slice) w first, then, while the launch has fewer wavefronts W than
 // items, items W + t for tickets t = 0, 1, ... drawn from the batch counter
-// after each item.  A launch with a wavefront per item draws no ticket.  An
-// item's result depends only on its request, so a request gives the same
-// bits alone or in any batch.  Each work-partition class of request
+// after each item.  A launch with a wavefront per item draws no ticket.  The
+// lanes class does the same per workgroup, an item being four i-groups of a
+// slice.  An item's result depends only on its request, so a request gives
+// the same bits alone or in any batch.  Each work-partition class of request
 // (SERVE_ONE_I, SERVE_LANES, SERVE_TWO_I) gets a launch of its own, so the
 // one-i kernel keeps the registers, hence the occupancy, of the plain one.
 template <int MODE, int CLASS>
@@ -1054,6 +1055,45 @@ serve_regf_kernel(BatchArgs b) {
     __shared__ int runs[WAVES * RUN * 64];
     int* const wruns = run_wave(runs);
     const_ptr<ReqDesc> reqs = (const_ptr<ReqDesc>)(b.reqs);
+    if constexpr (CLASS == SERVE_LANES) {
+        // A work item per workgroup: WAVES consecutive i-groups of one
+        // slice, wave w taking the w-th, so that at 16 or 32 lanes per i the waves share the slice's
+        // j-records through LDS as the plain call's workgroups do (the same
+        // bits either way).  The item and the exit are uniform across the
+        // workgroup, and every wave meets every barrier.
+        using Rec = typename RecOf<MODE>::T;
+        __shared__ Rec stage[LCHUNK];
+        __shared__ long long next;
+        const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+        long long item = blockIdx.x;
+        while (item < b.nitems) {
+            int lo = 0, hi = b.nreq - 1;  // last request with item0 <= item
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (reqs[mid].item0 <= item) lo = mid; else hi = mid - 1;
+            }
+            const RegfArgs a = load_regf_args(reqs + lo);
+            const long long local = item - reqs[lo].item0;
+            const int groups = reqs[lo].groups;
+            const int gblocks = (groups + WAVES - 1) / WAVES;
+            const int g = (int)(local % gblocks) * WAVES + w, s = (int)(local / gblocks);
+            const bool live = g < groups;  // uniform across the wave
+            bool staged = false;
+            if constexpr (MODE != MODE_LOC) {
+                if (lanes_staged(a.jl_shift, WAVES)) {
+                    regf_item_lanes_lds<MODE, NPART>(a, g, s, wruns, stage, live);
+                    staged = true;
+                }
+            }
+            if (!staged && live) regf_item_lanes<MODE, NPART>(a, g, s, wruns);
+            if ((long long)gridDim.x >= b.nitems) break;  // no item beyond the first
+            __syncthreads();  // every wave has read `next`
+            if (threadIdx.x == 0) next = (long long)gridDim.x + (long long)atomicAdd(b.counter, 1ull);
+            __syncthreads();
+            item = next;
+        }
+        return;
+    }
     const int wpb = blockDim.x >> 6;
     const long long waves = (long long)gridDim.x * wpb;
     long long item = (long long)blockIdx.x * wpb +
@@ -1070,8 +1110,6 @@ serve_regf_kernel(BatchArgs b) {
         const int g = (int)(local % groups), s = (int)(local / groups);
         if (CLASS == SERVE_TWO_I)
             regf_item<MODE, 2, NPART>(a, g, s, wruns);
-        else if (CLASS == SERVE_LANES)
-            regf_item_lanes<MODE, NPART>(a, g, s, wruns);
         else
             regf_item<MODE, 1, NPART>(a, g, s, wruns);
         if (waves >= b.nitems) break;  // uniform: no item beyond the first

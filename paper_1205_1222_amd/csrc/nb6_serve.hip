@@ -54,6 +54,14 @@ int serve_class(const Plan& p) {
     return p.jl_shift > 0 ? SERVE_LANES : p.ipl == 2 ? SERVE_TWO_I : SERVE_ONE_I;
 }
 
+// Work items of a request in its class's persistent launch: one per
+// (i-group, slice), or for the lanes class one per (four i-groups, slice),
+// which a workgroup takes whole.
+long long serve_items(int groups, const Plan& p) {
+    const long long units = serve_class(p) == SERVE_LANES ? (groups + 3) / 4 : groups;
+    return units * p.nslices;
+}
+
 // What a batch uploads ahead of its descriptors, zeroed on the host: the
 // persistent kernels' work-item counters (one per coordinate mode and
 // i-per-lane class) and the requests' status words.  Header and descriptors
@@ -669,7 +677,7 @@ class Engine {
             d.groups = (ni + gsize - 1) / gsize;
             d.item0 = item_in_mode;
             d.blk0 = blk0;
-            item_in_mode += (long long)d.groups * p.nslices;
+            item_in_mode += serve_items(d.groups, p);
             blk0 += final_blocks(ni, NPART);
             chunk_need = std::max<int64_t>(chunk_need, std::max<int64_t>(cl->n, ni));
         }
@@ -684,19 +692,21 @@ class Engine {
         all.nblk_total = blk0;
         HIP_TRY(nullptr, launch_serve_prepare(
                         all, (int)((chunk_need + PREPARE_CHUNK - 1) / PREPARE_CHUNK), st));
-        // one persistent force launch per class present: a wave per work item
-        // up to the number of waves the chip holds at the kernel's occupancy
+        // one persistent force launch per class present: a wave (lanes class:
+        // a workgroup) per work item up to the number the chip holds at the
+        // kernel's occupancy
         for (int b = 0; b < nreq;) {
             int e = b;
             long long items = 0;
             const int cls = launch_class(reqs[b]);
             while (e < nreq && launch_class(reqs[e]) == cls) {
-                items += (long long)sl.host_desc()[e].groups * reqs[e]->plan.nslices;
+                items += serve_items(sl.host_desc()[e].groups, reqs[e]->plan);
                 ++e;
             }
             const int mi = reqs[b]->km, k = serve_class(reqs[b]->plan);
             const long long fit = (long long)c_->num_cu * blocks_per_cu_[mi][k];
-            const int blocks = (int)std::min<long long>(fit, (items + 3) / 4);
+            const int blocks =
+                (int)std::min<long long>(fit, k == SERVE_LANES ? items : (items + 3) / 4);
             BatchArgs g{};
             g.reqs = sl.dev_desc() + b;
             g.nreq = e - b;
