@@ -608,8 +608,9 @@ __device__ __forceinline__ void regf_item_lanes(const RegfArgs& a, const int gro
     }
 }
 
-// j-records per chunk that a lanes workgroup stages through LDS: a multiple
-// of every lanes tile (TILE x 16, 32 or 64 j), so chunks nest in tiles.
+// j-records per chunk that a lanes workgroup stages through LDS: it divides
+// the tile of 16, 32 or 64 lanes per i (TILE x 16 .. TILE x 64 j), so chunks
+// nest in tiles (the smaller tiles of forced lane counts are one chunk each).
 constexpr int LCHUNK = 256;
 template <int MODE> constexpr size_t lanes_stage_bytes() { return LCHUNK * sizeof(typename RecOf<MODE>::T); }
 // Staged when the workgroup has several waves and each wave reads each
@@ -626,10 +627,11 @@ __host__ __device__ constexpr bool lanes_staged(int jl_shift, int wpb) {
 // regf_item_lanes for a workgroup of several waves (different i-groups, the
 // same slice): the workgroup copies each chunk of the slice's j-records into
 // LDS once, and every wave reads them there, where the plain form has each
-// wave load the whole slice through the vector cache (48 B per pair, the
-// launch's bound from 64 active particles on).  Each lane visits the same j
-// in the same order, folds its FP32 sums at the same tile ends and adds its
-// i's lanes in the same butterfly, so the partials have the same bits.
+// wave load the whole slice through the vector cache (a record per pair and
+// lane, which the waves of small blocks mostly wait for).  Each lane visits
+// the same j in the same order, folds its FP32 sums at the same tile ends
+// and adds its i's lanes in the same butterfly, so the partials have the
+// same bits.
 // Waves without particles (live false) still copy chunks and meet every
 // barrier; the chunk loop's bounds are uniform across the workgroup.
 template <int MODE, int NP>
@@ -736,7 +738,8 @@ regf_kernel(RegfArgs a, int gblocks) {
 }
 
 // The force kernel for lanes that share an i (a.jl_shift > 0), with the grid
-// and XCD mapping of regf_kernel.
+// and XCD mapping of regf_kernel; a workgroup of several waves at 16 or 32
+// lanes per i stages its slice's j-records through LDS.
 template <int MODE, int NP>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
 regf_lanes_kernel(RegfArgs a, int gblocks) {
