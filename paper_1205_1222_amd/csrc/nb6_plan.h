@@ -50,18 +50,21 @@ inline Plan plan_rule(const PlanInputs& in, int64_t n, int64_t ni, int ipl) {
     };
     // Lanes per i.  A block of at most 256 is latency-bound, not
     // throughput-bound: its i share the lanes of a wavefront (64 lanes per i
-    // up to 64 i, then 16, whose workgroups share the j-records through LDS:
-    // at N = 131072, N_i = 128 took 34.5 us per call with 16 lanes on 128
-    // slices against 36.5 with 32 on 64), with slices sized to balance the
-    // force kernel's dependent j-loads (slice_len / lanes / 4 per lane)
-    // against the finalize kernel's dependent partial loads (slices / 32).
+    // up to 64 i, then 16 and 8, whose workgroups share the j-records
+    // through LDS: at N = 131072, N_i = 128 took 34.5 us per call with 16
+    // lanes on 128 slices against 36.5 with 32 on 64, and N_i = 160, 200,
+    // 256 took 40.0-40.9, 44.4-44.7, 45.0-45.2 us with 8 lanes on 128 slices
+    // against 41.9-44.1, 44.5-47.7, 48.8-50.8 with 16), with slices sized to
+    // balance the force kernel's dependent j-loads (slice_len / lanes / 4
+    // per lane) against the finalize kernel's dependent partial loads
+    // (slices / 32).
     int sh = 0;
     bool lanes_plan = false, mid_lanes = false;
     if (p.ipl == 1) {
         if (in.jl_hint > 0) {
             while ((1 << sh) < in.jl_hint) ++sh;
         } else if (ni <= 256) {
-            sh = ni <= 64 ? 6 : 4;
+            sh = ni <= 64 ? 6 : ni <= 128 ? 4 : 3;
             lanes_plan = true;
         } else if (ni <= 1024 && groups_of(0) * max_slices(0) < (int64_t)in.num_cu * 8) {
             // A block of up to 1024 in a cluster too small for one lane per

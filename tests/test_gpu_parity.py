@@ -192,7 +192,7 @@ def test_lanes_per_i(ctx):
         import torch
         cus = torch.cuda.get_device_properties(0).multi_processor_count
         thin = -(-ni // 64) * max(1, -(-cl.n // 256)) < 8 * cus
-        assert lanes == (64 if ni <= 64 else 16 if ni <= 256
+        assert lanes == (64 if ni <= 64 else 16 if ni <= 128 else 8 if ni <= 256
                          else 16 if ni <= 1024 and thin else 1)
         # each lane takes at least 32 j of a slice (16 for blocks of at most
         # 8 groups, whose few waves are latency-bound, and for the blocks of

@@ -257,7 +257,7 @@ def test_mixed_coordinate_modes(clusters):
     """Requests in all four coordinate modes fused into the same batches
     (one persistent launch per mode and work-partition class): each equals,
     bit for bit, the plain call in its mode at its block time.  Blocks of 200
-    take 16 lanes per i, and blocks of 40 64 lanes per i: workgroups that
+    take 8 lanes per i, and blocks of 40 64 lanes per i: workgroups that
     share the j-records through LDS in the one case (a plain launch of
     several waves, a served workgroup item), lanes that read them from the
     vector cache in the other."""

@@ -51,7 +51,7 @@ int main() {
                 // fewer than 8 waves per CU at 256-j slices
                 const bool thin = ((ni + 63) / 64) * std::max<int64_t>(1, (n + 255) / 256) <
                                   8 * (int64_t)cu;
-                const int want = ni <= 64 ? 6 : ni <= 256 ? 4
+                const int want = ni <= 64 ? 6 : ni <= 128 ? 4 : ni <= 256 ? 3
                                : ni <= 1024 && thin ? 4 : 0;
                 CHECK(p.jl_shift == want, "ni %lld shift %d", (long long)ni, p.jl_shift);
                 // and then at most one slice per 256 j, about 4096 waves
