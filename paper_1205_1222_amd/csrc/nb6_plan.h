@@ -69,10 +69,14 @@ inline Plan plan_rule(const PlanInputs& in, int64_t n, int64_t ni, int ipl) {
         } else if (ni <= 1024 && groups_of(0) * max_slices(0) < (int64_t)in.num_cu * 8) {
             // A block of up to 1024 in a cluster too small for one lane per
             // i to fill the chip at 256-j slices (the short slices below)
-            // takes 16 lanes per i, on slices of at least 256 j and about
-            // 4096 waves (C1, N = N_i = 1024: 18.6 -> 16.1 us per call; C2,
-            // N_i = 1024 of N = 16384: 36.0 -> 33.3 us).
-            sh = 4;
+            // takes lanes per i, on slices of at least 256 j and about 4096
+            // waves: the power of 2 nearest 1024 / sqrt(N) lanes, 8 to 32
+            // (measured best at N = 1024, 4096, 16384 for N_i = 300, 512,
+            // 1024: 32, 16, 8 lanes; C1, N = N_i = 1024: 18.6 us per call
+            // with one lane per i, 16.5 with 32 lanes; C2, N_i = 1024 of
+            // N = 16384: 36.0 and 31.6 with 8 lanes).
+            const double best = 1024.0 / std::sqrt((double)n);
+            sh = std::min(5, std::max(3, (int)std::lround(std::log2(best))));
             mid_lanes = true;
         }
     }
@@ -108,7 +112,9 @@ inline Plan plan_rule(const PlanInputs& in, int64_t n, int64_t ni, int ipl) {
     // batches throughput (measured on the C4 trace: 872 Gint/s at
     // saturation with short slices wherever the root allowed them, 991 with
     // this bound).
-    int64_t cap = (lanes_plan && groups <= 8) || mid_lanes ? max_slices(sh, 16) : max_slices(sh);
+    int64_t cap = lanes_plan && groups <= 8 ? max_slices(sh, 16)
+                : mid_lanes                  ? max_slices(sh, 8)
+                                             : max_slices(sh);
     if (sh == 0 && groups * cap < (int64_t)in.num_cu * 8) {
         const double root = std::sqrt(1.5 * (double)n);
         const int64_t lim = (int64_t)1 << (int)std::floor(std::log2(std::max(1.0, root)));

@@ -187,19 +187,20 @@ def test_lanes_per_i(ctx):
         ipl, lanes, slices, slen = nb6.nb6_last_plan(ctx)
         print("plan", ni, ipl, lanes, slices, slen, flush=True)
         assert ipl == 1
-        # up to 1024 i take 16 lanes where one lane per i at 256-j slices
-        # would give fewer than 8 waves per CU
+        # up to 1024 i take 32, 16 or 8 lanes (by cluster size) where one
+        # lane per i at 256-j slices would give fewer than 8 waves per CU
         import torch
         cus = torch.cuda.get_device_properties(0).multi_processor_count
         thin = -(-ni // 64) * max(1, -(-cl.n // 256)) < 8 * cus
+        mid = 32 if cl.n <= 2048 else 16 if cl.n <= 8192 else 8
         assert lanes == (64 if ni <= 64 else 16 if ni <= 128 else 8 if ni <= 256
-                         else 16 if ni <= 1024 and thin else 1)
+                         else mid if ni <= 1024 and thin else 1)
         # each lane takes at least 32 j of a slice (16 for blocks of at most
-        # 8 groups, whose few waves are latency-bound, and for the blocks of
-        # more than 256, whose slices are at least 256 j)
+        # 8 groups, whose few waves are latency-bound; the blocks of more than
+        # 256 have slices of at least 256 j)
         groups = -(-ni // (64 // lanes))
-        per_lane = 16 if groups <= 8 or ni > 256 else 32
-        assert slen >= per_lane * lanes and slices * slen >= cl.n
+        min_len = 256 if ni > 256 else (16 if groups <= 8 else 32) * lanes
+        assert slen >= min(min_len, cl.n) and slices * slen >= cl.n
     idx = np.sort(rng.choice(cl.n, 3, replace=False)).astype(np.int32)
     for mode in ("fp64", "fp32"):
         check_mode(ctx, cl, idx, mode, f"lanes_auto_n3_{mode}")
@@ -543,7 +544,7 @@ def test_everything_neighbour_long_lists(ctx, n, mode):
     exactly (1023 entries, sorted on the GPU); N = 1500 overflows it and the
     ordered overflow scan must return the first 1023 indices (in the local
     mode it visits the particles through their slots in the spatial order).
-    Four i (64 lanes per i) and 300 i (16 lanes per i, and one lane per i)."""
+    Four i (64 lanes per i) and 300 i (32 lanes per i, and one lane per i)."""
     nb6 = _nb6()
     cl = make_cluster(n, 31, masses="equal", k_nb=8)
     load(ctx, cl)
@@ -557,7 +558,7 @@ def test_everything_neighbour_long_lists(ctx, n, mode):
     for q, i in enumerate(idx):
         want = [j for j in range(n) if j != i][:cap]
         np.testing.assert_array_equal(lst[q, :min(cap, n - 1)], want)
-    # 300 i: 16 lanes per i (a cluster this small), then one lane per i
+    # 300 i: 32 lanes per i (a cluster this small), then one lane per i
     # (forced): every work item finds more neighbours per lane than the
     # lane's staged run holds, so full runs, the per-neighbour reservations
     # past them and the flushes between tiles all take part
@@ -566,7 +567,7 @@ def test_everything_neighbour_long_lists(ctx, n, mode):
     one = nb6.nb6_create(0, jl_hint=1)
     try:
         load(one, cl)
-        for c, lanes in ((ctx, 16), (one, 1)):
+        for c, lanes in ((ctx, 32), (one, 1)):
             acc, jerk, nnb, lst, rc = nb6.regular_force_host(c, 0, idx, 1e30, cl.dtr[idx],
                                                              MODES[mode], cap)
             assert nb6.nb6_last_plan(c)[1] == lanes
@@ -702,7 +703,7 @@ def test_two_i_per_lane(mode):
     got = {}
     for ipl in (2, 1):
         # one lane per i forced: this block in this cluster would otherwise
-        # take 16 lanes per i
+        # take lanes per i
         c = nb6.nb6_create(0, ipl_hint=ipl, slice_hint=24, jl_hint=1 if ipl == 1 else 0)
         try:
             load(c, cl)

@@ -300,8 +300,8 @@ def test_admission_by_budget(clusters):
     nb6 = _nb6()
     budget = 6 << 20
     # one lane per i forced, so the 600-particle requests below keep their
-    # slice counts (this cluster size would otherwise give them 16 lanes per
-    # i and fewer slices)
+    # slice counts (this cluster size would otherwise give them lanes per i
+    # and fewer slices)
     ctx = nb6.nb6_create(0, hbm_budget=budget, jl_hint=1)
     try:
         _load_all(nb6, ctx, clusters)

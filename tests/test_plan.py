@@ -28,8 +28,9 @@ int main() {
     const std::vector<std::vector<int>> hints = {   // ipl, jl, slice
         {0, 0, 0}, {1, 0, 0}, {2, 0, 0}, {0, 16, 0}, {0, 64, 0}, {0, 3, 0},
         {0, 0, 1}, {0, 0, 7}, {0, 0, 40}, {2, 0, 9}};
-    const std::vector<int64_t> ns = {1, 2, 31, 32, 33, 255, 256, 257, 1000, 1024, 16383,
-                                     16384, 131072, 131073, 1048576, 2097155};
+    const std::vector<int64_t> ns = {1, 2, 31, 32, 33, 255, 256, 257, 1000, 1024, 2048, 2049,
+                                     8192, 8193, 16383, 16384, 131072, 131073, 1048576,
+                                     2097155};
     const std::vector<int64_t> nis = {1, 2, 63, 64, 65, 128, 129, 256, 257, 1000, 4096,
                                       131072, 1048576};
     long cases = 0;
@@ -47,19 +48,25 @@ int main() {
             CHECK(p.jl_shift >= 0 && p.jl_shift <= 6, "shift %d", p.jl_shift);
             CHECK(p.jl_shift == 0 || p.ipl == 1, "lanes with two i per lane");
             if (p.ipl == 1 && h[1] == 0) {
-                // up to 1024 i take 16 lanes when one lane per i would give
-                // fewer than 8 waves per CU at 256-j slices
+                // up to 1024 i take 8 to 32 lanes when one lane per i would
+                // give fewer than 8 waves per CU at 256-j slices
                 const bool thin = ((ni + 63) / 64) * std::max<int64_t>(1, (n + 255) / 256) <
                                   8 * (int64_t)cu;
-                const int want = ni <= 64 ? 6 : ni <= 128 ? 4 : ni <= 256 ? 3
-                               : ni <= 1024 && thin ? 4 : 0;
-                CHECK(p.jl_shift == want, "ni %lld shift %d", (long long)ni, p.jl_shift);
+                const bool mid = ni > 256 && ni <= 1024 && thin;
+                const int want = ni <= 64 ? 6 : ni <= 128 ? 4 : ni <= 256 ? 3 : mid ? -1 : 0;
+                if (want >= 0)
+                    CHECK(p.jl_shift == want, "ni %lld shift %d", (long long)ni, p.jl_shift);
+                else  // fewer lanes for the larger clusters
+                    CHECK(p.jl_shift == (n <= 2048 ? 5 : n <= 8192 ? 4 : 3),
+                          "mid lanes: n %lld ni %lld shift %d", (long long)n, (long long)ni,
+                          p.jl_shift);
                 // and then at most one slice per 256 j, about 4096 waves
-                if (ni > 256 && want == 4 && h[2] <= 0)
+                const int64_t g = (ni + (64 >> p.jl_shift) - 1) / (64 >> p.jl_shift);
+                if (mid && h[2] <= 0)
                     CHECK((int64_t)p.nslices <= std::max<int64_t>(1, (n + 255) / 256) &&
-                          (int64_t)p.nslices * ((ni + 3) / 4) <= 4096 &&
+                          (int64_t)p.nslices * g <= 4096 &&
                           (p.nslices >= 8 || (int64_t)p.nslices == std::max<int64_t>(1, std::min<int64_t>(
-                              4096 / ((ni + 3) / 4), (n + 255) / 256))),
+                              4096 / g, (n + 255) / 256))),
                           "mid lanes: n %lld ni %lld S %d len %d", (long long)n, (long long)ni,
                           p.nslices, p.slice_len);
             }
