@@ -72,9 +72,10 @@ inline Plan plan_rule(const PlanInputs& in, int64_t n, int64_t ni, int ipl) {
             // takes lanes per i, on slices of at least 256 j and about 4096
             // waves: the power of 2 nearest 1024 / sqrt(N) lanes, 8 to 32
             // (measured best at N = 1024, 4096, 16384 for N_i = 300, 512,
-            // 1024: 32, 16, 8 lanes; C1, N = N_i = 1024: 18.6 us per call
-            // with one lane per i, 16.5 with 32 lanes; C2, N_i = 1024 of
-            // N = 16384: 36.0 and 31.6 with 8 lanes).
+            // 1024: 32, 16, 8 lanes; in one sweep, C1, N = N_i = 1024: 18.6
+            // us per call with one lane per i, 15.3 with 32 lanes on 4
+            // slices; C2, N_i = 1024 of N = 16384: 36.0 and 31.9 with 8
+            // lanes on 32 slices).
             const double best = 1024.0 / std::sqrt((double)n);
             sh = std::min(5, std::max(3, (int)std::lround(std::log2(best))));
             mid_lanes = true;
