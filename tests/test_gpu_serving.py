@@ -2,7 +2,8 @@
 
 * every served result matches the FP64 oracle (same bars as the plain path);
 * a request gives bit-identical results alone and fused with others;
-* served results equal the plain call's when both use one i per lane;
+* served results equal the plain call's when both use one i per lane, and
+  under lanes per i (staged or not, forced lane counts, ragged slices);
 * requests of C4's size (32768- and 65536-body clusters, blocks of up to all
   their particles) fused with small ones match the oracle on sampled rows;
 * admission: a request larger than the HBM budget is refused; requests that
@@ -167,6 +168,44 @@ def test_served_equals_plain_call(clusters, hint, c, step, ni_max, mode):
         for q in range(len(idx)):
             k = min(64, nnb[q])
             np.testing.assert_array_equal(lst[q, :k], h.lst[q, :k])
+    finally:
+        nb6.nb6_destroy(ctx)
+
+
+@pytest.mark.parametrize("jl", [2, 8, 32])
+def test_served_lanes_items_forced_lane_counts(clusters, jl):
+    """Lanes-class requests under forced lane counts and ragged slices, fused
+    into one batch: the served workgroup items (staged through LDS, with idle
+    waves when a request has fewer i-groups than the workgroup has waves)
+    give the plain call's bits, whose single-wave workgroups read the
+    vector cache and whose larger ones stage too."""
+    nb6 = _nb6()
+    ctx = nb6.nb6_create(0, jl_hint=jl, slice_hint=3)
+    try:
+        _load_all(nb6, ctx, clusters)
+        rng = np.random.Generator(np.random.PCG64(jl))
+        reqs = []
+        for c, cl in enumerate(clusters):
+            for ni, mode in ((5, 1), (70, 8), (200, 1)):
+                idx = np.sort(rng.choice(cl.n, ni, replace=False)).astype(np.int32)
+                reqs.append((c, idx, mode))
+        subs = [_submit(nb6, ctx, clusters[c], c, clusters[c].tb, idx, 64, mode)
+                for c, idx, mode in reqs]
+        for t, h in subs:
+            rc, _ = nb6.nb6_poll(ctx, t, wait=1)
+            assert rc in (nb6.NB6_OK, nb6.NB6_WARN_NB_OVERFLOW)
+        for (t, h), (c, idx, mode) in zip(subs, reqs):
+            cl = clusters[c]
+            nb6.check(ctx, nb6.nb6_predict_j(ctx, c, cl.tb, mode))
+            acc, jerk, nnb, lst, _ = nb6.regular_force_host(ctx, c, idx, cl.h2[idx],
+                                                            cl.dtr[idx], mode, 64)
+            assert nb6.nb6_last_plan(ctx)[1] == jl
+            np.testing.assert_array_equal(acc, h.acc)
+            np.testing.assert_array_equal(jerk, h.jerk)
+            np.testing.assert_array_equal(nnb, h.nnb)
+            for q in range(len(idx)):
+                k = min(64, nnb[q])
+                np.testing.assert_array_equal(lst[q, :k], h.lst[q, :k])
     finally:
         nb6.nb6_destroy(ctx)
 
